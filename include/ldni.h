@@ -1,0 +1,156 @@
+/*
+ * ldni.h -- C ABI of the MI355X (gfx950) Layered Depth-Normal Image sampler.
+ *
+ * Implements the sampling step of Wang & Chen, "Layered Depth-Normal Images:
+ * a Sparse Implicit Representation of Solid Models": a closed triangle mesh
+ * is turned into three LDNIs, one per world axis (Sec. 2, Definitions 1-3;
+ * Sec. 3 builds them by rasterisation).  For axis a, a w x w grid of rays
+ * parallel to a passes through the pixel centres (Sec. 3, "centre of
+ * pixel"); every intersection of a ray with a triangle, except with faces
+ * parallel to the ray (the note after Definition 1), becomes a Hermite
+ * sample (depth, unit face normal) (Definition 2; accurate normal sampling
+ * in Sec. 3), and each pixel's samples are stored in ascending depth order
+ * (Definition 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Frame.   Axis a images the two other axes cyclically:
+ *           a=x -> (u,v)=(y,z), a=y -> (z,x), a=z -> (x,y).  Pixel (i,j) is
+ *           p = j*w + i, i along u, j along v.
+ *  Centres. c_u[i] = f32(lo_u + (i + 0.5) * h_u) evaluated in float64 with
+ *           h_u = (hi_u - lo_u) / w; the same formula on every axis, so the
+ *           rays of the three images meet at the nodes of one w^3 grid
+ *           (Definition 3).  Boxes need not be cubic.
+ *  Hits.    Vertices are translated into the ray frame in float32 and the
+ *           three edge functions are evaluated with exact signs; a ray that
+ *           meets an edge or vertex exactly is decided as if moved to
+ *           (+eps, +eps^2) in (u,v).  A non-silhouette edge or vertex is thus
+ *           owned by exactly one triangle and a silhouette gives 0 or 2 hits,
+ *           so every ray through a closed mesh has an even count
+ *           (Remark 1, Definition 4).  Rays are infinite lines: hits outside
+ *           the box along the axis are kept.
+ *  Depth.   float32 distance from lo_a along +a, from a float64 barycentric
+ *           interpolation of the hit triangle's axis coordinates; a zero
+ *           depth is stored as +0.
+ *  Normal.  float32 unit normal of the hit face, (B-A)x(C-A) normalised in
+ *           float64, in world (x,y,z) order, never flipped toward the ray
+ *           (outward for counter-clockwise-outward meshes).
+ *  Order.   Per pixel by depth, equal depths by ascending triangle id.
+ *  Layout.  Per axis, compact rows: offsets[w*w+1] (u32, exclusive prefix
+ *           sums, offsets[w*w] = n), then depth[n], normal[n][3], tri[n].
+ *  Device.  All pointers named "device" refer to memory of the current HIP
+ *           device.  All work is ordered on the given hipStream_t (NULL =
+ *           the null stream).  Inputs are read-only and stay owned by the
+ *           caller; they must stay valid until the call (or the plan) ends.
+ *  Errors.  Every call returns an ldni_status and never throws; on error
+ *           every output handle is set to NULL.  Argument errors are found
+ *           on the host before any GPU work; index, non-finite and overflow
+ *           errors are found on the device and reported at the call's
+ *           synchronisation point.  ldni_last_error() gives a thread-local
+ *           message for the last failing call.
+ *  Limits.  1 <= w <= 16384; fewer than 2^32 samples per axis; triangle
+ *           indices in [0, n_verts); 0 <= n_tris < 2^31.
+ */
+#ifndef LDNI_H
+#define LDNI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDNI_OK = 0,
+  LDNI_ERR_INVALID_ARG = 1,   /* host-detected bad argument */
+  LDNI_ERR_INDEX = 2,         /* a triangle index outside [0, n_verts) */
+  LDNI_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+  LDNI_ERR_OVERFLOW = 4,      /* 2^32 or more samples on one axis */
+  LDNI_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+  LDNI_ERR_NONFINITE = 6      /* a referenced vertex has a NaN/Inf coordinate */
+} ldni_status;
+
+enum { LDNI_AXIS_X = 1u, LDNI_AXIS_Y = 2u, LDNI_AXIS_Z = 4u, LDNI_AXIS_ALL = 7u };
+
+/* Read-only view of one axis of a result (borrowed; valid until the result
+ * is freed). */
+typedef struct {
+  int32_t w;
+  uint32_t max_layers;     /* largest per-pixel sample count (the paper's n_max) */
+  uint64_t n_samples;
+  const uint32_t *offsets; /* device [w*w+1] */
+  const float *depth;      /* device [n_samples] */
+  const float *normal;     /* device [n_samples][3] */
+  const int32_t *tri;      /* device [n_samples], id of the hit triangle */
+} ldni_axis_view;
+
+typedef struct ldni_result ldni_result; /* opaque; owns its device buffers */
+typedef struct ldni_plan ldni_plan;     /* opaque; a sampling call split in two */
+
+/*
+ * ldni_sample -- build the LDNIs of one mesh (Sec. 2 Definitions 1-3; Sec. 3).
+ *   verts     device f32 [n_verts][3], row-major.
+ *   tris      device i32 [n_tris][3], counter-clockwise seen from outside.
+ *   bbox      HOST f32 {xlo, ylo, zlo, xhi, yhi, zhi}, lo < hi, finite.  The
+ *             paper's working envelope (Sec. 3): it fixes the pixel grid
+ *             and the depth origin; it does not clip.
+ *   w         resolution, 1..16384.
+ *   axis_mask any non-empty subset of LDNI_AXIS_{X,Y,Z}.
+ *   out       receives a result that owns every output buffer (device memory
+ *             from the stream-ordered pool of the current device); release it
+ *             with ldni_free.  Axes not in the mask have empty views.
+ * One host synchronisation per call.  n_tris == 0 is valid (no samples).
+ */
+ldni_status ldni_sample(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                        const float bbox[6], int32_t w, uint32_t axis_mask, void *hip_stream,
+                        ldni_result **out);
+
+/* View of axis 0 (x), 1 (y) or 2 (z).  LDNI_ERR_INVALID_ARG for a NULL
+ * result or view, or an axis outside 0..2. */
+ldni_status ldni_result_axis(const ldni_result *r, int axis, ldni_axis_view *view);
+
+/* Release a result (NULL-safe).  The buffers return to the pool in the
+ * order of the stream the result was made on, which must still exist. */
+void ldni_free(ldni_result *r);
+
+/*
+ * ldni_sample_begin / ldni_sample_finish -- the same sampling with
+ * caller-owned outputs, split at the point where the sample counts become
+ * known.
+ *   offsets   device u32 [w*w+1] per axis in the mask (entries of other axes
+ *             are ignored and may be NULL); filled by begin.
+ *   n_samples HOST u64 [3]; begin writes the count of every axis (0 for
+ *             axes not in the mask).
+ *   plan      receives the state that finish needs (workspace on the device).
+ * Then finish writes, for every axis in the mask, depth f32 [n], normal f32
+ * [n][3] and tri i32 [n] into caller device buffers of at least n_samples[a]
+ * elements, and releases the plan whether or not it succeeds.  A plan not
+ * finished must be released with ldni_plan_free.  verts/tris must stay
+ * unchanged until finish returns.
+ */
+ldni_status ldni_sample_begin(const float *verts, int64_t n_verts, const int32_t *tris,
+                              int64_t n_tris, const float bbox[6], int32_t w, uint32_t axis_mask,
+                              uint32_t *const offsets[3], void *hip_stream, ldni_plan **plan,
+                              uint64_t n_samples[3]);
+ldni_status ldni_sample_finish(ldni_plan *plan, float *const depth[3], float *const normal[3],
+                               int32_t *const tri[3]);
+void ldni_plan_free(ldni_plan *plan);
+
+/* Largest per-pixel count of each axis of a plan (after begin). */
+ldni_status ldni_plan_max_layers(const ldni_plan *plan, uint32_t max_layers[3]);
+
+/* Status name ("LDNI_OK", ...), never NULL. */
+const char *ldni_status_string(ldni_status s);
+
+/* Thread-local detail of the last error ("" if none). */
+const char *ldni_last_error(void);
+
+/* Tile shape of the sampling kernels (pixels per tile along u and v).
+ * tw*th <= 1024, 8 <= tw <= 256, 1 <= th <= 64.  Process-wide; default
+ * 32 x 32.  Results do not depend on it. */
+ldni_status ldni_set_tile_shape(int32_t tw, int32_t th);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDNI_H */

@@ -1,0 +1,223 @@
+"""MI355X (gfx950) Layered Depth-Normal Image sampling.
+
+Python binding of the C ABI in ``include/ldni.h``: it marshals torch device
+tensors and the current HIP stream into the library; every step of the
+sampling runs in the library's HIP kernels.  There is no CPU fallback: if
+``libldni.so`` is missing, every entry point raises.
+
+``sample`` builds the LDNIs of a closed triangle mesh (Wang & Chen, Sec. 2
+Definitions 1-3, built by rasterisation in Sec. 3): per axis, every
+intersection of the w x w pixel-centre rays with the mesh as a (depth, unit
+face normal) sample, in compact per-pixel rows sorted by depth.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Dict
+
+from . import _lib
+from ._lib import LDNIError
+
+__all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ldni_free",
+           "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
+           "set_tile_shape", "axis_mask", "library_path"]
+
+AXES = "xyz"
+library_path = _lib.LIB_PATH
+
+
+def axis_mask(axes) -> int:
+    if isinstance(axes, int):
+        return axes
+    m = 0
+    for c in axes:
+        m |= 1 << AXES.index(c)
+    return m
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class LDNI:
+    """One axis of an LDNI in compact rows: the samples of pixel
+    p = j*w + i are ``[offsets[p], offsets[p+1])`` (offsets hold u32 values in
+    an int32 tensor)."""
+    axis: int
+    w: int
+    max_layers: int
+    offsets: "torch.Tensor"   # int32 [w*w+1] (u32 bit patterns)
+    depth: "torch.Tensor"     # float32 [n]
+    normal: "torch.Tensor"    # float32 [n, 3]
+    tri: "torch.Tensor"       # int32 [n]
+
+    @property
+    def n(self) -> int:
+        return int(self.depth.shape[0])
+
+    def offsets64(self):
+        return self.offsets.to(_torch().int64) & 0xFFFFFFFF
+
+    def counts(self):
+        return self.offsets64().diff()
+
+
+def _check_mesh(verts, tris):
+    torch = _torch()
+    if not (verts.is_cuda and tris.is_cuda):
+        raise ValueError("verts and tris must be device tensors")
+    if verts.dtype != torch.float32 or tris.dtype != torch.int32:
+        raise TypeError("verts must be float32 [V,3], tris int32 [T,3]")
+    if verts.dim() != 2 or verts.shape[1] != 3 or tris.dim() != 2 or tris.shape[1] != 3:
+        raise ValueError("verts must be [V,3], tris [T,3]")
+    return verts.contiguous(), tris.contiguous()
+
+
+def _bbox(bbox):
+    b = (ctypes.c_float * 6)(*[float(x) for x in bbox])
+    return b
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def ldni_sample_begin(verts, tris, bbox, w, axes="xyz"):
+    """First half of sampling: returns (plan handle, offsets tensors by axis,
+    sample counts by axis)."""
+    torch = _torch()
+    verts, tris = _check_mesh(verts, tris)
+    mask = axis_mask(axes)
+    L = _lib.lib()
+    dev = verts.device
+    offs = {}
+    optr = (ctypes.c_void_p * 3)()
+    for a in range(3):
+        if (mask >> a) & 1:
+            offs[a] = torch.empty(int(w) * int(w) + 1, dtype=torch.int32, device=dev)
+            optr[a] = offs[a].data_ptr()
+    plan = ctypes.c_void_p()
+    n = (ctypes.c_uint64 * 3)()
+    bb = _bbox(bbox)
+    _lib.check(L.ldni_sample_begin(verts.data_ptr(), verts.shape[0], tris.data_ptr(),
+                                   tris.shape[0], bb, int(w), mask, optr, _stream(dev),
+                                   ctypes.byref(plan), n))
+    return plan, offs, [int(x) for x in n]
+
+
+def ldni_sample_finish(plan, depth, normal, tri):
+    """Second half: writes the samples into the given tensors (dicts by axis)
+    and releases the plan."""
+    L = _lib.lib()
+    d, nm, t = (ctypes.c_void_p * 3)(), (ctypes.c_void_p * 3)(), (ctypes.c_void_p * 3)()
+    for a in depth:
+        d[a], nm[a], t[a] = depth[a].data_ptr(), normal[a].data_ptr(), tri[a].data_ptr()
+    _lib.check(L.ldni_sample_finish(plan, d, nm, t))
+
+
+def ldni_plan_free(plan):
+    _lib.lib().ldni_plan_free(plan)
+
+
+def sample(verts, tris, bbox, w: int, axes="xyz") -> Dict[int, LDNI]:
+    """LDNIs of a mesh as torch tensors on the mesh's device.
+
+    verts float32 [V,3] and tris int32 [T,3] (counter-clockwise seen from
+    outside) on a HIP device; bbox = (xlo, ylo, zlo, xhi, yhi, zhi) on the host;
+    returns ``{axis: LDNI}`` for the requested axes."""
+    torch = _torch()
+    verts, tris = _check_mesh(verts, tris)
+    plan, offs, n = ldni_sample_begin(verts, tris, bbox, w, axes)
+    L = _lib.lib()
+    ml = (ctypes.c_uint32 * 3)()
+    try:
+        _lib.check(L.ldni_plan_max_layers(plan, ml))
+        dev = verts.device
+        depth, normal, tri = {}, {}, {}
+        for a in offs:
+            depth[a] = torch.empty(n[a], dtype=torch.float32, device=dev)
+            normal[a] = torch.empty((n[a], 3), dtype=torch.float32, device=dev)
+            tri[a] = torch.empty(n[a], dtype=torch.int32, device=dev)
+    except BaseException:
+        ldni_plan_free(plan)
+        raise
+    ldni_sample_finish(plan, depth, normal, tri)
+    return {a: LDNI(a, int(w), int(ml[a]), offs[a], depth[a], normal[a], tri[a]) for a in offs}
+
+
+# ---- library-owned results -------------------------------------------------
+
+class Result:
+    """Owner of an ``ldni_result``; frees it when collected."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self.handle = handle
+
+    def view(self, axis: int) -> _lib.AxisView:
+        v = _lib.AxisView()
+        _lib.check(_lib.lib().ldni_result_axis(self.handle, int(axis), ctypes.byref(v)))
+        return v
+
+    def to_torch(self, axis: int, device=None) -> LDNI:
+        """Copy one axis into new torch tensors (device-to-device)."""
+        torch = _torch()
+        v = self.view(axis)
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        n = int(v.n_samples)
+        out = LDNI(axis, int(v.w), int(v.max_layers),
+                   torch.empty(int(v.w) * int(v.w) + 1, dtype=torch.int32, device=dev),
+                   torch.empty(n, dtype=torch.float32, device=dev),
+                   torch.empty((n, 3), dtype=torch.float32, device=dev),
+                   torch.empty(n, dtype=torch.int32, device=dev))
+        H = _lib.hip()
+        st = _stream(dev)
+        for dst, src, nbytes in ((out.offsets, v.offsets, 4 * out.offsets.numel()),
+                                 (out.depth, v.depth, 4 * n), (out.normal, v.normal, 12 * n),
+                                 (out.tri, v.tri, 4 * n)):
+            if nbytes:
+                rc = H.hipMemcpyAsync(dst.data_ptr(), src, nbytes, 3, st)
+                if rc != 0:
+                    raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+        return out
+
+    def free(self):
+        if self.handle:
+            _lib.lib().ldni_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ldni_sample(verts, tris, bbox, w: int, axes="xyz", stream=None) -> Result:
+    """The one-call C ABI: the library allocates and owns the outputs."""
+    verts, tris = _check_mesh(verts, tris)
+    h = ctypes.c_void_p()
+    st = _stream(verts.device) if stream is None else ctypes.c_void_p(stream)
+    _lib.check(_lib.lib().ldni_sample(verts.data_ptr(), verts.shape[0], tris.data_ptr(),
+                                      tris.shape[0], _bbox(bbox), int(w), axis_mask(axes), st,
+                                      ctypes.byref(h)))
+    return Result(h)
+
+
+def ldni_result_axis(result: Result, axis: int) -> _lib.AxisView:
+    return result.view(axis)
+
+
+def ldni_free(result: Result) -> None:
+    result.free()
+
+
+def ldni_status_string(code: int) -> str:
+    return _lib.lib().ldni_status_string(int(code)).decode()
+
+
+def set_tile_shape(tw: int, th: int) -> None:
+    _lib.check(_lib.lib().ldni_set_tile_shape(int(tw), int(th)))

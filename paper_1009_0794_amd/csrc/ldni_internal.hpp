@@ -1,0 +1,91 @@
+// ldni_internal.hpp -- types shared by the gfx950 kernels (ldni_kernels.hip)
+// and the host orchestration behind the C ABI (ldni_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ldni {
+
+// Pixel rectangle of a triangle on one image: columns [i0, i1), rows [j0, j1).
+// Only pixels whose centre satisfies min <= c < max in both image
+// coordinates can be hit, so this is exactly the candidate set.
+struct Rect {
+  int16_t i0, i1, j0, j1;
+};
+
+// Status bits raised by the device.
+enum : uint32_t {
+  kStatusBadIndex = 1u,
+  kStatusNonFinite = 2u,
+  kStatusOverflow = 4u,
+};
+
+// Everything one image (one axis of one mesh) needs on the device.
+struct Image {
+  // geometry
+  int32_t a, u, v;   // sampled axis and image axes (cyclic)
+  int32_t w;         // resolution
+  double lo_u, h_u;  // pixel centre c_u[i] = f32(lo_u + (i + 0.5) * h_u)
+  double lo_v, h_v;
+  double lo_a;       // depth origin
+  // tiling
+  int32_t tw, th;    // tile shape in pixels
+  int32_t ntx, nty;  // tiles along u and v
+  // mesh (shared by the images of one mesh)
+  const float* soup;   // [T][9] vertex coordinates A,B,C (x,y,z each)
+  const float* tnorm;  // [T][3] unit face normals
+  const Rect* rect;    // [T] candidate rectangle on this image
+  int64_t n_tris;
+  // workspace
+  uint32_t* tile_cnt;   // [n_tiles + 1] entries per tile -> exclusive offsets
+  uint32_t* tile_cur;   // [n_tiles] scatter cursors
+  int32_t* tile_list;   // triangle ids grouped by tile
+  uint32_t* counts;     // [w*w] samples per pixel
+  uint32_t* max_layers; // [1]
+  // outputs
+  uint32_t* offsets;  // [w*w + 1]
+  float* depth;       // [n]
+  float* normal;      // [n][3]
+  int32_t* tri;       // [n]
+  uint32_t* status;   // shared status word
+};
+
+constexpr int kMaxImages = 3;
+
+// Up to three images launched together; tile blocks are numbered through the
+// images in order.
+struct ImageSet {
+  Image img[kMaxImages];
+  int32_t n;
+  uint32_t tile_start[kMaxImages + 1];  // prefix of tile counts
+};
+
+// Mesh-level setup: per triangle gather, validate, face normal, candidate
+// rectangles for every image in the set.
+struct MeshSetup {
+  const float* verts;
+  int64_t n_verts;
+  const int32_t* tris;
+  int64_t n_tris;
+  float* soup;
+  float* tnorm;
+  Rect* rect[kMaxImages];
+  uint32_t* status;
+};
+
+// ---- launchers (ldni_kernels.hip) ----
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s);
+hipError_t launch_bin_count(const ImageSet& set, hipStream_t s);
+hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
+hipError_t launch_count(const ImageSet& set, hipStream_t s);
+hipError_t launch_write(const ImageSet& set, hipStream_t s);
+
+// Exclusive scan of n u32 values into out[0..n] (out[n] = total).  Totals of
+// 2^32 or more raise kStatusOverflow.  scratch: scan_scratch_bytes(n).
+size_t scan_scratch_bytes(int64_t n);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
+                       uint32_t* status, hipStream_t s);
+
+}  // namespace ldni

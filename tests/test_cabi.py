@@ -1,0 +1,100 @@
+"""The C ABI library on the host: it loads, exports every function that
+include/ldni.h declares, and rejects bad arguments before any GPU call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ldni.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ldni_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1009_0794_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "ldni_sample" in names and "ldni_free" in names
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_1009_0794_amd import _lib
+    assert sorted(_lib.exported_symbols()) == names
+
+
+def _call(L, verts=1, nv=3, tris=1, nt=1, bbox=(0, 0, 0, 1, 1, 1), w=8, mask=7):
+    bb = (ctypes.c_float * 6)(*bbox) if bbox is not None else None
+    out = ctypes.c_void_p(123)
+    rc = L.ldni_sample(verts, nv, tris, nt, bb, w, mask, None, ctypes.byref(out))
+    return rc, out.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(w=0), dict(w=16385), dict(w=-3), dict(mask=0), dict(mask=8),
+    dict(bbox=(0, 0, 0, 0, 1, 1)), dict(bbox=(0, 0, 0, 1, -1, 1)),
+    dict(bbox=(0, 0, float("nan"), 1, 1, 1)), dict(bbox=(0, 0, 0, float("inf"), 1, 1)),
+    dict(nv=-1), dict(nt=-1), dict(verts=None), dict(tris=None), dict(bbox=None),
+    dict(nt=2 ** 31),
+])
+def test_invalid_arguments_rejected_on_host(L, kw):
+    rc, out = _call(L, **kw)
+    assert rc == 1
+    assert out is None
+    assert L.ldni_last_error().decode()
+
+
+def test_status_strings(L):
+    for code, name in [(0, "LDNI_OK"), (1, "LDNI_ERR_INVALID_ARG"), (2, "LDNI_ERR_INDEX"),
+                       (3, "LDNI_ERR_OUT_OF_MEMORY"), (4, "LDNI_ERR_OVERFLOW"),
+                       (5, "LDNI_ERR_DEVICE"), (6, "LDNI_ERR_NONFINITE")]:
+        assert L.ldni_status_string(code).decode() == name
+    assert L.ldni_status_string(99).decode() == "LDNI_ERR_UNKNOWN"
+
+
+def test_tile_shape_validation(L):
+    assert L.ldni_set_tile_shape(7, 8) == 1
+    assert L.ldni_set_tile_shape(64, 32) == 1
+    assert L.ldni_set_tile_shape(32, 65) == 1
+    assert L.ldni_set_tile_shape(64, 16) == 0
+    assert L.ldni_set_tile_shape(32, 32) == 0
+
+
+def test_result_axis_rejects_null(L):
+    from paper_1009_0794_amd import _lib
+    v = _lib.AxisView()
+    assert L.ldni_result_axis(None, 0, ctypes.byref(v)) == 1
+    L.ldni_free(None)  # NULL-safe
+    L.ldni_plan_free(None)
+
+
+def test_begin_rejects_missing_offsets(L):
+    bb = (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1)
+    offs = (ctypes.c_void_p * 3)(None, None, None)
+    plan = ctypes.c_void_p()
+    n = (ctypes.c_uint64 * 3)()
+    assert L.ldni_sample_begin(1, 3, 1, 1, bb, 8, 1, offs, None, ctypes.byref(plan), n) == 1
+    assert plan.value is None
+
+
+def test_python_binding_refuses_host_tensors():
+    import torch
+    import paper_1009_0794_amd as ldni
+    with pytest.raises(ValueError):
+        ldni.sample(torch.zeros(3, 3), torch.zeros(1, 3, dtype=torch.int32), (0, 0, 0, 1, 1, 1), 8)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_1009_0794_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()

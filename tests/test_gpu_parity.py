@@ -1,0 +1,212 @@
+"""Parity of the HIP sampler with the CPU oracle, element by element.
+
+Counts, offsets, triangle ids and their order must be identical; depths must
+agree within 1e-5 x the box diagonal and normals within 1e-5 (float32), and
+are expected to be bit-identical because both sides evaluate the same
+float64 formulas in the same order.
+"""
+import json
+import glob
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1009_0794_amd as ldni
+from paper_1009_0794_amd import meshgen as mg
+from tests.golden.fixture_meshes import FIXTURES, BOX8
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _diag(bbox):
+    b = np.asarray(bbox, np.float64)
+    return float(np.linalg.norm(b[3:] - b[:3]))
+
+
+def _run(v, f, bbox, w, axes="xyz"):
+    vt = torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(DEV)
+    ft = torch.from_numpy(np.ascontiguousarray(f, np.int32)).to(DEV)
+    out = ldni.sample(vt, ft, bbox, w, axes)
+    torch.cuda.synchronize()
+    return out
+
+
+def _np(g):
+    return (g.offsets.cpu().numpy().view(np.uint32), g.depth.cpu().numpy(),
+            g.normal.cpu().numpy(), g.tri.cpu().numpy())
+
+
+def compare(got, ref, bbox, bitwise=True, label=""):
+    tol_d = 1e-5 * _diag(bbox)
+    for a, r in ref.items():
+        off, dep, nrm, tri = _np(got[a])
+        assert np.array_equal(off, r.offsets), f"{label} axis {a}: offsets differ"
+        assert np.array_equal(tri, r.tri), f"{label} axis {a}: triangle ids/order differ"
+        if r.n:
+            assert np.abs(dep.astype(np.float64) - r.depth).max() <= tol_d, f"{label} axis {a}: depth"
+            assert np.abs(nrm.astype(np.float64) - r.normal).max() <= 1e-5, f"{label} axis {a}: normal"
+        if bitwise:
+            assert np.array_equal(dep.view(np.uint32), r.depth.view(np.uint32)), f"{label} axis {a}: depth bits"
+            assert np.array_equal(nrm.view(np.uint32), r.normal.view(np.uint32)), f"{label} axis {a}: normal bits"
+        cnt = np.diff(off.astype(np.int64))
+        assert got[a].max_layers == (int(cnt.max()) if cnt.size else 0)
+
+
+@pytest.fixture(autouse=True)
+def _default_tiles():
+    ldni.set_tile_shape(32, 32)
+    yield
+    ldni.set_tile_shape(32, 32)
+
+
+@pytest.mark.parametrize("name", sorted(FIXTURES))
+def test_exact_fixture_meshes(name):
+    v, f, bb, w = FIXTURES[name]
+    compare(_run(v, f, bb, w), oracle.sample(v, f, bb, w), bb, label=name)
+
+
+@pytest.mark.parametrize("w", [1, 2, 33, 77, 128, 131])
+def test_icosphere_resolutions(w):
+    m = mg.c1_icosphere()
+    compare(_run(m.verts, m.tris, m.bbox, w), oracle.sample(m.verts, m.tris, m.bbox, w), m.bbox,
+            label=f"c1 w={w}")
+
+
+@pytest.mark.parametrize("tile", [(8, 1), (16, 16), (64, 16), (256, 4), (32, 32), (8, 64)])
+def test_tile_shapes(tile):
+    ldni.set_tile_shape(*tile)
+    rng = np.random.default_rng(1)
+    v, f = mg.concat([mg.uv_flower(48, 96, rng)])
+    bb = (-1.4, -1.3, -1.5, 1.4, 1.45, 1.3)
+    compare(_run(v, f, bb, 203), oracle.sample(v, f, bb, 203), bb, label=f"tile {tile}")
+
+
+def _nest(n, level=2):
+    rng = np.random.default_rng(3)
+    parts = [mg.icosphere(level, 0.95 - 0.04 * k, (0.01, -0.02, 0.015), mg.random_rotation(rng))
+             for k in range(n)]
+    return mg.concat(parts)
+
+
+@pytest.mark.parametrize("tile", [(32, 32), (256, 4), (16, 8)])
+def test_deep_pixels_chunked_and_oversized_rows(tile):
+    """40 layers per ray: 32x32 tiles need several LDS chunks; 256x4 tiles
+    have rows of more than 6144 samples, written and sorted in place."""
+    ldni.set_tile_shape(*tile)
+    v, f = _nest(20)
+    bb = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
+    ref = oracle.sample(v, f, bb, 256)
+    assert max(int(np.diff(r.offsets.astype(np.int64)).max()) for r in ref.values()) == 40
+    compare(_run(v, f, bb, 256), ref, bb, label=f"nest tile {tile}")
+
+
+def test_noncubic_box_and_hits_outside_box():
+    """Rays are infinite lines: a mesh sticking out of the box along the axis
+    still gives every hit (negative depths, depths beyond hi)."""
+    rng = np.random.default_rng(2)
+    v, f = mg.concat([mg.icosphere(3, 1.3, (0.2, -0.1, 0.3), mg.random_rotation(rng)),
+                      mg.torus(40, 20, 0.5, 0.2, (-0.3, 0.2, -0.2), mg.random_rotation(rng))])
+    bb = (-0.9, -1.2, -0.4, 0.8, 1.1, 0.5)
+    compare(_run(v, f, bb, 97), oracle.sample(v, f, bb, 97), bb, label="outside")
+
+
+def test_random_meshes_many_axes_masks():
+    rng = np.random.default_rng(9)
+    for k, axes in enumerate(["x", "y", "z", "xy", "yz", "xz", "xyz"]):
+        v, f = mg.concat([mg.icosphere(int(rng.integers(1, 4)), rng.uniform(0.3, 0.9),
+                                       rng.uniform(-0.2, 0.2, 3), mg.random_rotation(rng))])
+        bb = tuple(rng.uniform(-1.1, -0.95, 3)) + tuple(rng.uniform(0.95, 1.1, 3))
+        w = int(rng.integers(20, 150))
+        got = _run(v, f, bb, w, axes)
+        ref = oracle.sample(v, f, bb, w, axes)
+        assert set(got) == set(ref)
+        compare(got, ref, bb, label=f"random {k} {axes}")
+
+
+def test_c1_icosphere_full():
+    m = mg.c1_icosphere()
+    compare(_run(m.verts, m.tris, m.bbox, m.w), oracle.sample(m.verts, m.tris, m.bbox, m.w), m.bbox,
+            label="c1")
+
+
+def test_c2_flower_full():
+    m = mg.c2_flower()
+    compare(_run(m.verts, m.tris, m.bbox, m.w), oracle.sample(m.verts, m.tris, m.bbox, m.w), m.bbox,
+            label="c2")
+
+
+def test_c3_scene_rows_sampled():
+    """The w=2048 scene at full size; the oracle recomputes a band of rows
+    through the 32-layer nest centre and a band near the edge on every axis."""
+    m = mg.c3_scene64()
+    got = _run(m.verts, m.tris, m.bbox, m.w)
+    for a in range(3):
+        off, dep, nrm, tri = _np(got[a])
+        cnt = np.diff(off.astype(np.int64))
+        assert (cnt % 2 == 0).all()
+        assert int(cnt.max()) == 32
+        for j0, j1 in ((1016, 1032), (100, 108)):
+            r = oracle.sample(m.verts, m.tris, m.bbox, m.w, axes=[a], window=(0, m.w, j0, j1))[a]
+            s0, s1 = int(off[j0 * m.w]), int(off[j1 * m.w])
+            rc = np.diff(r.offsets.astype(np.int64))
+            assert np.array_equal(cnt[j0 * m.w:j1 * m.w], rc[j0 * m.w:j1 * m.w])
+            assert np.array_equal(tri[s0:s1], r.tri)
+            assert np.array_equal(dep[s0:s1].view(np.uint32), r.depth.view(np.uint32))
+            assert np.array_equal(nrm[s0:s1].view(np.uint32), r.normal.view(np.uint32))
+
+
+def test_empty_and_missed_meshes():
+    e = _run(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), BOX8, 17)
+    for a in range(3):
+        assert e[a].n == 0 and int(e[a].offsets.abs().sum()) == 0 and e[a].max_layers == 0
+    v, f = mg.concat([mg.box_mesh((20, 20, 20), (21, 21, 21))])
+    o = _run(v, f, BOX8, 16)
+    for a in range(3):
+        assert o[a].n == 0
+
+
+def test_library_owned_result_matches():
+    m = mg.c1_icosphere()
+    vt = torch.from_numpy(m.verts).to(DEV)
+    ft = torch.from_numpy(m.tris).to(DEV)
+    res = ldni.ldni_sample(vt, ft, m.bbox, m.w, "xz")
+    ref = oracle.sample(m.verts, m.tris, m.bbox, m.w, "xz")
+    got = {a: res.to_torch(a) for a in (0, 2)}
+    torch.cuda.synchronize()
+    compare(got, ref, m.bbox, label="owned")
+    assert res.view(1).n_samples == 0
+    res.free()
+
+
+def test_deterministic_repeat():
+    m = mg.c2_flower()
+    g1 = _run(m.verts, m.tris, m.bbox, m.w)
+    g2 = _run(m.verts, m.tris, m.bbox, m.w)
+    for a in range(3):
+        for x, y in zip(_np(g1[a]), _np(g2[a])):
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+def test_device_detected_errors():
+    v, f = mg.concat([mg.box_mesh((1, 1, 1), (2, 2, 2))])
+    bad = f.copy()
+    bad[5, 2] = 8
+    with pytest.raises(ldni.LDNIError) as e:
+        _run(v, bad, BOX8, 8)
+    assert e.value.code == 2
+    bad[5, 2] = -1
+    with pytest.raises(ldni.LDNIError) as e:
+        _run(v, bad, BOX8, 8)
+    assert e.value.code == 2
+    vn = v.copy()
+    vn[3, 1] = np.inf
+    with pytest.raises(ldni.LDNIError) as e:
+        _run(vn, f, BOX8, 8)
+    assert e.value.code == 6
+    # the library keeps working after an error
+    compare(_run(v, f, BOX8, 8), oracle.sample(v, f, BOX8, 8), BOX8, label="after error")
