@@ -150,6 +150,24 @@ const char *ldni_last_error(void);
  * 32 x 32.  Results do not depend on it. */
 ldni_status ldni_set_tile_shape(int32_t tw, int32_t th);
 
+/*
+ * Kernel timing (tracing support, not part of the paper's method).
+ * ldni_profile_enable(1) starts recording a pair of HIP events around every
+ * kernel the library launches from the calling process (on the stream the
+ * kernel runs on); ldni_profile_enable(0) stops.  Enabling clears earlier
+ * records.  ldni_profile_read waits for the recorded events, then writes up
+ * to max entries (one per kernel name, in first-launch order) and sets *n to
+ * the number of distinct kernels; names are static strings.
+ */
+typedef struct {
+  const char *name;
+  uint64_t launches;
+  double total_ms;
+} ldni_kernel_stat;
+
+ldni_status ldni_profile_enable(int enable);
+ldni_status ldni_profile_read(ldni_kernel_stat *stats, int32_t max, int32_t *n);
+
 #ifdef __cplusplus
 }
 #endif

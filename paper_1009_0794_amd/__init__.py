@@ -21,7 +21,7 @@ from ._lib import LDNIError
 
 __all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ldni_free",
            "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
-           "set_tile_shape", "axis_mask", "library_path"]
+           "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read"]
 
 AXES = "xyz"
 library_path = _lib.LIB_PATH
@@ -217,6 +217,22 @@ def ldni_free(result: Result) -> None:
 
 def ldni_status_string(code: int) -> str:
     return _lib.lib().ldni_status_string(int(code)).decode()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (clearing earlier records) or stop per-kernel HIP-event timing."""
+    _lib.check(_lib.lib().ldni_profile_enable(1 if on else 0))
+
+
+def profile_read() -> Dict[str, tuple]:
+    """{kernel name: (launches, total milliseconds)} of the recorded launches."""
+    L = _lib.lib()
+    n = ctypes.c_int32()
+    _lib.check(L.ldni_profile_read(None, 0, ctypes.byref(n)))
+    arr = (_lib.KernelStat * max(1, n.value))()
+    _lib.check(L.ldni_profile_read(arr, n.value, ctypes.byref(n)))
+    return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms))
+            for k in range(n.value)}
 
 
 def set_tile_shape(tw: int, th: int) -> None:

@@ -20,6 +20,11 @@ class AxisView(ctypes.Structure):
                 ("tri", ctypes.c_void_p)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double)]
+
+
 STATUS = {0: "LDNI_OK", 1: "LDNI_ERR_INVALID_ARG", 2: "LDNI_ERR_INDEX",
           3: "LDNI_ERR_OUT_OF_MEMORY", 4: "LDNI_ERR_OVERFLOW", 5: "LDNI_ERR_DEVICE",
           6: "LDNI_ERR_NONFINITE"}
@@ -68,6 +73,10 @@ def lib():
     L.ldni_last_error.restype = ctypes.c_char_p
     L.ldni_set_tile_shape.argtypes = [i32, i32]
     L.ldni_set_tile_shape.restype = st
+    L.ldni_profile_enable.argtypes = [ctypes.c_int]
+    L.ldni_profile_enable.restype = st
+    L.ldni_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+    L.ldni_profile_read.restype = st
     _lib = L
     return L
 
@@ -96,4 +105,5 @@ def exported_symbols():
     """Names of the C ABI functions declared in include/ldni.h."""
     return ["ldni_sample", "ldni_result_axis", "ldni_free", "ldni_sample_begin",
             "ldni_sample_finish", "ldni_plan_free", "ldni_plan_max_layers",
-            "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape"]
+            "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
+            "ldni_profile_enable", "ldni_profile_read"]

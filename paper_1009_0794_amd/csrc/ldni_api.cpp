@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/ldni.h"
 #include "ldni_internal.hpp"
@@ -94,6 +95,29 @@ ldni_status validate(const float* verts, int64_t n_verts, const int32_t* tris, i
     if (!(bbox[d] < bbox[3 + d])) return fail(LDNI_ERR_INVALID_ARG, "bbox needs lo < hi on every axis");
   }
   return LDNI_OK;
+}
+
+// ---- optional kernel timing ----
+struct ProfRecord {
+  const char* name;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+std::atomic<bool> g_prof_on{false};
+std::vector<ProfRecord> g_prof;
+
+template <class F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch) {
+  if (!g_prof_on.load(std::memory_order_relaxed)) return launch();
+  ProfRecord r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess)
+    return launch();
+  (void)hipEventRecord(r.start, s);
+  const hipError_t e = launch();
+  (void)hipEventRecord(r.stop, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+  return e;
 }
 
 }  // namespace
@@ -275,11 +299,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     STEP(launch_fill_u32(set.img[k].tile_cnt, 0u, n_tiles + 1, stream), "fill");
     STEP(launch_fill_u32(set.img[k].tile_cur, 0u, n_tiles, stream), "fill");
   }
-  STEP(launch_setup(ms, set, stream), "setup kernel");
-  STEP(launch_bin_count(set, stream), "bin count kernel");
+  STEP(timed("setup", stream, [&] { return launch_setup(ms, set, stream); }), "setup kernel");
+  STEP(timed("bin_count", stream, [&] { return launch_bin_count(set, stream); }), "bin count kernel");
   for (int k = 0; k < nimg; ++k)
-    STEP(launch_scan(set.img[k].tile_cnt, set.img[k].tile_cnt, n_tiles, scan_scratch, status, stream),
-         "tile scan");
+    STEP(timed("scan_tiles", stream, [&] {
+           return launch_scan(set.img[k].tile_cnt, set.img[k].tile_cnt, n_tiles, scan_scratch, status, stream);
+         }), "tile scan");
   // readback 1: tile-list sizes and input validity
   STEP(hipMemcpyAsync(rb, status, sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "readback");
   for (int k = 0; k < nimg; ++k)
@@ -302,11 +327,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   for (int k = 0; k < nimg; ++k)
     set.img[k].tile_list = reinterpret_cast<int32_t*>(static_cast<char*>(p->lists) + list_off[k]);
 
-  STEP(launch_bin_scatter(set, stream), "bin scatter kernel");
-  STEP(launch_count(set, stream), "count kernel");
+  STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
+  STEP(timed("count", stream, [&] { return launch_count(set, stream); }), "count kernel");
   for (int k = 0; k < nimg; ++k)
-    STEP(launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream),
-         "pixel scan");
+    STEP(timed("scan_pixels", stream, [&] {
+           return launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream);
+         }), "pixel scan");
   // readback 2: sample totals
   STEP(hipMemcpyAsync(rb, status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "readback");
   for (int k = 0; k < nimg; ++k)
@@ -349,13 +375,45 @@ ldni_status ldni_sample_finish(ldni_plan* p, float* const depth[3], float* const
     p->set.img[k].tri = tri[a];
   }
   hipError_t e = hipSuccess;
-  if (p->n_tris > 0) e = launch_write(p->set, p->stream);
+  if (p->n_tris > 0) e = timed("write", p->stream, [&] { return launch_write(p->set, p->stream); });
   release_plan(p);
   if (e != hipSuccess) return hip_fail(e, "write kernel");
   return LDNI_OK;
 }
 
 void ldni_plan_free(ldni_plan* plan) { release_plan(plan); }
+
+ldni_status ldni_profile_enable(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (enable) {
+    for (auto& r : g_prof) {
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+  }
+  g_prof_on.store(enable != 0);
+  return LDNI_OK;
+}
+
+ldni_status ldni_profile_read(ldni_kernel_stat* stats, int32_t max, int32_t* n) {
+  if (!n || (max > 0 && !stats)) return fail(LDNI_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<ldni_kernel_stat> acc;
+  for (auto& r : g_prof) {
+    if (hipEventSynchronize(r.stop) != hipSuccess) return fail(LDNI_ERR_DEVICE, "event wait");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return fail(LDNI_ERR_DEVICE, "event time");
+    size_t k = 0;
+    while (k < acc.size() && std::strcmp(acc[k].name, r.name) != 0) ++k;
+    if (k == acc.size()) acc.push_back(ldni_kernel_stat{r.name, 0, 0.0});
+    acc[k].launches += 1;
+    acc[k].total_ms += ms;
+  }
+  *n = (int32_t)acc.size();
+  for (int32_t k = 0; k < max && k < (int32_t)acc.size(); ++k) stats[k] = acc[k];
+  return LDNI_OK;
+}
 
 ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                         const float bbox[6], int32_t w, uint32_t axis_mask, void* hip_stream,
