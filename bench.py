@@ -1,12 +1,17 @@
 #!/usr/bin/env python3
 """Throughput of LDNI sampling on one MI355X.
 
-One step = one pass of the sampling path (triangle setup, tile binning, count,
-scan, write + per-pixel sort, for all three axes) over the workload's mesh,
-through the C ABI call ``ldni_sample`` (library-owned outputs from the
-stream-ordered pool) followed by ``ldni_free``.  Inputs are resident in HBM
-before the timed region starts.  The metric is LDNI samples written per
-second, summed over the three axes.
+Headline step: one pass of the sampling path (triangle setup, tile binning,
+count, scan, write + per-pixel sort, all three axes) over the scene64 mesh
+(2,152,448 triangles, w=2048) through the C ABI call ``ldni_sample``
+(library-owned outputs from the stream-ordered pool) followed by
+``ldni_free``.  Inputs are resident in HBM before the timed region starts.
+The metric is LDNI samples written per second, summed over the three axes.
+
+The same JSON line also carries the metric's other parts: the flower at
+w=512, the batched path (256 meshes in one captured graph vs 256 plain
+calls) and forward + backward on the flower.  ``--workload`` picks a single
+part (used for profiling runs).
 
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: this sampler runs on
 one GPU (how it would shard is described with the design).
@@ -25,10 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "LDNI samples written/sec (3 axes) at w=512/2048; batched vs plain; fwd+bwd"
 
-WORKLOADS = {
-    # name: (mesh builder, description)
-    "scene64-2048": ("c3_scene64", "64 disjoint closed shells, 2,152,448 triangles, up to 32 layers, w=2048, 3 axes"),
+PLAIN = {
+    "scene64-2048": ("c3_scene64", "64 disjoint closed shells, 2,152,448 triangles, up to 32 layers, "
+                                   "w=2048, 3 axes"),
     "flower-512": ("c2_flower", "seeded flower UV sphere 512x256, 261,120 triangles, w=512, 3 axes"),
     "icosphere-128": ("c1_icosphere", "icosphere level 3, 1,280 triangles, w=128, 3 axes"),
 }
@@ -39,7 +45,7 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(workload: str, kernel: str, launches_per_step: int):
+def read_traffic(workload: str, kernel: str):
     """HBM bytes per launch of ``kernel`` from the committed counter summary,
     or None if there is none or the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.txt")
@@ -53,15 +59,17 @@ def read_traffic(workload: str, kernel: str, launches_per_step: int):
     return float(m.group(1)) if m else None
 
 
-def algorithmic_bytes(mesh, n_axes):
-    """What the method must move (read the mesh once, write offsets and
-    (depth, normal) samples once), per kernel that moves it."""
-    V, T, w = mesh.n_verts, mesh.n_tris, mesh.w
-    return {
-        "setup": 12 * V + 12 * T,
-        "scan_pixels": 4 * (w * w + 1) * n_axes,
-        "write": None,  # 16 bytes per sample, filled in once the counts are known
-    }
+def fwd_bytes(mesh, samples):
+    """Algorithmic bytes of one 3-axis forward: read the mesh once, write the
+    offsets and the (depth, normal) samples once."""
+    return 12 * mesh.n_verts + 12 * mesh.n_tris + 3 * 4 * (mesh.w * mesh.w + 1) + 16 * samples
+
+
+def kernel_alg_bytes(name, mesh, samples):
+    """The share of the algorithmic bytes each kernel moves (per step)."""
+    return {"setup": 12 * mesh.n_verts + 12 * mesh.n_tris,
+            "scan_pixels": 3 * 4 * (mesh.w * mesh.w + 1),
+            "write": 16 * samples}.get(name)
 
 
 def cpu_baseline(mesh, seconds: float):
@@ -82,13 +90,170 @@ def cpu_baseline(mesh, seconds: float):
         elapsed = time.perf_counter() - t0
         if elapsed >= seconds or passes >= 20:
             break
+    return {"value": samples / elapsed, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole workload (3 axes, culled mode) {passes} time(s): "
+                      f"{samples} samples in {elapsed:.1f} s"}
+
+
+class Timer:
+    """HIP events on the current stream around a region, after a synchronise."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.a = self.torch.cuda.Event(enable_timing=True)
+        self.b = self.torch.cuda.Event(enable_timing=True)
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self.torch.cuda.synchronize()
+        self.ms = self.a.elapsed_time(self.b)
+
+
+def measure_plain(ldni, torch, mesh, steps, warmup, workload):
+    verts = torch.from_numpy(mesh.verts).cuda()
+    tris = torch.from_numpy(mesh.tris).cuda()
+
+    def step():
+        r = ldni.ldni_sample(verts, tris, mesh.bbox, mesh.w, "xyz")
+        n = [int(r.view(a).n_samples) for a in range(3)]
+        ml = [int(r.view(a).max_layers) for a in range(3)]
+        r.free()
+        return n, ml
+
+    for _ in range(max(1, warmup)):
+        n_axis, max_layers = step()
+    ldni.profile_enable(True)
+    with Timer(torch) as t:
+        for _ in range(steps):
+            n_axis, max_layers = step()
+    ldni.profile_enable(False)
+    kstats = ldni.profile_read()
+    ms_step = t.ms / steps
+    samples = sum(n_axis)
+    dom_name, (dom_launches, dom_ms) = max(kstats.items(), key=lambda kv: kv[1][1])
+    per_step = max(1, dom_launches // steps)
+    avg_s = dom_ms / dom_launches / 1e3
+    alg = kernel_alg_bytes(dom_name, mesh, samples)
+    alg_launch = alg / per_step if alg is not None else None
+    achieved = alg_launch / avg_s / 1e9 if alg_launch else 0.0
+    b = fwd_bytes(mesh, samples)
     return {
-        "value": samples / elapsed,
-        "unit": "samples/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": f"the whole workload (3 axes, culled mode) {passes} time(s): "
-                  f"{samples} samples in {elapsed:.1f} s",
+        "value": samples / (ms_step / 1e3),
+        "ms_per_step": ms_step,
+        "samples_per_step": samples,
+        "samples_per_axis": n_axis,
+        "max_layers": max_layers,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": read_traffic(workload, dom_name),
+                     "avg_launch_us": round(avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": alg_launch},
+        "path_roofline": {"algorithmic_bytes_per_step": b,
+                          "achieved_GBps": round(b / (ms_step / 1e3) / 1e9, 2),
+                          "frac_of_hbm_peak": round(b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms_per_step": {k: round(v[1] / steps, 4) for k, v in kstats.items()},
+    }
+
+
+def measure_batch(ldni, torch, mg, reps):
+    """256 seeded meshes, each at its own w: one graph replay vs 256 plain
+    ldni_sample calls on one stream."""
+    meshes = mg.c4_batch256()
+    dev = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.tris).cuda(), m) for m in meshes]
+    b = ldni.sample_batch([(v, f, m.bbox, m.w) for v, f, m in dev], "xyz")
+    samples = sum(int(b.view(k, a).n_samples) for k in range(len(dev)) for a in range(3))
+    b.run()
+    with Timer(torch) as t:
+        for _ in range(reps):
+            b.run()
+    ms_batch = t.ms / reps
+
+    def plain_all():
+        n = 0
+        for v, f, m in dev:
+            r = ldni.ldni_sample(v, f, m.bbox, m.w, "xyz")
+            n += sum(int(r.view(a).n_samples) for a in range(3))
+            r.free()
+        return n
+
+    n_plain = plain_all()
+    with Timer(torch) as t:
+        for _ in range(reps):
+            n_plain = plain_all()
+    ms_plain = t.ms / reps
+    b.free()
+    return {
+        "workload": "batch256",
+        "description": "256 seeded flower/torus/icosphere meshes, triangle counts log-uniform "
+                       "1e3..5e5, each at its own w in {64..1024}, 3 axes",
+        "n_tris": int(sum(m.n_tris for m in meshes)),
+        "sum_w2": int(sum(m.w * m.w for m in meshes)),
+        "samples_per_step": samples,
+        "batched": {"value": samples / (ms_batch / 1e3), "ms_per_step": round(ms_batch, 4)},
+        "plain_256_calls": {"value": n_plain / (ms_plain / 1e3), "ms_per_step": round(ms_plain, 4)},
+        "speedup": round(ms_plain / ms_batch, 3),
+        "identical_sample_count": n_plain == samples,
+    }
+
+
+def measure_fwd_bwd(ldni, torch, mg, reps):
+    """Flower at w=512: forward (torch-allocated outputs) and the backward of
+    the squared-error loss to a perturbed copy's LDNI."""
+    import numpy as np
+    m = mg.c2_flower()
+    tgt = mg.c5_target(m)
+    v = torch.from_numpy(m.verts).cuda()
+    f = torch.from_numpy(m.tris).cuda()
+    tv = torch.from_numpy(tgt.verts).cuda()
+    T = ldni.sample(tv, f, m.bbox, m.w, "xyz")
+    R = ldni.sample(v, f, m.bbox, m.w, "xyz")
+    gd, gn = {}, {}
+    for a in range(3):
+        c = R[a].counts().cpu().numpy()
+        ct = T[a].counts().cpu().numpy()
+        ro = R[a].offsets64().cpu().numpy()
+        to = T[a].offsets64().cpu().numpy()
+        pix = np.nonzero((c == ct) & (c > 0))[0]
+        cnt = c[pix]
+        k = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        s = torch.from_numpy(np.repeat(ro[pix], cnt) + k).cuda()
+        st = torch.from_numpy(np.repeat(to[pix], cnt) + k).cuda()
+        gd[a] = torch.zeros(R[a].n, device="cuda")
+        gn[a] = torch.zeros(R[a].n, 3, device="cuda")
+        gd[a][s] = 2 * (R[a].depth[s] - T[a].depth[st])
+        gn[a][s] = 2 * (R[a].normal[s] - T[a].normal[st])
+    samples = sum(R[a].n for a in range(3))
+    g = torch.zeros_like(v)
+    for _ in range(2):
+        ldni.sample(v, f, m.bbox, m.w, "xyz")
+        ldni.ldni_backward(v, f, m.bbox, m.w, R, gd, gn, grad_verts=g)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            ldni.sample(v, f, m.bbox, m.w, "xyz")
+    ms_f = t.ms / reps
+    ldni.profile_enable(True)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            ldni.ldni_backward(v, f, m.bbox, m.w, R, gd, gn, grad_verts=g)
+    ldni.profile_enable(False)
+    ms_b = t.ms / reps
+    kb = ldni.profile_read().get("backward", (1, 0.0))
+    bwd_bytes = 24 * m.n_verts + 12 * m.n_tris + 3 * 4 * (m.w * m.w + 1) + 20 * samples + 12 * m.n_verts
+    return {
+        "workload": "flower-512 forward+backward",
+        "samples": samples,
+        "forward_ms": round(ms_f, 4),
+        "backward_ms": round(ms_b, 4),
+        "bwd_over_fwd": round(ms_b / ms_f, 3),
+        "value": samples / ((ms_f + ms_b) / 1e3),
+        "backward_roofline": {"bound": "hbm", "algorithmic_bytes": bwd_bytes,
+                              "achieved_GBps": round(bwd_bytes / (kb[1] / kb[0] / 1e3) / 1e9, 2)
+                              if kb[1] > 0 else None},
     }
 
 
@@ -97,7 +262,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="scene64-2048", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=None,
+                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd"],
+                    help="measure one part only (default: the headline plus every part)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default=None, help="tile shape TWxTH")
@@ -117,120 +284,60 @@ def main():
     import paper_1009_0794_amd as ldni
     from paper_1009_0794_amd import meshgen as mg
 
-    builder, desc = WORKLOADS[args.workload]
-    mesh = getattr(mg, builder)()
+    torch.cuda.set_device(0)
     if args.tile:
         tw, th = (int(x) for x in args.tile.lower().split("x"))
         ldni.set_tile_shape(tw, th)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    verts = torch.from_numpy(mesh.verts).to(dev)
-    tris = torch.from_numpy(mesh.tris).to(dev)
-    torch.cuda.synchronize()
-
     if args.calib_copy_mib > 0:
-        nbytes = args.calib_copy_mib << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        src = torch.ones((args.calib_copy_mib << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
-        r = ldni.ldni_sample(verts, tris, mesh.bbox, mesh.w, "xyz")
-        n = [int(r.view(a).n_samples) for a in range(3)]
-        ml = [int(r.view(a).max_layers) for a in range(3)]
-        r.free()
-        return n, ml
-
-    for _ in range(args.warmup):
-        n_axis, max_layers = step()
-    if args.warmup == 0:
-        n_axis, max_layers = step()
-    torch.cuda.synchronize()
-
-    ldni.profile_enable(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    start.record()
-    total = 0
-    for _ in range(args.steps):
-        n_axis, max_layers = step()
-        total += sum(n_axis)
-    stop.record()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ldni.profile_enable(False)
-    kstats = ldni.profile_read()
-    ms = start.elapsed_time(stop)
-    ms_per_step = ms / args.steps
-    samples_per_step = sum(n_axis)
-    value = total / (ms / 1e3)
-
-    # roofline of the dominant kernel
-    alg = algorithmic_bytes(mesh, 3)
-    alg["write"] = 16 * samples_per_step
-    dom = max(kstats.items(), key=lambda kv: kv[1][1])
-    dom_name, (dom_launches, dom_ms) = dom
-    per_step_launches = max(1, dom_launches // args.steps)
-    avg_launch_s = dom_ms / dom_launches / 1e3
-    alg_per_launch = alg.get(dom_name)
-    if alg_per_launch is not None:
-        alg_per_launch = alg_per_launch / per_step_launches
-    achieved = (alg_per_launch / avg_launch_s / 1e9) if alg_per_launch else 0.0
-    traffic = read_traffic(args.workload, dom_name, per_step_launches)
-    roofline = {
-        "bound": "hbm",
-        "kernel": dom_name,
-        "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "avg_launch_us": round(avg_launch_s * 1e6, 2),
-        "algorithmic_bytes_per_launch": alg_per_launch,
-    }
-    b_fwd = 12 * mesh.n_verts + 12 * mesh.n_tris + 3 * 4 * (mesh.w * mesh.w + 1) + 16 * samples_per_step
-    path = {
-        "algorithmic_bytes_per_step": b_fwd,
-        "achieved_GBps": round(b_fwd / (ms_per_step / 1e3) / 1e9, 2),
-        "frac_of_hbm_peak": round(b_fwd / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-    }
-
-    line = {
-        "metric": "LDNI samples written/sec (3 axes) at w=512/2048; batched vs plain; fwd+bwd",
-        "value": round(value, 1),
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 out, f64 internal",
-        "data": "synthetic (seeded meshes generated in paper_1009_0794_amd/meshgen.py)",
-        "config": {
-            "workload": args.workload,
-            "description": desc,
-            "n_tris": mesh.n_tris,
-            "n_verts": mesh.n_verts,
-            "w": mesh.w,
-            "axes": "xyz",
-            "samples_per_step": samples_per_step,
-            "samples_per_axis": n_axis,
-            "max_layers": max_layers,
-            "parallelism": "single GPU",
-        },
-        "roofline": roofline,
-        "path_roofline": path,
-        "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in kstats.items()},
-        "wall_s": round(t_wall, 3),
-    }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_seconds)
+    head = args.workload if args.workload in PLAIN else "scene64-2048"
+    line = {"metric": METRIC, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 out, f64 internal",
+            "data": "synthetic (seeded meshes from paper_1009_0794_amd/meshgen.py)"}
+    if args.workload in (None, *PLAIN):
+        mesh = getattr(mg, PLAIN[head][0])()
+        r = measure_plain(ldni, torch, mesh, args.steps, args.warmup, head)
+        line.update({"value": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                     "config": {"workload": head, "description": PLAIN[head][1], "n_tris": mesh.n_tris,
+                                "n_verts": mesh.n_verts, "w": mesh.w, "axes": "xyz",
+                                "samples_per_step": r["samples_per_step"],
+                                "samples_per_axis": r["samples_per_axis"], "max_layers": r["max_layers"],
+                                "parallelism": "single GPU"},
+                     "roofline": r["roofline"], "path_roofline": r["path_roofline"],
+                     "kernels_ms_per_step": r["kernels_ms_per_step"]})
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_seconds)
+        del mesh
+    if args.workload is None:
+        fl = mg.c2_flower()
+        r2 = measure_plain(ldni, torch, fl, args.steps, args.warmup, "flower-512")
+        line["flower_512"] = {"value": round(r2["value"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
+                              "samples_per_step": r2["samples_per_step"],
+                              "path_roofline": r2["path_roofline"], "roofline": r2["roofline"],
+                              "kernels_ms_per_step": r2["kernels_ms_per_step"]}
+    if args.workload in (None, "batch256"):
+        rb = measure_batch(ldni, torch, mg, reps=max(1, args.steps // 4))
+        if args.workload == "batch256":
+            line.update({"value": round(rb["batched"]["value"], 1),
+                         "ms_per_step": rb["batched"]["ms_per_step"],
+                         "config": {"workload": "batch256", "description": rb["description"],
+                                    "parallelism": "single GPU"}})
+        line["batched"] = rb
+    if args.workload in (None, "flower-512-fwdbwd"):
+        rf = measure_fwd_bwd(ldni, torch, mg, reps=args.steps)
+        if args.workload == "flower-512-fwdbwd":
+            line.update({"value": round(rf["value"], 1),
+                         "ms_per_step": round(rf["forward_ms"] + rf["backward_ms"], 4),
+                         "config": {"workload": "flower-512 forward+backward",
+                                    "parallelism": "single GPU"}})
+        line["fwd_bwd"] = rf
     print(json.dumps(line), flush=True)
 
 

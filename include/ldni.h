@@ -99,7 +99,8 @@ typedef struct ldni_plan ldni_plan;     /* opaque; a sampling call split in two 
  *   out       receives a result that owns every output buffer (device memory
  *             from the stream-ordered pool of the current device); release it
  *             with ldni_free.  Axes not in the mask have empty views.
- * One host synchronisation per call.  n_tris == 0 is valid (no samples).
+ * One host synchronisation per call (a second only when a first estimate of
+ * the tile-list size was too small).  n_tris == 0 is valid (no samples).
  */
 ldni_status ldni_sample(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                         const float bbox[6], int32_t w, uint32_t axis_mask, void *hip_stream,
@@ -136,6 +137,33 @@ ldni_status ldni_sample_finish(ldni_plan *plan, float *const depth[3], float *co
                                int32_t *const tri[3]);
 void ldni_plan_free(ldni_plan *plan);
 
+/*
+ * ldni_backward -- vertex gradient of a loss through the sampling (not in the
+ * paper; the differentiation of its Definition 2 samples).  For upstream
+ * gradients gd = dL/d depth and gn = dL/d normal of every sample of a
+ * forward result, adds to grad_verts the gradient of
+ *   sum_s gd[s] * depth[s] + gn[s] . normal[s]
+ * with respect to the vertex positions: a sample moves along its fixed ray
+ * with its triangle's plane (d depth / dX = lambda_X n / n_a for barycentric
+ * weight lambda_X of vertex X), and its face normal n = N/|N| with
+ * N = (B-A)x(C-A).  The sample set is held fixed (piecewise-smooth
+ * derivative; it does not see samples appearing or vanishing).
+ *   verts..axis_mask  the same arguments as the forward call (device mesh,
+ *             host bbox, w, mask); the mesh must be the one that was sampled.
+ *   views     HOST array of 3 views; for each axis in the mask, w, n_samples,
+ *             offsets (device) and tri (device) of the forward result (depth
+ *             and normal are not read).
+ *   grad_depth, grad_normal  HOST arrays of 3 device pointers, f32 [n] and
+ *             f32 [n][3] per axis, or NULL (the array or an entry) for zero.
+ *   grad_verts device f32 [n_verts][3]; accumulated with +=, not cleared.
+ * Sums use float atomics, so the last bits vary from run to run.  Triangle
+ * ids outside [0, n_tris) in a view are ignored.  No host synchronisation.
+ */
+ldni_status ldni_backward(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                          const float bbox[6], int32_t w, uint32_t axis_mask,
+                          const ldni_axis_view views[3], const float *const grad_depth[3],
+                          const float *const grad_normal[3], float *grad_verts, void *hip_stream);
+
 /* Largest per-pixel count of each axis of a plan (after begin). */
 ldni_status ldni_plan_max_layers(const ldni_plan *plan, uint32_t max_layers[3]);
 
@@ -149,6 +177,53 @@ const char *ldni_last_error(void);
  * tw*th <= 1024, 8 <= tw <= 256, 1 <= th <= 64.  Process-wide; default
  * 32 x 32.  Results do not depend on it. */
 ldni_status ldni_set_tile_shape(int32_t tw, int32_t th);
+
+/*
+ * Batched sampling -- many meshes, each with its own resolution, box and
+ * tile shape, sampled by one captured HIP graph (the same definitions as
+ * ldni_sample, applied mesh by mesh; results are bit-identical to separate
+ * ldni_sample calls).  A batch keeps the mesh pointers: a run samples the
+ * current contents of the same device buffers.
+ */
+typedef struct {
+  const float *verts;   /* device f32 [n_verts][3] */
+  int64_t n_verts;
+  const int32_t *tris;  /* device i32 [n_tris][3] */
+  int64_t n_tris;
+  float bbox[6];        /* xlo, ylo, zlo, xhi, yhi, zhi */
+  int32_t w;            /* 1..16384 */
+  int32_t tile_w, tile_h; /* tile shape for this mesh; 0, 0 = the process default */
+} ldni_mesh_desc;
+
+typedef struct ldni_batch ldni_batch; /* opaque; owns its device memory and graph */
+
+/*
+ * ldni_batch_create -- validate the descriptors (host array of n_meshes >= 1;
+ * the same argument rules as ldni_sample for each), allocate the batch's
+ * workspace, capture the whole pipeline (setup, binning, count, segmented
+ * scan, placement, write) into a HIP graph on a private stream, and run it
+ * once on hip_stream, sizing the tile-list and output buffers.  Device
+ * memory is held until ldni_batch_free.  Errors as ldni_sample; on error
+ * *out is NULL.
+ */
+ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc *meshes, uint32_t axis_mask,
+                              void *hip_stream, ldni_batch **out);
+
+/* Replay the batch's graph on hip_stream and wait for it (one host
+ * synchronisation); if the meshes now need larger tile lists or outputs,
+ * the buffers grow, the graph is captured again and replayed.  Views from
+ * before are invalid afterwards. */
+ldni_status ldni_batch_run(ldni_batch *b, void *hip_stream);
+
+/* View of one mesh's axis (0..2) after the last run (empty for axes not in
+ * the mask); borrowed, valid until the next run or ldni_batch_free. */
+ldni_status ldni_batch_axis(const ldni_batch *b, int32_t mesh, int axis, ldni_axis_view *view);
+
+void ldni_batch_free(ldni_batch *b); /* NULL-safe; synchronous */
+
+/* ldni_batch_create under the name of the batched entry point. */
+ldni_status ldni_sample_batch(int32_t n_meshes, const ldni_mesh_desc *meshes, uint32_t axis_mask,
+                              void *hip_stream, ldni_batch **out);
 
 /*
  * Kernel timing (tracing support, not part of the paper's method).

@@ -21,7 +21,8 @@ from ._lib import LDNIError
 
 __all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ldni_free",
            "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
-           "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read"]
+           "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read",
+           "ldni_backward", "sample_diff", "LDNISample", "Batch", "sample_batch"]
 
 AXES = "xyz"
 library_path = _lib.LIB_PATH
@@ -149,6 +150,123 @@ def sample(verts, tris, bbox, w: int, axes="xyz") -> Dict[int, LDNI]:
     return {a: LDNI(a, int(w), int(ml[a]), offs[a], depth[a], normal[a], tri[a]) for a in offs}
 
 
+def _view(l: LDNI) -> _lib.AxisView:
+    ptr = lambda t: None if t is None else t.data_ptr()
+    return _lib.AxisView(int(l.w), int(max(l.max_layers, 0)), int(l.tri.shape[0]),
+                         l.offsets.data_ptr(), ptr(l.depth), ptr(l.normal), l.tri.data_ptr())
+
+
+def ldni_backward(verts, tris, bbox, w: int, ldnis: Dict[int, LDNI], grad_depth=None,
+                  grad_normal=None, grad_verts=None):
+    """Adds to ``grad_verts`` (created as zeros if None) the vertex gradient of
+    sum(gd * depth) + sum(gn . normal) over the samples of ``ldnis``;
+    ``grad_depth``/``grad_normal`` map axis -> float32 device tensors [n] and
+    [n, 3] (missing axes are zero).  Returns grad_verts."""
+    torch = _torch()
+    verts, tris = _check_mesh(verts, tris)
+    if grad_verts is None:
+        grad_verts = torch.zeros_like(verts)
+    grad_depth = grad_depth or {}
+    grad_normal = grad_normal or {}
+    views = (_lib.AxisView * 3)()
+    gd = (ctypes.c_void_p * 3)()
+    gn = (ctypes.c_void_p * 3)()
+    keep = []
+    mask = 0
+    for a, l in ldnis.items():
+        mask |= 1 << a
+        views[a] = _view(l)
+        n = int(l.tri.shape[0])
+        for src, dst, shape in ((grad_depth, gd, (n,)), (grad_normal, gn, (n, 3))):
+            g = src.get(a)
+            if g is not None:
+                g = g.to(device=verts.device, dtype=torch.float32).contiguous()
+                if tuple(g.shape) != shape:
+                    raise ValueError(f"gradient of axis {a} has shape {tuple(g.shape)}, expected {shape}")
+                keep.append(g)
+                dst[a] = g.data_ptr()
+    if mask == 0:
+        return grad_verts
+    if not (grad_verts.is_contiguous() and grad_verts.dtype == torch.float32
+            and tuple(grad_verts.shape) == tuple(verts.shape)):
+        raise ValueError("grad_verts must be a contiguous float32 tensor shaped like verts")
+    _lib.check(_lib.lib().ldni_backward(verts.data_ptr(), verts.shape[0], tris.data_ptr(),
+                                        tris.shape[0], _bbox(bbox), int(w), mask, views, gd, gn,
+                                        grad_verts.data_ptr(), _stream(verts.device)))
+    return grad_verts
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class LDNISample(torch.autograd.Function):
+        """Differentiable sampling: outputs (depth, normal) per requested axis,
+        then (offsets, tri, max_layers) per axis, the latter not
+        differentiable.  The backward pass is the library's ldni_backward."""
+
+        @staticmethod
+        def forward(ctx, verts, tris, bbox, w, axes):
+            res = sample(verts, tris, bbox, w, axes)
+            order = sorted(res)
+            ctx.order = order
+            ctx.bbox = tuple(bbox)
+            ctx.w = int(w)
+            ctx.save_for_backward(verts, tris, *[res[a].offsets for a in order],
+                                  *[res[a].tri for a in order])
+            outs = []
+            for a in order:
+                outs += [res[a].depth, res[a].normal]
+            extra = []
+            for a in order:
+                extra += [res[a].offsets, res[a].tri,
+                          torch.tensor(res[a].max_layers, dtype=torch.int64)]
+            ctx.mark_non_differentiable(*extra)
+            return tuple(outs + extra)
+
+        @staticmethod
+        def backward(ctx, *grads):
+            saved = ctx.saved_tensors
+            verts, tris = saved[0], saved[1]
+            k_ax = len(ctx.order)
+            ldnis = {a: LDNI(a, ctx.w, 0, saved[2 + i], None, None, saved[2 + k_ax + i])
+                     for i, a in enumerate(ctx.order)}
+            gd, gn = {}, {}
+            for k, a in enumerate(ctx.order):
+                if grads[2 * k] is not None:
+                    gd[a] = grads[2 * k]
+                if grads[2 * k + 1] is not None:
+                    gn[a] = grads[2 * k + 1]
+            g = ldni_backward(verts.detach(), tris, ctx.bbox, ctx.w, ldnis, gd, gn)
+            return g, None, None, None, None
+
+    return LDNISample
+
+
+_LDNISample = None
+
+
+def LDNISample():
+    """The torch.autograd.Function class behind ``sample_diff``."""
+    global _LDNISample
+    if _LDNISample is None:
+        _LDNISample = _autograd_function()
+    return _LDNISample
+
+
+def sample_diff(verts, tris, bbox, w: int, axes="xyz") -> Dict[int, LDNI]:
+    """Like ``sample`` but ``depth`` and ``normal`` carry gradients to
+    ``verts`` (through ldni_backward)."""
+    fn = LDNISample()
+    outs = fn.apply(verts, tris, tuple(float(x) for x in bbox), int(w), axes)
+    order = sorted(AXES.index(c) for c in axes) if isinstance(axes, str) else sorted(axes)
+    k = len(order)
+    res = {}
+    for i, a in enumerate(order):
+        off, tri, ml = outs[2 * k + 3 * i: 2 * k + 3 * i + 3]
+        res[a] = LDNI(a, int(w), int(ml), off, outs[2 * i], outs[2 * i + 1], tri)
+    return res
+
+
 # ---- library-owned results -------------------------------------------------
 
 class Result:
@@ -165,24 +283,8 @@ class Result:
     def to_torch(self, axis: int, device=None) -> LDNI:
         """Copy one axis into new torch tensors (device-to-device)."""
         torch = _torch()
-        v = self.view(axis)
         dev = torch.device("cuda") if device is None else torch.device(device)
-        n = int(v.n_samples)
-        out = LDNI(axis, int(v.w), int(v.max_layers),
-                   torch.empty(int(v.w) * int(v.w) + 1, dtype=torch.int32, device=dev),
-                   torch.empty(n, dtype=torch.float32, device=dev),
-                   torch.empty((n, 3), dtype=torch.float32, device=dev),
-                   torch.empty(n, dtype=torch.int32, device=dev))
-        H = _lib.hip()
-        st = _stream(dev)
-        for dst, src, nbytes in ((out.offsets, v.offsets, 4 * out.offsets.numel()),
-                                 (out.depth, v.depth, 4 * n), (out.normal, v.normal, 12 * n),
-                                 (out.tri, v.tri, 4 * n)):
-            if nbytes:
-                rc = H.hipMemcpyAsync(dst.data_ptr(), src, nbytes, 3, st)
-                if rc != 0:
-                    raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
-        return out
+        return _copy_view(self.view(axis), axis, dev)
 
     def free(self):
         if self.handle:
@@ -205,6 +307,90 @@ def ldni_sample(verts, tris, bbox, w: int, axes="xyz", stream=None) -> Result:
                                       tris.shape[0], _bbox(bbox), int(w), axis_mask(axes), st,
                                       ctypes.byref(h)))
     return Result(h)
+
+
+def _copy_view(v: _lib.AxisView, axis: int, device) -> LDNI:
+    torch = _torch()
+    n = int(v.n_samples)
+    out = LDNI(axis, int(v.w), int(v.max_layers),
+               torch.empty(int(v.w) * int(v.w) + 1, dtype=torch.int32, device=device),
+               torch.empty(n, dtype=torch.float32, device=device),
+               torch.empty((n, 3), dtype=torch.float32, device=device),
+               torch.empty(n, dtype=torch.int32, device=device))
+    H = _lib.hip()
+    st = _stream(device)
+    for dst, src, nbytes in ((out.offsets, v.offsets, 4 * out.offsets.numel()),
+                             (out.depth, v.depth, 4 * n), (out.normal, v.normal, 12 * n),
+                             (out.tri, v.tri, 4 * n)):
+        if nbytes:
+            rc = H.hipMemcpyAsync(dst.data_ptr(), src, nbytes, 3, st)
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+    return out
+
+
+class Batch:
+    """Many meshes sampled by one captured graph (``ldni_batch_*``).
+
+    ``meshes``: sequence of (verts, tris, bbox, w) or (verts, tris, bbox, w,
+    (tile_w, tile_h)) with device tensors, which must stay alive and at the
+    same addresses; ``run()`` samples their current contents again."""
+
+    def __init__(self, meshes, axes="xyz"):
+        torch = _torch()
+        self._keep = []
+        descs = (_lib.MeshDesc * len(meshes))()
+        dev = None
+        for k, m in enumerate(meshes):
+            verts, tris, bbox, w = m[:4]
+            tile = m[4] if len(m) > 4 and m[4] is not None else (0, 0)
+            verts, tris = _check_mesh(verts, tris)
+            dev = verts.device
+            self._keep += [verts, tris]
+            descs[k] = _lib.MeshDesc(verts.data_ptr(), verts.shape[0], tris.data_ptr(), tris.shape[0],
+                                     (ctypes.c_float * 6)(*[float(x) for x in bbox]), int(w),
+                                     int(tile[0]), int(tile[1]))
+        self.device = dev if dev is not None else torch.device("cuda")
+        self.n_meshes = len(meshes)
+        self.mask = axis_mask(axes)
+        self.handle = ctypes.c_void_p()
+        _lib.check(_lib.lib().ldni_batch_create(len(meshes), descs, self.mask, _stream(self.device),
+                                                ctypes.byref(self.handle)))
+
+    def run(self):
+        _lib.check(_lib.lib().ldni_batch_run(self.handle, _stream(self.device)))
+
+    def view(self, mesh: int, axis: int) -> _lib.AxisView:
+        v = _lib.AxisView()
+        _lib.check(_lib.lib().ldni_batch_axis(self.handle, int(mesh), int(axis), ctypes.byref(v)))
+        return v
+
+    def to_torch(self, mesh: int, axis: int) -> LDNI:
+        return _copy_view(self.view(mesh, axis), axis, self.device)
+
+    def free(self):
+        if self.handle:
+            _lib.lib().ldni_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sample_batch(meshes, axes="xyz", tiles="auto") -> Batch:
+    """Create (and run once) a batch; see ``Batch``.  With tiles="auto",
+    meshes given without a tile shape get the autotuned one for their
+    resolution and triangle density (``autotune.lookup``)."""
+    if tiles == "auto":
+        from . import autotune
+        table = autotune.load_table()
+        meshes = [tuple(m[:4]) + ((m[4] if len(m) > 4 and m[4] is not None
+                                   else autotune.lookup(int(m[3]), int(m[1].shape[0]), table)),)
+                  for m in meshes]
+    return Batch(meshes, axes)
 
 
 def ldni_result_axis(result: Result, axis: int) -> _lib.AxisView:

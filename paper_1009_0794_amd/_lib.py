@@ -20,6 +20,13 @@ class AxisView(ctypes.Structure):
                 ("tri", ctypes.c_void_p)]
 
 
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("n_verts", ctypes.c_int64),
+                ("tris", ctypes.c_void_p), ("n_tris", ctypes.c_int64),
+                ("bbox", ctypes.c_float * 6), ("w", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_uint64),
                 ("total_ms", ctypes.c_double)]
@@ -73,6 +80,19 @@ def lib():
     L.ldni_last_error.restype = ctypes.c_char_p
     L.ldni_set_tile_shape.argtypes = [i32, i32]
     L.ldni_set_tile_shape.restype = st
+    L.ldni_backward.argtypes = [vp, i64, vp, i64, vp, i32, u32, ctypes.POINTER(AxisView),
+                                ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp]
+    L.ldni_backward.restype = st
+    L.ldni_batch_create.argtypes = [i32, ctypes.POINTER(MeshDesc), u32, vp, ctypes.POINTER(vp)]
+    L.ldni_batch_create.restype = st
+    L.ldni_sample_batch.argtypes = [i32, ctypes.POINTER(MeshDesc), u32, vp, ctypes.POINTER(vp)]
+    L.ldni_sample_batch.restype = st
+    L.ldni_batch_run.argtypes = [vp, vp]
+    L.ldni_batch_run.restype = st
+    L.ldni_batch_axis.argtypes = [vp, i32, ctypes.c_int, ctypes.POINTER(AxisView)]
+    L.ldni_batch_axis.restype = st
+    L.ldni_batch_free.argtypes = [vp]
+    L.ldni_batch_free.restype = None
     L.ldni_profile_enable.argtypes = [ctypes.c_int]
     L.ldni_profile_enable.restype = st
     L.ldni_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -106,4 +126,5 @@ def exported_symbols():
     return ["ldni_sample", "ldni_result_axis", "ldni_free", "ldni_sample_begin",
             "ldni_sample_finish", "ldni_plan_free", "ldni_plan_max_layers",
             "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
-            "ldni_profile_enable", "ldni_profile_read"]
+            "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
+            "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch"]

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -23,6 +24,8 @@ namespace {
 thread_local std::string g_last_error;
 std::atomic<int> g_tile_w{32};
 std::atomic<int> g_tile_h{32};
+// largest (tile-list entries / triangles) seen, with headroom
+std::atomic<double> g_list_ratio{2.0};
 
 ldni_status fail(ldni_status s, const std::string& msg) {
   g_last_error = msg;
@@ -305,40 +308,66 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     STEP(timed("scan_tiles", stream, [&] {
            return launch_scan(set.img[k].tile_cnt, set.img[k].tile_cnt, n_tiles, scan_scratch, status, stream);
          }), "tile scan");
-  // readback 1: tile-list sizes and input validity
-  STEP(hipMemcpyAsync(rb, status, sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "readback");
-  for (int k = 0; k < nimg; ++k)
-    STEP(hipMemcpyAsync(rb + 4 + k, set.img[k].tile_cnt + n_tiles, sizeof(uint32_t),
-                        hipMemcpyDeviceToHost, stream), "readback");
-  STEP(hipStreamSynchronize(stream), "synchronise");
-  if (rb[0] & kStatusBadIndex) return bail(fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)"));
-  if (rb[0] & kStatusNonFinite) return bail(fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate"));
-  size_t list_off[kMaxImages];
-  size_t lbytes = 0;
-  for (int k = 0; k < nimg; ++k) {
-    list_off[k] = lbytes;
-    lbytes = align_up(lbytes + sizeof(int32_t) * (size_t)rb[4 + k]);
-  }
-  e = pool_alloc(&p->lists, lbytes, stream);
-  if (e != hipSuccess) {
+  // Tile lists are sized from the largest entries-per-triangle ratio seen so
+  // far; the scatter drops entries beyond the capacity and the call is redone
+  // with the exact size when that happens (entry totals are read back below).
+  // (capped per triangle: a mesh of few large triangles is covered by the
+  // per-tile term, and anything beyond is caught by the retry)
+  uint64_t cap = (uint64_t)std::ceil((double)n_tris * std::min(g_list_ratio.load(), 8.0)) +
+                 4 * (uint64_t)n_tiles + 1024;
+  auto alloc_lists = [&](uint64_t c) -> hipError_t {
+    if (p->lists) (void)hipFreeAsync(p->lists, stream);
     p->lists = nullptr;
-    return bail(hip_fail(e, "tile list allocation"));
+    const size_t per = align_up(sizeof(int32_t) * (size_t)c);
+    hipError_t ea = pool_alloc(&p->lists, per * nimg, stream);
+    if (ea != hipSuccess) {
+      p->lists = nullptr;
+      return ea;
+    }
+    for (int k = 0; k < nimg; ++k) {
+      set.img[k].tile_list = reinterpret_cast<int32_t*>(static_cast<char*>(p->lists) + k * per);
+      set.img[k].list_cap = c;
+    }
+    return hipSuccess;
+  };
+  STEP(alloc_lists(cap), "tile list allocation");
+  const uint32_t* gather_src[16];
+  int n_gather = 0;
+  gather_src[n_gather++] = status;      // rb[0]: status, rb[1..3]: max layers
+  gather_src[n_gather++] = status + 1;
+  gather_src[n_gather++] = status + 2;
+  gather_src[n_gather++] = status + 3;
+  for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].offsets + npix;      // rb[4+k]
+  for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].tile_cnt + n_tiles; // rb[4+nimg+k]
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
+    STEP(timed("count", stream, [&] { return launch_count(set, stream); }), "count kernel");
+    for (int k = 0; k < nimg; ++k)
+      STEP(timed("scan_pixels", stream, [&] {
+             return launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream);
+           }), "pixel scan");
+    // the single readback: status, max layers, sample and entry totals
+    STEP(launch_gather(gather_src, n_gather, rb, stream), "readback");
+    STEP(hipStreamSynchronize(stream), "synchronise");
+    if (rb[0] & kStatusBadIndex) return bail(fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)"));
+    if (rb[0] & kStatusNonFinite) return bail(fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate"));
+    uint64_t need = 0;
+    for (int k = 0; k < nimg; ++k) need = std::max<uint64_t>(need, rb[4 + nimg + k]);
+    if (n_tris > 0) {
+      const double ratio = std::min(8.0, (double)need / (double)n_tris * 1.1);
+      double cur = g_list_ratio.load();
+      while (ratio > cur && !g_list_ratio.compare_exchange_weak(cur, ratio)) {
+      }
+    }
+    if (need <= cap) break;
+    if (attempt == 1) return bail(fail(LDNI_ERR_DEVICE, "tile list sizing failed"));
+    cap = need;
+    STEP(alloc_lists(cap), "tile list allocation");
+    for (int k = 0; k < nimg; ++k) {
+      STEP(launch_fill_u32(set.img[k].tile_cur, 0u, n_tiles, stream), "fill");
+    }
+    STEP(launch_fill_u32(status + 1, 0u, 3, stream), "fill");
   }
-  for (int k = 0; k < nimg; ++k)
-    set.img[k].tile_list = reinterpret_cast<int32_t*>(static_cast<char*>(p->lists) + list_off[k]);
-
-  STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
-  STEP(timed("count", stream, [&] { return launch_count(set, stream); }), "count kernel");
-  for (int k = 0; k < nimg; ++k)
-    STEP(timed("scan_pixels", stream, [&] {
-           return launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream);
-         }), "pixel scan");
-  // readback 2: sample totals
-  STEP(hipMemcpyAsync(rb, status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "readback");
-  for (int k = 0; k < nimg; ++k)
-    STEP(hipMemcpyAsync(rb + 4 + k, set.img[k].offsets + npix, sizeof(uint32_t),
-                        hipMemcpyDeviceToHost, stream), "readback");
-  STEP(hipStreamSynchronize(stream), "synchronise");
   if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more samples on one axis"));
   for (int k = 0; k < nimg; ++k) {
     const int a = p->axis_of[k];
@@ -493,6 +522,63 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
   return LDNI_OK;
 }
 
+ldni_status ldni_backward(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                          const float bbox[6], int32_t w, uint32_t axis_mask,
+                          const ldni_axis_view views[3], const float* const grad_depth[3],
+                          const float* const grad_normal[3], float* grad_verts, void* hip_stream) {
+  ldni_status st = validate(verts, n_verts, tris, n_tris, bbox, w, axis_mask);
+  if (st != LDNI_OK) return st;
+  if (!views) return fail(LDNI_ERR_INVALID_ARG, "views is NULL");
+  if (n_verts > 0 && !grad_verts) return fail(LDNI_ERR_INVALID_ARG, "grad_verts is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!((axis_mask >> a) & 1u)) continue;
+    const ldni_axis_view& v = views[a];
+    if (v.w != w) return fail(LDNI_ERR_INVALID_ARG, "view resolution differs from w");
+    if (!v.offsets || (v.n_samples > 0 && !v.tri))
+      return fail(LDNI_ERR_INVALID_ARG, "view of a requested axis lacks offsets or triangle ids");
+  }
+  if (n_tris == 0) return LDNI_OK;
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  prepare_pool(device);
+  BackwardArgs args{};
+  args.w = w;
+  for (int d = 0; d < 6; ++d) args.bbox[d] = (double)bbox[d];
+  args.verts = verts;
+  args.n_verts = n_verts;
+  args.tris = tris;
+  args.n_tris = n_tris;
+  args.grad = grad_verts;
+  int nimg = 0;
+  for (int a = 0; a < 3; ++a)
+    if ((axis_mask >> a) & 1u) {
+      const float* gd = grad_depth ? grad_depth[a] : nullptr;
+      const float* gn = grad_normal ? grad_normal[a] : nullptr;
+      if (views[a].n_samples == 0 || (!gd && !gn)) continue;
+      BackwardAxis& ax = args.axis[nimg++];
+      ax.a = a;
+      ax.offsets = views[a].offsets;
+      ax.tri = views[a].tri;
+      ax.gd = gd;
+      ax.gn = gn;
+    }
+  args.n = nimg;
+  if (nimg == 0) return LDNI_OK;
+  void* ws = nullptr;
+  const size_t per = align_up(sizeof(float) * 3 * (size_t)n_tris);
+  hipError_t e = pool_alloc(&ws, per * (nimg + 1), stream);
+  if (e != hipSuccess) return hip_fail(e, "backward workspace");
+  char* base = static_cast<char*>(ws);
+  for (int k = 0; k < nimg; ++k) args.axis[k].acc = reinterpret_cast<float*>(base + k * per);
+  args.gnsum = reinterpret_cast<float*>(base + nimg * per);
+  e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, (int64_t)(per * (nimg + 1) / 4), stream);
+  if (e == hipSuccess) e = timed("backward", stream, [&] { return launch_backward(args, stream); });
+  (void)hipFreeAsync(ws, stream);
+  if (e != hipSuccess) return hip_fail(e, "backward kernels");
+  return LDNI_OK;
+}
+
 ldni_status ldni_result_axis(const ldni_result* r, int axis, ldni_axis_view* view) {
   if (!r || !view || axis < 0 || axis > 2) return fail(LDNI_ERR_INVALID_ARG, "bad result/axis/view");
   *view = r->view[axis];
@@ -504,6 +590,410 @@ void ldni_free(ldni_result* r) {
   if (r->samples_buf) hipFreeAsync(r->samples_buf, r->stream);
   if (r->offsets_buf) hipFreeAsync(r->offsets_buf, r->stream);
   delete r;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// batched sampling
+// ===========================================================================
+struct ldni_batch {
+  int32_t n_meshes = 0;
+  uint32_t mask = 0;
+  int32_t n_img = 0;
+  std::vector<ldni_mesh_desc> desc;
+  std::vector<int32_t> img_mesh, img_axis;
+  std::vector<uint32_t> tri_block_start, bin_block_start, tile_start;
+  std::vector<uint64_t> seg_start;
+  hipStream_t cs = nullptr;  // private stream the graph is captured on
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* lists = nullptr;
+  uint64_t list_cap = 0;
+  void* samples = nullptr;
+  uint64_t sample_cap = 0;
+  uint32_t* host_out = nullptr;
+  BatchDevice dev{};
+  uint32_t* offsets_arena = nullptr;
+  uint32_t* counts_arena = nullptr;
+  uint32_t* tile_arena = nullptr;
+  uint32_t* cur_arena = nullptr;
+  uint32_t* max_layers = nullptr;
+  void* scan_scratch = nullptr;
+  uint64_t total_tiles = 0, total_slots = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<Image> images_h;
+  std::vector<BatchMesh> meshes_h;
+  // results of the last run
+  std::vector<uint32_t> n, ml;
+  std::vector<uint64_t> base;
+};
+
+namespace {
+
+void batch_release_graph(ldni_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+void batch_destroy(ldni_batch* b) {
+  if (!b) return;
+  batch_release_graph(b);
+  if (b->cs) (void)hipStreamSynchronize(b->cs);
+  if (b->samples) (void)hipFree(b->samples);
+  if (b->lists) (void)hipFree(b->lists);
+  if (b->ws) (void)hipFree(b->ws);
+  if (b->host_out) (void)hipHostFree(b->host_out);
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  delete b;
+}
+
+// Points the image table at the current list and sample buffers and uploads it.
+hipError_t batch_upload(ldni_batch* b) {
+  for (int k = 0; k < b->n_img; ++k) {
+    b->images_h[k].tile_list = static_cast<int32_t*>(b->lists);
+    b->images_h[k].list_cap = b->list_cap;
+  }
+  b->dev.list_cap = b->list_cap;
+  b->dev.depth = static_cast<float*>(b->samples);
+  b->dev.normal = b->samples ? static_cast<float*>(b->samples) + b->sample_cap : nullptr;
+  b->dev.tri = b->samples ? reinterpret_cast<int32_t*>(static_cast<float*>(b->samples) + 4 * b->sample_cap)
+                          : nullptr;
+  b->dev.sample_cap = b->sample_cap;
+  hipError_t e = hipMemcpy(b->dev.images, b->images_h.data(), sizeof(Image) * b->n_img, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(b->dev.meshes, b->meshes_h.data(), sizeof(BatchMesh) * b->n_meshes, hipMemcpyHostToDevice);
+}
+
+// The whole batch, as launched on one stream (and captured).
+hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
+  hipError_t e;
+#define Q(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
+  Q(launch_fill_u32(b->dev.status, 0u, 16, s));  // status and work counters
+  Q(launch_fill_u32(b->max_layers, 0u, b->n_img, s));
+  Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)b->total_tiles + 1, s));
+  Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
+  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));
+  Q(launch_batch_bin(b->dev, false, b->bin_block_start.back(), s));
+  Q(launch_scan(b->tile_arena, b->tile_arena, (int64_t)b->total_tiles, b->scan_scratch, b->dev.status, s));
+  Q(launch_batch_bin(b->dev, true, b->bin_block_start.back(), s));
+  Q(launch_batch_count(b->dev, (uint32_t)b->total_tiles, s));
+  Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
+                            b->scan_scratch, s));
+  Q(launch_batch_finish_counts(b->dev, s));
+  Q(launch_batch_write(b->dev, (uint32_t)b->total_tiles, s));
+#undef Q
+  return hipSuccess;
+}
+
+hipError_t batch_capture(ldni_batch* b) {
+  batch_release_graph(b);
+  hipError_t e = hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const hipError_t eq = batch_enqueue(b, b->cs);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cs, &g);
+  if (eq != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return eq;
+  }
+  if (e != hipSuccess) return e;
+  b->graph = g;
+  return hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+}
+
+ldni_status batch_grow(ldni_batch* b, void** buf, uint64_t* cap, uint64_t need, size_t bytes_per) {
+  const uint64_t c = need + need / 16 + 1024;
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  hipError_t e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(buf, (size_t)c * bytes_per);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    *cap = 0;
+    return hip_fail(e, "batch buffer");
+  }
+  *cap = c;
+  return LDNI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
+  if (!b) return fail(LDNI_ERR_INVALID_ARG, "NULL batch");
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if (!b->exec) {
+      hipError_t e = batch_upload(b);
+      if (e == hipSuccess) e = batch_capture(b);
+      if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, stream), "batch graph launch");
+    HIP_TRY(hipStreamSynchronize(stream), "synchronise");
+    const uint32_t* h = b->host_out;
+    if (h[0] & kStatusBadIndex) return fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)");
+    if (h[0] & kStatusNonFinite) return fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate");
+    bool regrow = false;
+    const uint64_t entries = h[1];
+    if (entries > b->list_cap) {
+      ldni_status st = batch_grow(b, &b->lists, &b->list_cap, entries, sizeof(int32_t));
+      if (st != LDNI_OK) return st;
+      regrow = true;
+    }
+    uint64_t need = 0;
+    for (int k = 0; k < b->n_img; ++k) {
+      const uint32_t* r = h + 4 + 4 * (size_t)k;
+      const uint64_t n = r[0];
+      const uint64_t base = (uint64_t)r[1] | ((uint64_t)r[2] << 32);
+      b->n[k] = r[0];
+      b->base[k] = base;
+      b->ml[k] = r[3];
+      need = std::max(need, base + n);
+    }
+    if (regrow) {  // counts were made from truncated lists: sizes are not final
+      batch_release_graph(b);
+      continue;
+    }
+    if (need > b->sample_cap) {
+      // 5 floats per sample: depth, normal[3], tri
+      ldni_status st = batch_grow(b, &b->samples, &b->sample_cap, need, 5 * sizeof(float));
+      if (st != LDNI_OK) return st;
+      batch_release_graph(b);
+      continue;
+    }
+    return LDNI_OK;
+  }
+  return fail(LDNI_ERR_DEVICE, "batch sizing did not converge");
+}
+
+ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, uint32_t axis_mask,
+                              void* hip_stream, ldni_batch** out) {
+  if (out) *out = nullptr;
+  if (!out || !meshes || n_meshes < 1) return fail(LDNI_ERR_INVALID_ARG, "need meshes and an output handle");
+  if (axis_mask == 0 || axis_mask > 7) return fail(LDNI_ERR_INVALID_ARG, "axis_mask must be in [1, 7]");
+  const int naxes = __builtin_popcount(axis_mask);
+  if ((int64_t)n_meshes * naxes > 65536) return fail(LDNI_ERR_INVALID_ARG, "too many images in one batch");
+  for (int m = 0; m < n_meshes; ++m) {
+    const ldni_mesh_desc& d = meshes[m];
+    ldni_status st = validate(d.verts, d.n_verts, d.tris, d.n_tris, d.bbox, d.w, axis_mask);
+    if (st != LDNI_OK) return fail(st, "mesh " + std::to_string(m) + ": " + g_last_error);
+    if (d.tile_w != 0 || d.tile_h != 0) {
+      const int tw = d.tile_w, th = d.tile_h;
+      if (tw < 8 || tw > 256 || th < 1 || th > 64 || tw * th > 1024)
+        return fail(LDNI_ERR_INVALID_ARG, "mesh " + std::to_string(m) + ": bad tile shape");
+    }
+  }
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  ldni_batch* b = new (std::nothrow) ldni_batch();
+  if (!b) return fail(LDNI_ERR_OUT_OF_MEMORY, "batch");
+  auto bail = [&](ldni_status s) {
+    batch_destroy(b);
+    return s;
+  };
+  b->n_meshes = n_meshes;
+  b->mask = axis_mask;
+  b->desc.assign(meshes, meshes + n_meshes);
+  hipError_t e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(hip_fail(e, "stream"));
+  e = hipHostMalloc(reinterpret_cast<void**>(&b->host_out), sizeof(uint32_t) * (4 + 4 * (size_t)n_meshes * naxes),
+                    hipHostMallocCoherent);
+  if (e != hipSuccess) {
+    b->host_out = nullptr;
+    return bail(hip_fail(e, "pinned summary"));
+  }
+
+  // ---- tables ----
+  b->tri_block_start.push_back(0);
+  b->bin_block_start.push_back(0);
+  b->tile_start.push_back(0);
+  b->seg_start.push_back(0);
+  uint64_t tris_total = 0, rect_total = 0;
+  std::vector<uint64_t> tri_off(n_meshes), rect_off;
+  for (int m = 0; m < n_meshes; ++m) {
+    const ldni_mesh_desc& d = meshes[m];
+    tri_off[m] = tris_total;
+    tris_total += (uint64_t)d.n_tris;
+    const uint32_t tb = (uint32_t)((d.n_tris + 255) / 256);
+    b->tri_block_start.push_back(b->tri_block_start.back() + tb);
+    for (int a = 0; a < 3; ++a) {
+      if (!((axis_mask >> a) & 1u)) continue;
+      const int tw = d.tile_w ? d.tile_w : g_tile_w.load(), th = d.tile_h ? d.tile_h : g_tile_h.load();
+      const uint64_t tiles = (uint64_t)((d.w + tw - 1) / tw) * ((d.w + th - 1) / th);
+      b->img_mesh.push_back(m);
+      b->img_axis.push_back(a);
+      rect_off.push_back(rect_total);
+      rect_total += (uint64_t)d.n_tris;
+      b->bin_block_start.push_back(b->bin_block_start.back() + tb);
+      b->tile_start.push_back((uint32_t)(b->tile_start.back() + tiles));
+      b->seg_start.push_back(b->seg_start.back() + (uint64_t)d.w * d.w + 1);
+    }
+  }
+  b->n_img = (int32_t)b->img_mesh.size();
+  b->total_tiles = b->tile_start.back();
+  b->total_slots = b->seg_start.back();
+  if (b->total_tiles >= 0xffffffffull) return bail(fail(LDNI_ERR_INVALID_ARG, "too many tiles in one batch"));
+  const int n_img = b->n_img;
+  b->n.assign(n_img, 0);
+  b->ml.assign(n_img, 0);
+  b->base.assign(n_img, 0);
+
+  // ---- workspace ----
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t o_status = take(sizeof(uint32_t) * 64);
+  const size_t o_meshes = take(sizeof(BatchMesh) * n_meshes);
+  const size_t o_images = take(sizeof(Image) * n_img);
+  const size_t o_tbs = take(sizeof(uint32_t) * (n_meshes + 1));
+  const size_t o_bbs = take(sizeof(uint32_t) * (n_img + 1));
+  const size_t o_ts = take(sizeof(uint32_t) * (n_img + 1));
+  const size_t o_ss = take(sizeof(uint64_t) * (n_img + 1));
+  const size_t o_sb = take(sizeof(uint64_t) * n_img);
+  const size_t o_ml = take(sizeof(uint32_t) * n_img);
+  const size_t o_soup = take(sizeof(float) * 9 * tris_total);
+  const size_t o_tnorm = take(sizeof(float) * 3 * tris_total);
+  const size_t o_rect = take(sizeof(Rect) * rect_total);
+  const size_t o_tile = take(sizeof(uint32_t) * (b->total_tiles + 1));
+  const size_t o_cur = take(sizeof(uint32_t) * b->total_tiles);
+  const size_t o_counts = take(sizeof(uint32_t) * b->total_slots);
+  const size_t o_offs = take(sizeof(uint32_t) * b->total_slots);
+  const size_t o_scan = take(std::max(scan_scratch_bytes((int64_t)b->total_tiles),
+                                      scan_scratch_bytes((int64_t)b->total_slots)));
+  e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(&b->ws, off);
+  if (e != hipSuccess) {
+    b->ws = nullptr;
+    return bail(hip_fail(e, "batch workspace"));
+  }
+  b->ws_bytes = off;
+  char* ws = static_cast<char*>(b->ws);
+  BatchDevice& D = b->dev;
+  D.status = reinterpret_cast<uint32_t*>(ws + o_status);
+  D.work = D.status + 8;
+  D.meshes = reinterpret_cast<BatchMesh*>(ws + o_meshes);
+  D.n_meshes = n_meshes;
+  D.images = reinterpret_cast<Image*>(ws + o_images);
+  D.n_images = n_img;
+  D.tri_block_start = reinterpret_cast<uint32_t*>(ws + o_tbs);
+  D.bin_block_start = reinterpret_cast<uint32_t*>(ws + o_bbs);
+  D.tile_start = reinterpret_cast<uint32_t*>(ws + o_ts);
+  D.seg_start = reinterpret_cast<uint64_t*>(ws + o_ss);
+  D.sample_base = reinterpret_cast<uint64_t*>(ws + o_sb);
+  D.host_out = b->host_out;
+  b->max_layers = reinterpret_cast<uint32_t*>(ws + o_ml);
+  b->tile_arena = reinterpret_cast<uint32_t*>(ws + o_tile);
+  b->cur_arena = reinterpret_cast<uint32_t*>(ws + o_cur);
+  b->counts_arena = reinterpret_cast<uint32_t*>(ws + o_counts);
+  b->offsets_arena = reinterpret_cast<uint32_t*>(ws + o_offs);
+  b->scan_scratch = ws + o_scan;
+  D.tile_total = b->tile_arena + b->total_tiles;
+
+  b->meshes_h.assign(n_meshes, BatchMesh{});
+  b->images_h.assign(n_img, Image{});
+  float* soup = reinterpret_cast<float*>(ws + o_soup);
+  float* tnorm = reinterpret_cast<float*>(ws + o_tnorm);
+  Rect* rect = reinterpret_cast<Rect*>(ws + o_rect);
+  for (int m = 0; m < n_meshes; ++m) {
+    BatchMesh& bm = b->meshes_h[m];
+    bm.m.verts = meshes[m].verts;
+    bm.m.n_verts = meshes[m].n_verts;
+    bm.m.tris = meshes[m].tris;
+    bm.m.n_tris = meshes[m].n_tris;
+    bm.m.soup = soup + 9 * tri_off[m];
+    bm.m.tnorm = tnorm + 3 * tri_off[m];
+    bm.m.status = D.status;
+    bm.nimg = 0;
+  }
+  for (int k = 0; k < n_img; ++k) {
+    const int m = b->img_mesh[k], a = b->img_axis[k];
+    const ldni_mesh_desc& d = meshes[m];
+    BatchMesh& bm = b->meshes_h[m];
+    Image& im = b->images_h[k];
+    im.a = a;
+    im.u = (a + 1) % 3;
+    im.v = (a + 2) % 3;
+    im.w = d.w;
+    im.lo_u = (double)d.bbox[im.u];
+    im.h_u = ((double)d.bbox[3 + im.u] - (double)d.bbox[im.u]) / (double)d.w;
+    im.lo_v = (double)d.bbox[im.v];
+    im.h_v = ((double)d.bbox[3 + im.v] - (double)d.bbox[im.v]) / (double)d.w;
+    im.lo_a = (double)d.bbox[a];
+    im.tw = d.tile_w ? d.tile_w : g_tile_w.load();
+    im.th = d.tile_h ? d.tile_h : g_tile_h.load();
+    im.ntx = (d.w + im.tw - 1) / im.tw;
+    im.nty = (d.w + im.th - 1) / im.th;
+    im.soup = bm.m.soup;
+    im.tnorm = bm.m.tnorm;
+    im.rect = rect + rect_off[k];
+    bm.m.rect[bm.nimg] = rect + rect_off[k];
+    bm.img[bm.nimg++] = k;
+    im.n_tris = d.n_tris;
+    im.tile_cnt = b->tile_arena + b->tile_start[k];
+    im.tile_cur = b->cur_arena + b->tile_start[k];
+    im.counts = b->counts_arena + b->seg_start[k];
+    im.max_layers = b->max_layers + k;
+    im.offsets = b->offsets_arena + b->seg_start[k];
+    im.status = D.status;
+  }
+  e = hipMemcpy(const_cast<uint32_t*>(D.tri_block_start), b->tri_block_start.data(),
+                sizeof(uint32_t) * (n_meshes + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(const_cast<uint32_t*>(D.bin_block_start), b->bin_block_start.data(),
+                  sizeof(uint32_t) * (n_img + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(const_cast<uint32_t*>(D.tile_start), b->tile_start.data(), sizeof(uint32_t) * (n_img + 1),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(const_cast<uint64_t*>(D.seg_start), b->seg_start.data(), sizeof(uint64_t) * (n_img + 1),
+                  hipMemcpyHostToDevice);
+  // the last slot of every image's counts stays zero for the segmented scan
+  if (e == hipSuccess) e = launch_fill_u32(b->counts_arena, 0u, (int64_t)b->total_slots, b->cs);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->cs);
+  if (e != hipSuccess) return bail(hip_fail(e, "batch tables"));
+
+  // tile lists sized like the single-mesh path; outputs sized by the first run
+  uint64_t cap = 1024;
+  for (int k = 0; k < n_img; ++k)
+    cap += (uint64_t)std::ceil((double)meshes[b->img_mesh[k]].n_tris * std::min(g_list_ratio.load(), 8.0)) +
+           4 * (uint64_t)(b->tile_start[k + 1] - b->tile_start[k]);
+  ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, sizeof(int32_t));
+  if (st != LDNI_OK) return bail(st);
+  st = ldni_batch_run(b, hip_stream);
+  if (st != LDNI_OK) return bail(st);
+  *out = b;
+  return LDNI_OK;
+}
+
+ldni_status ldni_batch_axis(const ldni_batch* b, int32_t mesh, int axis, ldni_axis_view* view) {
+  if (!b || !view || mesh < 0 || mesh >= b->n_meshes || axis < 0 || axis > 2)
+    return fail(LDNI_ERR_INVALID_ARG, "bad batch/mesh/axis/view");
+  std::memset(view, 0, sizeof(*view));
+  for (int k = 0; k < b->n_img; ++k) {
+    if (b->img_mesh[k] != mesh || b->img_axis[k] != axis) continue;
+    view->w = b->desc[mesh].w;
+    view->max_layers = b->ml[k];
+    view->n_samples = b->n[k];
+    view->offsets = b->offsets_arena + b->seg_start[k];
+    view->depth = static_cast<const float*>(b->samples) + b->base[k];
+    view->normal = static_cast<const float*>(b->samples) + b->sample_cap + 3 * b->base[k];
+    view->tri = reinterpret_cast<const int32_t*>(static_cast<const float*>(b->samples) + 4 * b->sample_cap) +
+                b->base[k];
+  }
+  return LDNI_OK;
+}
+
+void ldni_batch_free(ldni_batch* b) { batch_destroy(b); }
+
+ldni_status ldni_sample_batch(int32_t n_meshes, const ldni_mesh_desc* meshes, uint32_t axis_mask,
+                              void* hip_stream, ldni_batch** out) {
+  return ldni_batch_create(n_meshes, meshes, axis_mask, hip_stream, out);
 }
 
 }  // extern "C"

@@ -19,6 +19,9 @@ enum : uint32_t {
   kStatusBadIndex = 1u,
   kStatusNonFinite = 2u,
   kStatusOverflow = 4u,
+  kStatusMismatch = 8u,  // write pass found more hits than the count pass
+  kStatusListFull = 16u, // batch: tile lists longer than their capacity
+  kStatusOutFull = 32u,  // batch: samples beyond the output capacity
 };
 
 // Everything one image (one axis of one mesh) needs on the device.
@@ -41,6 +44,7 @@ struct Image {
   uint32_t* tile_cnt;   // [n_tiles + 1] entries per tile -> exclusive offsets
   uint32_t* tile_cur;   // [n_tiles] scatter cursors
   int32_t* tile_list;   // triangle ids grouped by tile
+  uint64_t list_cap;    // capacity of tile_list (entries beyond it are dropped)
   uint32_t* counts;     // [w*w] samples per pixel
   uint32_t* max_layers; // [1]
   // outputs
@@ -81,6 +85,75 @@ hipError_t launch_bin_count(const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
 hipError_t launch_count(const ImageSet& set, hipStream_t s);
 hipError_t launch_write(const ImageSet& set, hipStream_t s);
+
+// ---- batched sampling: many meshes, each with its own w and tile shape ----
+struct BatchMesh {
+  MeshSetup m;
+  int32_t nimg;
+  int32_t img[kMaxImages];  // indices into the image table
+};
+
+struct BatchDevice {
+  BatchMesh* meshes;
+  int32_t n_meshes;
+  Image* images;
+  int32_t n_images;
+  const uint32_t* tri_block_start;  // [n_meshes+1] setup workgroups per mesh (prefix)
+  const uint32_t* bin_block_start;  // [n_images+1] binning workgroups per image (prefix)
+  const uint32_t* tile_start;       // [n_images+1] tiles per image (prefix)
+  const uint64_t* seg_start;        // [n_images+1] first slot of each image in counts/offsets
+  uint64_t* sample_base;            // [n_images] first sample of each image in the outputs
+  uint32_t* work;                   // [2] work counters of the persistent kernels
+  uint32_t* status;
+  float* depth;                     // output arenas, sample_cap samples
+  float* normal;
+  int32_t* tri;
+  uint64_t sample_cap;
+  uint32_t* tile_total;             // entries of all tile lists (end of the tile scan)
+  uint64_t list_cap;
+  uint32_t* host_out;               // pinned: [0] status, [1] list entries, then per image
+                                    // (n, base lo, base hi, max layers)
+};
+
+hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s);
+hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks, hipStream_t s);
+hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, hipStream_t s);
+hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, hipStream_t s);
+// Segmented exclusive scan of the per-image counts (segments of w*w+1 slots,
+// the last slot of each zero) into per-image offsets starting at 0, with the
+// u64 start of every segment in sample_base.
+hipError_t launch_batch_pixel_scan(const BatchDevice& b, const uint32_t* counts, uint32_t* offsets,
+                                   int64_t n_slots, void* scratch, hipStream_t s);
+// Places every image in the output arena (or flags kStatusOutFull) and
+// writes the host summary.
+hipError_t launch_batch_finish_counts(const BatchDevice& b, hipStream_t s);
+
+// Vertex gradient of sum(gd * depth) + sum(gn . normal) over the images of
+// one forward result.
+struct BackwardAxis {
+  int32_t a;
+  const uint32_t* offsets;
+  const int32_t* tri;
+  const float* gd;  // may be null
+  const float* gn;  // may be null
+  float* acc;       // workspace [T][3], zeroed
+};
+struct BackwardArgs {
+  BackwardAxis axis[kMaxImages];
+  int32_t n;
+  int32_t w;
+  double bbox[6];
+  const float* verts;
+  int64_t n_verts;
+  const int32_t* tris;
+  int64_t n_tris;
+  float* gnsum;  // workspace [T][3], zeroed
+  float* grad;   // [V][3], accumulated
+};
+hipError_t launch_backward(const BackwardArgs& args, hipStream_t s);
+
+// Copies n (<= 16) device words into pinned, device-visible host memory.
+hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, hipStream_t s);
 
 // Exclusive scan of n u32 values into out[0..n] (out[n] = total).  Totals of
 // 2^32 or more raise kStatusOverflow.  scratch: scan_scratch_bytes(n).

@@ -30,7 +30,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxTilePix = 1024;    // tw * th
 constexpr int kMaxTileW = 256;
 constexpr int kMaxTileH = 64;
-constexpr int kStageCap = 6144;      // (depth, tri) keys staged per tile chunk
+constexpr int kStageCap = 4096;      // (depth, tri) keys staged per tile chunk
 
 // ---------------------------------------------------------------------------
 // pixel centres and candidate rectangles
@@ -65,36 +65,6 @@ __device__ __forceinline__ int orient(float pu, float pv, float qu, float qv, do
   if (s == 0) s = (pv > qv) - (pv < qv);
   if (s == 0) s = (qu > pu) - (qu < pu);
   return s;
-}
-
-struct Coverage {
-  double e_ab, e_bc, e_ca;
-  bool hit;
-};
-
-__device__ __forceinline__ Coverage cover(float au, float av, float bu, float bv, float cu,
-                                          float cv, float ru, float rv) {
-  Coverage c;
-  const float pau = au - ru, pav = av - rv;
-  const float pbu = bu - ru, pbv = bv - rv;
-  const float pcu = cu - ru, pcv = cv - rv;
-  const int s0 = orient(pau, pav, pbu, pbv, c.e_ab);
-  const int s1 = orient(pbu, pbv, pcu, pcv, c.e_bc);
-  const int s2 = orient(pcu, pcv, pau, pav, c.e_ca);
-  c.hit = (s0 != 0) & (s0 == s1) & (s1 == s2);
-  return c;
-}
-
-// Depth of the hit from lo_a: the axis coordinate interpolated with the
-// barycentric weights E_BC, E_CA, E_AB over their sum, in float64.
-__device__ __forceinline__ float hit_depth(const Coverage& c, float az, float bz, float cz,
-                                           double lo_a) {
-  const double den = (c.e_ab + c.e_bc) + c.e_ca;
-  const double num = c.e_ca * ((double)bz - (double)az) + c.e_ab * ((double)cz - (double)az);
-  const double z = (double)az + num / den;
-  float d = (float)(z - lo_a);
-  if (d == 0.0f) d = 0.0f;
-  return d;
 }
 
 // (depth, triangle) as one unsigned key whose order is depth, then id.
@@ -164,8 +134,8 @@ __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+template <class ImageAt>
+__device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
   if (t >= m.n_tris) return;
   const int32_t ia = m.tris[3 * t], ib = m.tris[3 * t + 1], ic = m.tris[3 * t + 2];
   float P[9];
@@ -216,8 +186,8 @@ __global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set
     tn[0] = tn[1] = tn[2] = 0.0f;
   }
 
-  for (int k = 0; k < set.n; ++k) {
-    const Image& im = set.img[k];
+  for (int k = 0; k < nimg; ++k) {
+    const Image& im = image_at(k);
     const float umin = fminf(fminf(P[im.u], P[3 + im.u]), P[6 + im.u]);
     const float umax = fmaxf(fmaxf(P[im.u], P[3 + im.u]), P[6 + im.u]);
     const float vmin = fminf(fminf(P[im.v], P[3 + im.v]), P[6 + im.v]);
@@ -236,43 +206,85 @@ __global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set
   }
 }
 
+__global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set) {
+  setup_triangle(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
+                 (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
+// Every (triangle, tile) pair of a wave is counted (or placed) with one
+// atomic per distinct tile of the wave: lanes that share the tile are peeled
+// off together and ranked by their lane order.  Mesh order is spatially
+// coherent for most meshes, so a wave typically touches a handful of tiles.
+// All 64 lanes of every wave must call this (t beyond the mesh = no tiles).
+template <bool kScatter>
+__device__ void bin_triangles(const Image& im, int64_t t) {
+  const int lane = threadIdx.x & 63;
+  int tx0 = 0, ty0 = 0, nx = 1, n = 0;
+  if (t < im.n_tris) {
+    const Rect r = im.rect[t];
+    if (r.i0 < r.i1 && r.j0 < r.j1) {
+      tx0 = r.i0 / im.tw;
+      ty0 = r.j0 / im.th;
+      nx = (r.i1 - 1) / im.tw - tx0 + 1;
+      n = nx * ((r.j1 - 1) / im.th - ty0 + 1);
+    }
+  }
+  int nmax = n;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, __shfl_xor(nmax, d, 64));
+  const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int q = 0; q < nmax; ++q) {
+    int key = -1;
+    if (q < n) {
+      const int qy = q / nx;
+      key = (ty0 + qy) * im.ntx + tx0 + (q - qy * nx);
+    }
+    uint64_t pending = __ballot(key >= 0);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int k = __shfl(key, leader, 64);
+      const uint64_t same = __ballot(key == k);
+      uint32_t base = 0;
+      if (lane == leader)
+        base = atomicAdd(kScatter ? &im.tile_cur[k] : &im.tile_cnt[k], (uint32_t)__popcll(same));
+      base = (uint32_t)__shfl((int)base, leader, 64);
+      if (key == k) {
+        if (kScatter) {
+          const uint64_t pos = (uint64_t)im.tile_cnt[k] + base + (uint32_t)__popcll(same & lower);
+          if (pos < im.list_cap) im.tile_list[pos] = (int32_t)t;
+        }
+        key = -1;
+      }
+      pending &= ~same;
+    }
+  }
+}
+
 template <bool kScatter>
 __global__ void __launch_bounds__(kBlock) bin_kernel(ImageSet set) {
-  const Image& im = set.img[blockIdx.y];
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= im.n_tris) return;
-  const Rect r = im.rect[t];
-  if (r.i0 >= r.i1 || r.j0 >= r.j1) return;
-  const int tx0 = r.i0 / im.tw, tx1 = (r.i1 - 1) / im.tw;
-  const int ty0 = r.j0 / im.th, ty1 = (r.j1 - 1) / im.th;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const int tile = ty * im.ntx + tx;
-      if (kScatter) {
-        const uint32_t slot = atomicAdd(&im.tile_cur[tile], 1u);
-        im.tile_list[(size_t)im.tile_cnt[tile] + slot] = (int32_t)t;
-      } else {
-        atomicAdd(&im.tile_cnt[tile], 1u);
-      }
-    }
+  bin_triangles<kScatter>(set.img[blockIdx.y], (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // candidate enumeration inside one tile
 // ---------------------------------------------------------------------------
-// A chunk of up to kBlock tile-list entries is loaded into LDS together with
-// the prefix sum of their candidate counts; every thread then walks the
-// flattened (entry, pixel) candidates with a stride of kBlock, so large and
-// small triangles share the work evenly.
-template <int kNV>
+// A chunk of up to kBlock tile-list entries is loaded into LDS with the
+// prefix sum of their candidate counts (pixels of the triangle's rectangle
+// inside the tile rows being processed).  Each thread then walks a contiguous
+// run of kRun flattened candidates: one binary search finds the first owner,
+// after which pixels advance incrementally along the rows of the rectangle.
+constexpr int kRun = 16;
+
+template <bool kDepth>
 struct ChunkLds {
-  int32_t tri[kBlock];
-  int32_t start[kBlock];
-  int32_t box[kBlock];          // px0 | width << 10 | py0 << 20
-  float vtx[kNV][kBlock];       // (au, av, bu, bv, cu, cv[, az, bz, cz])
+  float4 ab[kBlock];                   // au, av, bu, bv
+  float2 c[kBlock];                    // cu, cv
+  float4 z[kDepth ? kBlock : 1];       // az, bz, cz, triangle id (bits)
+  int32_t geom[kBlock];                // px0 | py0 << 8 | (width - 1) << 16
+  int32_t start[kBlock + 1];           // exclusive prefix of candidates, start[m] = total
   int32_t wave_tmp[kWaves];
 };
 
@@ -281,13 +293,43 @@ struct TileGeom {
   int tile;            // tile index within its image
 };
 
-// Calls on_hit(k, px, py, cov) for every candidate of rows [r0, r1) of the
-// tile that is covered; k indexes the chunk arrays in L.
-template <int kNV, class OnHit>
+// Exact coverage of the ray (ru, rv) by the triangle whose vertices are
+// (au,av), (bu,bv), (cu,cv); tav/tbv/tcv are the v-translations of the row.
+// Each edge function is one exact product plus one fused multiply-add: since
+// both products of float32 values are exact in float64, the FMA returns the
+// same correctly rounded difference as two products and a subtraction.
+struct Edges {
+  double ab, bc, ca;
+};
+
+__device__ __forceinline__ bool covered(float au, float bu, float cu, float tav, float tbv,
+                                        float tcv, float ru, Edges& e) {
+  const float tau = au - ru, tbu = bu - ru, tcu = cu - ru;
+  const double dau = tau, dbu = tbu, dcu = tcu, dav = tav, dbv = tbv, dcv = tcv;
+  e.ab = fma(dau, dbv, -(dav * dbu));
+  e.bc = fma(dbu, dcv, -(dbv * dcu));
+  e.ca = fma(dcu, dav, -(dcv * dau));
+  const bool pos = (e.ab > 0.0) & (e.bc > 0.0) & (e.ca > 0.0);
+  const bool neg = (e.ab < 0.0) & (e.bc < 0.0) & (e.ca < 0.0);
+  if (pos | neg) return true;
+  if ((e.ab != 0.0) & (e.bc != 0.0) & (e.ca != 0.0)) return false;
+  // the ray meets an edge line: decide as if moved to (+eps, +eps^2)
+  double tmp;
+  const int s0 = orient(tau, tav, tbu, tbv, tmp);
+  const int s1 = orient(tbu, tbv, tcu, tcv, tmp);
+  const int s2 = orient(tcu, tcv, tau, tav, tmp);
+  return (s0 != 0) & (s0 == s1) & (s1 == s2);
+}
+
+// Calls on_hit(k, px, py, edges) for every covered candidate of rows
+// [r0, r1) of the tile; k indexes the chunk arrays in L.
+template <bool kDepth, class OnHit>
 __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int r1,
-                                ChunkLds<kNV>& L, const float* s_cu, const float* s_cv,
+                                ChunkLds<kDepth>& L, const float* s_cu, const float* s_cv,
                                 OnHit&& on_hit) {
-  const uint32_t e_begin = im.tile_cnt[g.tile], e_end = im.tile_cnt[g.tile + 1];
+  const uint64_t cap = im.list_cap;
+  const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[g.tile], cap);
+  const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[g.tile + 1], cap);
   const int ya = g.y0 + r0, yb = g.y0 + r1;
   for (uint32_t base = e_begin; base < e_end; base += kBlock) {
     const int m = (int)min((uint32_t)kBlock, e_end - base);
@@ -298,43 +340,71 @@ __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int 
       const Rect r = im.rect[t];
       const int px0 = max((int)r.i0, g.x0) - g.x0, px1 = min((int)r.i1, g.x0 + g.cw) - g.x0;
       const int py0 = max((int)r.j0, ya) - g.y0, py1 = min((int)r.j1, yb) - g.y0;
-      if (px1 > px0 && py1 > py0) nc = (px1 - px0) * (py1 - py0);
-      L.tri[k] = t;
-      L.box[k] = px0 | ((px1 - px0) << 10) | (py0 << 20);
-      const float* s = im.soup + 9 * (int64_t)t;
-      L.vtx[0][k] = s[im.u];
-      L.vtx[1][k] = s[im.v];
-      L.vtx[2][k] = s[3 + im.u];
-      L.vtx[3][k] = s[3 + im.v];
-      L.vtx[4][k] = s[6 + im.u];
-      L.vtx[5][k] = s[6 + im.v];
-      if (kNV == 9) {
-        L.vtx[kNV == 9 ? 6 : 0][k] = s[im.a];
-        L.vtx[kNV == 9 ? 7 : 0][k] = s[3 + im.a];
-        L.vtx[kNV == 9 ? 8 : 0][k] = s[6 + im.a];
+      int width = 1;
+      if (px1 > px0 && py1 > py0) {
+        width = px1 - px0;
+        nc = width * (py1 - py0);
       }
+      L.geom[k] = px0 | (max(py0, 0) << 8) | ((width - 1) << 16);
+      const float* s = im.soup + 9 * (int64_t)t;
+      L.ab[k] = make_float4(s[im.u], s[im.v], s[3 + im.u], s[3 + im.v]);
+      L.c[k] = make_float2(s[6 + im.u], s[6 + im.v]);
+      if constexpr (kDepth) L.z[k] = make_float4(s[im.a], s[3 + im.a], s[6 + im.a], __int_as_float(t));
     }
     int total;
     const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
     if (k < m) L.start[k] = excl;
+    if (k == 0) L.start[m] = total;
     __syncthreads();
-    for (int c = threadIdx.x; c < total; c += kBlock) {
-      // owner: the last entry whose start is <= c
-      int lo = 0, hi = m - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.start[mid] <= c) lo = mid; else hi = mid - 1;
+    for (int wb = 0; wb < total; wb += kBlock * kRun) {
+      int c = wb + threadIdx.x * kRun;
+      const int cend = min(c + kRun, total);
+      if (c < cend) {
+        // owner of c: the last entry whose start is <= c
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.start[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        int e = lo;
+        int gm = L.geom[e];
+        int width = ((gm >> 16) & 255) + 1;
+        int local = c - L.start[e];
+        int row = local / width;
+        int col = local - row * width;
+        int kend = L.start[e + 1];
+        float4 ab = L.ab[e];
+        float2 cc = L.c[e];
+        int px0 = gm & 255, py0 = (gm >> 8) & 255;
+        float rv = s_cv[py0 + row];
+        float tav = ab.y - rv, tbv = ab.w - rv, tcv = cc.y - rv;
+        for (; c < cend; ++c) {
+          if (c == kend) {  // next entry that has candidates
+            ++e;
+            while (L.start[e + 1] <= c) ++e;
+            gm = L.geom[e];
+            width = ((gm >> 16) & 255) + 1;
+            px0 = gm & 255;
+            py0 = (gm >> 8) & 255;
+            row = 0;
+            col = 0;
+            kend = L.start[e + 1];
+            ab = L.ab[e];
+            cc = L.c[e];
+            rv = s_cv[py0];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+          Edges ed;
+          if (covered(ab.x, ab.z, cc.x, tav, tbv, tcv, s_cu[px0 + col], ed))
+            on_hit(e, px0 + col, py0 + row, ed);
+          if (++col == width) {
+            col = 0;
+            ++row;
+            rv = s_cv[py0 + row];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+        }
       }
-      const int e = lo;
-      const int bx = L.box[e];
-      const int px0 = bx & 1023, width = (bx >> 10) & 1023, py0 = bx >> 20;
-      const int local = c - L.start[e];
-      const int row = local / width;
-      const int px = px0 + (local - row * width);
-      const int py = py0 + row;
-      const Coverage cov = cover(L.vtx[0][e], L.vtx[1][e], L.vtx[2][e], L.vtx[3][e],
-                                 L.vtx[4][e], L.vtx[5][e], s_cu[px], s_cv[py]);
-      if (cov.hit) on_hit(e, px, py, cov);
     }
     __syncthreads();
   }
@@ -351,31 +421,42 @@ __device__ __forceinline__ TileGeom tile_geom(const Image& im, int tile) {
   return g;
 }
 
+// Depth of the hit from lo_a: the axis coordinate interpolated with the
+// barycentric weights E_BC, E_CA, E_AB over their sum, in float64.
+__device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, float cz,
+                                          double lo_a) {
+  const double den = (e.ab + e.bc) + e.ca;
+  const double num = e.ca * ((double)bz - (double)az) + e.ab * ((double)cz - (double)az);
+  const double z = (double)az + num / den;
+  float d = (float)(z - lo_a);
+  if (d == 0.0f) d = 0.0f;
+  return d;
+}
+
 // ---------------------------------------------------------------------------
 // count pass
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
+__device__ void count_tile(const Image& im, int tile) {
   __shared__ uint32_t s_cnt[kMaxTilePix];
   __shared__ float s_cu[kMaxTileW];
-  __shared__ float s_cv[kMaxTileH];
-  __shared__ ChunkLds<6> L;
+  __shared__ float s_cv[kMaxTileH + 1];
+  __shared__ ChunkLds<false> L;
   __shared__ uint32_t s_red[kWaves];
 
-  const int k_img = image_of_block(set, blockIdx.x);
-  const Image& im = set.img[k_img];
-  const TileGeom g = tile_geom(im, (int)(blockIdx.x - set.tile_start[k_img]));
+  const TileGeom g = tile_geom(im, tile);
   const int npix = g.cw * g.ch;
+  const int tw = im.tw;
 
   for (int q = threadIdx.x; q < im.tw * im.th; q += kBlock) s_cnt[q] = 0;
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
-  for (int q = threadIdx.x; q < g.ch; q += kBlock) s_cv[q] = pixel_centre(im.lo_v, im.h_v, g.y0 + q);
+  for (int q = threadIdx.x; q <= g.ch; q += kBlock)
+    s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
   __syncthreads();
 
-  const int tw = im.tw;
-  tile_candidates<6>(im, g, 0, g.ch, L, s_cu, s_cv,
-                     [&](int, int px, int py, const Coverage&) {
-                       atomicAdd(&s_cnt[py * tw + px], 1u);
-                     });
+  tile_candidates<false>(im, g, 0, g.ch, L, s_cu, s_cv,
+                         [&](int, int px, int py, const Edges&) {
+                           atomicAdd(&s_cnt[py * tw + px], 1u);
+                         });
 
   uint32_t mx = 0;
   for (int q = threadIdx.x; q < npix; q += kBlock) {
@@ -388,140 +469,126 @@ __global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
   if (threadIdx.x == 0 && mx > 0) atomicMax(im.max_layers, mx);
 }
 
+__global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
+  const int k = image_of_block(set, blockIdx.x);
+  count_tile(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
+}
+
 // ---------------------------------------------------------------------------
 // write pass
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set) {
+// The tile's pixels are taken in runs (row-major within the tile) whose
+// samples fit in LDS.  Hits of a run are staged at their pixel's slots as
+// (depth, triangle) keys with the pixel alongside; each staged key then finds
+// its rank among its pixel's keys and is stored straight to its sorted
+// position, so sorting and storing are one pass over the staged keys.  Only a
+// single pixel with more samples than the LDS capacity is written directly to
+// its output range and sorted there.
+__device__ void write_tile(const Image& im, int tile) {
   __shared__ uint64_t s_keys[kStageCap];
-  __shared__ uint32_t s_rel[kMaxTilePix];   // pixel start within its row's range
-  __shared__ uint32_t s_pcnt[kMaxTilePix];  // samples of the pixel
-  __shared__ uint32_t s_cur[kMaxTilePix];   // fill cursor of the pixel
-  __shared__ uint32_t s_rowbase[kMaxTileH]; // global offset of the row's first sample
-  __shared__ uint32_t s_rowtot[kMaxTileH];
-  __shared__ uint32_t s_stage[kMaxTileH + 1];  // LDS start of each row of the chunk
+  __shared__ uint16_t s_pix[kStageCap];       // tile pixel index of each staged key
+  __shared__ uint32_t s_off[kMaxTilePix];     // output offset of each tile pixel
+  __shared__ uint32_t s_pre[kMaxTilePix + 1]; // prefix of samples over tile pixels
+  __shared__ uint32_t s_cur[kMaxTilePix];     // fill cursor of each tile pixel
   __shared__ float s_cu[kMaxTileW];
-  __shared__ float s_cv[kMaxTileH];
-  __shared__ ChunkLds<9> L;
-  __shared__ int s_chunk[3];                 // r1, global mode, chunk total
+  __shared__ float s_cv[kMaxTileH + 1];
+  __shared__ ChunkLds<true> L;
+  __shared__ uint32_t s_wave[kWaves];
+  __shared__ int s_run[2];                    // end pixel of the run, direct mode
 
-  const int k_img = image_of_block(set, blockIdx.x);
-  const Image& im = set.img[k_img];
-  const TileGeom g = tile_geom(im, (int)(blockIdx.x - set.tile_start[k_img]));
-  const int tw = im.tw;
-  const int npix = g.cw * g.ch;
+  const TileGeom g = tile_geom(im, tile);
+  const int npix = g.cw * g.ch;  // tile pixels, q = py * cw + px
 
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
-  for (int q = threadIdx.x; q < g.ch; q += kBlock) s_cv[q] = pixel_centre(im.lo_v, im.h_v, g.y0 + q);
-  for (int q = threadIdx.x; q < g.ch; q += kBlock) {
-    const size_t row0 = (size_t)(g.y0 + q) * im.w + g.x0;
-    const uint32_t b = im.offsets[row0];
-    s_rowbase[q] = b;
-    s_rowtot[q] = im.offsets[row0 + g.cw] - b;
+  for (int q = threadIdx.x; q <= g.ch; q += kBlock)
+    s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
+  // offsets and counts of the tile's pixels; s_pre = exclusive prefix
+  uint32_t carry = 0;
+  for (int base = 0; base < npix; base += kBlock) {
+    const int q = base + threadIdx.x;
+    uint32_t n = 0;
+    if (q < npix) {
+      const int py = q / g.cw, px = q - py * g.cw;
+      const size_t gp = (size_t)(g.y0 + py) * im.w + g.x0 + px;
+      const uint32_t o = im.offsets[gp];
+      n = im.offsets[gp + 1] - o;
+      s_off[q] = o;
+      s_cur[q] = 0;
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(n, s_wave, total);
+    if (q < npix) s_pre[q] = carry + ex;
+    carry += total;
   }
-  __syncthreads();
-  for (int q = threadIdx.x; q < npix; q += kBlock) {
-    const int py = q / g.cw, px = q - py * g.cw;
-    const size_t gp = (size_t)(g.y0 + py) * im.w + g.x0 + px;
-    const uint32_t o = im.offsets[gp];
-    s_rel[py * tw + px] = o - s_rowbase[py];
-    s_pcnt[py * tw + px] = im.offsets[gp + 1] - o;
-    s_cur[py * tw + px] = 0;
-  }
+  if (threadIdx.x == 0) s_pre[npix] = carry;
   __syncthreads();
 
-  int r0 = 0;
-  while (r0 < g.ch) {
+  int q0 = 0;
+  while (q0 < npix) {
     if (threadIdx.x == 0) {
-      int r1 = r0 + 1;
-      uint64_t acc = s_rowtot[r0];
-      const int global_mode = acc > (uint64_t)kStageCap;
-      if (!global_mode)
-        while (r1 < g.ch && acc + s_rowtot[r1] <= (uint64_t)kStageCap) acc += s_rowtot[r1++];
-      uint32_t st = 0;
-      for (int q = r0; q < r1; ++q) {
-        s_stage[q - r0] = st;
-        st += s_rowtot[q];
+      // longest run of pixels from q0 whose samples fit in LDS
+      int lo = q0 + 1, hi = npix;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] - s_pre[q0] <= (uint32_t)kStageCap) lo = mid; else hi = mid - 1;
       }
-      s_stage[r1 - r0] = st;
-      s_chunk[0] = r1;
-      s_chunk[1] = global_mode;
-      s_chunk[2] = (int)st;
+      s_run[0] = lo;
+      s_run[1] = (s_pre[q0 + 1] - s_pre[q0] > (uint32_t)kStageCap) ? 1 : 0;
     }
     __syncthreads();
-    const int r1 = s_chunk[0];
-    const bool global_mode = s_chunk[1] != 0;
-    const int chunk_total = s_chunk[2];
-    if (chunk_total == 0) {  // nothing to write in these rows
-      r0 = r1;
-      __syncthreads();
-      continue;
-    }
-
-    const double lo_a = im.lo_a;
-    tile_candidates<9>(im, g, r0, r1, L, s_cu, s_cv,
-                       [&](int e, int px, int py, const Coverage& cov) {
-                         const int p = py * tw + px;
-                         const uint32_t slot = atomicAdd(&s_cur[p], 1u);
-                         if (slot >= s_pcnt[p]) {  // count and write passes disagree
-                           atomicOr(im.status, kStatusOverflow);
-                           return;
-                         }
-                         const float d = hit_depth(cov, L.vtx[6][e], L.vtx[7][e], L.vtx[8][e], lo_a);
-                         const int32_t t = L.tri[e];
-                         if (!global_mode) {
-                           s_keys[s_stage[py - r0] + s_rel[p] + slot] = sample_key(d, t);
-                         } else {
-                           const size_t o = (size_t)s_rowbase[py] + s_rel[p] + slot;
-                           im.depth[o] = d;
-                           im.tri[o] = t;
-                         }
-                       });
-    // tile_candidates ends with a barrier
-
-    const int ncol = g.cw;
-    const int nchunkpix = (r1 - r0) * ncol;
-    if (!global_mode) {
-      // per-pixel insertion sort of the staged keys
-      for (int q = threadIdx.x; q < nchunkpix; q += kBlock) {
-        const int py = r0 + q / ncol, px = q % ncol;
-        const int p = py * tw + px;
-        uint64_t* seg = s_keys + s_stage[py - r0] + s_rel[p];
-        const uint32_t n = s_pcnt[p];
-        for (uint32_t x = 1; x < n; ++x) {
-          const uint64_t key = seg[x];
-          uint32_t y = x;
-          while (y > 0 && seg[y - 1] > key) {
-            seg[y] = seg[y - 1];
-            --y;
-          }
-          seg[y] = key;
+    const int q1 = s_run[0];
+    const bool direct = s_run[1] != 0;  // one pixel deeper than the LDS capacity
+    const uint32_t run_base = s_pre[q0];
+    const int run_total = (int)(s_pre[q1] - run_base);
+    if (run_total > 0) {
+      const int r0 = q0 / g.cw, r1 = (q1 - 1) / g.cw + 1;
+      const double lo_a = im.lo_a;
+      const int cw = g.cw;
+      tile_candidates<true>(im, g, r0, r1, L, s_cu, s_cv,
+                            [&](int e, int px, int py, const Edges& ed) {
+                              const int q = py * cw + px;
+                              if (q < q0 || q >= q1) return;
+                              const uint32_t slot = atomicAdd(&s_cur[q], 1u);
+                              if (slot >= s_pre[q + 1] - s_pre[q]) {  // count/write disagree
+                                atomicOr(im.status, kStatusMismatch);
+                                return;
+                              }
+                              const float4 z = L.z[e];
+                              const float d = depth_of(ed, z.x, z.y, z.z, lo_a);
+                              const int32_t t = __float_as_int(z.w);
+                              if (!direct) {
+                                const uint32_t at = s_pre[q] - run_base + slot;
+                                s_keys[at] = sample_key(d, t);
+                                s_pix[at] = (uint16_t)q;
+                              } else {
+                                const size_t o = (size_t)s_off[q] + slot;
+                                im.depth[o] = d;
+                                im.tri[o] = t;
+                              }
+                            });
+      // tile_candidates ends with a barrier
+      if (!direct) {
+        for (int s2 = threadIdx.x; s2 < run_total; s2 += kBlock) {
+          const uint64_t key = s_keys[s2];
+          const int q = s_pix[s2];
+          const uint32_t b = s_pre[q] - run_base;
+          const uint32_t n = s_pre[q + 1] - s_pre[q];
+          uint32_t rank = 0;
+          for (uint32_t k = 0; k < n; ++k) rank += (s_keys[b + k] < key) ? 1u : 0u;
+          const size_t o = (size_t)s_off[q] + rank;
+          const int32_t t = (int32_t)(uint32_t)key;
+          im.depth[o] = key_depth(key);
+          im.tri[o] = t;
+          const float* nrm = im.tnorm + 3 * (int64_t)t;
+          float* dst = im.normal + 3 * o;
+          dst[0] = nrm[0];
+          dst[1] = nrm[1];
+          dst[2] = nrm[2];
         }
-      }
-      __syncthreads();
-      // contiguous stores, row range by row range
-      for (int s = threadIdx.x; s < chunk_total; s += kBlock) {
-        int lo = 0, hi = r1 - r0 - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_stage[mid] <= (uint32_t)s) lo = mid; else hi = mid - 1;
-        }
-        const size_t o = (size_t)s_rowbase[r0 + lo] + (s - s_stage[lo]);
-        const uint64_t key = s_keys[s];
-        const int32_t t = (int32_t)(uint32_t)key;
-        im.depth[o] = key_depth(key);
-        im.tri[o] = t;
-        const float* n = im.tnorm + 3 * (int64_t)t;
-        float* dst = im.normal + 3 * o;
-        dst[0] = n[0];
-        dst[1] = n[1];
-        dst[2] = n[2];
-      }
-    } else {
-      // one oversized row: sort each pixel's range in place in global memory
-      for (int q = threadIdx.x; q < ncol; q += kBlock) {
-        const int p = r0 * tw + q;
-        const size_t o = (size_t)s_rowbase[r0] + s_rel[p];
-        const uint32_t n = s_pcnt[p];
+      } else if (threadIdx.x == 0) {
+        // insertion sort of the one deep pixel in its output range
+        const size_t o = s_off[q0];
+        const uint32_t n = s_pre[q0 + 1] - s_pre[q0];
         for (uint32_t x = 1; x < n; ++x) {
           const float dk = im.depth[o + x];
           const int32_t tk = im.tri[o + x];
@@ -536,20 +603,173 @@ __global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set) {
           im.tri[o + y] = tk;
         }
       }
-      __syncthreads();
-      for (int s = threadIdx.x; s < chunk_total; s += kBlock) {
-        const size_t o = (size_t)s_rowbase[r0] + s;
-        const int32_t t = im.tri[o];
-        const float* n = im.tnorm + 3 * (int64_t)t;
-        float* dst = im.normal + 3 * o;
-        dst[0] = n[0];
-        dst[1] = n[1];
-        dst[2] = n[2];
+      if (direct) {
+        __syncthreads();
+        const size_t o0 = s_off[q0];
+        for (int s2 = threadIdx.x; s2 < run_total; s2 += kBlock) {
+          const int32_t t = im.tri[o0 + s2];
+          const float* nrm = im.tnorm + 3 * (int64_t)t;
+          float* dst = im.normal + 3 * (o0 + s2);
+          dst[0] = nrm[0];
+          dst[1] = nrm[1];
+          dst[2] = nrm[2];
+        }
       }
     }
     __syncthreads();
-    r0 = r1;
+    q0 = q1;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set) {
+  const int k = image_of_block(set, blockIdx.x);
+  write_tile(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// For a sample on triangle (A,B,C) at pixel centre c, with barycentric
+// weights lambda of c in the projected triangle and unit normal n:
+//   depth:  moving vertex X moves the hit along the fixed ray by
+//           lambda_X (n . dX) / n_a, so dL/dX += gd * lambda_X * n / n_a;
+//   normal: n = N/|N|, N = (B-A)x(C-A): dL/dN = (gn - n (n.gn)) / |N| and
+//           dL/dA = (B-C) x dL/dN, dL/dB = (C-A) x dL/dN, dL/dC = (A-B) x dL/dN.
+// n / n_a and the normal Jacobian are constant per triangle, so the
+// sample-parallel kernel only accumulates sum(gd * lambda_X) per (triangle,
+// image) and sum(gn) per triangle; the triangle-parallel kernel applies the
+// per-triangle factors and adds to the three vertices.
+struct BackwardImage {
+  int32_t a, u, v, w;
+  double lo_u, h_u, lo_v, h_v;
+  const uint32_t* offsets;  // [w*w+1]
+  const int32_t* tri;       // [n]
+  const float* gd;          // [n] or null
+  const float* gn;          // [n][3] or null
+  float* acc;               // [T][3] sum of gd * lambda per vertex
+};
+
+struct BackwardSet {
+  BackwardImage img[kMaxImages];
+  int32_t n;
+  uint32_t block_start[kMaxImages + 1];  // pixel blocks per image
+  const float* verts;
+  int64_t n_verts;
+  const int32_t* tris;
+  int64_t n_tris;
+  float* gnsum;                          // [T][3] sum of gn
+};
+
+__global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs) {
+  int k = 0;
+  while (k + 1 < bs.n && blockIdx.x >= bs.block_start[k + 1]) ++k;
+  const BackwardImage& im = bs.img[k];
+  const int64_t p = (int64_t)(blockIdx.x - bs.block_start[k]) * kBlock + threadIdx.x;
+  if (p >= (int64_t)im.w * im.w) return;
+  const uint32_t s0 = im.offsets[p], s1 = im.offsets[p + 1];
+  if (s0 == s1) return;
+  const int i = (int)(p % im.w), j = (int)(p / im.w);
+  const double cu = im.lo_u + ((double)i + 0.5) * im.h_u;
+  const double cv = im.lo_v + ((double)j + 0.5) * im.h_v;
+  for (uint32_t s = s0; s < s1; ++s) {
+    const int32_t t = im.tri[s];
+    if (t < 0 || t >= bs.n_tris) continue;  // not a triangle of this mesh
+    if (im.gd) {
+      const float g = im.gd[s];
+      if (g != 0.0f) {
+        const int32_t* f = bs.tris + 3 * (int64_t)t;
+        double xu[3], xv[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float* P = bs.verts + 3 * (int64_t)min(max(f[q], 0), (int32_t)(bs.n_verts - 1));
+          xu[q] = (double)P[im.u] - cu;
+          xv[q] = (double)P[im.v] - cv;
+        }
+        const double e_bc = xu[1] * xv[2] - xv[1] * xu[2];
+        const double e_ca = xu[2] * xv[0] - xv[2] * xu[0];
+        const double e_ab = xu[0] * xv[1] - xv[0] * xu[1];
+        const double den = e_ab + e_bc + e_ca;
+        if (den != 0.0) {
+          const double gs = (double)g / den;
+          float* acc = im.acc + 3 * (int64_t)t;
+          atomicAdd(acc + 0, (float)(gs * e_bc));
+          atomicAdd(acc + 1, (float)(gs * e_ca));
+          atomicAdd(acc + 2, (float)(gs * e_ab));
+        }
+      }
+    }
+    if (im.gn) {
+      const float* g = im.gn + 3 * (int64_t)s;
+      float* gs = bs.gnsum + 3 * (int64_t)t;
+      const float g0 = g[0], g1 = g[1], g2 = g[2];
+      if (g0 != 0.0f) atomicAdd(gs + 0, g0);
+      if (g1 != 0.0f) atomicAdd(gs + 1, g1);
+      if (g2 != 0.0f) atomicAdd(gs + 2, g2);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) backward_triangles_kernel(BackwardSet bs, int64_t n_tris,
+                                                                    float* grad) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n_tris) return;
+  const int32_t* f = bs.tris + 3 * t;
+  for (int q = 0; q < 3; ++q)
+    if (f[q] < 0 || f[q] >= bs.n_verts) return;  // not a valid triangle
+  double P[3][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P[q][c] = (double)bs.verts[3 * (int64_t)f[q] + c];
+  double e1[3], e2[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    e1[c] = P[1][c] - P[0][c];
+    e2[c] = P[2][c] - P[0][c];
+  }
+  const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+  const double len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+  if (!(len > 0.0)) return;
+  const double n[3] = {N[0] / len, N[1] / len, N[2] / len};
+  double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // per vertex
+  for (int k = 0; k < bs.n; ++k) {
+    const BackwardImage& im = bs.img[k];
+    if (n[im.a] == 0.0) continue;
+    const float* acc = im.acc + 3 * t;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double s = (double)acc[q] / n[im.a];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[q][c] += s * n[c];
+    }
+  }
+  const float* gsum = bs.gnsum + 3 * t;
+  const double G[3] = {gsum[0], gsum[1], gsum[2]};
+  if (G[0] != 0.0 || G[1] != 0.0 || G[2] != 0.0) {
+    const double dot = n[0] * G[0] + n[1] * G[1] + n[2] * G[2];
+    double gN[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gN[c] = (G[c] - n[c] * dot) / len;
+    double ed[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ed[0][c] = P[1][c] - P[2][c];
+      ed[1][c] = P[2][c] - P[0][c];
+      ed[2][c] = P[0][c] - P[1][c];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      g[q][0] += ed[q][1] * gN[2] - ed[q][2] * gN[1];
+      g[q][1] += ed[q][2] * gN[0] - ed[q][0] * gN[2];
+      g[q][2] += ed[q][0] * gN[1] - ed[q][1] * gN[0];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (g[q][c] != 0.0) atomicAdd(grad + 3 * (int64_t)f[q] + c, (float)g[q][c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -644,6 +864,128 @@ __global__ void __launch_bounds__(kBlock) scan_apply_kernel(const uint32_t* in, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// batched sampling
+// ---------------------------------------------------------------------------
+// Index of the segment of a prefix array (n+1 entries) that contains x.
+template <class T>
+__device__ __forceinline__ int segment_of(const T* start, int n, T x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kBlock) batch_setup_kernel(BatchDevice B) {
+  const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
+  const BatchMesh& bm = B.meshes[mi];
+  const int64_t t = (int64_t)(blockIdx.x - B.tri_block_start[mi]) * kBlock + threadIdx.x;
+  setup_triangle(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
+}
+
+template <bool kScatter>
+__global__ void __launch_bounds__(kBlock) batch_bin_kernel(BatchDevice B) {
+  const int k = segment_of(B.bin_block_start, B.n_images, (uint32_t)blockIdx.x);
+  bin_triangles<kScatter>(B.images[k],
+                          (int64_t)(blockIdx.x - B.bin_block_start[k]) * kBlock + threadIdx.x);
+}
+
+// Persistent workgroups take (image, tile) items from a counter until none
+// are left; every workgroup reaches the exit.
+template <bool kWrite>
+__global__ void __launch_bounds__(kBlock) batch_tiles_kernel(BatchDevice B, uint32_t n_items) {
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&B.work[kWrite ? 1 : 0], 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int k = segment_of(B.tile_start, B.n_images, item);
+    const Image& im = B.images[k];
+    const int tile = (int)(item - B.tile_start[k]);
+    if (kWrite) {
+      if (im.depth != nullptr) write_tile(im, tile);
+    } else {
+      count_tile(im, tile);
+    }
+  }
+}
+
+// Start of every segment in the global exclusive prefix: partial sum of the
+// segment's scan tile before its first slot.  One workgroup per segment.
+__global__ void __launch_bounds__(kBlock) segment_base_kernel(const uint32_t* in, const uint64_t* partial,
+                                                              const uint64_t* seg_start, uint64_t* seg_base) {
+  __shared__ uint64_t s_w[kWaves];
+  const uint64_t pos = seg_start[blockIdx.x];
+  const uint64_t b = pos / kScanTile;
+  uint64_t acc = 0;
+  for (uint64_t i = b * kScanTile + threadIdx.x; i < pos; i += kBlock) acc += in[i];
+  uint64_t total;
+  block_exclusive_scan<uint64_t>(acc, s_w, total);
+  if (threadIdx.x == 0) seg_base[blockIdx.x] = partial[b] + total;
+}
+
+__global__ void __launch_bounds__(kBlock) scan_apply_segmented_kernel(
+    const uint32_t* in, int64_t n, const uint64_t* partial, const uint64_t* seg_start,
+    const uint64_t* seg_base, int n_seg, uint32_t* out) {
+  __shared__ uint64_t s_w[kWaves];
+  const int64_t i = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[16];
+  load16(in, n, i, v);
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s += v[k];
+  uint64_t total;
+  uint64_t run = block_exclusive_scan<uint64_t>(s, s_w, total) + partial[blockIdx.x];
+  if (i >= n) return;
+  int seg = segment_of(seg_start, n_seg, (uint64_t)i);
+  for (int k = 0; k < 16 && i + k < n; ++k) {
+    while (seg + 1 < n_seg && seg_start[seg + 1] <= (uint64_t)(i + k)) ++seg;
+    out[i + k] = (uint32_t)(run - seg_base[seg]);
+    run += v[k];
+  }
+}
+
+// One thread per image: sample count, placement in the output arena (or
+// the capacity flag), host summary.
+__global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice B) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k == 0) {
+    B.host_out[0] = *B.status;
+    B.host_out[1] = *B.tile_total;
+  }
+  if (k < B.n_images) {
+    Image& im = B.images[k];
+    const uint64_t n = im.offsets[(size_t)im.w * im.w];
+    const uint64_t base = B.sample_base[k];
+    const bool fits = base + n <= B.sample_cap && (uint64_t)*B.tile_total <= B.list_cap;
+    im.depth = fits ? B.depth + base : nullptr;
+    im.normal = fits ? B.normal + 3 * base : nullptr;
+    im.tri = fits ? B.tri + base : nullptr;
+    uint32_t* h = B.host_out + 4 + 4 * (size_t)k;
+    h[0] = (uint32_t)n;
+    h[1] = (uint32_t)base;
+    h[2] = (uint32_t)(base >> 32);
+    h[3] = *im.max_layers;  // the host compares n and base with the capacities
+  }
+  __threadfence_system();
+}
+
+struct GatherArgs {
+  const uint32_t* src[16];
+  int n;
+};
+
+// Copies a few scattered device words into pinned host memory in one launch.
+__global__ void gather_kernel(GatherArgs g, uint32_t* dst) {
+  const int k = threadIdx.x;
+  if (k < g.n) dst[k] = *g.src[k];
+  __threadfence_system();
+}
+
 inline unsigned grid_for(int64_t n, int per_block) {
   return (unsigned)((n + per_block - 1) / per_block);
 }
@@ -695,9 +1037,110 @@ hipError_t launch_write(const ImageSet& set, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_backward(const BackwardArgs& args, hipStream_t s) {
+  BackwardSet bs{};
+  bs.n = args.n;
+  bs.verts = args.verts;
+  bs.n_verts = args.n_verts;
+  bs.tris = args.tris;
+  bs.n_tris = args.n_tris;
+  bs.gnsum = args.gnsum;
+  bs.block_start[0] = 0;
+  for (int k = 0; k < args.n; ++k) {
+    const BackwardAxis& a = args.axis[k];
+    BackwardImage& im = bs.img[k];
+    im.a = a.a;
+    im.u = (a.a + 1) % 3;
+    im.v = (a.a + 2) % 3;
+    im.w = args.w;
+    im.lo_u = args.bbox[im.u];
+    im.h_u = (args.bbox[3 + im.u] - args.bbox[im.u]) / (double)args.w;
+    im.lo_v = args.bbox[im.v];
+    im.h_v = (args.bbox[3 + im.v] - args.bbox[im.v]) / (double)args.w;
+    im.offsets = a.offsets;
+    im.tri = a.tri;
+    im.gd = a.gd;
+    im.gn = a.gn;
+    im.acc = a.acc;
+    bs.block_start[k + 1] = bs.block_start[k] + grid_for((int64_t)args.w * args.w, kBlock);
+  }
+  if (args.n > 0 && bs.block_start[args.n] > 0)
+    hipLaunchKernelGGL(backward_samples_kernel, dim3(bs.block_start[args.n]), dim3(kBlock), 0, s, bs);
+  if (args.n_tris > 0)
+    hipLaunchKernelGGL(backward_triangles_kernel, dim3(grid_for(args.n_tris, kBlock)), dim3(kBlock), 0, s,
+                       bs, args.n_tris, args.grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, hipStream_t s) {
+  GatherArgs g;
+  g.n = n < 16 ? n : 16;
+  for (int k = 0; k < 16; ++k) g.src[k] = k < g.n ? src[k] : nullptr;
+  hipLaunchKernelGGL(gather_kernel, dim3(1), dim3(64), 0, s, g, host_dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_setup_kernel, dim3(blocks), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (scatter) hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, b);
+  else hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+static unsigned persistent_grid(uint32_t n_items, int per_cu) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const uint32_t g = (uint32_t)(cus * per_cu);
+  return n_items < g ? (n_items > 0 ? n_items : 1) : g;
+}
+
+hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, hipStream_t s) {
+  hipLaunchKernelGGL(batch_tiles_kernel<false>, dim3(persistent_grid(n_items, 8)), dim3(kBlock), 0, s, b,
+                     n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, hipStream_t s) {
+  hipLaunchKernelGGL(batch_tiles_kernel<true>, dim3(persistent_grid(n_items, 2)), dim3(kBlock), 0, s, b,
+                     n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pixel_scan(const BatchDevice& b, const uint32_t* counts, uint32_t* offsets,
+                                   int64_t n_slots, void* scratch, hipStream_t s) {
+  uint64_t* partial = static_cast<uint64_t*>(scratch);
+  const int64_t nb = (n_slots + kScanTile - 1) / kScanTile;
+  if (nb == 0 || b.n_images == 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, counts, n_slots, partial);
+  // the spine writes the grand total one past the end; its overflow check
+  // does not apply to a batch, whose images are checked one by one
+  hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kBlock), 0, s, partial, nb,
+                     reinterpret_cast<uint32_t*>(partial + nb), (int64_t)0, reinterpret_cast<uint32_t*>(partial + nb) + 1);
+  hipLaunchKernelGGL(segment_base_kernel, dim3((unsigned)b.n_images), dim3(kBlock), 0, s, counts, partial,
+                     b.seg_start, b.sample_base);
+  hipLaunchKernelGGL(scan_apply_segmented_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, counts, n_slots,
+                     partial, b.seg_start, b.sample_base, b.n_images, offsets);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finish_counts(const BatchDevice& b, hipStream_t s) {
+  hipLaunchKernelGGL(batch_finish_counts_kernel, dim3(grid_for(b.n_images > 0 ? b.n_images : 1, kBlock)),
+                     dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
 size_t scan_scratch_bytes(int64_t n) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  return (size_t)(nb > 0 ? nb : 1) * sizeof(uint64_t);
+  return (size_t)((nb > 0 ? nb : 1) + 2) * sizeof(uint64_t);
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,

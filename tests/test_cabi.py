@@ -98,3 +98,40 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_batch_create_rejects_bad_descriptors(L):
+    from paper_1009_0794_amd import _lib
+    out = ctypes.c_void_p(7)
+    d = (_lib.MeshDesc * 2)()
+    for k in range(2):
+        d[k] = _lib.MeshDesc(1, 3, 1, 1, (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1), 8, 0, 0)
+    assert L.ldni_batch_create(0, d, 7, None, ctypes.byref(out)) == 1 and out.value is None
+    assert L.ldni_batch_create(2, d, 0, None, ctypes.byref(out)) == 1
+    d[1].w = 0
+    assert L.ldni_batch_create(2, d, 7, None, ctypes.byref(out)) == 1
+    assert b"mesh 1" in L.ldni_last_error()
+    d[1].w = 8
+    d[0].tile_w, d[0].tile_h = 4, 4
+    assert L.ldni_batch_create(2, d, 7, None, ctypes.byref(out)) == 1
+    d[0].tile_w, d[0].tile_h = 0, 0
+    d[0].bbox[3] = -1.0
+    assert L.ldni_batch_create(2, d, 7, None, ctypes.byref(out)) == 1
+    L.ldni_batch_free(None)
+    v = _lib.AxisView()
+    assert L.ldni_batch_axis(None, 0, 0, ctypes.byref(v)) == 1
+
+
+def test_backward_rejects_bad_arguments(L):
+    from paper_1009_0794_amd import _lib
+    bb = (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1)
+    views = (_lib.AxisView * 3)()
+    gd = (ctypes.c_void_p * 3)()
+    gn = (ctypes.c_void_p * 3)()
+    # NULL views, NULL grad_verts, mismatched resolution: rejected on the host
+    assert L.ldni_backward(1, 3, 1, 1, bb, 8, 1, None, gd, gn, 1, None) == 1
+    assert L.ldni_backward(1, 3, 1, 1, bb, 8, 1, views, gd, gn, None, None) == 1
+    views[0].w = 16
+    views[0].offsets = 1
+    assert L.ldni_backward(1, 3, 1, 1, bb, 8, 1, views, gd, gn, 1, None) == 1
+    assert L.ldni_backward(1, 3, 1, 1, bb, 0, 1, views, gd, gn, 1, None) == 1

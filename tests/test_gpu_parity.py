@@ -95,8 +95,8 @@ def _nest(n, level=2):
 
 @pytest.mark.parametrize("tile", [(32, 32), (256, 4), (16, 8)])
 def test_deep_pixels_chunked_and_oversized_rows(tile):
-    """40 layers per ray: 32x32 tiles need several LDS chunks; 256x4 tiles
-    have rows of more than 6144 samples, written and sorted in place."""
+    """40 layers per ray: the samples of a 32x32 or 256x4 tile do not fit in
+    LDS at once, so each tile is written in several runs of pixels."""
     ldni.set_tile_shape(*tile)
     v, f = _nest(20)
     bb = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
@@ -210,3 +210,27 @@ def test_device_detected_errors():
     assert e.value.code == 6
     # the library keeps working after an error
     compare(_run(v, f, BOX8, 8), oracle.sample(v, f, BOX8, 8), BOX8, label="after error")
+
+
+def test_pixel_deeper_than_lds_stage():
+    """A stack of 2,100 thin boxes: the rays through its middle cross 4,200
+    faces, more samples than one workgroup stages in LDS, so those pixels
+    are written to their output ranges and sorted there."""
+    parts = [mg.box_mesh((3.2, 3.2, 0.5 + 0.003 * k), (4.8, 4.8, 0.5 + 0.003 * k + 0.0015))
+             for k in range(2100)]
+    v, f = mg.concat(parts)
+    ref = oracle.sample(v, f, BOX8, 8, axes="z")
+    assert int(np.diff(ref[2].offsets.astype(np.int64)).max()) == 4200
+    compare(_run(v, f, BOX8, 8, "z"), ref, BOX8, label="stack")
+    ldni.set_tile_shape(8, 2)
+    compare(_run(v, f, BOX8, 8, "xyz"), oracle.sample(v, f, BOX8, 8), BOX8, label="stack xyz")
+
+
+def test_tile_list_retry_on_large_triangles():
+    """A dozen triangles spanning thousands of 8x8 tiles overflow the first
+    tile-list estimate; the call is redone with the exact size."""
+    ldni.set_tile_shape(8, 8)
+    v, f = mg.concat([mg.box_mesh((-0.9, -0.95, -0.8), (0.93, 0.9, 0.85))])
+    bb = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
+    for _ in range(2):
+        compare(_run(v, f, bb, 1024), oracle.sample(v, f, bb, 1024), bb, label="big triangles")

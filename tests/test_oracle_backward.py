@@ -90,3 +90,25 @@ def test_normal_gradient_is_tangent():
     gn = np.random.default_rng(1).normal(size=(ref.n, 3)).astype(np.float32)
     g = oracle.backward(v, f, bb, w, 2, ref, None, gn)
     assert abs(float((g * v.astype(np.float64)).sum())) <= 1e-9 * max(1.0, np.abs(g).sum())
+
+
+def test_loss_gradient_harness_on_small_flower():
+    """The finite-difference harness used for the flower workload, checked
+    with the oracle's own analytic gradient on a reduced flower."""
+    from tests import fdcheck
+    rng = np.random.default_rng(0)
+    v, f = mg.concat([mg.uv_flower(24, 48, rng)])
+    base = mg.Mesh(v, f, (-1.4, -1.4, -1.4, 1.4, 1.4, 1.4), 96)
+    tgt_mesh = mg.c5_target(base)
+    w, bb = base.w, base.bbox
+    ref = oracle.sample(v, f, bb, w)
+    tgt = oracle.sample(tgt_mesh.verts, f, bb, w)
+    R = {a: (ref[a].offsets, ref[a].depth, ref[a].normal) for a in range(3)}
+    T = {a: (tgt[a].offsets, tgt[a].depth, tgt[a].normal) for a in range(3)}
+    gd, gn = fdcheck.upstream_grads(R, T)
+    g = sum(oracle.backward(v, f, bb, w, a, ref[a], gd[a], gn[a]) for a in range(3))
+    ids, fd = fdcheck.finite_differences(v, f, bb, w, T, n_vertices=16, seed=4)
+    assert len(ids) == 16
+    got = g[ids]
+    tol = 1e-3 * np.abs(fd) + 1e-4 * np.abs(fd).max()
+    assert (np.abs(got - fd) <= tol).all(), np.max(np.abs(got - fd) / tol)
