@@ -174,8 +174,9 @@ const char *ldni_status_string(ldni_status s);
 const char *ldni_last_error(void);
 
 /* Tile shape of the sampling kernels (pixels per tile along u and v).
- * tw*th <= 1024, 8 <= tw <= 256, 1 <= th <= 64.  Process-wide; default
- * 32 x 32.  Results do not depend on it. */
+ * tw*th <= 1024, 8 <= tw <= 256, 1 <= th <= 64; or 0, 0 (the default): chosen
+ * per call from the triangles per pixel (8x8 from 0.75, 16x16 from 0.02,
+ * else 32x32).  Process-wide.  Results do not depend on it. */
 ldni_status ldni_set_tile_shape(int32_t tw, int32_t th);
 
 /*

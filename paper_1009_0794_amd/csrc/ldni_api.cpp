@@ -22,8 +22,26 @@ using namespace ldni;
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int> g_tile_w{32};
-std::atomic<int> g_tile_h{32};
+// 0 x 0 = choose per call from the triangle density (auto_tile)
+std::atomic<int> g_tile_w{0};
+std::atomic<int> g_tile_h{0};
+
+// Tile shape from triangles per pixel: many small triangles and deep pixels
+// favour small tiles (short serial work per workgroup), few large triangles
+// favour large ones (fewer tile-list entries per triangle).
+void auto_tile(int32_t w, int64_t n_tris, int* tw, int* th) {
+  const double d = (double)n_tris / ((double)w * (double)w);
+  if (d >= 0.75) { *tw = 8; *th = 8; }
+  else if (d >= 0.02) { *tw = 16; *th = 16; }
+  else { *tw = 32; *th = 32; }
+}
+
+void tile_shape(int32_t w, int64_t n_tris, int req_w, int req_h, int* tw, int* th) {
+  if (req_w > 0 && req_h > 0) { *tw = req_w; *th = req_h; return; }
+  const int gw = g_tile_w.load(), gh = g_tile_h.load();
+  if (gw > 0 && gh > 0) { *tw = gw; *th = gh; return; }
+  auto_tile(w, n_tris, tw, th);
+}
 // largest (tile-list entries / triangles) seen, with headroom
 std::atomic<double> g_list_ratio{2.0};
 
@@ -177,8 +195,8 @@ const char* ldni_status_string(ldni_status s) {
 const char* ldni_last_error(void) { return g_last_error.c_str(); }
 
 ldni_status ldni_set_tile_shape(int32_t tw, int32_t th) {
-  if (tw < 8 || tw > 256 || th < 1 || th > 64 || tw * th > 1024)
-    return fail(LDNI_ERR_INVALID_ARG, "tile shape needs 8<=tw<=256, 1<=th<=64, tw*th<=1024");
+  if (!(tw == 0 && th == 0) && (tw < 8 || tw > 256 || th < 1 || th > 64 || tw * th > 1024))
+    return fail(LDNI_ERR_INVALID_ARG, "tile shape needs 8<=tw<=256, 1<=th<=64, tw*th<=1024 (or 0, 0)");
   g_tile_w.store(tw);
   g_tile_h.store(th);
   return LDNI_OK;
@@ -211,7 +229,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   p->mask = axis_mask;
   p->n_tris = n_tris;
 
-  const int tw = g_tile_w.load(), th = g_tile_h.load();
+  int tw = 0, th = 0;
+  tile_shape(w, n_tris, 0, 0, &tw, &th);
   const int ntx = (w + tw - 1) / tw, nty = (w + th - 1) / th;
   const int64_t n_tiles = (int64_t)ntx * nty;
   const int64_t npix = (int64_t)w * w;
@@ -680,11 +699,13 @@ hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   Q(launch_batch_bin(b->dev, false, b->bin_block_start.back(), s));
   Q(launch_scan(b->tile_arena, b->tile_arena, (int64_t)b->total_tiles, b->scan_scratch, b->dev.status, s));
   Q(launch_batch_bin(b->dev, true, b->bin_block_start.back(), s));
-  Q(launch_batch_count(b->dev, (uint32_t)b->total_tiles, s));
+  bool small = true;
+  for (const Image& im : b->images_h) small = small && im.tw * im.th <= 256;
+  Q(launch_batch_count(b->dev, (uint32_t)b->total_tiles, small, s));
   Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
                             b->scan_scratch, s));
   Q(launch_batch_finish_counts(b->dev, s));
-  Q(launch_batch_write(b->dev, (uint32_t)b->total_tiles, s));
+  Q(launch_batch_write(b->dev, (uint32_t)b->total_tiles, small, s));
 #undef Q
   return hipSuccess;
 }
@@ -822,7 +843,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     b->tri_block_start.push_back(b->tri_block_start.back() + tb);
     for (int a = 0; a < 3; ++a) {
       if (!((axis_mask >> a) & 1u)) continue;
-      const int tw = d.tile_w ? d.tile_w : g_tile_w.load(), th = d.tile_h ? d.tile_h : g_tile_h.load();
+      int tw = 0, th = 0;
+      tile_shape(d.w, d.n_tris, d.tile_w, d.tile_h, &tw, &th);
       const uint64_t tiles = (uint64_t)((d.w + tw - 1) / tw) * ((d.w + th - 1) / th);
       b->img_mesh.push_back(m);
       b->img_axis.push_back(a);
@@ -925,8 +947,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.lo_v = (double)d.bbox[im.v];
     im.h_v = ((double)d.bbox[3 + im.v] - (double)d.bbox[im.v]) / (double)d.w;
     im.lo_a = (double)d.bbox[a];
-    im.tw = d.tile_w ? d.tile_w : g_tile_w.load();
-    im.th = d.tile_h ? d.tile_h : g_tile_h.load();
+    tile_shape(d.w, d.n_tris, d.tile_w, d.tile_h, &im.tw, &im.th);
     im.ntx = (d.w + im.tw - 1) / im.tw;
     im.nty = (d.w + im.th - 1) / im.th;
     im.soup = bm.m.soup;

@@ -117,8 +117,9 @@ struct BatchDevice {
 
 hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s);
 hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks, hipStream_t s);
-hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, hipStream_t s);
-hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, hipStream_t s);
+// small: every image's tiles have at most 256 pixels
+hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s);
+hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s);
 // Segmented exclusive scan of the per-image counts (segments of w*w+1 slots,
 // the last slot of each zero) into per-image offsets starting at 0, with the
 // u64 start of every segment in sample_base.

@@ -30,7 +30,11 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxTilePix = 1024;    // tw * th
 constexpr int kMaxTileW = 256;
 constexpr int kMaxTileH = 64;
-constexpr int kStageCap = 4096;      // (depth, tri) keys staged per tile chunk
+// Two builds of the tile kernels: tiles of up to 256 pixels (less LDS, more
+// workgroups per CU) and of up to 1024 pixels; the stage holds the (depth,
+// triangle) keys of one run of pixels.
+constexpr int kSmallTilePix = 256;
+__host__ __device__ constexpr int stage_cap(int tile_pix) { return tile_pix <= 256 ? 2048 : 4096; }
 
 // ---------------------------------------------------------------------------
 // pixel centres and candidate rectangles
@@ -436,8 +440,9 @@ __device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, fl
 // ---------------------------------------------------------------------------
 // count pass
 // ---------------------------------------------------------------------------
+template <int kTilePix>
 __device__ void count_tile(const Image& im, int tile) {
-  __shared__ uint32_t s_cnt[kMaxTilePix];
+  __shared__ uint32_t s_cnt[kTilePix];
   __shared__ float s_cu[kMaxTileW];
   __shared__ float s_cv[kMaxTileH + 1];
   __shared__ ChunkLds<false> L;
@@ -469,9 +474,10 @@ __device__ void count_tile(const Image& im, int tile) {
   if (threadIdx.x == 0 && mx > 0) atomicMax(im.max_layers, mx);
 }
 
+template <int kTilePix>
 __global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
-  count_tile(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
+  count_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
 }
 
 // ---------------------------------------------------------------------------
@@ -484,12 +490,14 @@ __global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
 // position, so sorting and storing are one pass over the staged keys.  Only a
 // single pixel with more samples than the LDS capacity is written directly to
 // its output range and sorted there.
+template <int kTilePix>
 __device__ void write_tile(const Image& im, int tile) {
+  constexpr int kStageCap = stage_cap(kTilePix);
   __shared__ uint64_t s_keys[kStageCap];
   __shared__ uint16_t s_pix[kStageCap];       // tile pixel index of each staged key
-  __shared__ uint32_t s_off[kMaxTilePix];     // output offset of each tile pixel
-  __shared__ uint32_t s_pre[kMaxTilePix + 1]; // prefix of samples over tile pixels
-  __shared__ uint32_t s_cur[kMaxTilePix];     // fill cursor of each tile pixel
+  __shared__ uint32_t s_off[kTilePix];        // output offset of each tile pixel
+  __shared__ uint32_t s_pre[kTilePix + 1];    // prefix of samples over tile pixels
+  __shared__ uint32_t s_cur[kTilePix];        // fill cursor of each tile pixel
   __shared__ float s_cu[kMaxTileW];
   __shared__ float s_cv[kMaxTileH + 1];
   __shared__ ChunkLds<true> L;
@@ -568,22 +576,42 @@ __device__ void write_tile(const Image& im, int tile) {
                             });
       // tile_candidates ends with a barrier
       if (!direct) {
-        for (int s2 = threadIdx.x; s2 < run_total; s2 += kBlock) {
-          const uint64_t key = s_keys[s2];
-          const int q = s_pix[s2];
-          const uint32_t b = s_pre[q] - run_base;
-          const uint32_t n = s_pre[q + 1] - s_pre[q];
-          uint32_t rank = 0;
-          for (uint32_t k = 0; k < n; ++k) rank += (s_keys[b + k] < key) ? 1u : 0u;
-          const size_t o = (size_t)s_off[q] + rank;
-          const int32_t t = (int32_t)(uint32_t)key;
-          im.depth[o] = key_depth(key);
-          im.tri[o] = t;
-          const float* nrm = im.tnorm + 3 * (int64_t)t;
-          float* dst = im.normal + 3 * o;
-          dst[0] = nrm[0];
-          dst[1] = nrm[1];
-          dst[2] = nrm[2];
+        // four staged keys per thread at a time: their normal gathers are in
+        // flight while the ranks are counted
+        constexpr int kU = 4;
+        for (int s0 = threadIdx.x; s0 < run_total; s0 += kBlock * kU) {
+          uint64_t key[kU];
+          int qq[kU];
+          float nx[kU], ny[kU], nz[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int s2 = s0 + u * kBlock;
+            qq[u] = -1;
+            if (s2 < run_total) {
+              key[u] = s_keys[s2];
+              qq[u] = s_pix[s2];
+              const float* nrm = im.tnorm + 3 * (int64_t)(int32_t)(uint32_t)key[u];
+              nx[u] = nrm[0];
+              ny[u] = nrm[1];
+              nz[u] = nrm[2];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            if (qq[u] < 0) continue;
+            const int q = qq[u];
+            const uint32_t b = s_pre[q] - run_base;
+            const uint32_t n = s_pre[q + 1] - s_pre[q];
+            uint32_t rank = 0;
+            for (uint32_t k = 0; k < n; ++k) rank += (s_keys[b + k] < key[u]) ? 1u : 0u;
+            const size_t o = (size_t)s_off[q] + rank;
+            im.depth[o] = key_depth(key[u]);
+            im.tri[o] = (int32_t)(uint32_t)key[u];
+            float* dst = im.normal + 3 * o;
+            dst[0] = nx[u];
+            dst[1] = ny[u];
+            dst[2] = nz[u];
+          }
         }
       } else if (threadIdx.x == 0) {
         // insertion sort of the one deep pixel in its output range
@@ -621,9 +649,10 @@ __device__ void write_tile(const Image& im, int tile) {
   }
 }
 
+template <int kTilePix>
 __global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
-  write_tile(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
+  write_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
 }
 
 // ---------------------------------------------------------------------------
@@ -894,7 +923,7 @@ __global__ void __launch_bounds__(kBlock) batch_bin_kernel(BatchDevice B) {
 
 // Persistent workgroups take (image, tile) items from a counter until none
 // are left; every workgroup reaches the exit.
-template <bool kWrite>
+template <bool kWrite, int kTilePix>
 __global__ void __launch_bounds__(kBlock) batch_tiles_kernel(BatchDevice B, uint32_t n_items) {
   __shared__ uint32_t s_item;
   for (;;) {
@@ -907,9 +936,9 @@ __global__ void __launch_bounds__(kBlock) batch_tiles_kernel(BatchDevice B, uint
     const Image& im = B.images[k];
     const int tile = (int)(item - B.tile_start[k]);
     if (kWrite) {
-      if (im.depth != nullptr) write_tile(im, tile);
+      if (im.depth != nullptr) write_tile<kTilePix>(im, tile);
     } else {
-      count_tile(im, tile);
+      count_tile<kTilePix>(im, tile);
     }
   }
 }
@@ -1023,17 +1052,29 @@ hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s) {
   return hipGetLastError();
 }
 
+static bool small_tiles(const ImageSet& set) {
+  for (int k = 0; k < set.n; ++k)
+    if (set.img[k].tw * set.img[k].th > kSmallTilePix) return false;
+  return true;
+}
+
 hipError_t launch_count(const ImageSet& set, hipStream_t s) {
   const uint32_t blocks = set.tile_start[set.n];
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(count_kernel, dim3(blocks), dim3(kBlock), 0, s, set);
+  if (small_tiles(set))
+    hipLaunchKernelGGL(count_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+  else
+    hipLaunchKernelGGL(count_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
   return hipGetLastError();
 }
 
 hipError_t launch_write(const ImageSet& set, hipStream_t s) {
   const uint32_t blocks = set.tile_start[set.n];
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(write_kernel, dim3(blocks), dim3(kBlock), 0, s, set);
+  if (small_tiles(set))
+    hipLaunchKernelGGL(write_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+  else
+    hipLaunchKernelGGL(write_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
   return hipGetLastError();
 }
 
@@ -1103,15 +1144,23 @@ static unsigned persistent_grid(uint32_t n_items, int per_cu) {
   return n_items < g ? (n_items > 0 ? n_items : 1) : g;
 }
 
-hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, hipStream_t s) {
-  hipLaunchKernelGGL(batch_tiles_kernel<false>, dim3(persistent_grid(n_items, 8)), dim3(kBlock), 0, s, b,
-                     n_items);
+hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s) {
+  if (small)
+    hipLaunchKernelGGL((batch_tiles_kernel<false, kSmallTilePix>), dim3(persistent_grid(n_items, 8)),
+                       dim3(kBlock), 0, s, b, n_items);
+  else
+    hipLaunchKernelGGL((batch_tiles_kernel<false, kMaxTilePix>), dim3(persistent_grid(n_items, 8)),
+                       dim3(kBlock), 0, s, b, n_items);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, hipStream_t s) {
-  hipLaunchKernelGGL(batch_tiles_kernel<true>, dim3(persistent_grid(n_items, 2)), dim3(kBlock), 0, s, b,
-                     n_items);
+hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s) {
+  if (small)
+    hipLaunchKernelGGL((batch_tiles_kernel<true, kSmallTilePix>), dim3(persistent_grid(n_items, 4)),
+                       dim3(kBlock), 0, s, b, n_items);
+  else
+    hipLaunchKernelGGL((batch_tiles_kernel<true, kMaxTilePix>), dim3(persistent_grid(n_items, 2)),
+                       dim3(kBlock), 0, s, b, n_items);
   return hipGetLastError();
 }
 

@@ -65,7 +65,9 @@ def test_tile_shape_validation(L):
     assert L.ldni_set_tile_shape(64, 32) == 1
     assert L.ldni_set_tile_shape(32, 65) == 1
     assert L.ldni_set_tile_shape(64, 16) == 0
+    assert L.ldni_set_tile_shape(0, 4) == 1
     assert L.ldni_set_tile_shape(32, 32) == 0
+    assert L.ldni_set_tile_shape(0, 0) == 0
 
 
 def test_result_axis_rejects_null(L):

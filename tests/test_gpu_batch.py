@@ -45,11 +45,11 @@ def test_batch_equals_single_mesh_calls():
     dev = [(_dev(m.verts, m.tris), m, w, t) for m, w, t in items]
     b = ldni.sample_batch([(v, f, m.bbox, w, t) for (v, f), m, w, t in dev], "xyz")
     for k, ((v, f), m, w, t) in enumerate(dev):
-        ldni.set_tile_shape(*(t or (32, 32)))
+        ldni.set_tile_shape(*(t or (0, 0)))
         single = ldni.sample(v, f, m.bbox, w, "xyz")
         for a in range(3):
             _same(b.to_torch(k, a), single[a], f"mesh {k} axis {a}")
-    ldni.set_tile_shape(32, 32)
+    ldni.set_tile_shape(0, 0)
     # one mesh against the oracle directly
     m, w = items[0][0], items[0][1]
     ref = oracle.sample(m.verts, m.tris, m.bbox, w)
@@ -88,11 +88,11 @@ def test_batch_follows_changed_vertices_and_regrows():
         v.mul_(1.6)  # grows each mesh within its padded box (and beyond it)
     b.run()
     for k, ((v, f), m, w, t) in enumerate(dev):
-        ldni.set_tile_shape(*(t or (32, 32)))
+        ldni.set_tile_shape(*(t or (0, 0)))
         single = ldni.sample(v, f, m.bbox, w, "xyz")
         for a in range(3):
             _same(b.to_torch(k, a), single[a], f"scaled mesh {k} axis {a}")
-    ldni.set_tile_shape(32, 32)
+    ldni.set_tile_shape(0, 0)
     b.free()
 
 

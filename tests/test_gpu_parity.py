@@ -61,7 +61,7 @@ def compare(got, ref, bbox, bitwise=True, label=""):
 def _default_tiles():
     ldni.set_tile_shape(32, 32)
     yield
-    ldni.set_tile_shape(32, 32)
+    ldni.set_tile_shape(0, 0)
 
 
 @pytest.mark.parametrize("name", sorted(FIXTURES))
@@ -77,7 +77,7 @@ def test_icosphere_resolutions(w):
             label=f"c1 w={w}")
 
 
-@pytest.mark.parametrize("tile", [(8, 1), (16, 16), (64, 16), (256, 4), (32, 32), (8, 64)])
+@pytest.mark.parametrize("tile", [(8, 1), (16, 16), (64, 16), (256, 4), (32, 32), (8, 64), (0, 0), (8, 8)])
 def test_tile_shapes(tile):
     ldni.set_tile_shape(*tile)
     rng = np.random.default_rng(1)
@@ -93,7 +93,7 @@ def _nest(n, level=2):
     return mg.concat(parts)
 
 
-@pytest.mark.parametrize("tile", [(32, 32), (256, 4), (16, 8)])
+@pytest.mark.parametrize("tile", [(32, 32), (256, 4), (16, 8), (16, 16), (8, 8)])
 def test_deep_pixels_chunked_and_oversized_rows(tile):
     """40 layers per ray: the samples of a 32x32 or 256x4 tile do not fit in
     LDS at once, so each tile is written in several runs of pixels."""
