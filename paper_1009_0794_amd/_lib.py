@@ -6,7 +6,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libldni.so")
+LIB_PATH = os.environ.get("LDNI_LIBRARY", os.path.join(HERE, "libldni.so"))
 
 c_u32p = ctypes.POINTER(ctypes.c_uint32)
 c_f32p = ctypes.POINTER(ctypes.c_float)

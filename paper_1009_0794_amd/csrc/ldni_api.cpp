@@ -74,7 +74,7 @@ void prepare_pool(int device) {
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
     uint64_t thr = UINT64_MAX;
-    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
   }
   done[device] = true;
 }
@@ -155,6 +155,9 @@ struct ldni_plan {
   int axis_of[kMaxImages] = {0, 0, 0};  // image k samples axis axis_of[k]
   void* ws = nullptr;     // workspace
   void* lists = nullptr;  // tile lists
+  uint32_t* plan_dense = nullptr;   // write work items (prefix over tiles)
+  uint32_t* plan_sparse = nullptr;
+  uint32_t* write_counter = nullptr;
   uint64_t n[3] = {0, 0, 0};
   uint32_t max_layers[3] = {0, 0, 0};
 };
@@ -170,8 +173,8 @@ namespace {
 
 void release_plan(ldni_plan* p) {
   if (!p) return;
-  if (p->lists) hipFreeAsync(p->lists, p->stream);
-  if (p->ws) hipFreeAsync(p->ws, p->stream);
+  if (p->lists) (void)hipFreeAsync(p->lists, p->stream);
+  if (p->ws) (void)hipFreeAsync(p->ws, p->stream);
   delete p;
 }
 
@@ -250,8 +253,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     o_tcur[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
     o_counts[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)npix);
   }
+  const size_t o_plan_d = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles + 1));
+  const size_t o_plan_s = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles + 1));
   const size_t o_scan = off;
-  off = align_up(off + std::max(scan_scratch_bytes(npix), scan_scratch_bytes(n_tiles)));
+  off = align_up(off + std::max(scan_scratch_bytes(npix), scan_scratch_bytes(nimg * n_tiles)));
 
   hipError_t e = pool_alloc(&p->ws, off, stream);
   if (e != hipSuccess) {
@@ -305,6 +310,9 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     set.tile_start[k + 1] = set.tile_start[k] + (uint32_t)n_tiles;
   }
   void* scan_scratch = ws + o_scan;
+  p->plan_dense = reinterpret_cast<uint32_t*>(ws + o_plan_d);
+  p->plan_sparse = reinterpret_cast<uint32_t*>(ws + o_plan_s);
+  p->write_counter = status + 12;
 
   auto bail = [&](ldni_status s) {
     release_plan(p);
@@ -365,6 +373,9 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
       STEP(timed("scan_pixels", stream, [&] {
              return launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream);
            }), "pixel scan");
+    STEP(timed("write_plan", stream, [&] {
+           return launch_write_plan(set, p->plan_dense, p->plan_sparse, scan_scratch, status, stream);
+         }), "write plan");
     // the single readback: status, max layers, sample and entry totals
     STEP(launch_gather(gather_src, n_gather, rb, stream), "readback");
     STEP(hipStreamSynchronize(stream), "synchronise");
@@ -423,7 +434,10 @@ ldni_status ldni_sample_finish(ldni_plan* p, float* const depth[3], float* const
     p->set.img[k].tri = tri[a];
   }
   hipError_t e = hipSuccess;
-  if (p->n_tris > 0) e = timed("write", p->stream, [&] { return launch_write(p->set, p->stream); });
+  if (p->n_tris > 0)
+    e = timed("write", p->stream, [&] {
+      return launch_write(p->set, p->plan_dense, p->plan_sparse, p->write_counter, p->stream);
+    });
   release_plan(p);
   if (e != hipSuccess) return hip_fail(e, "write kernel");
   return LDNI_OK;
@@ -606,8 +620,8 @@ ldni_status ldni_result_axis(const ldni_result* r, int axis, ldni_axis_view* vie
 
 void ldni_free(ldni_result* r) {
   if (!r) return;
-  if (r->samples_buf) hipFreeAsync(r->samples_buf, r->stream);
-  if (r->offsets_buf) hipFreeAsync(r->offsets_buf, r->stream);
+  if (r->samples_buf) (void)hipFreeAsync(r->samples_buf, r->stream);
+  if (r->offsets_buf) (void)hipFreeAsync(r->offsets_buf, r->stream);
   delete r;
 }
 

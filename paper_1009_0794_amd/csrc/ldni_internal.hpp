@@ -84,7 +84,12 @@ hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_count(const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
 hipError_t launch_count(const ImageSet& set, hipStream_t s);
-hipError_t launch_write(const ImageSet& set, hipStream_t s);
+// Work items of the write pass (after the pixel scan): dense/sparse are
+// [n_tiles + 1] u32 arrays receiving exclusive prefixes.
+hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* scratch,
+                             uint32_t* status, hipStream_t s);
+hipError_t launch_write(const ImageSet& set, const uint32_t* dense, const uint32_t* sparse,
+                        uint32_t* counter, hipStream_t s);
 
 // ---- batched sampling: many meshes, each with its own w and tile shape ----
 struct BatchMesh {

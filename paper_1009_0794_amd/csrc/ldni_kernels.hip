@@ -128,6 +128,17 @@ __device__ __forceinline__ uint32_t block_max(uint32_t x, uint32_t* s_wave) {
   return m;
 }
 
+// Index of the segment of a prefix array (n+1 entries) that contains x.
+template <class T>
+__device__ __forceinline__ int segment_of(const T* start, int n, T x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Map a workgroup to (image, tile).
 __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
   int k = 0;
@@ -350,10 +361,12 @@ __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int 
         nc = width * (py1 - py0);
       }
       L.geom[k] = px0 | (max(py0, 0) << 8) | ((width - 1) << 16);
-      const float* s = im.soup + 9 * (int64_t)t;
-      L.ab[k] = make_float4(s[im.u], s[im.v], s[3 + im.u], s[3 + im.v]);
-      L.c[k] = make_float2(s[6 + im.u], s[6 + im.v]);
-      if constexpr (kDepth) L.z[k] = make_float4(s[im.a], s[3 + im.a], s[6 + im.a], __int_as_float(t));
+      if (nc > 0) {  // vertex data only for entries with candidates in these rows
+        const float* s = im.soup + 9 * (int64_t)t;
+        L.ab[k] = make_float4(s[im.u], s[im.v], s[3 + im.u], s[3 + im.v]);
+        L.c[k] = make_float2(s[6 + im.u], s[6 + im.v]);
+        if constexpr (kDepth) L.z[k] = make_float4(s[im.a], s[3 + im.a], s[6 + im.a], __int_as_float(t));
+      }
     }
     int total;
     const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
@@ -483,6 +496,50 @@ __global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
 // ---------------------------------------------------------------------------
 // write pass
 // ---------------------------------------------------------------------------
+// Output of one run of staged keys: each key finds its rank among its
+// pixel's keys and is stored at its sorted position; four keys per thread at
+// a time, their normal gathers in flight while the ranks are counted.
+template <int kTilePix>
+__device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t* s_keys,
+                                                 const uint16_t* s_pix, const uint32_t* s_pre,
+                                                 const uint32_t* s_off, uint32_t run_base, int run_total) {
+  constexpr int kU = 4;
+  for (int s0 = threadIdx.x; s0 < run_total; s0 += kBlock * kU) {
+    uint64_t key[kU];
+    int qq[kU];
+    float nx[kU], ny[kU], nz[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int s2 = s0 + u * kBlock;
+      qq[u] = -1;
+      if (s2 < run_total) {
+        key[u] = s_keys[s2];
+        qq[u] = s_pix[s2];
+        const float* nrm = im.tnorm + 3 * (int64_t)(int32_t)(uint32_t)key[u];
+        nx[u] = nrm[0];
+        ny[u] = nrm[1];
+        nz[u] = nrm[2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (qq[u] < 0) continue;
+      const int q = qq[u];
+      const uint32_t b = s_pre[q] - run_base;
+      const uint32_t n = s_pre[q + 1] - s_pre[q];
+      uint32_t rank = 0;
+      for (uint32_t k = 0; k < n; ++k) rank += (s_keys[b + k] < key[u]) ? 1u : 0u;
+      const size_t o = (size_t)s_off[q] + rank;
+      im.depth[o] = key_depth(key[u]);
+      im.tri[o] = (int32_t)(uint32_t)key[u];
+      float* dst = im.normal + 3 * o;
+      dst[0] = nx[u];
+      dst[1] = ny[u];
+      dst[2] = nz[u];
+    }
+  }
+}
+
 // The tile's pixels are taken in runs (row-major within the tile) whose
 // samples fit in LDS.  Hits of a run are staged at their pixel's slots as
 // (depth, triangle) keys with the pixel alongside; each staged key then finds
@@ -490,8 +547,10 @@ __global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
 // position, so sorting and storing are one pass over the staged keys.  Only a
 // single pixel with more samples than the LDS capacity is written directly to
 // its output range and sorted there.
+// Runs of the tile's greedy split with index = part (mod parts) are written
+// by this call; the split is the same for every part.
 template <int kTilePix>
-__device__ void write_tile(const Image& im, int tile) {
+__device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 1) {
   constexpr int kStageCap = stage_cap(kTilePix);
   __shared__ uint64_t s_keys[kStageCap];
   __shared__ uint16_t s_pix[kStageCap];       // tile pixel index of each staged key
@@ -532,7 +591,7 @@ __device__ void write_tile(const Image& im, int tile) {
   __syncthreads();
 
   int q0 = 0;
-  while (q0 < npix) {
+  for (int run = 0; q0 < npix; ++run) {
     if (threadIdx.x == 0) {
       // longest run of pixels from q0 whose samples fit in LDS
       int lo = q0 + 1, hi = npix;
@@ -548,7 +607,7 @@ __device__ void write_tile(const Image& im, int tile) {
     const bool direct = s_run[1] != 0;  // one pixel deeper than the LDS capacity
     const uint32_t run_base = s_pre[q0];
     const int run_total = (int)(s_pre[q1] - run_base);
-    if (run_total > 0) {
+    if (run_total > 0 && run % parts == part) {
       const int r0 = q0 / g.cw, r1 = (q1 - 1) / g.cw + 1;
       const double lo_a = im.lo_a;
       const int cw = g.cw;
@@ -576,43 +635,7 @@ __device__ void write_tile(const Image& im, int tile) {
                             });
       // tile_candidates ends with a barrier
       if (!direct) {
-        // four staged keys per thread at a time: their normal gathers are in
-        // flight while the ranks are counted
-        constexpr int kU = 4;
-        for (int s0 = threadIdx.x; s0 < run_total; s0 += kBlock * kU) {
-          uint64_t key[kU];
-          int qq[kU];
-          float nx[kU], ny[kU], nz[kU];
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int s2 = s0 + u * kBlock;
-            qq[u] = -1;
-            if (s2 < run_total) {
-              key[u] = s_keys[s2];
-              qq[u] = s_pix[s2];
-              const float* nrm = im.tnorm + 3 * (int64_t)(int32_t)(uint32_t)key[u];
-              nx[u] = nrm[0];
-              ny[u] = nrm[1];
-              nz[u] = nrm[2];
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            if (qq[u] < 0) continue;
-            const int q = qq[u];
-            const uint32_t b = s_pre[q] - run_base;
-            const uint32_t n = s_pre[q + 1] - s_pre[q];
-            uint32_t rank = 0;
-            for (uint32_t k = 0; k < n; ++k) rank += (s_keys[b + k] < key[u]) ? 1u : 0u;
-            const size_t o = (size_t)s_off[q] + rank;
-            im.depth[o] = key_depth(key[u]);
-            im.tri[o] = (int32_t)(uint32_t)key[u];
-            float* dst = im.normal + 3 * o;
-            dst[0] = nx[u];
-            dst[1] = ny[u];
-            dst[2] = nz[u];
-          }
-        }
+        write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, run_base, run_total);
       } else if (threadIdx.x == 0) {
         // insertion sort of the one deep pixel in its output range
         const size_t o = s_off[q0];
@@ -649,10 +672,48 @@ __device__ void write_tile(const Image& im, int tile) {
   }
 }
 
+// Work items of the write pass: a tile with S samples gets
+// K = ceil(S / stage) items (at least one).  Tiles with K >= 2 are counted in
+// `dense`, the others in `sparse`, so the persistent writer can take the
+// long tiles first.
+__global__ void __launch_bounds__(kBlock) write_plan_kernel(ImageSet set, int cap, uint32_t* dense,
+                                                            uint32_t* sparse) {
+  const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
+  if (gt >= set.tile_start[set.n]) return;
+  const int k = image_of_block(set, gt);
+  const Image& im = set.img[k];
+  const TileGeom g = tile_geom(im, (int)(gt - set.tile_start[k]));
+  uint64_t S = 0;
+  for (int r = 0; r < g.ch; ++r) {
+    const size_t row0 = (size_t)(g.y0 + r) * im.w + g.x0;
+    S += im.offsets[row0 + g.cw] - im.offsets[row0];
+  }
+  const uint64_t K = S > (uint64_t)cap ? min((S + cap - 1) / (uint64_t)cap, (uint64_t)65535) : 1;
+  dense[gt] = K >= 2 ? (uint32_t)K : 0u;
+  sparse[gt] = K >= 2 ? 0u : 1u;
+}
+
+// Persistent writer: items of dense tiles first, then one item per other
+// tile; dense/sparse hold the exclusive prefixes of the plan (n_tiles + 1).
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set) {
-  const int k = image_of_block(set, blockIdx.x);
-  write_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
+__global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set, const uint32_t* dense,
+                                                       const uint32_t* sparse, uint32_t* counter) {
+  __shared__ uint32_t s_item;
+  const int n_tiles = (int)set.tile_start[set.n];
+  const uint32_t n_dense = dense[n_tiles], n_sparse = sparse[n_tiles];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= n_dense + n_sparse) break;
+    const uint32_t* pre = item < n_dense ? dense : sparse;
+    const uint32_t x = item < n_dense ? item : item - n_dense;
+    const int gt = segment_of(pre, n_tiles, x);
+    const int k = image_of_block(set, (uint32_t)gt);
+    write_tile<kTilePix>(set.img[k], (int)(gt - set.tile_start[k]), (int)(x - pre[gt]),
+                         (int)(pre[gt + 1] - pre[gt]));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -896,17 +957,6 @@ __global__ void __launch_bounds__(kBlock) scan_apply_kernel(const uint32_t* in, 
 // ---------------------------------------------------------------------------
 // batched sampling
 // ---------------------------------------------------------------------------
-// Index of the segment of a prefix array (n+1 entries) that contains x.
-template <class T>
-__device__ __forceinline__ int segment_of(const T* start, int n, T x) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= x) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __global__ void __launch_bounds__(kBlock) batch_setup_kernel(BatchDevice B) {
   const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
   const BatchMesh& bm = B.meshes[mi];
@@ -1024,6 +1074,16 @@ inline unsigned grid_for(int64_t n, int per_block) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static unsigned persistent_grid(uint32_t n_items, int per_cu) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const uint32_t g = (uint32_t)(cus * per_cu);
+  return n_items < g ? (n_items > 0 ? n_items : 1) : g;
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   unsigned g = grid_for(n, kBlock);
@@ -1068,13 +1128,30 @@ hipError_t launch_count(const ImageSet& set, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_write(const ImageSet& set, hipStream_t s) {
-  const uint32_t blocks = set.tile_start[set.n];
-  if (blocks == 0) return hipSuccess;
-  if (small_tiles(set))
-    hipLaunchKernelGGL(write_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* scratch,
+                             uint32_t* status, hipStream_t s) {
+  const uint32_t n = set.tile_start[set.n];
+  if (n == 0) return hipSuccess;
+  const int cap = small_tiles(set) ? stage_cap(kSmallTilePix) : stage_cap(kMaxTilePix);
+  hipLaunchKernelGGL(write_plan_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set, cap, dense, sparse);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_scan(dense, dense, n, scratch, status, s);
+  if (e == hipSuccess) e = launch_scan(sparse, sparse, n, scratch, status, s);
+  return e;
+}
+
+hipError_t launch_write(const ImageSet& set, const uint32_t* dense, const uint32_t* sparse,
+                        uint32_t* counter, hipStream_t s) {
+  const uint32_t n = set.tile_start[set.n];
+  if (n == 0) return hipSuccess;
+  hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  const bool small = small_tiles(set);
+  const unsigned grid = persistent_grid(2 * n, small ? 4 : 2);
+  if (small)
+    hipLaunchKernelGGL(write_kernel<kSmallTilePix>, dim3(grid), dim3(kBlock), 0, s, set, dense, sparse, counter);
   else
-    hipLaunchKernelGGL(write_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+    hipLaunchKernelGGL(write_kernel<kMaxTilePix>, dim3(grid), dim3(kBlock), 0, s, set, dense, sparse, counter);
   return hipGetLastError();
 }
 
@@ -1132,16 +1209,6 @@ hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks,
   if (scatter) hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, b);
   else hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, b);
   return hipGetLastError();
-}
-
-static unsigned persistent_grid(uint32_t n_items, int per_cu) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-  }
-  const uint32_t g = (uint32_t)(cus * per_cu);
-  return n_items < g ? (n_items > 0 ? n_items : 1) : g;
 }
 
 hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s) {
