@@ -44,6 +44,14 @@ void tile_shape(int32_t w, int64_t n_tris, int req_w, int req_h, int* tw, int* t
 }
 // largest (tile-list entries / triangles) seen, with headroom
 std::atomic<double> g_list_ratio{2.0};
+// largest (staging entries asked for / image pixels) seen, with headroom
+std::atomic<double> g_stage_ratio{8.0};
+
+void raise_ratio(std::atomic<double>& r, double v) {
+  double cur = r.load();
+  while (v > cur && !r.compare_exchange_weak(cur, v)) {
+  }
+}
 
 ldni_status fail(ldni_status s, const std::string& msg) {
   g_last_error = msg;
@@ -158,6 +166,10 @@ struct ldni_plan {
   uint32_t* plan_dense = nullptr;   // write work items (prefix over tiles)
   uint32_t* plan_sparse = nullptr;
   uint32_t* write_counter = nullptr;
+  void* items = nullptr;  // place-pass work items
+  uint32_t n_items = 0;
+  void* stage = nullptr;  // hits staged by the sampling pass
+  uint32_t n_walk = 0;    // tiles the write pass walks again
   uint64_t n[3] = {0, 0, 0};
   uint32_t max_layers[3] = {0, 0, 0};
 };
@@ -174,6 +186,7 @@ namespace {
 void release_plan(ldni_plan* p) {
   if (!p) return;
   if (p->lists) (void)hipFreeAsync(p->lists, p->stream);
+  if (p->stage) (void)hipFreeAsync(p->stage, p->stream);
   if (p->ws) (void)hipFreeAsync(p->ws, p->stream);
   delete p;
 }
@@ -243,7 +256,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   const size_t o_status = off; off += 256;
   const size_t o_soup = off; off = align_up(off + sizeof(float) * 9 * (size_t)n_tris);
   const size_t o_tnorm = off; off = align_up(off + sizeof(float) * 3 * (size_t)n_tris);
-  size_t o_rect[kMaxImages], o_tcnt[kMaxImages], o_tcur[kMaxImages], o_counts[kMaxImages];
+  size_t o_rect[kMaxImages], o_tcnt[kMaxImages], o_tcur[kMaxImages], o_counts[kMaxImages],
+      o_tstage[kMaxImages], o_thits[kMaxImages];
   int nimg = 0;
   for (int a = 0; a < 3; ++a)
     if ((axis_mask >> a) & 1u) p->axis_of[nimg++] = a;
@@ -252,7 +266,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     o_tcnt[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)(n_tiles + 1));
     o_tcur[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
     o_counts[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)npix);
+    o_tstage[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
+    o_thits[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
   }
+  const size_t o_walk = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles));
+  const size_t o_items = off;
+  off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th) * (size_t)(nimg * n_tiles));
   const size_t o_plan_d = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles + 1));
   const size_t o_plan_s = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles + 1));
   const size_t o_scan = off;
@@ -265,7 +284,11 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     return hip_fail(e, "workspace allocation");
   }
   char* ws = static_cast<char*>(p->ws);
-  uint32_t* status = reinterpret_cast<uint32_t*>(ws + o_status);  // [0]=status, [1..3]=max layers
+  // [0] status, [1..3] max layers, [12..13] write-pass work counters,
+  // [16..17] staging cursor (u64), [18] tiles to walk again
+  uint32_t* status = reinterpret_cast<uint32_t*>(ws + o_status);
+  unsigned long long* stage_cursor = reinterpret_cast<unsigned long long*>(status + 16);
+  uint32_t* walk_count = status + 18;
 
   MeshSetup ms{};
   ms.verts = verts;
@@ -307,12 +330,40 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.max_layers = status + 1 + k;
     im.offsets = offsets[a];
     im.status = status;
+    im.stage_cursor = stage_cursor;
+    im.tile_stage = reinterpret_cast<uint32_t*>(ws + o_tstage[k]);
+    im.tile_hits = reinterpret_cast<uint32_t*>(ws + o_thits[k]);
+    im.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
+    im.walk_count = walk_count;
     set.tile_start[k + 1] = set.tile_start[k] + (uint32_t)n_tiles;
+  }
+  // Staging buffer for the hits of the sampling pass, sized from the largest
+  // demand per image pixel seen so far.  A tile that finds no room is walked
+  // again by the write pass, so a short buffer costs time, never results.
+  {
+    const double px = (double)npix * nimg;
+    const double want = std::min(px * std::min(g_stage_ratio.load(), 64.0) + 65536.0,
+                                 std::min(px * 64.0 + 65536.0, (double)0xfffff000u));
+    uint64_t stage_cap = (uint64_t)want;
+    // test hook: a smaller buffer (0: none) forces tiles onto the walk path
+    if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
+      stage_cap = std::min<uint64_t>(stage_cap, std::strtoull(env, nullptr, 10));
+    if (stage_cap == 0 ||
+        pool_alloc(&p->stage, stage_cap * (sizeof(uint64_t) + sizeof(uint32_t)), stream) != hipSuccess)
+      p->stage = nullptr;  // no staging: every tile with hits is walked again
+    for (int k = 0; k < nimg; ++k) {
+      Image& im = set.img[k];
+      im.stage_key = p->stage ? static_cast<uint64_t*>(p->stage) : nullptr;
+      im.stage_qs = p->stage ? reinterpret_cast<uint32_t*>(static_cast<uint64_t*>(p->stage) + stage_cap)
+                             : nullptr;
+      im.stage_cap = p->stage ? stage_cap : 0;
+    }
   }
   void* scan_scratch = ws + o_scan;
   p->plan_dense = reinterpret_cast<uint32_t*>(ws + o_plan_d);
   p->plan_sparse = reinterpret_cast<uint32_t*>(ws + o_plan_s);
   p->write_counter = status + 12;
+  p->items = ws + o_items;
 
   auto bail = [&](ldni_status s) {
     release_plan(p);
@@ -358,7 +409,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     return hipSuccess;
   };
   STEP(alloc_lists(cap), "tile list allocation");
-  const uint32_t* gather_src[16];
+  const uint32_t* gather_src[kMaxGather];
   int n_gather = 0;
   gather_src[n_gather++] = status;      // rb[0]: status, rb[1..3]: max layers
   gather_src[n_gather++] = status + 1;
@@ -366,21 +417,34 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   gather_src[n_gather++] = status + 3;
   for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].offsets + npix;      // rb[4+k]
   for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].tile_cnt + n_tiles; // rb[4+nimg+k]
+  const int rb_stage = n_gather;  // staging demand (u64), tiles to walk again, place items
+  gather_src[n_gather++] = status + 16;
+  gather_src[n_gather++] = status + 17;
+  gather_src[n_gather++] = status + 18;
+  gather_src[n_gather++] = p->plan_dense + (size_t)nimg * n_tiles;
+  gather_src[n_gather++] = p->plan_sparse + (size_t)nimg * n_tiles;
   for (int attempt = 0; attempt < 2; ++attempt) {
     STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
-    STEP(timed("count", stream, [&] { return launch_count(set, stream); }), "count kernel");
+    STEP(launch_fill_u32(status + 16, 0u, 3, stream), "fill");
+    STEP(timed("sample", stream, [&] { return launch_sample(set, stream); }), "sampling kernel");
     for (int k = 0; k < nimg; ++k)
       STEP(timed("scan_pixels", stream, [&] {
              return launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream);
            }), "pixel scan");
     STEP(timed("write_plan", stream, [&] {
-           return launch_write_plan(set, p->plan_dense, p->plan_sparse, scan_scratch, status, stream);
+           return launch_write_plan(set, p->plan_dense, p->plan_sparse, p->items, scan_scratch, status, stream);
          }), "write plan");
     // the single readback: status, max layers, sample and entry totals
     STEP(launch_gather(gather_src, n_gather, rb, stream), "readback");
     STEP(hipStreamSynchronize(stream), "synchronise");
     if (rb[0] & kStatusBadIndex) return bail(fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)"));
     if (rb[0] & kStatusNonFinite) return bail(fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate"));
+    {
+      const uint64_t demand = (uint64_t)rb[rb_stage] | ((uint64_t)rb[rb_stage + 1] << 32);
+      raise_ratio(g_stage_ratio, (double)demand / ((double)npix * nimg) * 1.1);
+      p->n_walk = rb[rb_stage + 2];
+      p->n_items = rb[rb_stage + 3] + rb[rb_stage + 4];
+    }
     uint64_t need = 0;
     for (int k = 0; k < nimg; ++k) need = std::max<uint64_t>(need, rb[4 + nimg + k]);
     if (n_tris > 0) {
@@ -435,8 +499,8 @@ ldni_status ldni_sample_finish(ldni_plan* p, float* const depth[3], float* const
   }
   hipError_t e = hipSuccess;
   if (p->n_tris > 0)
-    e = timed("write", p->stream, [&] {
-      return launch_write(p->set, p->plan_dense, p->plan_sparse, p->write_counter, p->stream);
+    e = timed("place", p->stream, [&] {
+      return launch_place(p->set, p->items, p->n_items, p->write_counter, p->n_walk, p->stream);
     });
   release_plan(p);
   if (e != hipSuccess) return hip_fail(e, "write kernel");

@@ -53,7 +53,21 @@ struct Image {
   float* normal;      // [n][3]
   int32_t* tri;       // [n]
   uint32_t* status;   // shared status word
+  // Hits of the sampling pass, grouped by tile.  With stage_key null the
+  // count pass only counts and the write pass walks every tile again.
+  uint64_t* stage_key;               // (depth key, triangle) of each hit
+  uint32_t* stage_qs;                // tile pixel | (slot within the pixel << 10)
+  unsigned long long* stage_cursor;  // bump allocator over the buffer (shared by the set)
+  uint64_t stage_cap;                // entries in the buffer
+  uint32_t* tile_stage;              // [n_tiles] first entry of the tile's hits (a multiple
+                                     // of 4; regions are whole 4-entry groups), or kNoStage
+  uint32_t* tile_hits;               // [n_tiles] hits of the tile
+  uint32_t* walk_list;               // set-wide tile numbers the write pass walks again
+  uint32_t* walk_count;              // entries of walk_list (shared by the set)
 };
+
+// tile_stage value of a tile whose hits did not fit its staging region
+constexpr uint32_t kNoStage = 0xffffffffu;
 
 constexpr int kMaxImages = 3;
 
@@ -83,13 +97,19 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_count(const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
-hipError_t launch_count(const ImageSet& set, hipStream_t s);
-// Work items of the write pass (after the pixel scan): dense/sparse are
-// [n_tiles + 1] u32 arrays receiving exclusive prefixes.
-hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* scratch,
-                             uint32_t* status, hipStream_t s);
-hipError_t launch_write(const ImageSet& set, const uint32_t* dense, const uint32_t* sparse,
-                        uint32_t* counter, hipStream_t s);
+// Sampling pass: per-pixel counts, and every hit staged by tile (see Image).
+hipError_t launch_sample(const ImageSet& set, hipStream_t s);
+// Work items of the place pass (after the pixel scan and the sampling pass):
+// dense/sparse are [n_tiles + 1] u32 arrays receiving exclusive prefixes of
+// the items per tile, items receives the item records (16 bytes each, at
+// most max_place_items_per_tile(tw * th) per tile).
+int max_place_items_per_tile(int tile_pix);
+hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* items,
+                             void* scratch, uint32_t* status, hipStream_t s);
+// Place pass: n_items workgroups place the staged tiles; the n_walk tiles of
+// walk_list are then walked again (persistent, counter[0]).
+hipError_t launch_place(const ImageSet& set, const void* items, uint32_t n_items, uint32_t* counter,
+                        uint32_t n_walk, hipStream_t s);
 
 // ---- batched sampling: many meshes, each with its own w and tile shape ----
 struct BatchMesh {
@@ -159,6 +179,8 @@ struct BackwardArgs {
 hipError_t launch_backward(const BackwardArgs& args, hipStream_t s);
 
 // Copies n (<= 16) device words into pinned, device-visible host memory.
+// Copies n <= kMaxGather scattered device words to pinned host memory.
+constexpr int kMaxGather = 32;
 hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, hipStream_t s);
 
 // Exclusive scan of n u32 values into out[0..n] (out[n] = total).  Totals of

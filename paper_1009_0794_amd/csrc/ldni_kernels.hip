@@ -336,12 +336,18 @@ __device__ __forceinline__ bool covered(float au, float bu, float cu, float tav,
   return (s0 != 0) & (s0 == s1) & (s1 == s2);
 }
 
+struct NoChunkHook {
+  __device__ void operator()(bool, int) const {}
+};
+
 // Calls on_hit(k, px, py, edges) for every covered candidate of rows
-// [r0, r1) of the tile; k indexes the chunk arrays in L.
-template <bool kDepth, class OnHit>
+// [r0, r1) of the tile; k indexes the chunk arrays in L.  Thread 0 calls
+// on_chunk(first, candidates) once the candidate count of a chunk is known,
+// before the barrier that precedes its walk (first: the tile's first chunk).
+template <bool kDepth, class OnHit, class OnChunk = NoChunkHook>
 __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int r1,
                                 ChunkLds<kDepth>& L, const float* s_cu, const float* s_cv,
-                                OnHit&& on_hit) {
+                                OnHit&& on_hit, OnChunk&& on_chunk = OnChunk()) {
   const uint64_t cap = im.list_cap;
   const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[g.tile], cap);
   const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[g.tile + 1], cap);
@@ -371,7 +377,10 @@ __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int 
     int total;
     const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
     if (k < m) L.start[k] = excl;
-    if (k == 0) L.start[m] = total;
+    if (k == 0) {
+      L.start[m] = total;
+      on_chunk(base == e_begin, total);
+    }
     __syncthreads();
     for (int wb = 0; wb < total; wb += kBlock * kRun) {
       int c = wb + threadIdx.x * kRun;
@@ -487,10 +496,133 @@ __device__ void count_tile(const Image& im, int tile) {
   if (threadIdx.x == 0 && mx > 0) atomicMax(im.max_layers, mx);
 }
 
+
+// ---------------------------------------------------------------------------
+// sampling pass: count and stage every hit
+// ---------------------------------------------------------------------------
+// A tile's staging region holds at most this many hits per tile pixel (and
+// never more than the tile's candidates); a tile with more hits than its
+// region is walked again by the write pass.
+constexpr int kStageLayers = 64;
+
+// One walk of the tile: every hit gets its (depth, triangle) key, its pixel
+// and its arrival slot within the pixel, appended to the tile's region of
+// the staging buffer.  Hits of a wave are appended together (one LDS atomic
+// per wave), so consecutive lanes store to consecutive entries.  The region
+// is reserved up front from the tile's candidate count (pixels of the
+// clipped rectangles), which bounds its hits.
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
+__device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
+  __shared__ uint32_t s_cnt[kTilePix];
+  __shared__ float s_cu[kMaxTileW];
+  __shared__ float s_cv[kMaxTileH + 1];
+  __shared__ ChunkLds<true> L;
+  __shared__ uint32_t s_red[kWaves];
+  __shared__ uint32_t s_region[2];  // first entry, size
+  __shared__ uint32_t s_fill;
+
+  const TileGeom g = tile_geom(im, tile);
+  const int npix = g.cw * g.ch;
+  const int cw = g.cw;
+
+  for (int q = threadIdx.x; q < npix; q += kBlock) s_cnt[q] = 0;
+  for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
+  for (int q = threadIdx.x; q <= g.ch; q += kBlock)
+    s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
+
+  // Reserve the tile's region: its candidate count (rounded up to whole
+  // 4-entry groups so the write pass can read 16-byte vectors), capped at
+  // kStageLayers per pixel.  One chunk of entries: its count comes with the
+  // chunk; more: the entries are counted first.
+  const uint32_t region_max = (uint32_t)(kStageLayers * npix);
+  auto reserve = [&](uint32_t cand) {
+    uint32_t size = min((min(cand, region_max) + 3u) & ~3u, region_max);
+    uint64_t base = 0;
+    if (size > 0 && im.stage_key != nullptr) {
+      base = atomicAdd(im.stage_cursor, (unsigned long long)size);
+      if (base + size > im.stage_cap) size = 0;  // no room left: walked again later
+    } else {
+      size = 0;
+    }
+    s_region[0] = (uint32_t)base;
+    s_region[1] = size;
+  };
+  const uint64_t cap = im.list_cap;
+  const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[tile], cap);
+  const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[tile + 1], cap);
+  const bool one_chunk = e_end - e_begin <= (uint32_t)kBlock;
+  if (threadIdx.x == 0) {
+    s_fill = 0;
+    s_region[0] = 0;
+    s_region[1] = 0;
+  }
+  if (!one_chunk) {
+    // clamped per thread so the sum fits 32 bits
+    uint32_t cand = 0;
+    for (uint32_t e = e_begin + threadIdx.x; e < e_end; e += kBlock) {
+      const Rect r = im.rect[im.tile_list[e]];
+      const int nx = min((int)r.i1, g.x0 + g.cw) - max((int)r.i0, g.x0);
+      const int ny = min((int)r.j1, g.y0 + g.ch) - max((int)r.j0, g.y0);
+      if (nx > 0 && ny > 0) cand = min(cand + (uint32_t)(nx * ny), region_max);
+    }
+    uint32_t total;
+    (void)block_exclusive_scan<uint32_t>(cand, s_red, total);
+    if (threadIdx.x == 0) reserve(total);
+  }
+  __syncthreads();
+  const double lo_a = im.lo_a;
+
+  tile_candidates<true>(im, g, 0, g.ch, L, s_cu, s_cv,
+                        [&](int e, int px, int py, const Edges& ed) {
+                          const int q = py * cw + px;
+                          const uint32_t slot = atomicAdd(&s_cnt[q], 1u);
+                          const float4 z = L.z[e];
+                          const float d = depth_of(ed, z.x, z.y, z.z, lo_a);
+                          const uint64_t key = sample_key(d, __float_as_int(z.w));
+                          // the hitting lanes of the wave take consecutive entries
+                          const uint64_t act = __ballot(1);
+                          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                              (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+                          uint32_t first = 0;
+                          if (rank == 0) first = atomicAdd(&s_fill, (uint32_t)__popcll(act));
+                          const uint32_t pos = __builtin_amdgcn_readfirstlane(first) + rank;
+                          if (pos < s_region[1]) {
+                            const size_t at = (size_t)s_region[0] + pos;
+                            im.stage_key[at] = key;
+                            im.stage_qs[at] = (uint32_t)q | (slot << 10);
+                          }
+                        },
+                        [&](bool first_chunk, int cand) {
+                          if (first_chunk && one_chunk) reserve((uint32_t)cand);
+                        });
+  // tile_candidates ends with a barrier
+  uint32_t mx = 0;
+  for (int q = threadIdx.x; q < npix; q += kBlock) {
+    const int py = q / cw, px = q - py * cw;
+    const uint32_t c = s_cnt[q];
+    mx = max(mx, c);
+    im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = c;
+  }
+  mx = block_max(mx, s_red);
+  if (threadIdx.x == 0) {
+    if (mx > 0) atomicMax(im.max_layers, mx);
+    const uint32_t hits = s_fill;
+    im.tile_hits[tile] = hits;
+    if (hits == 0) {
+      im.tile_stage[tile] = 0;
+    } else if (hits <= s_region[1]) {
+      im.tile_stage[tile] = s_region[0];
+    } else {
+      im.tile_stage[tile] = kNoStage;
+      im.walk_list[atomicAdd(im.walk_count, 1u)] = gtile;
+    }
+  }
+}
+
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) sample_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
-  count_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]));
+  sample_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -540,6 +672,80 @@ __device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t
   }
 }
 
+// Output offsets (s_off) and exclusive prefix of the sample counts (s_pre,
+// npix + 1 entries) of the tile's pixels, q = py * cw + px; s_cur (if given)
+// is cleared.  Ends with a barrier.
+__device__ void tile_prefix(const Image& im, const TileGeom& g, uint32_t* s_off, uint32_t* s_pre,
+                            uint32_t* s_cur, uint32_t* s_wave) {
+  const int npix = g.cw * g.ch;
+  uint32_t carry = 0;
+  for (int base = 0; base < npix; base += kBlock) {
+    const int q = base + threadIdx.x;
+    uint32_t n = 0;
+    if (q < npix) {
+      const int py = q / g.cw, px = q - py * g.cw;
+      const size_t gp = (size_t)(g.y0 + py) * im.w + g.x0 + px;
+      const uint32_t o = im.offsets[gp];
+      n = im.offsets[gp + 1] - o;
+      s_off[q] = o;
+      if (s_cur) s_cur[q] = 0;
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(n, s_wave, total);
+    if (q < npix) s_pre[q] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) s_pre[npix] = carry;
+  __syncthreads();
+}
+
+// The next run of pixels from q0: the longest whose samples fit in cap
+// (at least one pixel).  Returns its end; direct is set when that one pixel
+// alone holds more than cap samples.  Ends with a barrier.
+__device__ int next_run(const uint32_t* s_pre, int q0, int npix, int cap, int* s_run, bool& direct) {
+  if (threadIdx.x == 0) {
+    int lo = q0 + 1, hi = npix;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] - s_pre[q0] <= (uint32_t)cap) lo = mid; else hi = mid - 1;
+    }
+    s_run[0] = lo;
+    s_run[1] = (s_pre[q0 + 1] - s_pre[q0] > (uint32_t)cap) ? 1 : 0;
+  }
+  __syncthreads();
+  direct = s_run[1] != 0;
+  return s_run[0];
+}
+
+// The n samples of one pixel were stored unsorted from output offset o:
+// sort them by key in place (one thread), then fill their normals.
+__device__ void finish_deep_pixel(const Image& im, size_t o, uint32_t n) {
+  if (threadIdx.x == 0) {
+    for (uint32_t x = 1; x < n; ++x) {
+      const float dk = im.depth[o + x];
+      const int32_t tk = im.tri[o + x];
+      const uint64_t key = sample_key(dk, tk);
+      uint32_t y = x;
+      while (y > 0 && sample_key(im.depth[o + y - 1], im.tri[o + y - 1]) > key) {
+        im.depth[o + y] = im.depth[o + y - 1];
+        im.tri[o + y] = im.tri[o + y - 1];
+        --y;
+      }
+      im.depth[o + y] = dk;
+      im.tri[o + y] = tk;
+    }
+  }
+  __syncthreads();
+  for (uint32_t s2 = threadIdx.x; s2 < n; s2 += kBlock) {
+    const int32_t t = im.tri[o + s2];
+    const float* nrm = im.tnorm + 3 * (int64_t)t;
+    float* dst = im.normal + 3 * (o + s2);
+    dst[0] = nrm[0];
+    dst[1] = nrm[1];
+    dst[2] = nrm[2];
+  }
+}
+
 // The tile's pixels are taken in runs (row-major within the tile) whose
 // samples fit in LDS.  Hits of a run are staged at their pixel's slots as
 // (depth, triangle) keys with the pixel alongside; each staged key then finds
@@ -569,42 +775,12 @@ __device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
   for (int q = threadIdx.x; q <= g.ch; q += kBlock)
     s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
-  // offsets and counts of the tile's pixels; s_pre = exclusive prefix
-  uint32_t carry = 0;
-  for (int base = 0; base < npix; base += kBlock) {
-    const int q = base + threadIdx.x;
-    uint32_t n = 0;
-    if (q < npix) {
-      const int py = q / g.cw, px = q - py * g.cw;
-      const size_t gp = (size_t)(g.y0 + py) * im.w + g.x0 + px;
-      const uint32_t o = im.offsets[gp];
-      n = im.offsets[gp + 1] - o;
-      s_off[q] = o;
-      s_cur[q] = 0;
-    }
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(n, s_wave, total);
-    if (q < npix) s_pre[q] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) s_pre[npix] = carry;
-  __syncthreads();
+  tile_prefix(im, g, s_off, s_pre, s_cur, s_wave);
 
   int q0 = 0;
   for (int run = 0; q0 < npix; ++run) {
-    if (threadIdx.x == 0) {
-      // longest run of pixels from q0 whose samples fit in LDS
-      int lo = q0 + 1, hi = npix;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] - s_pre[q0] <= (uint32_t)kStageCap) lo = mid; else hi = mid - 1;
-      }
-      s_run[0] = lo;
-      s_run[1] = (s_pre[q0 + 1] - s_pre[q0] > (uint32_t)kStageCap) ? 1 : 0;
-    }
-    __syncthreads();
-    const int q1 = s_run[0];
-    const bool direct = s_run[1] != 0;  // one pixel deeper than the LDS capacity
+    bool direct;
+    const int q1 = next_run(s_pre, q0, npix, kStageCap, s_run, direct);
     const uint32_t run_base = s_pre[q0];
     const int run_total = (int)(s_pre[q1] - run_base);
     if (run_total > 0 && run % parts == part) {
@@ -636,35 +812,8 @@ __device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 
       // tile_candidates ends with a barrier
       if (!direct) {
         write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, run_base, run_total);
-      } else if (threadIdx.x == 0) {
-        // insertion sort of the one deep pixel in its output range
-        const size_t o = s_off[q0];
-        const uint32_t n = s_pre[q0 + 1] - s_pre[q0];
-        for (uint32_t x = 1; x < n; ++x) {
-          const float dk = im.depth[o + x];
-          const int32_t tk = im.tri[o + x];
-          const uint64_t key = sample_key(dk, tk);
-          uint32_t y = x;
-          while (y > 0 && sample_key(im.depth[o + y - 1], im.tri[o + y - 1]) > key) {
-            im.depth[o + y] = im.depth[o + y - 1];
-            im.tri[o + y] = im.tri[o + y - 1];
-            --y;
-          }
-          im.depth[o + y] = dk;
-          im.tri[o + y] = tk;
-        }
-      }
-      if (direct) {
-        __syncthreads();
-        const size_t o0 = s_off[q0];
-        for (int s2 = threadIdx.x; s2 < run_total; s2 += kBlock) {
-          const int32_t t = im.tri[o0 + s2];
-          const float* nrm = im.tnorm + 3 * (int64_t)t;
-          float* dst = im.normal + 3 * (o0 + s2);
-          dst[0] = nrm[0];
-          dst[1] = nrm[1];
-          dst[2] = nrm[2];
-        }
+      } else {
+        finish_deep_pixel(im, s_off[q0], s_pre[q0 + 1] - s_pre[q0]);
       }
     }
     __syncthreads();
@@ -672,47 +821,188 @@ __device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 
   }
 }
 
-// Work items of the write pass: a tile with S samples gets
-// K = ceil(S / stage) items (at least one).  Tiles with K >= 2 are counted in
-// `dense`, the others in `sparse`, so the persistent writer can take the
-// long tiles first.
+// Work items of the place pass: a staged tile with S hits gets
+// K = ceil(S / stage) items; tiles without hits or walked again get none.
+// Tiles with K >= 2 are counted in `dense`, the others in `sparse`, so the
+// long tiles are launched first.  K <= kStageLayers * tile pixels / stage.
 __global__ void __launch_bounds__(kBlock) write_plan_kernel(ImageSet set, int cap, uint32_t* dense,
                                                             uint32_t* sparse) {
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   if (gt >= set.tile_start[set.n]) return;
   const int k = image_of_block(set, gt);
   const Image& im = set.img[k];
-  const TileGeom g = tile_geom(im, (int)(gt - set.tile_start[k]));
-  uint64_t S = 0;
-  for (int r = 0; r < g.ch; ++r) {
-    const size_t row0 = (size_t)(g.y0 + r) * im.w + g.x0;
-    S += im.offsets[row0 + g.cw] - im.offsets[row0];
-  }
-  const uint64_t K = S > (uint64_t)cap ? min((S + cap - 1) / (uint64_t)cap, (uint64_t)65535) : 1;
-  dense[gt] = K >= 2 ? (uint32_t)K : 0u;
-  sparse[gt] = K >= 2 ? 0u : 1u;
+  const int tile = (int)(gt - set.tile_start[k]);
+  const uint32_t S = im.tile_stage[tile] == kNoStage ? 0u : im.tile_hits[tile];
+  const uint32_t K = S == 0 ? 0u : (S + cap - 1) / (uint32_t)cap;
+  dense[gt] = K >= 2 ? K : 0u;
+  sparse[gt] = K == 1 ? 1u : 0u;
 }
 
-// Persistent writer: items of dense tiles first, then one item per other
-// tile; dense/sparse hold the exclusive prefixes of the plan (n_tiles + 1).
+// One work item of the place pass.
+struct PlaceItem {
+  uint32_t gtile;       // set-wide tile number
+  uint32_t part_parts;  // part | parts << 16
+  uint32_t first;       // first staged entry of the tile
+  uint32_t hits;        // staged entries of the tile
+};
+
+// Items in launch order (dense tiles first), from the scanned plan.
+__global__ void __launch_bounds__(kBlock) plan_items_kernel(ImageSet set, const uint32_t* dense,
+                                                            const uint32_t* sparse, PlaceItem* items) {
+  const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t n_tiles = set.tile_start[set.n];
+  if (gt >= n_tiles) return;
+  const int k = image_of_block(set, gt);
+  const Image& im = set.img[k];
+  const int tile = (int)(gt - set.tile_start[k]);
+  const uint32_t kd = dense[gt + 1] - dense[gt];
+  const uint32_t ks = sparse[gt + 1] - sparse[gt];
+  const uint32_t K = kd + ks;
+  if (K == 0) return;
+  const uint32_t at = kd ? dense[gt] : dense[n_tiles] + sparse[gt];
+  PlaceItem it;
+  it.gtile = gt;
+  it.first = im.tile_stage[tile];
+  it.hits = im.tile_hits[tile];
+  for (uint32_t j = 0; j < K; ++j) {
+    it.part_parts = j | (K << 16);
+    items[at + j] = it;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// place pass: write the hits staged by the sampling pass
+// ---------------------------------------------------------------------------
+// The tile's pixels are split into the same runs as in write_tile.  A run
+// reads the tile's staged entries, keeps those of its pixels and puts each key
+// at its pixel's slot in LDS (the slot came with the hit), then ranks and
+// stores the keys like write_tile.  A single pixel deeper than the stage is
+// stored unsorted straight to its output range and sorted there.
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set, const uint32_t* dense,
-                                                       const uint32_t* sparse, uint32_t* counter) {
+__device__ void place_tile(const Image& im, int tile, uint32_t first, uint32_t hits, int part,
+                           int parts) {
+  constexpr int kStageCap = stage_cap(kTilePix);
+  constexpr int kPer = kStageCap / kBlock;  // staged entries per thread of a one-run tile
+  __shared__ uint64_t s_keys[kStageCap];
+  __shared__ uint16_t s_pix[kStageCap];
+  __shared__ uint32_t s_off[kTilePix];
+  __shared__ uint32_t s_pre[kTilePix + 1];
+  __shared__ uint32_t s_wave[kWaves];
+  __shared__ int s_run[2];
+
+  const TileGeom g = tile_geom(im, tile);
+  const int npix = g.cw * g.ch;
+  const uint64_t* keys = im.stage_key + first;
+  const uint32_t* qs = im.stage_qs + first;
+
+  if (hits <= (uint32_t)kStageCap) {
+    // One run holds the whole tile: the staged entries are loaded before the
+    // pixel offsets are scanned, so the two reads overlap.
+    uint32_t rq[kPer];
+    uint64_t rk[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t i = threadIdx.x + u * kBlock;
+      rq[u] = i < hits ? qs[i] : 0xffffffffu;
+      rk[u] = i < hits ? keys[i] : 0;
+    }
+    tile_prefix(im, g, s_off, s_pre, nullptr, s_wave);
+    if (s_pre[npix] != hits) {  // staging and counts disagree
+      if (threadIdx.x == 0) atomicOr(im.status, kStatusMismatch);
+      return;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (rq[u] == 0xffffffffu) continue;
+      const int q = (int)(rq[u] & 1023u);
+      const uint32_t slot = rq[u] >> 10;
+      if (q >= npix || slot >= s_pre[q + 1] - s_pre[q]) {
+        atomicOr(im.status, kStatusMismatch);
+        continue;
+      }
+      s_keys[s_pre[q] + slot] = rk[u];
+      s_pix[s_pre[q] + slot] = (uint16_t)q;
+    }
+    __syncthreads();
+    write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, 0u, (int)hits);
+    return;
+  }
+
+  tile_prefix(im, g, s_off, s_pre, nullptr, s_wave);
+  if (s_pre[npix] != hits) {
+    if (threadIdx.x == 0) atomicOr(im.status, kStatusMismatch);
+    return;
+  }
+  int q0 = 0;
+  for (int run = 0; q0 < npix; ++run) {
+    bool direct;
+    const int q1 = next_run(s_pre, q0, npix, kStageCap, s_run, direct);
+    const uint32_t run_base = s_pre[q0];
+    const int run_total = (int)(s_pre[q1] - run_base);
+    if (run_total > 0 && run % parts == part) {
+      // four entries per thread per step (one 16-byte load; regions are
+      // whole 4-entry groups), keys read only for the run's pixels
+      for (uint32_t i0 = 4 * threadIdx.x; i0 < hits; i0 += 4 * kBlock) {
+        const uint4 x4 = *reinterpret_cast<const uint4*>(qs + i0);
+        const uint32_t xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (i0 + u >= hits) break;
+          const int q = (int)(xs[u] & 1023u);
+          const uint32_t slot = xs[u] >> 10;
+          if (q < q0 || q >= q1) continue;
+          if (slot >= s_pre[q + 1] - s_pre[q]) {
+            atomicOr(im.status, kStatusMismatch);
+            continue;
+          }
+          const uint64_t key = keys[i0 + u];
+          if (!direct) {
+            const uint32_t at = s_pre[q] - run_base + slot;
+            s_keys[at] = key;
+            s_pix[at] = (uint16_t)q;
+          } else {
+            const size_t o = (size_t)s_off[q] + slot;
+            im.depth[o] = key_depth(key);
+            im.tri[o] = (int32_t)(uint32_t)key;
+          }
+        }
+      }
+      __syncthreads();
+      if (!direct) {
+        write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, run_base, run_total);
+      } else {
+        finish_deep_pixel(im, s_off[q0], s_pre[q0 + 1] - s_pre[q0]);
+      }
+    }
+    __syncthreads();
+    q0 = q1;
+  }
+}
+
+// One workgroup per place item.
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) place_kernel(ImageSet set, const PlaceItem* items) {
+  const PlaceItem it = items[blockIdx.x];
+  const int k = image_of_block(set, it.gtile);
+  place_tile<kTilePix>(set.img[k], (int)(it.gtile - set.tile_start[k]), it.first, it.hits,
+                       (int)(it.part_parts & 0xffffu), (int)(it.part_parts >> 16));
+}
+
+// Tiles whose hits did not fit their staging region: walked and written
+// again, one workgroup per tile.
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) walk_kernel(ImageSet set, const uint32_t* list, uint32_t n,
+                                                      uint32_t* counter) {
   __shared__ uint32_t s_item;
-  const int n_tiles = (int)set.tile_start[set.n];
-  const uint32_t n_dense = dense[n_tiles], n_sparse = sparse[n_tiles];
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
     __syncthreads();
     const uint32_t item = s_item;
     __syncthreads();
-    if (item >= n_dense + n_sparse) break;
-    const uint32_t* pre = item < n_dense ? dense : sparse;
-    const uint32_t x = item < n_dense ? item : item - n_dense;
-    const int gt = segment_of(pre, n_tiles, x);
-    const int k = image_of_block(set, (uint32_t)gt);
-    write_tile<kTilePix>(set.img[k], (int)(gt - set.tile_start[k]), (int)(x - pre[gt]),
-                         (int)(pre[gt + 1] - pre[gt]));
+    if (item >= n) break;
+    const uint32_t gt = list[item];
+    const int k = image_of_block(set, gt);
+    write_tile<kTilePix>(set.img[k], (int)(gt - set.tile_start[k]));
   }
 }
 
@@ -1054,7 +1344,7 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
 }
 
 struct GatherArgs {
-  const uint32_t* src[16];
+  const uint32_t* src[kMaxGather];
   int n;
 };
 
@@ -1118,40 +1408,61 @@ static bool small_tiles(const ImageSet& set) {
   return true;
 }
 
-hipError_t launch_count(const ImageSet& set, hipStream_t s) {
+hipError_t launch_sample(const ImageSet& set, hipStream_t s) {
   const uint32_t blocks = set.tile_start[set.n];
   if (blocks == 0) return hipSuccess;
   if (small_tiles(set))
-    hipLaunchKernelGGL(count_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+    hipLaunchKernelGGL(sample_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
   else
-    hipLaunchKernelGGL(count_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+    hipLaunchKernelGGL(sample_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
   return hipGetLastError();
 }
 
-hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* scratch,
-                             uint32_t* status, hipStream_t s) {
+static int place_cap(const ImageSet& set) {
+  return small_tiles(set) ? stage_cap(kSmallTilePix) : stage_cap(kMaxTilePix);
+}
+
+int max_place_items_per_tile(int tile_pix) {
+  const int pix = tile_pix <= kSmallTilePix ? kSmallTilePix : kMaxTilePix;
+  return (kStageLayers * pix + stage_cap(pix) - 1) / stage_cap(pix);
+}
+
+hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* items,
+                             void* scratch, uint32_t* status, hipStream_t s) {
   const uint32_t n = set.tile_start[set.n];
   if (n == 0) return hipSuccess;
-  const int cap = small_tiles(set) ? stage_cap(kSmallTilePix) : stage_cap(kMaxTilePix);
-  hipLaunchKernelGGL(write_plan_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set, cap, dense, sparse);
+  hipLaunchKernelGGL(write_plan_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set, place_cap(set),
+                     dense, sparse);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = launch_scan(dense, dense, n, scratch, status, s);
   if (e == hipSuccess) e = launch_scan(sparse, sparse, n, scratch, status, s);
-  return e;
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(plan_items_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set, dense, sparse,
+                     static_cast<PlaceItem*>(items));
+  return hipGetLastError();
 }
 
-hipError_t launch_write(const ImageSet& set, const uint32_t* dense, const uint32_t* sparse,
-                        uint32_t* counter, hipStream_t s) {
-  const uint32_t n = set.tile_start[set.n];
-  if (n == 0) return hipSuccess;
+hipError_t launch_place(const ImageSet& set, const void* items, uint32_t n_items, uint32_t* counter,
+                        uint32_t n_walk, hipStream_t s) {
+  const bool small = small_tiles(set);
+  const PlaceItem* it = static_cast<const PlaceItem*>(items);
+  if (n_items > 0) {
+    if (small)
+      hipLaunchKernelGGL(place_kernel<kSmallTilePix>, dim3(n_items), dim3(kBlock), 0, s, set, it);
+    else
+      hipLaunchKernelGGL(place_kernel<kMaxTilePix>, dim3(n_items), dim3(kBlock), 0, s, set, it);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_walk == 0) return hipSuccess;
   hipError_t e = launch_fill_u32(counter, 0u, 1, s);
   if (e != hipSuccess) return e;
-  const bool small = small_tiles(set);
-  const unsigned grid = persistent_grid(2 * n, small ? 4 : 2);
+  const unsigned wgrid = persistent_grid(n_walk, small ? 4 : 2);
+  const uint32_t* list = set.img[0].walk_list;
   if (small)
-    hipLaunchKernelGGL(write_kernel<kSmallTilePix>, dim3(grid), dim3(kBlock), 0, s, set, dense, sparse, counter);
+    hipLaunchKernelGGL(walk_kernel<kSmallTilePix>, dim3(wgrid), dim3(kBlock), 0, s, set, list, n_walk, counter);
   else
-    hipLaunchKernelGGL(write_kernel<kMaxTilePix>, dim3(grid), dim3(kBlock), 0, s, set, dense, sparse, counter);
+    hipLaunchKernelGGL(walk_kernel<kMaxTilePix>, dim3(wgrid), dim3(kBlock), 0, s, set, list, n_walk, counter);
   return hipGetLastError();
 }
 
@@ -1191,9 +1502,10 @@ hipError_t launch_backward(const BackwardArgs& args, hipStream_t s) {
 }
 
 hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, hipStream_t s) {
+  if (n < 0 || n > kMaxGather) return hipErrorInvalidValue;
   GatherArgs g;
-  g.n = n < 16 ? n : 16;
-  for (int k = 0; k < 16; ++k) g.src[k] = k < g.n ? src[k] : nullptr;
+  g.n = n;
+  for (int k = 0; k < kMaxGather; ++k) g.src[k] = k < n ? src[k] : nullptr;
   hipLaunchKernelGGL(gather_kernel, dim3(1), dim3(64), 0, s, g, host_dst);
   return hipGetLastError();
 }

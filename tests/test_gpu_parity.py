@@ -234,3 +234,20 @@ def test_tile_list_retry_on_large_triangles():
     bb = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
     for _ in range(2):
         compare(_run(v, f, bb, 1024), oracle.sample(v, f, bb, 1024), bb, label="big triangles")
+
+
+@pytest.mark.parametrize("tile", [(0, 0), (32, 32)])
+def test_staging_capacity_does_not_change_results(tile, monkeypatch):
+    """The sampling pass stages hits by tile; tiles that find no room are
+    walked again by the write pass.  No staging, a buffer that holds only
+    some tiles, and the default buffer all give the oracle's result."""
+    ldni.set_tile_shape(*tile)
+    m = mg.c2_flower()
+    w = 160
+    ref = oracle.sample(m.verts, m.tris, m.bbox, w)
+    for entries in ("0", "60000", None):
+        if entries is None:
+            monkeypatch.delenv("LDNI_STAGE_ENTRIES", raising=False)
+        else:
+            monkeypatch.setenv("LDNI_STAGE_ENTRIES", entries)
+        compare(_run(m.verts, m.tris, m.bbox, w), ref, m.bbox, label=f"staging {entries} tile {tile}")
