@@ -20,6 +20,8 @@
 // integer/FP64 ALU plus HBM traffic.
 #pragma clang fp contract(off)
 
+#include <type_traits>
+
 #include "ldni_internal.hpp"
 
 namespace ldni {
@@ -505,18 +507,36 @@ __device__ void count_tile(const Image& im, int tile) {
 // region is walked again by the write pass.
 constexpr int kStageLayers = 64;
 
-// One walk of the tile: every hit gets its (depth, triangle) key, its pixel
-// and its arrival slot within the pixel, appended to the tile's region of
-// the staging buffer.  Hits of a wave are appended together (one LDS atomic
-// per wave), so consecutive lanes store to consecutive entries.  The region
-// is reserved up front from the tile's candidate count (pixels of the
-// clipped rectangles), which bounds its hits.
+// Hits found by a wave in one window of its walk, waiting for their depth.
+constexpr int kMaxRun = 16;                 // candidates per thread per window
+constexpr int kWaveHits = 64 * kMaxRun;     // hit descriptors per wave per window
+
+template <int kTilePix>
+struct SampleLds {
+  // descriptor: tile pixel q | chunk entry << kQBits
+  static constexpr int kQBits = kTilePix <= 256 ? 8 : 10;
+  using Desc = typename std::conditional<(kTilePix <= 256), uint16_t, uint32_t>::type;
+  Desc hit[kWaves][kWaveHits];
+};
+
+// One walk of the tile.  Candidates are split into runs of equal length
+// over all threads of the workgroup (one binary search per run, then
+// incremental pixel steps).  A covered candidate only appends its (entry,
+// pixel) descriptor to its wave's list; after each window the wave takes its
+// hits 64 at a time, recomputes their edge functions, and computes depth,
+// key and arrival slot with every lane busy, storing them to consecutive
+// entries of the tile's staging region.  The region is reserved from the
+// tile's candidate count (pixels of the clipped rectangles), which bounds
+// its hits.
 template <int kTilePix>
 __device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
+  using Lds = SampleLds<kTilePix>;
+  constexpr int kQBits = Lds::kQBits;
   __shared__ uint32_t s_cnt[kTilePix];
   __shared__ float s_cu[kMaxTileW];
   __shared__ float s_cv[kMaxTileH + 1];
   __shared__ ChunkLds<true> L;
+  __shared__ Lds H;
   __shared__ uint32_t s_red[kWaves];
   __shared__ uint32_t s_region[2];  // first entry, size
   __shared__ uint32_t s_fill;
@@ -524,6 +544,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
   const TileGeom g = tile_geom(im, tile);
   const int npix = g.cw * g.ch;
   const int cw = g.cw;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   for (int q = threadIdx.x; q < npix; q += kBlock) s_cnt[q] = 0;
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
@@ -571,31 +592,143 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
   }
   __syncthreads();
   const double lo_a = im.lo_a;
+  const float inv_cw = 1.0f / (float)cw;
+  typename Lds::Desc* my_hits = H.hit[wave];
 
-  tile_candidates<true>(im, g, 0, g.ch, L, s_cu, s_cv,
-                        [&](int e, int px, int py, const Edges& ed) {
-                          const int q = py * cw + px;
-                          const uint32_t slot = atomicAdd(&s_cnt[q], 1u);
-                          const float4 z = L.z[e];
-                          const float d = depth_of(ed, z.x, z.y, z.z, lo_a);
-                          const uint64_t key = sample_key(d, __float_as_int(z.w));
-                          // the hitting lanes of the wave take consecutive entries
-                          const uint64_t act = __ballot(1);
-                          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                              (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
-                          uint32_t first = 0;
-                          if (rank == 0) first = atomicAdd(&s_fill, (uint32_t)__popcll(act));
-                          const uint32_t pos = __builtin_amdgcn_readfirstlane(first) + rank;
-                          if (pos < s_region[1]) {
-                            const size_t at = (size_t)s_region[0] + pos;
-                            im.stage_key[at] = key;
-                            im.stage_qs[at] = (uint32_t)q | (slot << 10);
-                          }
-                        },
-                        [&](bool first_chunk, int cand) {
-                          if (first_chunk && one_chunk) reserve((uint32_t)cand);
-                        });
-  // tile_candidates ends with a barrier
+  for (uint32_t cbase = e_begin; cbase < e_end; cbase += kBlock) {
+    // ---- load a chunk of entries with their candidate counts
+    const int m = (int)min((uint32_t)kBlock, e_end - cbase);
+    {
+      const int k = threadIdx.x;
+      int nc = 0;
+      if (k < m) {
+        const int32_t t = im.tile_list[cbase + k];
+        const Rect r = im.rect[t];
+        const int px0 = max((int)r.i0, g.x0) - g.x0, px1 = min((int)r.i1, g.x0 + g.cw) - g.x0;
+        const int py0 = max((int)r.j0, g.y0) - g.y0, py1 = min((int)r.j1, g.y0 + g.ch) - g.y0;
+        int width = 1;
+        if (px1 > px0 && py1 > py0) {
+          width = px1 - px0;
+          nc = width * (py1 - py0);
+        }
+        L.geom[k] = px0 | (max(py0, 0) << 8) | ((width - 1) << 16);
+        if (nc > 0) {
+          const float* sp = im.soup + 9 * (int64_t)t;
+          L.ab[k] = make_float4(sp[im.u], sp[im.v], sp[3 + im.u], sp[3 + im.v]);
+          L.c[k] = make_float2(sp[6 + im.u], sp[6 + im.v]);
+          L.z[k] = make_float4(sp[im.a], sp[3 + im.a], sp[6 + im.a], __int_as_float(t));
+        }
+      }
+      int total;
+      const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
+      if (k < m) L.start[k] = excl;
+      if (k == 0) {
+        L.start[m] = total;
+        if (cbase == e_begin && one_chunk) reserve((uint32_t)total);
+      }
+      __syncthreads();
+    }
+    const int total = L.start[m];
+    const int run = min(max((total + kBlock - 1) / kBlock, 2), kMaxRun);
+    const uint32_t region_first = s_region[0], region_size = s_region[1];
+
+    for (int wb = 0; wb < total; wb += kBlock * run) {
+      // ---- walk: covered candidates append their descriptor
+      uint32_t nh = 0;  // hits of this wave in the window (wave-uniform)
+      int c = wb + threadIdx.x * run;
+      const int cend = min(c + run, total);
+      if (c < cend) {
+        int lo = 0, hi = m - 1;  // owner of c: the last entry whose start is <= c
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.start[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        int e = lo;
+        int gm = L.geom[e];
+        int width = ((gm >> 16) & 255) + 1;
+        int local = c - L.start[e];
+        int row = local / width;
+        int col = local - row * width;
+        int kend = L.start[e + 1];
+        float4 ab = L.ab[e];
+        float2 cc = L.c[e];
+        int px0 = gm & 255, py0 = (gm >> 8) & 255;
+        float rv = s_cv[py0 + row];
+        float tav = ab.y - rv, tbv = ab.w - rv, tcv = cc.y - rv;
+        for (; c < cend; ++c) {
+          if (c == kend) {  // next entry (every entry of a tile list has candidates)
+            ++e;
+            while (L.start[e + 1] <= c) ++e;
+            gm = L.geom[e];
+            width = ((gm >> 16) & 255) + 1;
+            px0 = gm & 255;
+            py0 = (gm >> 8) & 255;
+            row = 0;
+            col = 0;
+            kend = L.start[e + 1];
+            ab = L.ab[e];
+            cc = L.c[e];
+            rv = s_cv[py0];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+          Edges ed;
+          const bool hit = covered(ab.x, ab.z, cc.x, tav, tbv, tcv, s_cu[px0 + col], ed);
+          const uint64_t mask = __ballot(hit);
+          if (hit) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            const uint32_t q = (uint32_t)((py0 + row) * cw + px0 + col);
+            my_hits[nh + rank] = (typename Lds::Desc)(q | ((uint32_t)e << kQBits));
+          }
+          nh += (uint32_t)__popcll(mask);
+          if (++col == width) {
+            col = 0;
+            ++row;
+            rv = s_cv[py0 + row];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+        }
+      }
+      // lanes that left the walk early did not see the later ballots: the
+      // wave's count is the largest
+      for (int d = 32; d >= 1; d >>= 1) nh = max(nh, (uint32_t)__shfl_xor((int)nh, d, 64));
+      nh = __builtin_amdgcn_readfirstlane(nh);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+      // ---- the wave's hits, 64 at a time: depth, key, slot, stage
+      uint32_t first = 0;
+      if (lane == 0 && nh > 0) first = atomicAdd(&s_fill, nh);
+      first = __shfl((int)first, 0, 64);
+      for (uint32_t i = lane; i < nh; i += 64) {
+        const uint32_t d = my_hits[i];
+        const int q = (int)(d & ((1u << kQBits) - 1u));
+        const int e = (int)(d >> kQBits);
+        const int py = (int)(((float)q + 0.5f) * inv_cw);
+        const int px = q - py * cw;
+        const float4 ab = L.ab[e];
+        const float2 cc = L.c[e];
+        const float4 z = L.z[e];
+        const float rv = s_cv[py];
+        Edges ed;
+        (void)covered(ab.x, ab.z, cc.x, ab.y - rv, ab.w - rv, cc.y - rv, s_cu[px], ed);
+        const float dep = depth_of(ed, z.x, z.y, z.z, lo_a);
+        const uint32_t slot = atomicAdd(&s_cnt[q], 1u);
+        const uint32_t pos = first + i;
+        if (pos < region_size) {
+          const size_t at = (size_t)region_first + pos;
+          im.stage_key[at] = sample_key(dep, __float_as_int(z.w));
+          im.stage_qs[at] = (uint32_t)q | (slot << 10);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();  // before the next chunk replaces L
+  }
+
   uint32_t mx = 0;
   for (int q = threadIdx.x; q < npix; q += kBlock) {
     const int py = q / cw, px = q - py * cw;
