@@ -20,6 +20,9 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # no packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # atomics are aggregated by hand (one lane per distinct address); the
+    # compiler's own rewrite would wait for each result inside the loop
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -313,6 +313,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.h_u = ((double)bbox[3 + im.u] - (double)bbox[im.u]) / (double)w;
     im.lo_v = (double)bbox[im.v];
     im.h_v = ((double)bbox[3 + im.v] - (double)bbox[im.v]) / (double)w;
+    im.inv_h_u = 1.0 / im.h_u;
+    im.inv_h_v = 1.0 / im.h_v;
     im.lo_a = (double)bbox[a];
     im.tw = tw;
     im.th = th;
@@ -1024,6 +1026,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.h_u = ((double)d.bbox[3 + im.u] - (double)d.bbox[im.u]) / (double)d.w;
     im.lo_v = (double)d.bbox[im.v];
     im.h_v = ((double)d.bbox[3 + im.v] - (double)d.bbox[im.v]) / (double)d.w;
+    im.inv_h_u = 1.0 / im.h_u;
+    im.inv_h_v = 1.0 / im.h_v;
     im.lo_a = (double)d.bbox[a];
     tile_shape(d.w, d.n_tris, d.tile_w, d.tile_h, &im.tw, &im.th);
     im.ntx = (d.w + im.tw - 1) / im.tw;

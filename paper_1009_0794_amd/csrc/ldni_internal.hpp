@@ -31,6 +31,7 @@ struct Image {
   int32_t w;         // resolution
   double lo_u, h_u;  // pixel centre c_u[i] = f32(lo_u + (i + 0.5) * h_u)
   double lo_v, h_v;
+  double inv_h_u, inv_h_v;  // 1 / h (first estimates of pixel indices only)
   double lo_a;       // depth origin
   // tiling
   int32_t tw, th;    // tile shape in pixels

@@ -47,8 +47,8 @@ __device__ __forceinline__ float pixel_centre(double lo, double h, int i) {
 
 // Smallest i in [0, w] whose centre is >= x (centres are non-decreasing in i).
 // The float64 estimate is corrected against the exact float32 centres.
-__device__ int first_centre_at_or_above(double lo, double h, int w, float x) {
-  double t = ((double)x - lo) / h - 0.5;
+__device__ int first_centre_at_or_above(double lo, double h, double inv_h, int w, float x) {
+  double t = ((double)x - lo) * inv_h - 0.5;
   int i;
   if (!(t > 0.0)) i = 0;
   else if (t >= (double)w) i = w;
@@ -210,10 +210,10 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
     const float vmin = fminf(fminf(P[im.v], P[3 + im.v]), P[6 + im.v]);
     const float vmax = fmaxf(fmaxf(P[im.v], P[3 + im.v]), P[6 + im.v]);
     Rect r;
-    const int i0 = first_centre_at_or_above(im.lo_u, im.h_u, im.w, umin);
-    const int i1 = first_centre_at_or_above(im.lo_u, im.h_u, im.w, umax);
-    const int j0 = first_centre_at_or_above(im.lo_v, im.h_v, im.w, vmin);
-    const int j1 = first_centre_at_or_above(im.lo_v, im.h_v, im.w, vmax);
+    const int i0 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.w, umin);
+    const int i1 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.w, umax);
+    const int j0 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.w, vmin);
+    const int j1 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.w, vmax);
     if (i0 < i1 && j0 < j1) {
       r.i0 = (int16_t)i0; r.i1 = (int16_t)i1; r.j0 = (int16_t)j0; r.j1 = (int16_t)j1;
     } else {
@@ -259,23 +259,35 @@ __device__ void bin_triangles(const Image& im, int64_t t) {
       const int qy = q / nx;
       key = (ty0 + qy) * im.ntx + tx0 + (q - qy * nx);
     }
+    // Peel the wave's distinct tiles; each group's leader issues one atomic.
+    // The scatter's atomics return the group's base: all of them are issued
+    // before any is waited for, and every lane then reads its leader's.
+    const uint32_t list_at = (kScatter && key >= 0) ? im.tile_cnt[key] : 0u;
     uint64_t pending = __ballot(key >= 0);
+    int my_leader = 0;
+    uint32_t my_rank = 0, lead_base = 0;
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int k = __shfl(key, leader, 64);
+      const int k = __builtin_amdgcn_readfirstlane(__shfl(key, leader, 64));
       const uint64_t same = __ballot(key == k);
-      uint32_t base = 0;
-      if (lane == leader)
-        base = atomicAdd(kScatter ? &im.tile_cur[k] : &im.tile_cnt[k], (uint32_t)__popcll(same));
-      base = (uint32_t)__shfl((int)base, leader, 64);
+      if (lane == leader) {
+        if (kScatter)
+          lead_base = atomicAdd(&im.tile_cur[k], (uint32_t)__popcll(same));
+        else
+          atomicAdd(&im.tile_cnt[k], (uint32_t)__popcll(same));
+      }
       if (key == k) {
-        if (kScatter) {
-          const uint64_t pos = (uint64_t)im.tile_cnt[k] + base + (uint32_t)__popcll(same & lower);
-          if (pos < im.list_cap) im.tile_list[pos] = (int32_t)t;
-        }
-        key = -1;
+        my_leader = leader;
+        my_rank = (uint32_t)__popcll(same & lower);
       }
       pending &= ~same;
+    }
+    if (kScatter) {
+      const uint32_t base = (uint32_t)__shfl((int)lead_base, my_leader, 64);
+      if (key >= 0) {
+        const uint64_t pos = (uint64_t)list_at + base + my_rank;
+        if (pos < im.list_cap) im.tile_list[pos] = (int32_t)t;
+      }
     }
   }
 }
