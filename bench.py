@@ -2,7 +2,7 @@
 """Throughput of LDNI sampling on one MI355X.
 
 Headline step: one pass of the sampling path (triangle setup, tile binning,
-count, scan, write + per-pixel sort, all three axes) over the scene64 mesh
+sampling pass, scans, place + per-pixel sort, all three axes) over the scene64 mesh
 (2,152,448 triangles, w=2048) through the C ABI call ``ldni_sample``
 (library-owned outputs from the stream-ordered pool) followed by
 ``ldni_free``.  Inputs are resident in HBM before the timed region starts.
@@ -30,6 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CUs x 2.4 GHz x 64 lanes x 2 flops per FMA)
+# algorithmic arithmetic of the sampling pass: per candidate pixel the exact
+# coverage test (6 translations into the ray frame, 3 edge functions of one
+# product and one fused multiply-add); per hit the barycentric depth
+# (2 adds for the denominator, 5 for the numerator, divide, add, subtract)
+FLOPS_PER_CANDIDATE = 15
+FLOPS_PER_HIT = 10
 METRIC = "LDNI samples written/sec (3 axes) at w=512/2048; batched vs plain; fwd+bwd"
 
 PLAIN = {
@@ -70,6 +77,28 @@ def kernel_alg_bytes(name, mesh, samples):
     return {"setup": 12 * mesh.n_verts + 12 * mesh.n_tris,
             "scan_pixels": 3 * 4 * (mesh.w * mesh.w + 1),
             "place": 16 * samples, "write": 16 * samples}.get(name)
+
+
+def candidate_count(mesh, axes=(0, 1, 2)) -> int:
+    """Candidate pixels of the sampling pass: for every triangle and axis, the
+    pixels of its rectangle (centres c with min <= c < max in both image
+    coordinates, centres rounded to float32 as the sampler does)."""
+    import numpy as np
+    lo = np.asarray(mesh.bbox[:3], np.float64)
+    hi = np.asarray(mesh.bbox[3:], np.float64)
+    P = mesh.verts[mesh.tris]  # (T, 3, 3) float32
+    total = 0
+    for a in axes:
+        ext = []
+        for d in ((a + 1) % 3, (a + 2) % 3):
+            h = (hi[d] - lo[d]) / mesh.w
+            c = (lo[d] + (np.arange(mesh.w, dtype=np.float64) + 0.5) * h).astype(np.float32)
+            mn = P[:, :, d].min(axis=1)
+            mx = P[:, :, d].max(axis=1)
+            ext.append(np.searchsorted(c, mx, "left").astype(np.int64)
+                       - np.searchsorted(c, mn, "left").astype(np.int64))
+        total += int((np.maximum(ext[0], 0) * np.maximum(ext[1], 0)).sum())
+    return total
 
 
 def cpu_baseline(mesh, seconds: float):
@@ -144,9 +173,26 @@ def measure_plain(ldni, torch, mesh, steps, warmup, workload):
     dom_name, (dom_launches, dom_ms) = max(kstats.items(), key=lambda kv: kv[1][1])
     per_step = max(1, dom_launches // steps)
     avg_s = dom_ms / dom_launches / 1e3
-    alg = kernel_alg_bytes(dom_name, mesh, samples)
-    alg_launch = alg / per_step if alg is not None else None
-    achieved = alg_launch / avg_s / 1e9 if alg_launch else 0.0
+    if dom_name == "sample":
+        # arithmetic-bound: algorithmic flops against the vector FP64 peak
+        cand = candidate_count(mesh)
+        flops = (FLOPS_PER_CANDIDATE * cand + FLOPS_PER_HIT * samples) / per_step
+        achieved = flops / avg_s / 1e12
+        roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3),
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                    "traffic": read_traffic(workload, dom_name),
+                    "avg_launch_us": round(avg_s * 1e6, 2),
+                    "algorithmic_flops_per_launch": flops, "candidates_per_step": cand}
+    else:
+        alg = kernel_alg_bytes(dom_name, mesh, samples)
+        alg_launch = alg / per_step if alg is not None else None
+        achieved = alg_launch / avg_s / 1e9 if alg_launch else 0.0
+        roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": read_traffic(workload, dom_name),
+                    "avg_launch_us": round(avg_s * 1e6, 2),
+                    "algorithmic_bytes_per_launch": alg_launch}
     b = fwd_bytes(mesh, samples)
     return {
         "value": samples / (ms_step / 1e3),
@@ -154,11 +200,7 @@ def measure_plain(ldni, torch, mesh, steps, warmup, workload):
         "samples_per_step": samples,
         "samples_per_axis": n_axis,
         "max_layers": max_layers,
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": read_traffic(workload, dom_name),
-                     "avg_launch_us": round(avg_s * 1e6, 2),
-                     "algorithmic_bytes_per_launch": alg_launch},
+        "roofline": roofline,
         "path_roofline": {"algorithmic_bytes_per_step": b,
                           "achieved_GBps": round(b / (ms_step / 1e3) / 1e9, 2),
                           "frac_of_hbm_peak": round(b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
