@@ -44,13 +44,41 @@ void tile_shape(int32_t w, int64_t n_tris, int req_w, int req_h, int* tw, int* t
 }
 // largest (tile-list entries / triangles) seen, with headroom
 std::atomic<double> g_list_ratio{2.0};
-// largest (staging entries asked for / image pixels) seen, with headroom
-std::atomic<double> g_stage_ratio{8.0};
-
-void raise_ratio(std::atomic<double>& r, double v) {
-  double cur = r.load();
-  while (v > cur && !r.compare_exchange_weak(cur, v)) {
+// Staging entries the sampling pass asked for in recent calls, keyed by the
+// call's shape: a repeated call on the same mesh gets what the last one
+// needed (plus headroom for moved vertices).
+struct StageKey {
+  int64_t n_verts, n_tris;
+  int32_t w, tw, th;
+  uint32_t mask;
+  bool operator==(const StageKey& o) const {
+    return n_verts == o.n_verts && n_tris == o.n_tris && w == o.w && tw == o.tw && th == o.th &&
+           mask == o.mask;
   }
+};
+std::mutex g_stage_mu;
+std::vector<std::pair<StageKey, uint64_t>> g_stage_demand;  // most recent last
+constexpr size_t kStageMemory = 64;
+
+bool stage_demand_lookup(const StageKey& k, uint64_t* demand) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  for (auto& e : g_stage_demand)
+    if (e.first == k) {
+      *demand = e.second;
+      return true;
+    }
+  return false;
+}
+
+void stage_demand_record(const StageKey& k, uint64_t demand) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  for (size_t i = 0; i < g_stage_demand.size(); ++i)
+    if (g_stage_demand[i].first == k) {
+      g_stage_demand.erase(g_stage_demand.begin() + i);
+      break;
+    }
+  if (g_stage_demand.size() >= kStageMemory) g_stage_demand.erase(g_stage_demand.begin());
+  g_stage_demand.emplace_back(k, demand);
 }
 
 ldni_status fail(ldni_status s, const std::string& msg) {
@@ -163,8 +191,6 @@ struct ldni_plan {
   int axis_of[kMaxImages] = {0, 0, 0};  // image k samples axis axis_of[k]
   void* ws = nullptr;     // workspace
   void* lists = nullptr;  // tile lists
-  uint32_t* plan_dense = nullptr;   // write work items (prefix over tiles)
-  uint32_t* plan_sparse = nullptr;
   uint32_t* write_counter = nullptr;
   void* items = nullptr;  // place-pass work items
   uint32_t n_items = 0;
@@ -252,30 +278,33 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   const int64_t npix = (int64_t)w * w;
 
   // ---- workspace layout ----
-  size_t off = 0;
-  const size_t o_status = off; off += 256;
-  const size_t o_soup = off; off = align_up(off + sizeof(float) * 9 * (size_t)n_tris);
-  const size_t o_tnorm = off; off = align_up(off + sizeof(float) * 3 * (size_t)n_tris);
-  size_t o_rect[kMaxImages], o_tcnt[kMaxImages], o_tcur[kMaxImages], o_counts[kMaxImages],
-      o_tstage[kMaxImages], o_thits[kMaxImages];
   int nimg = 0;
   for (int a = 0; a < 3; ++a)
     if ((axis_mask >> a) & 1u) p->axis_of[nimg++] = a;
+  const int64_t n_all = nimg * n_tiles;  // tiles of all images, numbered image after image
+  size_t off = 0;
+  // status words, tile entry counts (all images, then their total) and
+  // scatter cursors are adjacent and cleared by one fill
+  const size_t o_status = off; off += 256;
+  const size_t o_tcnt = off; off += sizeof(uint32_t) * (size_t)(n_all + 1);
+  const size_t o_tcur = off; off += sizeof(uint32_t) * (size_t)n_all;
+  const int64_t n_clear = (int64_t)(off / sizeof(uint32_t));
+  off = align_up(off);
+  const size_t o_soup = off; off = align_up(off + sizeof(float) * 9 * (size_t)n_tris);
+  const size_t o_tnorm = off; off = align_up(off + sizeof(float) * 3 * (size_t)n_tris);
+  size_t o_rect[kMaxImages], o_counts[kMaxImages], o_tstage[kMaxImages], o_thits[kMaxImages];
   for (int k = 0; k < nimg; ++k) {
     o_rect[k] = off; off = align_up(off + sizeof(Rect) * (size_t)n_tris);
-    o_tcnt[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)(n_tiles + 1));
-    o_tcur[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
     o_counts[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)npix);
     o_tstage[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
     o_thits[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
   }
-  const size_t o_walk = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles));
+  const size_t o_walk = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_all);
   const size_t o_items = off;
-  off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th) * (size_t)(nimg * n_tiles));
-  const size_t o_plan_d = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles + 1));
-  const size_t o_plan_s = off; off = align_up(off + sizeof(uint32_t) * (size_t)(nimg * n_tiles + 1));
+  off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th) * (size_t)n_all);
+  const size_t o_plan = off; off = align_up(off + sizeof(uint32_t) * (size_t)(2 * n_all + 1));
   const size_t o_scan = off;
-  off = align_up(off + std::max(scan_scratch_bytes(npix), scan_scratch_bytes(nimg * n_tiles)));
+  off = align_up(off + std::max(scan_scratch_bytes(npix, nimg), scan_scratch_bytes(2 * n_all, 1)));
 
   hipError_t e = pool_alloc(&p->ws, off, stream);
   if (e != hipSuccess) {
@@ -325,8 +354,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.rect = reinterpret_cast<const Rect*>(ws + o_rect[k]);
     ms.rect[k] = reinterpret_cast<Rect*>(ws + o_rect[k]);
     im.n_tris = n_tris;
-    im.tile_cnt = reinterpret_cast<uint32_t*>(ws + o_tcnt[k]);
-    im.tile_cur = reinterpret_cast<uint32_t*>(ws + o_tcur[k]);
+    im.tile_cnt = reinterpret_cast<uint32_t*>(ws + o_tcnt) + k * n_tiles;
+    im.tile_cur = reinterpret_cast<uint32_t*>(ws + o_tcur) + k * n_tiles;
     im.tile_list = nullptr;
     im.counts = reinterpret_cast<uint32_t*>(ws + o_counts[k]);
     im.max_layers = status + 1 + k;
@@ -339,14 +368,20 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.walk_count = walk_count;
     set.tile_start[k + 1] = set.tile_start[k] + (uint32_t)n_tiles;
   }
-  // Staging buffer for the hits of the sampling pass, sized from the largest
-  // demand per image pixel seen so far.  A tile that finds no room is walked
-  // again by the write pass, so a short buffer costs time, never results.
+  // Staging buffer for the hits of the sampling pass: what the last call of
+  // the same shape asked for, else a first guess (24 entries per triangle
+  // plus one per pixel).  A tile that finds no room is walked again by the
+  // write pass, so a short buffer costs time, never results.  Never more than
+  // kStageLayers (64) entries per pixel, which is all the tiles can ask for.
+  const StageKey stage_key{n_verts, n_tris, w, tw, th, axis_mask};
   {
     const double px = (double)npix * nimg;
-    const double want = std::min(px * std::min(g_stage_ratio.load(), 64.0) + 65536.0,
-                                 std::min(px * 64.0 + 65536.0, (double)0xfffff000u));
-    uint64_t stage_cap = (uint64_t)want;
+    uint64_t last = 0;
+    const double want = stage_demand_lookup(stage_key, &last)
+                            ? (double)last * 1.1 + 65536.0
+                            : 24.0 * (double)n_tris + px + 65536.0;
+    const double most = std::min(64.0 * px + 65536.0, (double)0xfffff000u);
+    uint64_t stage_cap = (uint64_t)std::min(want, most);
     // test hook: a smaller buffer (0: none) forces tiles onto the walk path
     if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
       stage_cap = std::min<uint64_t>(stage_cap, std::strtoull(env, nullptr, 10));
@@ -362,8 +397,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     }
   }
   void* scan_scratch = ws + o_scan;
-  p->plan_dense = reinterpret_cast<uint32_t*>(ws + o_plan_d);
-  p->plan_sparse = reinterpret_cast<uint32_t*>(ws + o_plan_s);
+  set.plan = reinterpret_cast<uint32_t*>(ws + o_plan);
+  set.place_cap = place_stage_cap(tw * th);
   p->write_counter = status + 12;
   p->items = ws + o_items;
 
@@ -377,35 +412,33 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if (e_ != hipSuccess) return bail(hip_fail(e_, what)); \
   } while (0)
 
-  STEP(launch_fill_u32(status, 0u, 64, stream), "fill");
-  for (int k = 0; k < nimg; ++k) {
-    STEP(launch_fill_u32(set.img[k].tile_cnt, 0u, n_tiles + 1, stream), "fill");
-    STEP(launch_fill_u32(set.img[k].tile_cur, 0u, n_tiles, stream), "fill");
-  }
+  uint32_t* tile_cnt_all = reinterpret_cast<uint32_t*>(ws + o_tcnt);
+  uint32_t* tile_cur_all = reinterpret_cast<uint32_t*>(ws + o_tcur);
+  STEP(launch_fill_u32(status, 0u, n_clear, stream), "fill");
   STEP(timed("setup", stream, [&] { return launch_setup(ms, set, stream); }), "setup kernel");
   STEP(timed("bin_count", stream, [&] { return launch_bin_count(set, stream); }), "bin count kernel");
-  for (int k = 0; k < nimg; ++k)
-    STEP(timed("scan_tiles", stream, [&] {
-           return launch_scan(set.img[k].tile_cnt, set.img[k].tile_cnt, n_tiles, scan_scratch, status, stream);
-         }), "tile scan");
+  // one scan over the tile counts of all images: the images' lists follow
+  // each other in one array
+  STEP(timed("scan_tiles", stream, [&] {
+         return launch_scan(tile_cnt_all, tile_cnt_all, n_all, scan_scratch, status, stream);
+       }), "tile scan");
   // Tile lists are sized from the largest entries-per-triangle ratio seen so
   // far; the scatter drops entries beyond the capacity and the call is redone
-  // with the exact size when that happens (entry totals are read back below).
+  // with the exact size when that happens (the entry total is read back below).
   // (capped per triangle: a mesh of few large triangles is covered by the
   // per-tile term, and anything beyond is caught by the retry)
-  uint64_t cap = (uint64_t)std::ceil((double)n_tris * std::min(g_list_ratio.load(), 8.0)) +
-                 4 * (uint64_t)n_tiles + 1024;
+  uint64_t cap = (uint64_t)std::ceil((double)n_tris * nimg * std::min(g_list_ratio.load(), 8.0)) +
+                 4 * (uint64_t)n_all + 1024;
   auto alloc_lists = [&](uint64_t c) -> hipError_t {
     if (p->lists) (void)hipFreeAsync(p->lists, stream);
     p->lists = nullptr;
-    const size_t per = align_up(sizeof(int32_t) * (size_t)c);
-    hipError_t ea = pool_alloc(&p->lists, per * nimg, stream);
+    hipError_t ea = pool_alloc(&p->lists, sizeof(int32_t) * (size_t)c, stream);
     if (ea != hipSuccess) {
       p->lists = nullptr;
       return ea;
     }
     for (int k = 0; k < nimg; ++k) {
-      set.img[k].tile_list = reinterpret_cast<int32_t*>(static_cast<char*>(p->lists) + k * per);
+      set.img[k].tile_list = static_cast<int32_t*>(p->lists);
       set.img[k].list_cap = c;
     }
     return hipSuccess;
@@ -417,40 +450,42 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   gather_src[n_gather++] = status + 1;
   gather_src[n_gather++] = status + 2;
   gather_src[n_gather++] = status + 3;
-  for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].offsets + npix;      // rb[4+k]
-  for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].tile_cnt + n_tiles; // rb[4+nimg+k]
-  const int rb_stage = n_gather;  // staging demand (u64), tiles to walk again, place items
-  gather_src[n_gather++] = status + 16;
+  for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].offsets + npix;  // rb[4+k]
+  const int rb_more = n_gather;
+  gather_src[n_gather++] = tile_cnt_all + n_all;  // list entries
+  gather_src[n_gather++] = status + 16;           // staging demand (u64)
   gather_src[n_gather++] = status + 17;
-  gather_src[n_gather++] = status + 18;
-  gather_src[n_gather++] = p->plan_dense + (size_t)nimg * n_tiles;
-  gather_src[n_gather++] = p->plan_sparse + (size_t)nimg * n_tiles;
+  gather_src[n_gather++] = status + 18;           // tiles to walk again
+  gather_src[n_gather++] = set.plan + 2 * n_all;  // place items
+  const uint32_t* counts_k[kMaxImages];
+  uint32_t* offsets_k[kMaxImages];
+  for (int k = 0; k < nimg; ++k) {
+    counts_k[k] = set.img[k].counts;
+    offsets_k[k] = set.img[k].offsets;
+  }
   for (int attempt = 0; attempt < 2; ++attempt) {
     STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
-    STEP(launch_fill_u32(status + 16, 0u, 3, stream), "fill");
     STEP(timed("sample", stream, [&] { return launch_sample(set, stream); }), "sampling kernel");
-    for (int k = 0; k < nimg; ++k)
-      STEP(timed("scan_pixels", stream, [&] {
-             return launch_scan(set.img[k].counts, set.img[k].offsets, npix, scan_scratch, status, stream);
-           }), "pixel scan");
-    STEP(timed("write_plan", stream, [&] {
-           return launch_write_plan(set, p->plan_dense, p->plan_sparse, p->items, scan_scratch, status, stream);
-         }), "write plan");
+    STEP(timed("scan_pixels", stream, [&] {
+           return launch_scan_segments(counts_k, offsets_k, nimg, npix, scan_scratch, status, stream);
+         }), "pixel scan");
+    STEP(timed("plan_items", stream, [&] {
+           return launch_plan_items(set, p->items, scan_scratch, status, stream);
+         }), "place plan");
     // the single readback: status, max layers, sample and entry totals
     STEP(launch_gather(gather_src, n_gather, rb, stream), "readback");
     STEP(hipStreamSynchronize(stream), "synchronise");
     if (rb[0] & kStatusBadIndex) return bail(fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)"));
     if (rb[0] & kStatusNonFinite) return bail(fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate"));
+    const uint64_t need = rb[rb_more];
     {
-      const uint64_t demand = (uint64_t)rb[rb_stage] | ((uint64_t)rb[rb_stage + 1] << 32);
-      raise_ratio(g_stage_ratio, (double)demand / ((double)npix * nimg) * 1.1);
-      p->n_walk = rb[rb_stage + 2];
-      p->n_items = rb[rb_stage + 3] + rb[rb_stage + 4];
+      const uint64_t demand = (uint64_t)rb[rb_more + 1] | ((uint64_t)rb[rb_more + 2] << 32);
+      stage_demand_record(stage_key, demand);
+      p->n_walk = rb[rb_more + 3];
+      p->n_items = rb[rb_more + 4];
     }
-    uint64_t need = 0;
-    for (int k = 0; k < nimg; ++k) need = std::max<uint64_t>(need, rb[4 + nimg + k]);
     if (n_tris > 0) {
-      const double ratio = std::min(8.0, (double)need / (double)n_tris * 1.1);
+      const double ratio = std::min(8.0, (double)need / ((double)n_tris * nimg) * 1.1);
       double cur = g_list_ratio.load();
       while (ratio > cur && !g_list_ratio.compare_exchange_weak(cur, ratio)) {
       }
@@ -459,10 +494,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if (attempt == 1) return bail(fail(LDNI_ERR_DEVICE, "tile list sizing failed"));
     cap = need;
     STEP(alloc_lists(cap), "tile list allocation");
-    for (int k = 0; k < nimg; ++k) {
-      STEP(launch_fill_u32(set.img[k].tile_cur, 0u, n_tiles, stream), "fill");
-    }
+    // cursors, max layers, staging cursor and walk count start again
+    STEP(launch_fill_u32(tile_cur_all, 0u, n_all, stream), "fill");
     STEP(launch_fill_u32(status + 1, 0u, 3, stream), "fill");
+    STEP(launch_fill_u32(status + 16, 0u, 3, stream), "fill");
   }
   if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more samples on one axis"));
   for (int k = 0; k < nimg; ++k) {

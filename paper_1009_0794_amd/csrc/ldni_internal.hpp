@@ -78,6 +78,11 @@ struct ImageSet {
   Image img[kMaxImages];
   int32_t n;
   uint32_t tile_start[kMaxImages + 1];  // prefix of tile counts
+  // place-pass plan written by the sampling pass (null: none): items per
+  // tile, [0, n_tiles) for tiles of two or more items, [n_tiles, 2 n_tiles)
+  // for tiles of one, scanned in place into item positions
+  uint32_t* plan;
+  int32_t place_cap;  // stage capacity of the place pass
 };
 
 // Mesh-level setup: per triangle gather, validate, face normal, candidate
@@ -100,13 +105,13 @@ hipError_t launch_bin_count(const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
 // Sampling pass: per-pixel counts, and every hit staged by tile (see Image).
 hipError_t launch_sample(const ImageSet& set, hipStream_t s);
-// Work items of the place pass (after the pixel scan and the sampling pass):
-// dense/sparse are [n_tiles + 1] u32 arrays receiving exclusive prefixes of
-// the items per tile, items receives the item records (16 bytes each, at
-// most max_place_items_per_tile(tw * th) per tile).
+// Work items of the place pass: scans the plan the sampling pass wrote and
+// writes the item records (16 bytes each, at most
+// max_place_items_per_tile(tw * th) per tile) in launch order.
 int max_place_items_per_tile(int tile_pix);
-hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* items,
-                             void* scratch, uint32_t* status, hipStream_t s);
+int place_stage_cap(int tile_pix);
+hipError_t launch_plan_items(const ImageSet& set, void* items, void* scratch, uint32_t* status,
+                             hipStream_t s);
 // Place pass: n_items workgroups place the staged tiles; the n_walk tiles of
 // walk_list are then walked again (persistent, counter[0]).
 hipError_t launch_place(const ImageSet& set, const void* items, uint32_t n_items, uint32_t* counter,
@@ -185,9 +190,13 @@ constexpr int kMaxGather = 32;
 hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, hipStream_t s);
 
 // Exclusive scan of n u32 values into out[0..n] (out[n] = total).  Totals of
-// 2^32 or more raise kStatusOverflow.  scratch: scan_scratch_bytes(n).
-size_t scan_scratch_bytes(int64_t n);
+// 2^32 or more raise kStatusOverflow.  scratch: scan_scratch_bytes(n, 1).
+size_t scan_scratch_bytes(int64_t n, int nseg = 1);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
                        uint32_t* status, hipStream_t s);
+// nseg <= kMaxImages such scans of n values each, in one set of launches
+// (in place allowed); scratch: scan_scratch_bytes(n, nseg).
+hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
+                                void* scratch, uint32_t* status, hipStream_t s);
 
 }  // namespace ldni

@@ -541,7 +541,8 @@ struct SampleLds {
 // tile's candidate count (pixels of the clipped rectangles), which bounds
 // its hits.
 template <int kTilePix>
-__device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
+__device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t* plan, uint32_t n_total,
+                            int place_cap) {
   using Lds = SampleLds<kTilePix>;
   constexpr int kQBits = Lds::kQBits;
   __shared__ uint32_t s_cnt[kTilePix];
@@ -752,14 +753,21 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
   if (threadIdx.x == 0) {
     if (mx > 0) atomicMax(im.max_layers, mx);
     const uint32_t hits = s_fill;
+    const bool staged = hits <= s_region[1];
     im.tile_hits[tile] = hits;
     if (hits == 0) {
       im.tile_stage[tile] = 0;
-    } else if (hits <= s_region[1]) {
+    } else if (staged) {
       im.tile_stage[tile] = s_region[0];
     } else {
       im.tile_stage[tile] = kNoStage;
       im.walk_list[atomicAdd(im.walk_count, 1u)] = gtile;
+    }
+    // place items: ceil(hits / stage) for a staged tile with hits
+    if (plan) {
+      const uint32_t K = (hits == 0 || !staged) ? 0u : (hits + place_cap - 1) / (uint32_t)place_cap;
+      plan[gtile] = K >= 2 ? K : 0u;
+      plan[n_total + gtile] = K == 1 ? 1u : 0u;
     }
   }
 }
@@ -767,7 +775,8 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile) {
 template <int kTilePix>
 __global__ void __launch_bounds__(kBlock) sample_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
-  sample_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x);
+  sample_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x, set.plan,
+                        set.tile_start[set.n], set.place_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -968,21 +977,9 @@ __device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 
 
 // Work items of the place pass: a staged tile with S hits gets
 // K = ceil(S / stage) items; tiles without hits or walked again get none.
-// Tiles with K >= 2 are counted in `dense`, the others in `sparse`, so the
-// long tiles are launched first.  K <= kStageLayers * tile pixels / stage.
-__global__ void __launch_bounds__(kBlock) write_plan_kernel(ImageSet set, int cap, uint32_t* dense,
-                                                            uint32_t* sparse) {
-  const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
-  if (gt >= set.tile_start[set.n]) return;
-  const int k = image_of_block(set, gt);
-  const Image& im = set.img[k];
-  const int tile = (int)(gt - set.tile_start[k]);
-  const uint32_t S = im.tile_stage[tile] == kNoStage ? 0u : im.tile_hits[tile];
-  const uint32_t K = S == 0 ? 0u : (S + cap - 1) / (uint32_t)cap;
-  dense[gt] = K >= 2 ? K : 0u;
-  sparse[gt] = K == 1 ? 1u : 0u;
-}
-
+// The sampling pass writes K to the plan ([0, n) for K >= 2, [n, 2n) for
+// K = 1), so after one scan of the plan the long tiles come first.
+// K <= kStageLayers * tile pixels / stage.
 // One work item of the place pass.
 struct PlaceItem {
   uint32_t gtile;       // set-wide tile number
@@ -992,19 +989,19 @@ struct PlaceItem {
 };
 
 // Items in launch order (dense tiles first), from the scanned plan.
-__global__ void __launch_bounds__(kBlock) plan_items_kernel(ImageSet set, const uint32_t* dense,
-                                                            const uint32_t* sparse, PlaceItem* items) {
+__global__ void __launch_bounds__(kBlock) plan_items_kernel(ImageSet set, PlaceItem* items) {
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t n_tiles = set.tile_start[set.n];
   if (gt >= n_tiles) return;
   const int k = image_of_block(set, gt);
   const Image& im = set.img[k];
   const int tile = (int)(gt - set.tile_start[k]);
-  const uint32_t kd = dense[gt + 1] - dense[gt];
-  const uint32_t ks = sparse[gt + 1] - sparse[gt];
+  const uint32_t* plan = set.plan;
+  const uint32_t kd = plan[gt + 1] - plan[gt];
+  const uint32_t ks = plan[n_tiles + gt + 1] - plan[n_tiles + gt];
   const uint32_t K = kd + ks;
   if (K == 0) return;
-  const uint32_t at = kd ? dense[gt] : dense[n_tiles] + sparse[gt];
+  const uint32_t at = kd ? plan[gt] : plan[n_tiles + gt];
   PlaceItem it;
   it.gtile = gt;
   it.first = im.tile_stage[tile];
@@ -1185,48 +1182,58 @@ struct BackwardSet {
   float* gnsum;                          // [T][3] sum of gn
 };
 
+// One workgroup per run of kBlock consecutive pixels: their samples are
+// contiguous, so threads take samples (not pixels) and find their pixel by a
+// binary search over the run's offsets in LDS.
 __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs) {
+  __shared__ uint32_t s_off[kBlock + 1];
   int k = 0;
   while (k + 1 < bs.n && blockIdx.x >= bs.block_start[k + 1]) ++k;
   const BackwardImage& im = bs.img[k];
-  const int64_t p = (int64_t)(blockIdx.x - bs.block_start[k]) * kBlock + threadIdx.x;
-  if (p >= (int64_t)im.w * im.w) return;
-  const uint32_t s0 = im.offsets[p], s1 = im.offsets[p + 1];
-  if (s0 == s1) return;
-  const int i = (int)(p % im.w), j = (int)(p / im.w);
-  const double cu = im.lo_u + ((double)i + 0.5) * im.h_u;
-  const double cv = im.lo_v + ((double)j + 0.5) * im.h_v;
-  for (uint32_t s = s0; s < s1; ++s) {
+  const int64_t npix = (int64_t)im.w * im.w;
+  const int64_t p0 = (int64_t)(blockIdx.x - bs.block_start[k]) * kBlock;
+  const int n = (int)min((int64_t)kBlock, npix - p0);
+  for (int q = threadIdx.x; q <= n; q += kBlock) s_off[q] = im.offsets[p0 + q];
+  __syncthreads();
+  const uint32_t S0 = s_off[0], S1 = s_off[n];
+  for (uint32_t s = S0 + threadIdx.x; s < S1; s += kBlock) {
     const int32_t t = im.tri[s];
     if (t < 0 || t >= bs.n_tris) continue;  // not a triangle of this mesh
-    if (im.gd) {
-      const float g = im.gd[s];
-      if (g != 0.0f) {
-        const int32_t* f = bs.tris + 3 * (int64_t)t;
-        double xu[3], xv[3];
+    const float g = im.gd ? im.gd[s] : 0.0f;
+    if (g != 0.0f) {
+      int lo = 0, hi = n - 1;  // pixel of s: the last q with s_off[q] <= s
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= s) lo = mid; else hi = mid - 1;
+      }
+      const int64_t p = p0 + lo;
+      const int i = (int)(p % im.w), j = (int)(p / im.w);
+      const double cu = im.lo_u + ((double)i + 0.5) * im.h_u;
+      const double cv = im.lo_v + ((double)j + 0.5) * im.h_v;
+      const int32_t* f = bs.tris + 3 * (int64_t)t;
+      double xu[3], xv[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const float* P = bs.verts + 3 * (int64_t)min(max(f[q], 0), (int32_t)(bs.n_verts - 1));
-          xu[q] = (double)P[im.u] - cu;
-          xv[q] = (double)P[im.v] - cv;
-        }
-        const double e_bc = xu[1] * xv[2] - xv[1] * xu[2];
-        const double e_ca = xu[2] * xv[0] - xv[2] * xu[0];
-        const double e_ab = xu[0] * xv[1] - xv[0] * xu[1];
-        const double den = e_ab + e_bc + e_ca;
-        if (den != 0.0) {
-          const double gs = (double)g / den;
-          float* acc = im.acc + 3 * (int64_t)t;
-          atomicAdd(acc + 0, (float)(gs * e_bc));
-          atomicAdd(acc + 1, (float)(gs * e_ca));
-          atomicAdd(acc + 2, (float)(gs * e_ab));
-        }
+      for (int q = 0; q < 3; ++q) {
+        const float* P = bs.verts + 3 * (int64_t)min(max(f[q], 0), (int32_t)(bs.n_verts - 1));
+        xu[q] = (double)P[im.u] - cu;
+        xv[q] = (double)P[im.v] - cv;
+      }
+      const double e_bc = xu[1] * xv[2] - xv[1] * xu[2];
+      const double e_ca = xu[2] * xv[0] - xv[2] * xu[0];
+      const double e_ab = xu[0] * xv[1] - xv[0] * xu[1];
+      const double den = e_ab + e_bc + e_ca;
+      if (den != 0.0) {
+        const double gs = (double)g / den;
+        float* acc = im.acc + 3 * (int64_t)t;
+        atomicAdd(acc + 0, (float)(gs * e_bc));
+        atomicAdd(acc + 1, (float)(gs * e_ca));
+        atomicAdd(acc + 2, (float)(gs * e_ab));
       }
     }
     if (im.gn) {
-      const float* g = im.gn + 3 * (int64_t)s;
+      const float* gv = im.gn + 3 * (int64_t)s;
       float* gs = bs.gnsum + 3 * (int64_t)t;
-      const float g0 = g[0], g1 = g[1], g2 = g[2];
+      const float g0 = gv[0], g1 = gv[1], g2 = gv[2];
       if (g0 != 0.0f) atomicAdd(gs + 0, g0);
       if (g1 != 0.0f) atomicAdd(gs + 1, g1);
       if (g2 != 0.0f) atomicAdd(gs + 2, g2);
@@ -1326,12 +1333,24 @@ __device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) scan_reduce_kernel(const uint32_t* in, int64_t n,
-                                                              uint64_t* partial) {
+// Up to kMaxImages scans of n values each (input, output and where the
+// total goes per segment), nb workgroups per segment.
+struct ScanSegs {
+  const uint32_t* in[kMaxImages];
+  uint32_t* out[kMaxImages];
+  uint32_t* total[kMaxImages];
+  int64_t n;
+  int64_t nb;
+  int32_t nseg;
+};
+
+__global__ void __launch_bounds__(kBlock) scan_reduce_kernel(ScanSegs sg, uint64_t* partial) {
   __shared__ uint64_t s_w[kWaves];
-  const int64_t i = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int seg = (int)(blockIdx.x / sg.nb);
+  const int64_t b = (int64_t)blockIdx.x - (int64_t)seg * sg.nb;
+  const int64_t i = b * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[16];
-  load16(in, n, i, v);
+  load16(sg.in[seg], sg.n, i, v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
@@ -1340,33 +1359,36 @@ __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(const uint32_t* in,
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// One workgroup: exclusive scan of the per-tile partial sums, total to out[n].
-__global__ void __launch_bounds__(kBlock) scan_spine_kernel(uint64_t* partial, int64_t nb,
-                                                             uint32_t* out, int64_t n,
+// One workgroup per segment: exclusive scan of its per-tile partial sums,
+// and the segment total (2^32 or more raises the overflow bit).
+__global__ void __launch_bounds__(kBlock) scan_spine_kernel(ScanSegs sg, uint64_t* partial,
                                                              uint32_t* status) {
   __shared__ uint64_t s_w[kWaves];
+  uint64_t* part = partial + (int64_t)blockIdx.x * sg.nb;
   uint64_t carry = 0;
-  for (int64_t base = 0; base < nb; base += kBlock) {
+  for (int64_t base = 0; base < sg.nb; base += kBlock) {
     const int64_t q = base + threadIdx.x;
-    const uint64_t x = q < nb ? partial[q] : 0;
+    const uint64_t x = q < sg.nb ? part[q] : 0;
     uint64_t total;
     const uint64_t e = block_exclusive_scan<uint64_t>(x, s_w, total);
-    if (q < nb) partial[q] = carry + e;
+    if (q < sg.nb) part[q] = carry + e;
     carry += total;
   }
   if (threadIdx.x == 0) {
-    out[n] = (uint32_t)carry;
-    if (carry > 0xffffffffull) atomicOr(status, kStatusOverflow);
+    *sg.total[blockIdx.x] = (uint32_t)carry;
+    if (carry > 0xffffffffull && status) atomicOr(status, kStatusOverflow);
   }
 }
 
-__global__ void __launch_bounds__(kBlock) scan_apply_kernel(const uint32_t* in, int64_t n,
-                                                            const uint64_t* partial,
-                                                            uint32_t* out) {
+__global__ void __launch_bounds__(kBlock) scan_apply_kernel(ScanSegs sg, const uint64_t* partial) {
   __shared__ uint64_t s_w[kWaves];
-  const int64_t i = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int seg = (int)(blockIdx.x / sg.nb);
+  const int64_t b = (int64_t)blockIdx.x - (int64_t)seg * sg.nb;
+  const int64_t i = b * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int64_t n = sg.n;
+  uint32_t* out = sg.out[seg];
   uint32_t v[16];
-  load16(in, n, i, v);
+  load16(sg.in[seg], n, i, v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
@@ -1563,8 +1585,8 @@ hipError_t launch_sample(const ImageSet& set, hipStream_t s) {
   return hipGetLastError();
 }
 
-static int place_cap(const ImageSet& set) {
-  return small_tiles(set) ? stage_cap(kSmallTilePix) : stage_cap(kMaxTilePix);
+int place_stage_cap(int tile_pix) {
+  return stage_cap(tile_pix <= kSmallTilePix ? kSmallTilePix : kMaxTilePix);
 }
 
 int max_place_items_per_tile(int tile_pix) {
@@ -1572,17 +1594,13 @@ int max_place_items_per_tile(int tile_pix) {
   return (kStageLayers * pix + stage_cap(pix) - 1) / stage_cap(pix);
 }
 
-hipError_t launch_write_plan(const ImageSet& set, uint32_t* dense, uint32_t* sparse, void* items,
-                             void* scratch, uint32_t* status, hipStream_t s) {
+hipError_t launch_plan_items(const ImageSet& set, void* items, void* scratch, uint32_t* status,
+                             hipStream_t s) {
   const uint32_t n = set.tile_start[set.n];
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(write_plan_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set, place_cap(set),
-                     dense, sparse);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = launch_scan(dense, dense, n, scratch, status, s);
-  if (e == hipSuccess) e = launch_scan(sparse, sparse, n, scratch, status, s);
+  hipError_t e = launch_scan(set.plan, set.plan, 2 * (int64_t)n, scratch, status, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(plan_items_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set, dense, sparse,
+  hipLaunchKernelGGL(plan_items_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set,
                      static_cast<PlaceItem*>(items));
   return hipGetLastError();
 }
@@ -1693,11 +1711,16 @@ hipError_t launch_batch_pixel_scan(const BatchDevice& b, const uint32_t* counts,
   uint64_t* partial = static_cast<uint64_t*>(scratch);
   const int64_t nb = (n_slots + kScanTile - 1) / kScanTile;
   if (nb == 0 || b.n_images == 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, counts, n_slots, partial);
-  // the spine writes the grand total one past the end; its overflow check
-  // does not apply to a batch, whose images are checked one by one
-  hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kBlock), 0, s, partial, nb,
-                     reinterpret_cast<uint32_t*>(partial + nb), (int64_t)0, reinterpret_cast<uint32_t*>(partial + nb) + 1);
+  ScanSegs sg{};
+  sg.in[0] = counts;
+  sg.n = n_slots;
+  sg.nb = nb;
+  sg.nseg = 1;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, sg, partial);
+  // the spine's grand total goes one past the partial sums; its overflow
+  // check does not apply to a batch, whose images are checked one by one
+  sg.total[0] = reinterpret_cast<uint32_t*>(partial + nb);
+  hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kBlock), 0, s, sg, partial, (uint32_t*)nullptr);
   hipLaunchKernelGGL(segment_base_kernel, dim3((unsigned)b.n_images), dim3(kBlock), 0, s, counts, partial,
                      b.seg_start, b.sample_base);
   hipLaunchKernelGGL(scan_apply_segmented_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, counts, n_slots,
@@ -1711,20 +1734,41 @@ hipError_t launch_batch_finish_counts(const BatchDevice& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t scan_scratch_bytes(int64_t n) {
+size_t scan_scratch_bytes(int64_t n, int nseg) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  return (size_t)((nb > 0 ? nb : 1) + 2) * sizeof(uint64_t);
+  return (size_t)((nb > 0 ? nb : 1) * (nseg > 0 ? nseg : 1) + 2) * sizeof(uint64_t);
+}
+
+hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
+                                void* scratch, uint32_t* status, hipStream_t s) {
+  if (nseg < 1 || nseg > kMaxImages) return hipErrorInvalidValue;
+  if (n <= 0) {
+    for (int k = 0; k < nseg; ++k) {
+      hipError_t e = launch_fill_u32(out[k], 0u, 1, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  ScanSegs sg{};
+  for (int k = 0; k < nseg; ++k) {
+    sg.in[k] = in[k];
+    sg.out[k] = out[k];
+    sg.total[k] = out[k] + n;
+  }
+  sg.n = n;
+  sg.nb = (n + kScanTile - 1) / kScanTile;
+  sg.nseg = nseg;
+  uint64_t* partial = static_cast<uint64_t*>(scratch);
+  const unsigned blocks = (unsigned)(sg.nb * nseg);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kBlock), 0, s, sg, partial);
+  hipLaunchKernelGGL(scan_spine_kernel, dim3((unsigned)nseg), dim3(kBlock), 0, s, sg, partial, status);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, sg, partial);
+  return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
                        uint32_t* status, hipStream_t s) {
-  uint64_t* partial = static_cast<uint64_t*>(scratch);
-  if (n <= 0) return launch_fill_u32(out, 0u, 1, s);
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, partial);
-  hipLaunchKernelGGL(scan_spine_kernel, dim3(1), dim3(kBlock), 0, s, partial, nb, out, n, status);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, partial, out);
-  return hipGetLastError();
+  return launch_scan_segments(&in, &out, 1, n, scratch, status, s);
 }
 
 }  // namespace ldni
