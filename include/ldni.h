@@ -110,9 +110,17 @@ ldni_status ldni_sample(const float *verts, int64_t n_verts, const int32_t *tris
  * result or view, or an axis outside 0..2. */
 ldni_status ldni_result_axis(const ldni_result *r, int axis, ldni_axis_view *view);
 
-/* Release a result (NULL-safe).  The buffers return to the pool in the
- * order of the stream the result was made on, which must still exist. */
+/* Release a result (NULL-safe).  Its buffers are kept by the library for
+ * later calls on the stream the result was made on (reused in that stream's
+ * order, like hipFreeAsync), which must still exist. */
 void ldni_free(ldni_result *r);
+
+/* Device memory the library keeps between calls: the buffers of released
+ * results and each call's workspace, per (device, stream), at most 8 per
+ * stream.  ldni_trim hands all of it back to the device (synchronous; no
+ * call may be in flight, and every stream the library was used on must
+ * still exist).  Returns LDNI_OK or LDNI_ERR_DEVICE. */
+ldni_status ldni_trim(void);
 
 /*
  * ldni_sample_begin / ldni_sample_finish -- the same sampling with

@@ -19,7 +19,7 @@ from typing import Dict
 from . import _lib
 from ._lib import LDNIError
 
-__all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ldni_free",
+__all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ldni_free", "ldni_trim",
            "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
            "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read",
            "ldni_backward", "sample_diff", "LDNISample", "Batch", "sample_batch"]
@@ -399,6 +399,12 @@ def ldni_result_axis(result: Result, axis: int) -> _lib.AxisView:
 
 def ldni_free(result: Result) -> None:
     result.free()
+
+
+def ldni_trim() -> None:
+    """Hand the device buffers the library keeps between calls back to the
+    device (no call may be in flight)."""
+    _lib.check(_lib.lib().ldni_trim())
 
 
 def ldni_status_string(code: int) -> str:

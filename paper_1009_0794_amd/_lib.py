@@ -65,6 +65,8 @@ def lib():
     L.ldni_result_axis.restype = st
     L.ldni_free.argtypes = [vp]
     L.ldni_free.restype = None
+    L.ldni_trim.argtypes = []
+    L.ldni_trim.restype = st
     L.ldni_sample_begin.argtypes = [vp, i64, vp, i64, vp, i32, u32, ctypes.POINTER(vp), vp,
                                     ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]
     L.ldni_sample_begin.restype = st
@@ -123,7 +125,7 @@ def hip():
 
 def exported_symbols():
     """Names of the C ABI functions declared in include/ldni.h."""
-    return ["ldni_sample", "ldni_result_axis", "ldni_free", "ldni_sample_begin",
+    return ["ldni_sample", "ldni_result_axis", "ldni_free", "ldni_trim", "ldni_sample_begin",
             "ldni_sample_finish", "ldni_plan_free", "ldni_plan_max_layers",
             "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",

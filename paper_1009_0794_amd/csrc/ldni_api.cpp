@@ -130,10 +130,107 @@ bool env_fault(const char* what) {
   return f && std::strstr(f, what) != nullptr;
 }
 
-hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// Stream-ordered buffer cache.  Allocating and freeing through the pool
+// costs tens of microseconds of host time per call; buffers a call releases
+// are kept for later requests on the same stream instead.  Work on one
+// stream runs in order, so the memory's earlier user has finished with it by
+// the time a later request's work runs (the same rule as hipFreeAsync).
+// ---------------------------------------------------------------------------
+struct CachedBuffer {
+  int device;
+  hipStream_t stream;
+  void* ptr;
+  size_t bytes;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBuffer> g_cache;  // oldest first
+constexpr size_t kCachePerStream = 8;
+
+// sizes rounded up to sixteenths of the next power of two, so that requests
+// of slightly different sizes share buffers
+size_t round_alloc(size_t b) {
+  if (b <= 4096) return 4096;
+  size_t p = 4096;
+  while (p < b) p <<= 1;
+  const size_t step = p / 16;
+  return (b + step - 1) / step * step;
+}
+
+hipError_t cache_get(void** out, size_t bytes, hipStream_t s, size_t* got) {
+  *out = nullptr;
+  *got = 0;
   if (env_fault("alloc")) return hipErrorOutOfMemory;
-  if (bytes == 0) bytes = 256;
-  return hipMallocAsync(p, bytes, s);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      const CachedBuffer& c = g_cache[i];
+      if (c.device != dev || c.stream != s || c.bytes < bytes) continue;
+      if (best < 0 || c.bytes < g_cache[best].bytes) best = (int)i;
+    }
+    // not a buffer far larger than asked for (it may be needed for a larger request)
+    if (best >= 0 && g_cache[best].bytes <= 4 * bytes + ((size_t)1 << 20)) {
+      *out = g_cache[best].ptr;
+      *got = g_cache[best].bytes;
+      g_cache.erase(g_cache.begin() + best);
+      return hipSuccess;
+    }
+  }
+  const size_t b = round_alloc(bytes);
+  e = hipMallocAsync(out, b, s);
+  if (e != hipSuccess) {
+    // give the stream's cached buffers back to the pool and try once more
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      for (size_t i = 0; i < g_cache.size();) {
+        if (g_cache[i].device == dev && g_cache[i].stream == s) {
+          drop.push_back(g_cache[i].ptr);
+          g_cache.erase(g_cache.begin() + i);
+        } else {
+          ++i;
+        }
+      }
+    }
+    for (void* q : drop) (void)hipFreeAsync(q, s);
+    (void)hipGetLastError();
+    e = hipMallocAsync(out, b, s);
+  }
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return e;
+  }
+  *got = b;
+  return hipSuccess;
+}
+
+void cache_put(void* ptr, size_t bytes, hipStream_t s) {
+  if (!ptr) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipFreeAsync(ptr, s);
+    return;
+  }
+  void* evict = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.push_back(CachedBuffer{dev, s, ptr, bytes});
+    size_t n = 0, oldest = g_cache.size();
+    for (size_t i = 0; i < g_cache.size(); ++i)
+      if (g_cache[i].device == dev && g_cache[i].stream == s) {
+        if (oldest == g_cache.size()) oldest = i;
+        ++n;
+      }
+    if (n > kCachePerStream) {
+      evict = g_cache[oldest].ptr;
+      g_cache.erase(g_cache.begin() + oldest);
+    }
+  }
+  if (evict) (void)hipFreeAsync(evict, s);
 }
 
 ldni_status validate(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
@@ -190,11 +287,14 @@ struct ldni_plan {
   ImageSet set{};
   int axis_of[kMaxImages] = {0, 0, 0};  // image k samples axis axis_of[k]
   void* ws = nullptr;     // workspace
+  size_t ws_bytes = 0;
   void* lists = nullptr;  // tile lists
+  size_t lists_bytes = 0;
   uint32_t* write_counter = nullptr;
   void* items = nullptr;  // place-pass work items
   uint32_t n_items = 0;
   void* stage = nullptr;  // hits staged by the sampling pass
+  size_t stage_bytes = 0;
   uint32_t n_walk = 0;    // tiles the write pass walks again
   uint64_t n[3] = {0, 0, 0};
   uint32_t max_layers[3] = {0, 0, 0};
@@ -203,7 +303,9 @@ struct ldni_plan {
 struct ldni_result {
   hipStream_t stream = nullptr;
   void* offsets_buf = nullptr;
+  size_t offsets_bytes = 0;
   void* samples_buf = nullptr;
+  size_t samples_bytes = 0;
   ldni_axis_view view[3];
 };
 
@@ -211,9 +313,9 @@ namespace {
 
 void release_plan(ldni_plan* p) {
   if (!p) return;
-  if (p->lists) (void)hipFreeAsync(p->lists, p->stream);
-  if (p->stage) (void)hipFreeAsync(p->stage, p->stream);
-  if (p->ws) (void)hipFreeAsync(p->ws, p->stream);
+  cache_put(p->lists, p->lists_bytes, p->stream);
+  cache_put(p->stage, p->stage_bytes, p->stream);
+  cache_put(p->ws, p->ws_bytes, p->stream);
   delete p;
 }
 
@@ -306,7 +408,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   const size_t o_scan = off;
   off = align_up(off + std::max(scan_scratch_bytes(npix, nimg), scan_scratch_bytes(2 * n_all, 1)));
 
-  hipError_t e = pool_alloc(&p->ws, off, stream);
+  hipError_t e = cache_get(&p->ws, off, stream, &p->ws_bytes);
   if (e != hipSuccess) {
     p->ws = nullptr;
     release_plan(p);
@@ -386,7 +488,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
       stage_cap = std::min<uint64_t>(stage_cap, std::strtoull(env, nullptr, 10));
     if (stage_cap == 0 ||
-        pool_alloc(&p->stage, stage_cap * (sizeof(uint64_t) + sizeof(uint32_t)), stream) != hipSuccess)
+        cache_get(&p->stage, stage_cap * (sizeof(uint64_t) + sizeof(uint32_t)), stream, &p->stage_bytes) !=
+            hipSuccess)
       p->stage = nullptr;  // no staging: every tile with hits is walked again
     for (int k = 0; k < nimg; ++k) {
       Image& im = set.img[k];
@@ -430,9 +533,9 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   uint64_t cap = (uint64_t)std::ceil((double)n_tris * nimg * std::min(g_list_ratio.load(), 8.0)) +
                  4 * (uint64_t)n_all + 1024;
   auto alloc_lists = [&](uint64_t c) -> hipError_t {
-    if (p->lists) (void)hipFreeAsync(p->lists, stream);
+    cache_put(p->lists, p->lists_bytes, stream);
     p->lists = nullptr;
-    hipError_t ea = pool_alloc(&p->lists, sizeof(int32_t) * (size_t)c, stream);
+    hipError_t ea = cache_get(&p->lists, sizeof(int32_t) * (size_t)c, stream, &p->lists_bytes);
     if (ea != hipSuccess) {
       p->lists = nullptr;
       return ea;
@@ -595,7 +698,7 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
   std::memset(r->view, 0, sizeof(r->view));
   r->stream = stream;
   const size_t per_axis = align_up(sizeof(uint32_t) * ((size_t)w * w + 1));
-  hipError_t e = pool_alloc(&r->offsets_buf, 3 * per_axis, stream);
+  hipError_t e = cache_get(&r->offsets_buf, 3 * per_axis, stream, &r->offsets_bytes);
   if (e != hipSuccess) {
     delete r;
     return hip_fail(e, "offsets allocation");
@@ -619,7 +722,7 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
     o_normal[a] = bytes; bytes = align_up(bytes + sizeof(float) * 3 * n[a]);
     o_tri[a] = bytes; bytes = align_up(bytes + sizeof(int32_t) * n[a]);
   }
-  e = pool_alloc(&r->samples_buf, bytes, stream);
+  e = cache_get(&r->samples_buf, bytes, stream, &r->samples_bytes);
   if (e != hipSuccess) {
     r->samples_buf = nullptr;
     ldni_plan_free(plan);
@@ -700,15 +803,16 @@ ldni_status ldni_backward(const float* verts, int64_t n_verts, const int32_t* tr
   args.n = nimg;
   if (nimg == 0) return LDNI_OK;
   void* ws = nullptr;
+  size_t ws_bytes = 0;
   const size_t per = align_up(sizeof(float) * 3 * (size_t)n_tris);
-  hipError_t e = pool_alloc(&ws, per * (nimg + 1), stream);
+  hipError_t e = cache_get(&ws, per * (nimg + 1), stream, &ws_bytes);
   if (e != hipSuccess) return hip_fail(e, "backward workspace");
   char* base = static_cast<char*>(ws);
   for (int k = 0; k < nimg; ++k) args.axis[k].acc = reinterpret_cast<float*>(base + k * per);
   args.gnsum = reinterpret_cast<float*>(base + nimg * per);
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, (int64_t)(per * (nimg + 1) / 4), stream);
   if (e == hipSuccess) e = timed("backward", stream, [&] { return launch_backward(args, stream); });
-  (void)hipFreeAsync(ws, stream);
+  cache_put(ws, ws_bytes, stream);
   if (e != hipSuccess) return hip_fail(e, "backward kernels");
   return LDNI_OK;
 }
@@ -719,10 +823,28 @@ ldni_status ldni_result_axis(const ldni_result* r, int axis, ldni_axis_view* vie
   return LDNI_OK;
 }
 
+ldni_status ldni_trim(void) {
+  std::vector<CachedBuffer> all;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    all.swap(g_cache);
+  }
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  bool ok = true;
+  for (const CachedBuffer& c : all) {
+    ok &= hipSetDevice(c.device) == hipSuccess;
+    ok &= hipStreamSynchronize(c.stream) == hipSuccess;
+    ok &= hipFree(c.ptr) == hipSuccess;
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+  return ok ? LDNI_OK : fail(LDNI_ERR_DEVICE, "releasing cached buffers");
+}
+
 void ldni_free(ldni_result* r) {
   if (!r) return;
-  if (r->samples_buf) (void)hipFreeAsync(r->samples_buf, r->stream);
-  if (r->offsets_buf) (void)hipFreeAsync(r->offsets_buf, r->stream);
+  cache_put(r->samples_buf, r->samples_bytes, r->stream);
+  cache_put(r->offsets_buf, r->offsets_bytes, r->stream);
   delete r;
 }
 

@@ -137,3 +137,9 @@ def test_backward_rejects_bad_arguments(L):
     views[0].offsets = 1
     assert L.ldni_backward(1, 3, 1, 1, bb, 8, 1, views, gd, gn, 1, None) == 1
     assert L.ldni_backward(1, 3, 1, 1, bb, 0, 1, views, gd, gn, 1, None) == 1
+
+
+def test_trim_with_nothing_cached(L):
+    """ldni_trim releases the buffers kept between calls; with none kept it
+    touches no device."""
+    assert L.ldni_trim() == 0

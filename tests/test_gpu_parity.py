@@ -251,3 +251,38 @@ def test_staging_capacity_does_not_change_results(tile, monkeypatch):
         else:
             monkeypatch.setenv("LDNI_STAGE_ENTRIES", entries)
         compare(_run(m.verts, m.tris, m.bbox, w), ref, m.bbox, label=f"staging {entries} tile {tile}")
+
+
+def test_buffers_reused_across_calls_and_results_kept_alive():
+    """Calls of different sizes on one stream reuse the buffers earlier calls
+    released (the library keeps them per stream), through both the
+    torch-output call and the library-owned-output call; results that stay
+    alive keep theirs; ldni_trim in between changes nothing."""
+    m1 = mg.c1_icosphere()
+    m2 = mg.c2_flower()
+    cases = [(m1, 128), (m2, 160), (m1, 64), (m2, 96), (m1, 128)]
+    refs = {(id(m), w): oracle.sample(m.verts, m.tris, m.bbox, w) for m, w in cases}
+    kept = []
+    for it, (m, w) in enumerate(cases * 2):
+        ref = refs[(id(m), w)]
+        if it % 2 == 0:
+            compare(_run(m.verts, m.tris, m.bbox, w), ref, m.bbox, label=f"call {it} w={w}")
+        else:
+            vt = torch.from_numpy(m.verts).to(DEV)
+            ft = torch.from_numpy(m.tris).to(DEV)
+            r = ldni.ldni_sample(vt, ft, m.bbox, w, "xyz")
+            got = {a: r.to_torch(a) for a in range(3)}
+            torch.cuda.synchronize()
+            compare(got, ref, m.bbox, label=f"owned call {it} w={w}")
+            if it % 4 == 1:
+                kept.append((r, ref, m.bbox))  # stays alive across later calls
+            else:
+                r.free()
+        if it == 4:
+            torch.cuda.synchronize()
+            ldni.ldni_trim()
+    for r, ref, bb in kept:
+        got = {a: r.to_torch(a) for a in range(3)}
+        torch.cuda.synchronize()
+        compare(got, ref, bb, label="kept result")
+        r.free()
