@@ -44,6 +44,10 @@ void tile_shape(int32_t w, int64_t n_tris, int req_w, int req_h, int* tw, int* t
 }
 // largest (tile-list entries / triangles) seen, with headroom
 std::atomic<double> g_list_ratio{2.0};
+// Staging buffers hold fewer than 2^32 entries (tile regions start at 32-bit
+// entry indices); batch_grow adds up to 1/16 + 1024 to what it is asked for.
+constexpr uint64_t kMaxStageEntries = 0xf0000000ull;
+
 // Staging entries the sampling pass asked for in recent calls, keyed by the
 // call's shape: a repeated call on the same mesh gets what the last one
 // needed (plus headroom for moved vertices).
@@ -482,7 +486,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     const double want = stage_demand_lookup(stage_key, &last)
                             ? (double)last * 1.1 + 65536.0
                             : 24.0 * (double)n_tris + px + 65536.0;
-    const double most = std::min(64.0 * px + 65536.0, (double)0xfffff000u);
+    const double most = std::min(64.0 * px + 65536.0, (double)kMaxStageEntries);
     uint64_t stage_cap = (uint64_t)std::min(want, most);
     // test hook: a smaller buffer (0: none) forces tiles onto the walk path
     if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
@@ -868,6 +872,9 @@ struct ldni_batch {
   uint64_t list_cap = 0;
   void* samples = nullptr;
   uint64_t sample_cap = 0;
+  void* stage = nullptr;  // hits staged by the sampling pass
+  uint64_t stage_cap = 0;
+  bool small = true;      // every image's tiles have at most 256 pixels
   uint32_t* host_out = nullptr;
   BatchDevice dev{};
   uint32_t* offsets_arena = nullptr;
@@ -900,6 +907,7 @@ void batch_destroy(ldni_batch* b) {
   batch_release_graph(b);
   if (b->cs) (void)hipStreamSynchronize(b->cs);
   if (b->samples) (void)hipFree(b->samples);
+  if (b->stage) (void)hipFree(b->stage);
   if (b->lists) (void)hipFree(b->lists);
   if (b->ws) (void)hipFree(b->ws);
   if (b->host_out) (void)hipHostFree(b->host_out);
@@ -919,6 +927,13 @@ hipError_t batch_upload(ldni_batch* b) {
   b->dev.tri = b->samples ? reinterpret_cast<int32_t*>(static_cast<float*>(b->samples) + 4 * b->sample_cap)
                           : nullptr;
   b->dev.sample_cap = b->sample_cap;
+  for (int k = 0; k < b->n_img; ++k) {
+    Image& im = b->images_h[k];
+    im.stage_key = b->stage ? static_cast<uint64_t*>(b->stage) : nullptr;
+    im.stage_qs = b->stage ? reinterpret_cast<uint32_t*>(static_cast<uint64_t*>(b->stage) + b->stage_cap)
+                           : nullptr;
+    im.stage_cap = b->stage ? b->stage_cap : 0;
+  }
   hipError_t e = hipMemcpy(b->dev.images, b->images_h.data(), sizeof(Image) * b->n_img, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   return hipMemcpy(b->dev.meshes, b->meshes_h.data(), sizeof(BatchMesh) * b->n_meshes, hipMemcpyHostToDevice);
@@ -928,7 +943,7 @@ hipError_t batch_upload(ldni_batch* b) {
 hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   hipError_t e;
 #define Q(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
-  Q(launch_fill_u32(b->dev.status, 0u, 16, s));  // status and work counters
+  Q(launch_fill_u32(b->dev.status, 0u, 20, s));  // status, work counters, staging cursor, walk count
   Q(launch_fill_u32(b->max_layers, 0u, b->n_img, s));
   Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)b->total_tiles + 1, s));
   Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
@@ -936,13 +951,11 @@ hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   Q(launch_batch_bin(b->dev, false, b->bin_block_start.back(), s));
   Q(launch_scan(b->tile_arena, b->tile_arena, (int64_t)b->total_tiles, b->scan_scratch, b->dev.status, s));
   Q(launch_batch_bin(b->dev, true, b->bin_block_start.back(), s));
-  bool small = true;
-  for (const Image& im : b->images_h) small = small && im.tw * im.th <= 256;
-  Q(launch_batch_count(b->dev, (uint32_t)b->total_tiles, small, s));
+  Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, b->small, s));
   Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
                             b->scan_scratch, s));
   Q(launch_batch_finish_counts(b->dev, s));
-  Q(launch_batch_write(b->dev, (uint32_t)b->total_tiles, small, s));
+  Q(launch_batch_place(b->dev, (uint32_t)b->total_tiles, b->small, b->scan_scratch, s));
 #undef Q
   return hipSuccess;
 }
@@ -1023,6 +1036,19 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
       batch_release_graph(b);
       continue;
     }
+    // Tiles that found no room in the staging buffer were walked again, so
+    // the results stand; the buffer grows for the next run.
+    const uint32_t* tail = h + 4 + 4 * (size_t)b->n_img;
+    // (tile regions start at 32-bit entry indices)
+    const uint64_t demand = std::min<uint64_t>((uint64_t)tail[0] | ((uint64_t)tail[1] << 32), kMaxStageEntries);
+    if (demand > b->stage_cap) {
+      // 12 bytes per entry: key and pixel/slot
+      if (batch_grow(b, &b->stage, &b->stage_cap, demand, sizeof(uint64_t) + sizeof(uint32_t)) != LDNI_OK) {
+        b->stage = nullptr;  // no staging: every tile is walked again
+        b->stage_cap = 0;
+      }
+      batch_release_graph(b);
+    }
     return LDNI_OK;
   }
   return fail(LDNI_ERR_DEVICE, "batch sizing did not converge");
@@ -1058,8 +1084,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   b->desc.assign(meshes, meshes + n_meshes);
   hipError_t e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(e, "stream"));
-  e = hipHostMalloc(reinterpret_cast<void**>(&b->host_out), sizeof(uint32_t) * (4 + 4 * (size_t)n_meshes * naxes),
-                    hipHostMallocCoherent);
+  e = hipHostMalloc(reinterpret_cast<void**>(&b->host_out),
+                    sizeof(uint32_t) * (4 + 4 * (size_t)n_meshes * naxes + 4), hipHostMallocCoherent);
   if (e != hipSuccess) {
     b->host_out = nullptr;
     return bail(hip_fail(e, "pinned summary"));
@@ -1124,7 +1150,21 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const size_t o_cur = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_counts = take(sizeof(uint32_t) * b->total_slots);
   const size_t o_offs = take(sizeof(uint32_t) * b->total_slots);
-  const size_t o_scan = take(std::max(scan_scratch_bytes((int64_t)b->total_tiles),
+  b->small = true;
+  for (int m = 0; m < n_meshes; ++m)
+    for (int a = 0; a < 3; ++a) {
+      if (!((axis_mask >> a) & 1u)) continue;
+      int tw = 0, th = 0;
+      tile_shape(meshes[m].w, meshes[m].n_tris, meshes[m].tile_w, meshes[m].tile_h, &tw, &th);
+      b->small = b->small && tw * th <= 256;
+    }
+  const int tile_pix = b->small ? 256 : 1024;
+  const size_t o_tstage = take(sizeof(uint32_t) * b->total_tiles);
+  const size_t o_thits = take(sizeof(uint32_t) * b->total_tiles);
+  const size_t o_walk = take(sizeof(uint32_t) * b->total_tiles);
+  const size_t o_plan = take(sizeof(uint32_t) * (2 * b->total_tiles + 1));
+  const size_t o_items = take(16 * (size_t)max_place_items_per_tile(tile_pix) * b->total_tiles);
+  const size_t o_scan = take(std::max(scan_scratch_bytes(2 * (int64_t)b->total_tiles),
                                       scan_scratch_bytes((int64_t)b->total_slots)));
   e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(&b->ws, off);
   if (e != hipSuccess) {
@@ -1153,6 +1193,14 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   b->offsets_arena = reinterpret_cast<uint32_t*>(ws + o_offs);
   b->scan_scratch = ws + o_scan;
   D.tile_total = b->tile_arena + b->total_tiles;
+  D.plan = reinterpret_cast<uint32_t*>(ws + o_plan);
+  D.items = ws + o_items;
+  D.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
+  D.walk_count = D.status + 18;
+  D.stage_cursor = reinterpret_cast<unsigned long long*>(D.status + 16);
+  D.place_cap = place_stage_cap(tile_pix);
+  uint32_t* tstage = reinterpret_cast<uint32_t*>(ws + o_tstage);
+  uint32_t* thits = reinterpret_cast<uint32_t*>(ws + o_thits);
 
   b->meshes_h.assign(n_meshes, BatchMesh{});
   b->images_h.assign(n_img, Image{});
@@ -1201,6 +1249,11 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.max_layers = b->max_layers + k;
     im.offsets = b->offsets_arena + b->seg_start[k];
     im.status = D.status;
+    im.stage_cursor = D.stage_cursor;
+    im.tile_stage = tstage + b->tile_start[k];
+    im.tile_hits = thits + b->tile_start[k];
+    im.walk_list = D.walk_list;
+    im.walk_count = D.walk_count;
   }
   e = hipMemcpy(const_cast<uint32_t*>(D.tri_block_start), b->tri_block_start.data(),
                 sizeof(uint32_t) * (n_meshes + 1), hipMemcpyHostToDevice);
@@ -1225,6 +1278,19 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
            4 * (uint64_t)(b->tile_start[k + 1] - b->tile_start[k]);
   ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, sizeof(int32_t));
   if (st != LDNI_OK) return bail(st);
+  // staging: a first guess (24 entries per triangle plus one per pixel),
+  // grown to the demand after the first run if it was short
+  {
+    uint64_t guess = 65536;
+    for (int k = 0; k < n_img; ++k)
+      guess += 24 * (uint64_t)meshes[b->img_mesh[k]].n_tris +
+               (uint64_t)meshes[b->img_mesh[k]].w * meshes[b->img_mesh[k]].w;
+    guess = std::min<uint64_t>(guess, kMaxStageEntries);
+    if (batch_grow(b, &b->stage, &b->stage_cap, guess, sizeof(uint64_t) + sizeof(uint32_t)) != LDNI_OK) {
+      b->stage = nullptr;
+      b->stage_cap = 0;
+    }
+  }
   st = ldni_batch_run(b, hip_stream);
   if (st != LDNI_OK) return bail(st);
   *out = b;

@@ -143,14 +143,27 @@ struct BatchDevice {
   uint32_t* tile_total;             // entries of all tile lists (end of the tile scan)
   uint64_t list_cap;
   uint32_t* host_out;               // pinned: [0] status, [1] list entries, then per image
-                                    // (n, base lo, base hi, max layers)
+                                    // (n, base lo, base hi, max layers), then staging
+                                    // demand (lo, hi) and tiles walked again
+  // staged sampling (see Image): place plan over all tiles of the batch,
+  // item records, tiles walked again
+  uint32_t* plan;                   // [2 * total tiles + 1]
+  void* items;                      // place items
+  uint32_t* walk_list;
+  uint32_t* walk_count;
+  unsigned long long* stage_cursor;
+  int32_t place_cap;
 };
 
 hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s);
 hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks, hipStream_t s);
-// small: every image's tiles have at most 256 pixels
-hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s);
-hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s);
+// small: every image's tiles have at most 256 pixels.  n_tiles: tiles of
+// the batch.  Sampling pass (counts, staged hits, place plan), then after the
+// pixel scan and the placement of the images: the place items, the place
+// pass and the walk of the tiles whose hits were not staged.
+hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s);
+hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
+                              hipStream_t s);
 // Segmented exclusive scan of the per-image counts (segments of w*w+1 slots,
 // the last slot of each zero) into per-image offsets starting at 0, with the
 // u64 start of every segment in sample_base.

@@ -474,44 +474,6 @@ __device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, fl
 }
 
 // ---------------------------------------------------------------------------
-// count pass
-// ---------------------------------------------------------------------------
-template <int kTilePix>
-__device__ void count_tile(const Image& im, int tile) {
-  __shared__ uint32_t s_cnt[kTilePix];
-  __shared__ float s_cu[kMaxTileW];
-  __shared__ float s_cv[kMaxTileH + 1];
-  __shared__ ChunkLds<false> L;
-  __shared__ uint32_t s_red[kWaves];
-
-  const TileGeom g = tile_geom(im, tile);
-  const int npix = g.cw * g.ch;
-  const int tw = im.tw;
-
-  for (int q = threadIdx.x; q < im.tw * im.th; q += kBlock) s_cnt[q] = 0;
-  for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
-  for (int q = threadIdx.x; q <= g.ch; q += kBlock)
-    s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
-  __syncthreads();
-
-  tile_candidates<false>(im, g, 0, g.ch, L, s_cu, s_cv,
-                         [&](int, int px, int py, const Edges&) {
-                           atomicAdd(&s_cnt[py * tw + px], 1u);
-                         });
-
-  uint32_t mx = 0;
-  for (int q = threadIdx.x; q < npix; q += kBlock) {
-    const int py = q / g.cw, px = q - py * g.cw;
-    const uint32_t c = s_cnt[py * tw + px];
-    mx = max(mx, c);
-    im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = c;
-  }
-  mx = block_max(mx, s_red);
-  if (threadIdx.x == 0 && mx > 0) atomicMax(im.max_layers, mx);
-}
-
-
-// ---------------------------------------------------------------------------
 // sampling pass: count and stage every hit
 // ---------------------------------------------------------------------------
 // A tile's staging region holds at most this many hits per tile pixel (and
@@ -1182,39 +1144,71 @@ struct BackwardSet {
   float* gnsum;                          // [T][3] sum of gn
 };
 
-// One workgroup per run of kBlock consecutive pixels: their samples are
-// contiguous, so threads take samples (not pixels) and find their pixel by a
-// binary search over the run's offsets in LDS.
+// One workgroup per kBwdTile x kBwdTile pixel tile.  The tile's samples (one
+// contiguous range per pixel row) are spread over the threads; each sample's
+// six values (gd * lambda per vertex, gn) are summed per triangle in an LDS
+// hash table, and every triangle of the tile then adds its sums to global
+// memory once.  A sample that finds no free slot adds its own directly.
+constexpr int kBwdTile = 16;
+constexpr int kBwdSlots = 1024;
+constexpr int kBwdProbe = 32;
+
 __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs) {
-  __shared__ uint32_t s_off[kBlock + 1];
+  __shared__ uint32_t s_row[kBwdTile + 1][kBwdTile + 1];  // offsets of the tile's rows
+  __shared__ uint32_t s_pre[kBwdTile + 1];                // samples before each row
+  __shared__ uint32_t s_key[kBwdSlots];                   // triangle + 1, 0 = free
+  __shared__ float s_val[kBwdSlots][6];
   int k = 0;
   while (k + 1 < bs.n && blockIdx.x >= bs.block_start[k + 1]) ++k;
   const BackwardImage& im = bs.img[k];
-  const int64_t npix = (int64_t)im.w * im.w;
-  const int64_t p0 = (int64_t)(blockIdx.x - bs.block_start[k]) * kBlock;
-  const int n = (int)min((int64_t)kBlock, npix - p0);
-  for (int q = threadIdx.x; q <= n; q += kBlock) s_off[q] = im.offsets[p0 + q];
+  const int ntx = (im.w + kBwdTile - 1) / kBwdTile;
+  const int tile = (int)(blockIdx.x - bs.block_start[k]);
+  const int x0 = (tile % ntx) * kBwdTile, y0 = (tile / ntx) * kBwdTile;
+  const int cw = min(kBwdTile, im.w - x0), ch = min(kBwdTile, im.w - y0);
+
+  for (int q = threadIdx.x; q < kBwdSlots; q += kBlock) {
+    s_key[q] = 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s_val[q][c] = 0.0f;
+  }
+  for (int q = threadIdx.x; q < ch * (cw + 1); q += kBlock) {
+    const int r = q / (cw + 1), x = q - r * (cw + 1);
+    s_row[r][x] = im.offsets[(int64_t)(y0 + r) * im.w + x0 + x];
+  }
   __syncthreads();
-  const uint32_t S0 = s_off[0], S1 = s_off[n];
-  for (uint32_t s = S0 + threadIdx.x; s < S1; s += kBlock) {
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int r = 0; r < ch; ++r) {
+      s_pre[r] = acc;
+      acc += s_row[r][cw] - s_row[r][0];
+    }
+    s_pre[ch] = acc;
+  }
+  __syncthreads();
+  const uint32_t S = s_pre[ch];
+  float* const accp = im.acc;
+
+  for (uint32_t f = threadIdx.x; f < S; f += kBlock) {
+    int r = 0;  // row of f: the last r with s_pre[r] <= f
+    while (r + 1 < ch && s_pre[r + 1] <= f) ++r;
+    const uint32_t s = s_row[r][0] + (f - s_pre[r]);
     const int32_t t = im.tri[s];
     if (t < 0 || t >= bs.n_tris) continue;  // not a triangle of this mesh
+    float v[6] = {0, 0, 0, 0, 0, 0};
     const float g = im.gd ? im.gd[s] : 0.0f;
     if (g != 0.0f) {
-      int lo = 0, hi = n - 1;  // pixel of s: the last q with s_off[q] <= s
+      int lo = 0, hi = cw - 1;  // pixel of s in the row: the last x with s_row[r][x] <= s
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= s) lo = mid; else hi = mid - 1;
+        if (s_row[r][mid] <= s) lo = mid; else hi = mid - 1;
       }
-      const int64_t p = p0 + lo;
-      const int i = (int)(p % im.w), j = (int)(p / im.w);
-      const double cu = im.lo_u + ((double)i + 0.5) * im.h_u;
-      const double cv = im.lo_v + ((double)j + 0.5) * im.h_v;
-      const int32_t* f = bs.tris + 3 * (int64_t)t;
+      const double cu = im.lo_u + ((double)(x0 + lo) + 0.5) * im.h_u;
+      const double cv = im.lo_v + ((double)(y0 + r) + 0.5) * im.h_v;
+      const int32_t* fv = bs.tris + 3 * (int64_t)t;
       double xu[3], xv[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const float* P = bs.verts + 3 * (int64_t)min(max(f[q], 0), (int32_t)(bs.n_verts - 1));
+        const float* P = bs.verts + 3 * (int64_t)min(max(fv[q], 0), (int32_t)(bs.n_verts - 1));
         xu[q] = (double)P[im.u] - cu;
         xv[q] = (double)P[im.v] - cv;
       }
@@ -1224,19 +1218,56 @@ __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs
       const double den = e_ab + e_bc + e_ca;
       if (den != 0.0) {
         const double gs = (double)g / den;
-        float* acc = im.acc + 3 * (int64_t)t;
-        atomicAdd(acc + 0, (float)(gs * e_bc));
-        atomicAdd(acc + 1, (float)(gs * e_ca));
-        atomicAdd(acc + 2, (float)(gs * e_ab));
+        v[0] = (float)(gs * e_bc);
+        v[1] = (float)(gs * e_ca);
+        v[2] = (float)(gs * e_ab);
       }
     }
     if (im.gn) {
       const float* gv = im.gn + 3 * (int64_t)s;
-      float* gs = bs.gnsum + 3 * (int64_t)t;
-      const float g0 = gv[0], g1 = gv[1], g2 = gv[2];
-      if (g0 != 0.0f) atomicAdd(gs + 0, g0);
-      if (g1 != 0.0f) atomicAdd(gs + 1, g1);
-      if (g2 != 0.0f) atomicAdd(gs + 2, g2);
+      v[3] = gv[0];
+      v[4] = gv[1];
+      v[5] = gv[2];
+    }
+    if (v[0] == 0.0f && v[1] == 0.0f && v[2] == 0.0f && v[3] == 0.0f && v[4] == 0.0f && v[5] == 0.0f)
+      continue;
+    // slot of t in the table (linear probing, a bounded number of steps)
+    const uint32_t key = (uint32_t)t + 1u;
+    uint32_t h = ((uint32_t)t * 2654435761u) >> 22;  // 10 bits
+    int slot = -1;
+    for (int step = 0; step < kBwdProbe; ++step) {
+      const uint32_t old = atomicCAS(&s_key[h], 0u, key);
+      if (old == 0u || old == key) {
+        slot = (int)h;
+        break;
+      }
+      h = (h + 1) & (kBwdSlots - 1);
+    }
+    if (slot >= 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (v[c] != 0.0f) atomicAdd(&s_val[slot][c], v[c]);
+    } else {
+      float* a3 = accp + 3 * (int64_t)t;
+      float* g3 = bs.gnsum + 3 * (int64_t)t;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (v[c] != 0.0f) atomicAdd(a3 + c, v[c]);
+        if (v[3 + c] != 0.0f) atomicAdd(g3 + c, v[3 + c]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kBwdSlots; q += kBlock) {
+    const uint32_t key = s_key[q];
+    if (key == 0u) continue;
+    const int64_t t = (int64_t)(key - 1u);
+    float* a3 = accp + 3 * t;
+    float* g3 = bs.gnsum + 3 * t;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (s_val[q][c] != 0.0f) atomicAdd(a3 + c, s_val[q][c]);
+      if (s_val[q][3 + c] != 0.0f) atomicAdd(g3 + c, s_val[q][3 + c]);
     }
   }
 }
@@ -1428,25 +1459,92 @@ __global__ void __launch_bounds__(kBlock) batch_bin_kernel(BatchDevice B) {
                           (int64_t)(blockIdx.x - B.bin_block_start[k]) * kBlock + threadIdx.x);
 }
 
-// Persistent workgroups take (image, tile) items from a counter until none
-// are left; every workgroup reaches the exit.
-template <bool kWrite, int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_tiles_kernel(BatchDevice B, uint32_t n_items) {
-  __shared__ uint32_t s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&B.work[kWrite ? 1 : 0], 1u);
-    __syncthreads();
-    const uint32_t item = s_item;
-    __syncthreads();
-    if (item >= n_items) break;
-    const int k = segment_of(B.tile_start, B.n_images, item);
-    const Image& im = B.images[k];
-    const int tile = (int)(item - B.tile_start[k]);
-    if (kWrite) {
-      if (im.depth != nullptr) write_tile<kTilePix>(im, tile);
-    } else {
-      count_tile<kTilePix>(im, tile);
+// Persistent workgroups take items from a counter, kGrab at a time, until
+// none are left; every workgroup reaches the exit.
+constexpr uint32_t kGrab = 4;
+
+struct ItemGrabber {
+  uint32_t next = 0, left = 0;
+  // the next item for the whole workgroup (all threads call it)
+  __device__ uint32_t operator()(uint32_t* counter, uint32_t* s_item) {
+    if (left == 0) {
+      if (threadIdx.x == 0) *s_item = atomicAdd(counter, kGrab);
+      __syncthreads();
+      next = *s_item;
+      __syncthreads();
+      left = kGrab;
     }
+    --left;
+    return next++;
+  }
+};
+
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) batch_sample_kernel(BatchDevice B, uint32_t n_tiles) {
+  __shared__ uint32_t s_item;
+  ItemGrabber grab;
+  for (;;) {
+    const uint32_t item = grab(&B.work[0], &s_item);
+    if (item >= n_tiles) break;
+    const int k = segment_of(B.tile_start, B.n_images, item);
+    sample_tile<kTilePix>(B.images[k], (int)(item - B.tile_start[k]), item, B.plan, n_tiles, B.place_cap);
+  }
+}
+
+// Place items of the batch, in launch order, from the scanned plan.
+__global__ void __launch_bounds__(kBlock) batch_plan_items_kernel(BatchDevice B, uint32_t n_tiles) {
+  const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
+  if (gt >= n_tiles) return;
+  const uint32_t kd = B.plan[gt + 1] - B.plan[gt];
+  const uint32_t ks = B.plan[n_tiles + gt + 1] - B.plan[n_tiles + gt];
+  const uint32_t K = kd + ks;
+  if (K == 0) return;
+  const int k = segment_of(B.tile_start, B.n_images, gt);
+  const Image& im = B.images[k];
+  const int tile = (int)(gt - B.tile_start[k]);
+  const uint32_t at = kd ? B.plan[gt] : B.plan[n_tiles + gt];
+  PlaceItem it;
+  it.gtile = gt;
+  it.first = im.tile_stage[tile];
+  it.hits = im.tile_hits[tile];
+  PlaceItem* items = static_cast<PlaceItem*>(B.items);
+  for (uint32_t j = 0; j < K; ++j) {
+    it.part_parts = j | (K << 16);
+    items[at + j] = it;
+  }
+}
+
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) batch_place_kernel(BatchDevice B, uint32_t n_tiles) {
+  __shared__ uint32_t s_item;
+  const uint32_t n_items = B.plan[2 * n_tiles];
+  const PlaceItem* items = static_cast<const PlaceItem*>(B.items);
+  ItemGrabber grab;
+  for (;;) {
+    const uint32_t item = grab(&B.work[1], &s_item);
+    if (item >= n_items) break;
+    const PlaceItem it = items[item];
+    const int k = segment_of(B.tile_start, B.n_images, it.gtile);
+    const Image& im = B.images[k];
+    if (im.depth == nullptr) continue;  // the image did not fit the output arena
+    place_tile<kTilePix>(im, (int)(it.gtile - B.tile_start[k]), it.first, it.hits,
+                         (int)(it.part_parts & 0xffffu), (int)(it.part_parts >> 16));
+  }
+}
+
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) batch_walk_kernel(BatchDevice B) {
+  __shared__ uint32_t s_item;
+  const uint32_t n = *B.walk_count;
+  ItemGrabber grab;
+  for (;;) {
+    const uint32_t item = grab(&B.work[2], &s_item);
+    if (item >= n) break;
+    const uint32_t gt = B.walk_list[item];
+    const int k = segment_of(B.tile_start, B.n_images, gt);
+    const Image& im = B.images[k];
+    if (im.depth == nullptr) continue;
+    write_tile<kTilePix>(im, (int)(gt - B.tile_start[k]));
   }
 }
 
@@ -1492,6 +1590,11 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
   if (k == 0) {
     B.host_out[0] = *B.status;
     B.host_out[1] = *B.tile_total;
+    uint32_t* tail = B.host_out + 4 + 4 * (size_t)B.n_images;
+    const unsigned long long demand = *B.stage_cursor;
+    tail[0] = (uint32_t)demand;
+    tail[1] = (uint32_t)(demand >> 32);
+    tail[2] = *B.walk_count;
   }
   if (k < B.n_images) {
     Image& im = B.images[k];
@@ -1654,7 +1757,8 @@ hipError_t launch_backward(const BackwardArgs& args, hipStream_t s) {
     im.gd = a.gd;
     im.gn = a.gn;
     im.acc = a.acc;
-    bs.block_start[k + 1] = bs.block_start[k] + grid_for((int64_t)args.w * args.w, kBlock);
+    const uint32_t nt = (uint32_t)((args.w + kBwdTile - 1) / kBwdTile);
+    bs.block_start[k + 1] = bs.block_start[k] + nt * nt;
   }
   if (args.n > 0 && bs.block_start[args.n] > 0)
     hipLaunchKernelGGL(backward_samples_kernel, dim3(bs.block_start[args.n]), dim3(kBlock), 0, s, bs);
@@ -1686,23 +1790,33 @@ hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks,
   return hipGetLastError();
 }
 
-hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s) {
+hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
   if (small)
-    hipLaunchKernelGGL((batch_tiles_kernel<false, kSmallTilePix>), dim3(persistent_grid(n_items, 8)),
-                       dim3(kBlock), 0, s, b, n_items);
+    hipLaunchKernelGGL(batch_sample_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 7)), dim3(kBlock), 0,
+                       s, b, n_tiles);
   else
-    hipLaunchKernelGGL((batch_tiles_kernel<false, kMaxTilePix>), dim3(persistent_grid(n_items, 8)),
-                       dim3(kBlock), 0, s, b, n_items);
+    hipLaunchKernelGGL(batch_sample_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 4)), dim3(kBlock), 0,
+                       s, b, n_tiles);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_items, bool small, hipStream_t s) {
-  if (small)
-    hipLaunchKernelGGL((batch_tiles_kernel<true, kSmallTilePix>), dim3(persistent_grid(n_items, 4)),
-                       dim3(kBlock), 0, s, b, n_items);
-  else
-    hipLaunchKernelGGL((batch_tiles_kernel<true, kMaxTilePix>), dim3(persistent_grid(n_items, 2)),
-                       dim3(kBlock), 0, s, b, n_items);
+hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
+                              hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  hipError_t e = launch_scan(b.plan, b.plan, 2 * (int64_t)n_tiles, scratch, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_plan_items_kernel, dim3(grid_for(n_tiles, kBlock)), dim3(kBlock), 0, s, b, n_tiles);
+  const unsigned grid = persistent_grid(2 * n_tiles, small ? 7 : 3);
+  if (small) {
+    hipLaunchKernelGGL(batch_place_kernel<kSmallTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+    hipLaunchKernelGGL(batch_walk_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 4)), dim3(kBlock), 0,
+                       s, b);
+  } else {
+    hipLaunchKernelGGL(batch_place_kernel<kMaxTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+    hipLaunchKernelGGL(batch_walk_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 2)), dim3(kBlock), 0,
+                       s, b);
+  }
   return hipGetLastError();
 }
 
