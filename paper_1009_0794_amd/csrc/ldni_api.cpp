@@ -522,8 +522,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   uint32_t* tile_cnt_all = reinterpret_cast<uint32_t*>(ws + o_tcnt);
   uint32_t* tile_cur_all = reinterpret_cast<uint32_t*>(ws + o_tcur);
   STEP(launch_fill_u32(status, 0u, n_clear, stream), "fill");
+  // setup also counts every triangle's tiles
   STEP(timed("setup", stream, [&] { return launch_setup(ms, set, stream); }), "setup kernel");
-  STEP(timed("bin_count", stream, [&] { return launch_bin_count(set, stream); }), "bin count kernel");
   // one scan over the tile counts of all images: the images' lists follow
   // each other in one array
   STEP(timed("scan_tiles", stream, [&] {
@@ -947,10 +947,9 @@ hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   Q(launch_fill_u32(b->max_layers, 0u, b->n_img, s));
   Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)b->total_tiles + 1, s));
   Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
-  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));
-  Q(launch_batch_bin(b->dev, false, b->bin_block_start.back(), s));
+  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles
   Q(launch_scan(b->tile_arena, b->tile_arena, (int64_t)b->total_tiles, b->scan_scratch, b->dev.status, s));
-  Q(launch_batch_bin(b->dev, true, b->bin_block_start.back(), s));
+  Q(launch_batch_scatter(b->dev, b->bin_block_start.back(), s));
   Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, b->small, s));
   Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
                             b->scan_scratch, s));

@@ -100,8 +100,9 @@ struct MeshSetup {
 
 // ---- launchers (ldni_kernels.hip) ----
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+// per triangle: gather, validate, normal, candidate rectangles, and the
+// count of its tiles on every image (tile_cnt, cleared before)
 hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s);
-hipError_t launch_bin_count(const ImageSet& set, hipStream_t s);
 hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
 // Sampling pass: per-pixel counts, and every hit staged by tile (see Image).
 hipError_t launch_sample(const ImageSet& set, hipStream_t s);
@@ -156,7 +157,7 @@ struct BatchDevice {
 };
 
 hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s);
-hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks, hipStream_t s);
+hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t blocks, hipStream_t s);
 // small: every image's tiles have at most 256 pixels.  n_tiles: tiles of
 // the batch.  Sampling pass (counts, staged hits, place plan), then after the
 // pixel scan and the placement of the images: the place items, the place

@@ -151,12 +151,23 @@ __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-template <class ImageAt>
+template <bool kScatter>
+__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r);
+
+// kCount: also count the triangle's tiles on every image (all 64 lanes of
+// every wave must then call this; lanes past the mesh count nothing).
+template <bool kCount, class ImageAt>
 __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
-  if (t >= m.n_tris) return;
-  const int32_t ia = m.tris[3 * t], ib = m.tris[3 * t + 1], ic = m.tris[3 * t + 2];
+  const bool live = t < m.n_tris;
+  if (!kCount && !live) return;
+  int32_t ia = 0, ib = 0, ic = 0;
+  if (live) {
+    ia = m.tris[3 * t];
+    ib = m.tris[3 * t + 1];
+    ic = m.tris[3 * t + 2];
+  }
   float P[9];
-  const bool idx_ok = ia >= 0 && ia < m.n_verts && ib >= 0 && ib < m.n_verts && ic >= 0 &&
+  const bool idx_ok = live && ia >= 0 && ia < m.n_verts && ib >= 0 && ib < m.n_verts && ic >= 0 &&
                       ic < m.n_verts;
   bool ok = idx_ok;
   if (idx_ok) {
@@ -173,7 +184,7 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
       atomicOr(m.status, kStatusNonFinite);
       ok = false;
     }
-  } else {
+  } else if (live) {
     atomicOr(m.status, kStatusBadIndex);
   }
   if (!ok) {
@@ -181,9 +192,11 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
 #pragma unroll
     for (int c = 0; c < 9; ++c) P[c] = 0.0f;
   }
-  float* soup = m.soup + 9 * t;
+  if (live) {
+    float* soup = m.soup + 9 * t;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) soup[c] = P[c];
+    for (int c = 0; c < 9; ++c) soup[c] = P[c];
+  }
 
   // unit face normal (B-A)x(C-A) in float64
   const double e1x = (double)P[3] - (double)P[0], e1y = (double)P[4] - (double)P[1],
@@ -194,13 +207,15 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
   const double ny = e1z * e2x - e1x * e2z;
   const double nz = e1x * e2y - e1y * e2x;
   const double len = sqrt((nx * nx + ny * ny) + nz * nz);
-  float* tn = m.tnorm + 3 * t;
-  if (len > 0.0) {
-    tn[0] = (float)(nx / len);
-    tn[1] = (float)(ny / len);
-    tn[2] = (float)(nz / len);
-  } else {
-    tn[0] = tn[1] = tn[2] = 0.0f;
+  if (live) {
+    float* tn = m.tnorm + 3 * t;
+    if (len > 0.0) {
+      tn[0] = (float)(nx / len);
+      tn[1] = (float)(ny / len);
+      tn[2] = (float)(nz / len);
+    } else {
+      tn[0] = tn[1] = tn[2] = 0.0f;
+    }
   }
 
   for (int k = 0; k < nimg; ++k) {
@@ -219,13 +234,14 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
     } else {
       r.i0 = r.i1 = r.j0 = r.j1 = 0;
     }
-    m.rect[k][t] = r;
+    if (live) m.rect[k][t] = r;
+    if (kCount) bin_rect<false>(im, t, live, r);
   }
 }
 
 __global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set) {
-  setup_triangle(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
-                 (int64_t)blockIdx.x * kBlock + threadIdx.x);
+  setup_triangle<true>(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
+                       (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,17 +253,14 @@ __global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set
 // coherent for most meshes, so a wave typically touches a handful of tiles.
 // All 64 lanes of every wave must call this (t beyond the mesh = no tiles).
 template <bool kScatter>
-__device__ void bin_triangles(const Image& im, int64_t t) {
+__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
   const int lane = threadIdx.x & 63;
   int tx0 = 0, ty0 = 0, nx = 1, n = 0;
-  if (t < im.n_tris) {
-    const Rect r = im.rect[t];
-    if (r.i0 < r.i1 && r.j0 < r.j1) {
-      tx0 = r.i0 / im.tw;
-      ty0 = r.j0 / im.th;
-      nx = (r.i1 - 1) / im.tw - tx0 + 1;
-      n = nx * ((r.j1 - 1) / im.th - ty0 + 1);
-    }
+  if (live && r.i0 < r.i1 && r.j0 < r.j1) {
+    tx0 = r.i0 / im.tw;
+    ty0 = r.j0 / im.th;
+    nx = (r.i1 - 1) / im.tw - tx0 + 1;
+    n = nx * ((r.j1 - 1) / im.th - ty0 + 1);
   }
   int nmax = n;
 #pragma unroll
@@ -290,6 +303,14 @@ __device__ void bin_triangles(const Image& im, int64_t t) {
       }
     }
   }
+}
+
+template <bool kScatter>
+__device__ void bin_triangles(const Image& im, int64_t t) {
+  const bool live = t < im.n_tris;
+  Rect r{0, 0, 0, 0};
+  if (live) r = im.rect[t];
+  bin_rect<kScatter>(im, t, live, r);
 }
 
 template <bool kScatter>
@@ -338,10 +359,9 @@ __device__ __forceinline__ bool covered(float au, float bu, float cu, float tav,
   e.ab = fma(dau, dbv, -(dav * dbu));
   e.bc = fma(dbu, dcv, -(dbv * dcu));
   e.ca = fma(dcu, dav, -(dcv * dau));
-  const bool pos = (e.ab > 0.0) & (e.bc > 0.0) & (e.ca > 0.0);
-  const bool neg = (e.ab < 0.0) & (e.bc < 0.0) & (e.ca < 0.0);
-  if (pos | neg) return true;
-  if ((e.ab != 0.0) & (e.bc != 0.0) & (e.ca != 0.0)) return false;
+  const double mn = fmin(fmin(e.ab, e.bc), e.ca), mx = fmax(fmax(e.ab, e.bc), e.ca);
+  if ((mn > 0.0) | (mx < 0.0)) return true;   // one strict sign
+  if ((mn < 0.0) & (mx > 0.0)) return false;  // two strictly opposite signs: no tie can help
   // the ray meets an edge line: decide as if moved to (+eps, +eps^2)
   double tmp;
   const int s0 = orient(tau, tav, tbu, tbv, tmp);
@@ -734,8 +754,9 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   }
 }
 
+// (at most 72 VGPRs: seven workgroups per CU)
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) sample_kernel(ImageSet set) {
+__global__ void __launch_bounds__(kBlock, kTilePix <= kSmallTilePix ? 7 : 4) sample_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
   sample_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x, set.plan,
                         set.tile_start[set.n], set.place_cap);
@@ -1449,7 +1470,7 @@ __global__ void __launch_bounds__(kBlock) batch_setup_kernel(BatchDevice B) {
   const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
   const BatchMesh& bm = B.meshes[mi];
   const int64_t t = (int64_t)(blockIdx.x - B.tri_block_start[mi]) * kBlock + threadIdx.x;
-  setup_triangle(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
+  setup_triangle<true>(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
 }
 
 template <bool kScatter>
@@ -1470,7 +1491,7 @@ struct ItemGrabber {
     if (left == 0) {
       if (threadIdx.x == 0) *s_item = atomicAdd(counter, kGrab);
       __syncthreads();
-      next = *s_item;
+      next = __builtin_amdgcn_readfirstlane(*s_item);  // uniform: scalar table loads
       __syncthreads();
       left = kGrab;
     }
@@ -1486,7 +1507,7 @@ __global__ void __launch_bounds__(kBlock) batch_sample_kernel(BatchDevice B, uin
   for (;;) {
     const uint32_t item = grab(&B.work[0], &s_item);
     if (item >= n_tiles) break;
-    const int k = segment_of(B.tile_start, B.n_images, item);
+    const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, item));
     sample_tile<kTilePix>(B.images[k], (int)(item - B.tile_start[k]), item, B.plan, n_tiles, B.place_cap);
   }
 }
@@ -1524,7 +1545,7 @@ __global__ void __launch_bounds__(kBlock) batch_place_kernel(BatchDevice B, uint
     const uint32_t item = grab(&B.work[1], &s_item);
     if (item >= n_items) break;
     const PlaceItem it = items[item];
-    const int k = segment_of(B.tile_start, B.n_images, it.gtile);
+    const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, it.gtile));
     const Image& im = B.images[k];
     if (im.depth == nullptr) continue;  // the image did not fit the output arena
     place_tile<kTilePix>(im, (int)(it.gtile - B.tile_start[k]), it.first, it.hits,
@@ -1541,7 +1562,7 @@ __global__ void __launch_bounds__(kBlock) batch_walk_kernel(BatchDevice B) {
     const uint32_t item = grab(&B.work[2], &s_item);
     if (item >= n) break;
     const uint32_t gt = B.walk_list[item];
-    const int k = segment_of(B.tile_start, B.n_images, gt);
+    const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, gt));
     const Image& im = B.images[k];
     if (im.depth == nullptr) continue;
     write_tile<kTilePix>(im, (int)(gt - B.tile_start[k]));
@@ -1655,13 +1676,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s) {
   if (m.n_tris <= 0) return hipSuccess;
   hipLaunchKernelGGL(setup_kernel, dim3(grid_for(m.n_tris, kBlock)), dim3(kBlock), 0, s, m, set);
-  return hipGetLastError();
-}
-
-hipError_t launch_bin_count(const ImageSet& set, hipStream_t s) {
-  if (set.n == 0 || set.img[0].n_tris <= 0) return hipSuccess;
-  dim3 grid(grid_for(set.img[0].n_tris, kBlock), set.n);
-  hipLaunchKernelGGL(bin_kernel<false>, grid, dim3(kBlock), 0, s, set);
   return hipGetLastError();
 }
 
@@ -1783,10 +1797,9 @@ hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_batch_bin(const BatchDevice& b, bool scatter, uint32_t blocks, hipStream_t s) {
+hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t blocks, hipStream_t s) {
   if (blocks == 0) return hipSuccess;
-  if (scatter) hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, b);
-  else hipLaunchKernelGGL(batch_bin_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, b);
+  hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, b);
   return hipGetLastError();
 }
 
