@@ -60,29 +60,33 @@ struct StageKey {
            mask == o.mask;
   }
 };
+struct StageSeen {
+  uint64_t demand;      // staging entries asked for
+  uint32_t max_layers;  // deepest pixel
+};
 std::mutex g_stage_mu;
-std::vector<std::pair<StageKey, uint64_t>> g_stage_demand;  // most recent last
-constexpr size_t kStageMemory = 64;
+std::vector<std::pair<StageKey, StageSeen>> g_stage_seen;  // most recent last
+constexpr size_t kStageMemory = 1024;
 
-bool stage_demand_lookup(const StageKey& k, uint64_t* demand) {
+bool stage_seen_lookup(const StageKey& k, StageSeen* seen) {
   std::lock_guard<std::mutex> lk(g_stage_mu);
-  for (auto& e : g_stage_demand)
-    if (e.first == k) {
-      *demand = e.second;
+  for (size_t i = g_stage_seen.size(); i-- > 0;)
+    if (g_stage_seen[i].first == k) {
+      *seen = g_stage_seen[i].second;
       return true;
     }
   return false;
 }
 
-void stage_demand_record(const StageKey& k, uint64_t demand) {
+void stage_seen_record(const StageKey& k, StageSeen seen) {
   std::lock_guard<std::mutex> lk(g_stage_mu);
-  for (size_t i = 0; i < g_stage_demand.size(); ++i)
-    if (g_stage_demand[i].first == k) {
-      g_stage_demand.erase(g_stage_demand.begin() + i);
+  for (size_t i = 0; i < g_stage_seen.size(); ++i)
+    if (g_stage_seen[i].first == k) {
+      g_stage_seen.erase(g_stage_seen.begin() + i);
       break;
     }
-  if (g_stage_demand.size() >= kStageMemory) g_stage_demand.erase(g_stage_demand.begin());
-  g_stage_demand.emplace_back(k, demand);
+  if (g_stage_seen.size() >= kStageMemory) g_stage_seen.erase(g_stage_seen.begin());
+  g_stage_seen.emplace_back(k, seen);
 }
 
 ldni_status fail(ldni_status s, const std::string& msg) {
@@ -383,6 +387,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   const int64_t n_tiles = (int64_t)ntx * nty;
   const int64_t npix = (int64_t)w * w;
 
+  // what the last call of this shape needed (staging entries, deepest pixel)
+  const StageKey stage_key{n_verts, n_tris, w, tw, th, axis_mask};
+  StageSeen seen{0, 0};
+  const bool have_seen = stage_seen_lookup(stage_key, &seen);
+  const uint32_t stage_layers = stage_layers_for(seen.max_layers);
+
   // ---- workspace layout ----
   int nimg = 0;
   for (int a = 0; a < 3; ++a)
@@ -407,7 +417,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   }
   const size_t o_walk = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_all);
   const size_t o_items = off;
-  off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th) * (size_t)n_all);
+  off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th, stage_layers) * (size_t)n_all);
   const size_t o_plan = off; off = align_up(off + sizeof(uint32_t) * (size_t)(2 * n_all + 1));
   const size_t o_scan = off;
   off = align_up(off + std::max(scan_scratch_bytes(npix, nimg), scan_scratch_bytes(2 * n_all, 1)));
@@ -476,17 +486,14 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   }
   // Staging buffer for the hits of the sampling pass: what the last call of
   // the same shape asked for, else a first guess (24 entries per triangle
-  // plus one per pixel).  A tile that finds no room is walked again by the
+  // plus four per pixel).  A tile that finds no room is walked again by the
   // write pass, so a short buffer costs time, never results.  Never more than
-  // kStageLayers (64) entries per pixel, which is all the tiles can ask for.
-  const StageKey stage_key{n_verts, n_tris, w, tw, th, axis_mask};
+  // stage_layers entries per pixel, which is all the tiles can ask for.
   {
     const double px = (double)npix * nimg;
-    uint64_t last = 0;
-    const double want = stage_demand_lookup(stage_key, &last)
-                            ? (double)last * 1.1 + 65536.0
-                            : 24.0 * (double)n_tris + px + 65536.0;
-    const double most = std::min(64.0 * px + 65536.0, (double)kMaxStageEntries);
+    const double want = have_seen ? (double)seen.demand * 1.1 + 65536.0
+                                  : 24.0 * (double)n_tris + 4.0 * px + 65536.0;
+    const double most = std::min((double)stage_layers * px + 65536.0, (double)kMaxStageEntries);
     uint64_t stage_cap = (uint64_t)std::min(want, most);
     // test hook: a smaller buffer (0: none) forces tiles onto the walk path
     if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
@@ -501,6 +508,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
       im.stage_qs = p->stage ? reinterpret_cast<uint32_t*>(static_cast<uint64_t*>(p->stage) + stage_cap)
                              : nullptr;
       im.stage_cap = p->stage ? stage_cap : 0;
+      im.stage_layers = stage_layers;
     }
   }
   void* scan_scratch = ws + o_scan;
@@ -587,7 +595,9 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     const uint64_t need = rb[rb_more];
     {
       const uint64_t demand = (uint64_t)rb[rb_more + 1] | ((uint64_t)rb[rb_more + 2] << 32);
-      stage_demand_record(stage_key, demand);
+      uint32_t ml = 0;
+      for (int k = 0; k < nimg; ++k) ml = std::max(ml, rb[1 + k]);
+      stage_seen_record(stage_key, StageSeen{demand, ml});
       p->n_walk = rb[rb_more + 3];
       p->n_items = rb[rb_more + 4];
     }
@@ -874,6 +884,9 @@ struct ldni_batch {
   uint64_t sample_cap = 0;
   void* stage = nullptr;  // hits staged by the sampling pass
   uint64_t stage_cap = 0;
+  uint32_t stage_layers = 64;  // staging entries per tile pixel (grows with the deepest pixel)
+  void* items = nullptr;  // place items, sized for stage_layers
+  uint64_t items_cap = 0;
   bool small = true;      // every image's tiles have at most 256 pixels
   uint32_t* host_out = nullptr;
   BatchDevice dev{};
@@ -908,6 +921,7 @@ void batch_destroy(ldni_batch* b) {
   if (b->cs) (void)hipStreamSynchronize(b->cs);
   if (b->samples) (void)hipFree(b->samples);
   if (b->stage) (void)hipFree(b->stage);
+  if (b->items) (void)hipFree(b->items);
   if (b->lists) (void)hipFree(b->lists);
   if (b->ws) (void)hipFree(b->ws);
   if (b->host_out) (void)hipHostFree(b->host_out);
@@ -933,7 +947,9 @@ hipError_t batch_upload(ldni_batch* b) {
     im.stage_qs = b->stage ? reinterpret_cast<uint32_t*>(static_cast<uint64_t*>(b->stage) + b->stage_cap)
                            : nullptr;
     im.stage_cap = b->stage ? b->stage_cap : 0;
+    im.stage_layers = b->stage_layers;
   }
+  b->dev.items = b->items;
   hipError_t e = hipMemcpy(b->dev.images, b->images_h.data(), sizeof(Image) * b->n_img, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   return hipMemcpy(b->dev.meshes, b->meshes_h.data(), sizeof(BatchMesh) * b->n_meshes, hipMemcpyHostToDevice);
@@ -1036,7 +1052,26 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
       continue;
     }
     // Tiles that found no room in the staging buffer were walked again, so
-    // the results stand; the buffer grows for the next run.
+    // the results stand; the buffer and the per-pixel cap grow for the next run.
+    uint32_t ml = 0;
+    for (int k = 0; k < b->n_img; ++k) ml = std::max(ml, b->ml[k]);
+    const uint32_t layers = stage_layers_for(ml);
+    if (layers > b->stage_layers) {
+      // a larger item buffer first; without one the batch keeps its cap
+      const uint64_t need_items =
+          (uint64_t)max_place_items_per_tile(b->small ? 256 : 1024, layers) * b->total_tiles;
+      void* grown = nullptr;
+      if (!env_fault("alloc") && hipMalloc(&grown, (size_t)need_items * 16) == hipSuccess) {
+        (void)hipStreamSynchronize(b->cs);
+        (void)hipFree(b->items);
+        b->items = grown;
+        b->items_cap = need_items;
+        b->stage_layers = layers;
+        batch_release_graph(b);
+      } else {
+        (void)hipGetLastError();
+      }
+    }
     const uint32_t* tail = h + 4 + 4 * (size_t)b->n_img;
     // (tile regions start at 32-bit entry indices)
     const uint64_t demand = std::min<uint64_t>((uint64_t)tail[0] | ((uint64_t)tail[1] << 32), kMaxStageEntries);
@@ -1162,7 +1197,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const size_t o_thits = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_walk = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_plan = take(sizeof(uint32_t) * (2 * b->total_tiles + 1));
-  const size_t o_items = take(16 * (size_t)max_place_items_per_tile(tile_pix) * b->total_tiles);
   const size_t o_scan = take(std::max(scan_scratch_bytes(2 * (int64_t)b->total_tiles),
                                       scan_scratch_bytes((int64_t)b->total_slots)));
   e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(&b->ws, off);
@@ -1193,7 +1227,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   b->scan_scratch = ws + o_scan;
   D.tile_total = b->tile_arena + b->total_tiles;
   D.plan = reinterpret_cast<uint32_t*>(ws + o_plan);
-  D.items = ws + o_items;
   D.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
   D.walk_count = D.status + 18;
   D.stage_cursor = reinterpret_cast<unsigned long long*>(D.status + 16);
@@ -1290,6 +1323,10 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
       b->stage_cap = 0;
     }
   }
+  st = batch_grow(b, &b->items, &b->items_cap,
+                  (uint64_t)max_place_items_per_tile(b->small ? 256 : 1024, b->stage_layers) * b->total_tiles,
+                  16);
+  if (st != LDNI_OK) return bail(st);
   st = ldni_batch_run(b, hip_stream);
   if (st != LDNI_OK) return bail(st);
   *out = b;

@@ -60,6 +60,7 @@ struct Image {
   uint32_t* stage_qs;                // tile pixel | (slot within the pixel << 10)
   unsigned long long* stage_cursor;  // bump allocator over the buffer (shared by the set)
   uint64_t stage_cap;                // entries in the buffer
+  uint32_t stage_layers;             // a tile reserves at most this many entries per pixel
   uint32_t* tile_stage;              // [n_tiles] first entry of the tile's hits (a multiple
                                      // of 4; regions are whole 4-entry groups), or kNoStage
   uint32_t* tile_hits;               // [n_tiles] hits of the tile
@@ -108,8 +109,11 @@ hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
 hipError_t launch_sample(const ImageSet& set, hipStream_t s);
 // Work items of the place pass: scans the plan the sampling pass wrote and
 // writes the item records (16 bytes each, at most
-// max_place_items_per_tile(tw * th) per tile) in launch order.
-int max_place_items_per_tile(int tile_pix);
+// max_place_items_per_tile(tw * th, stage_layers) per tile) in launch order.
+int max_place_items_per_tile(int tile_pix, uint32_t stage_layers);
+// Entries per pixel a tile may reserve in the staging buffer: the deepest
+// pixel seen, rounded up to a power of two, within [64, 1024].
+uint32_t stage_layers_for(uint32_t max_layers_seen);
 int place_stage_cap(int tile_pix);
 hipError_t launch_plan_items(const ImageSet& set, void* items, void* scratch, uint32_t* status,
                              hipStream_t s);

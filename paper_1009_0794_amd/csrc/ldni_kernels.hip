@@ -496,10 +496,10 @@ __device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, fl
 // ---------------------------------------------------------------------------
 // sampling pass: count and stage every hit
 // ---------------------------------------------------------------------------
-// A tile's staging region holds at most this many hits per tile pixel (and
-// never more than the tile's candidates); a tile with more hits than its
+// A tile's staging region holds at most im.stage_layers hits per tile pixel
+// (and never more than the tile's candidates); a tile with more hits than its
 // region is walked again by the write pass.
-constexpr int kStageLayers = 64;
+constexpr uint32_t kMinStageLayers = 64, kMaxStageLayers = 1024;
 
 // Hits found by a wave in one window of its walk, waiting for their depth.
 constexpr int kMaxRun = 16;                 // candidates per thread per window
@@ -548,9 +548,9 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
 
   // Reserve the tile's region: its candidate count (rounded up to whole
   // 4-entry groups so the write pass can read 16-byte vectors), capped at
-  // kStageLayers per pixel.  One chunk of entries: its count comes with the
+  // stage_layers per pixel.  One chunk of entries: its count comes with the
   // chunk; more: the entries are counted first.
-  const uint32_t region_max = (uint32_t)(kStageLayers * npix);
+  const uint32_t region_max = im.stage_layers * (uint32_t)npix;
   auto reserve = [&](uint32_t cand) {
     uint32_t size = min((min(cand, region_max) + 3u) & ~3u, region_max);
     uint64_t base = 0;
@@ -962,7 +962,7 @@ __device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 
 // K = ceil(S / stage) items; tiles without hits or walked again get none.
 // The sampling pass writes K to the plan ([0, n) for K >= 2, [n, 2n) for
 // K = 1), so after one scan of the plan the long tiles come first.
-// K <= kStageLayers * tile pixels / stage.
+// K <= stage_layers * tile pixels / stage.
 // One work item of the place pass.
 struct PlaceItem {
   uint32_t gtile;       // set-wide tile number
@@ -1706,9 +1706,15 @@ int place_stage_cap(int tile_pix) {
   return stage_cap(tile_pix <= kSmallTilePix ? kSmallTilePix : kMaxTilePix);
 }
 
-int max_place_items_per_tile(int tile_pix) {
+int max_place_items_per_tile(int tile_pix, uint32_t stage_layers) {
   const int pix = tile_pix <= kSmallTilePix ? kSmallTilePix : kMaxTilePix;
-  return (kStageLayers * pix + stage_cap(pix) - 1) / stage_cap(pix);
+  return (int)(((uint64_t)stage_layers * pix + stage_cap(pix) - 1) / stage_cap(pix));
+}
+
+uint32_t stage_layers_for(uint32_t max_layers_seen) {
+  uint32_t l = kMinStageLayers;
+  while (l < max_layers_seen && l < kMaxStageLayers) l <<= 1;
+  return l;
 }
 
 hipError_t launch_plan_items(const ImageSet& set, void* items, void* scratch, uint32_t* status,

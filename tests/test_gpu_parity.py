@@ -286,3 +286,20 @@ def test_buffers_reused_across_calls_and_results_kept_alive():
         torch.cuda.synchronize()
         compare(got, ref, bb, label="kept result")
         r.free()
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
+def test_staging_cap_follows_the_deepest_pixel(tile):
+    """A stack of 150 thin boxes (300 faces on the rays through it): more hits
+    per pixel than the first call's staging cap, so its tiles are walked
+    again; later calls of the same shape raise the cap to the deepest pixel
+    seen and stage them.  Every call gives the oracle's result."""
+    ldni.set_tile_shape(*tile)
+    parts = [mg.box_mesh((1.1, 1.3, 0.5 + 0.04 * k), (6.7, 6.1, 0.5 + 0.04 * k + 0.02))
+             for k in range(150)]
+    v, f = mg.concat(parts)
+    w = 48
+    ref = oracle.sample(v, f, BOX8, w)
+    assert int(np.diff(ref[2].offsets.astype(np.int64)).max()) == 300
+    for call in range(3):
+        compare(_run(v, f, BOX8, w), ref, BOX8, label=f"call {call}")
