@@ -498,6 +498,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     // test hook: a smaller buffer (0: none) forces tiles onto the walk path
     if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
       stage_cap = std::min<uint64_t>(stage_cap, std::strtoull(env, nullptr, 10));
+    stage_cap &= ~(uint64_t)3;  // whole 4-entry groups: 16-byte aligned pixel/slot words
     if (stage_cap == 0 ||
         cache_get(&p->stage, stage_cap * (sizeof(uint64_t) + sizeof(uint32_t)), stream, &p->stage_bytes) !=
             hipSuccess)
@@ -992,7 +993,7 @@ hipError_t batch_capture(ldni_batch* b) {
 }
 
 ldni_status batch_grow(ldni_batch* b, void** buf, uint64_t* cap, uint64_t need, size_t bytes_per) {
-  const uint64_t c = need + need / 16 + 1024;
+  const uint64_t c = (need + need / 16 + 1024) & ~(uint64_t)3;  // whole 4-entry groups
   if (*buf) (void)hipFree(*buf);
   *buf = nullptr;
   hipError_t e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(buf, (size_t)c * bytes_per);

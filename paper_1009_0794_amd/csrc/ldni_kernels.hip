@@ -1065,22 +1065,37 @@ __device__ void place_tile(const Image& im, int tile, uint32_t first, uint32_t h
     const uint32_t run_base = s_pre[q0];
     const int run_total = (int)(s_pre[q1] - run_base);
     if (run_total > 0 && run % parts == part) {
-      // four entries per thread per step (one 16-byte load; regions are
-      // whole 4-entry groups), keys read only for the run's pixels
-      for (uint32_t i0 = 4 * threadIdx.x; i0 < hits; i0 += 4 * kBlock) {
-        const uint4 x4 = *reinterpret_cast<const uint4*>(qs + i0);
-        const uint32_t xs[4] = {x4.x, x4.y, x4.z, x4.w};
+      // Eight entries per thread per step: two 16-byte loads (regions are
+      // whole 4-entry groups) issued together, then the keys of the run's
+      // entries, also together, so a step costs two round trips.
+      for (uint32_t b0 = 0; b0 < hits; b0 += 8 * kBlock) {
+        uint32_t xs[8];
+        uint64_t ks[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (i0 + u >= hits) break;
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t i0 = b0 + 4 * (h * kBlock + threadIdx.x);
+          uint4 x4 = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+          if (i0 < hits) x4 = *reinterpret_cast<const uint4*>(qs + i0);
+          xs[4 * h] = x4.x; xs[4 * h + 1] = x4.y; xs[4 * h + 2] = x4.z; xs[4 * h + 3] = x4.w;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t i = b0 + 4 * ((u >> 2) * kBlock + threadIdx.x) + (u & 3);
+          const int q = (int)(xs[u] & 1023u);
+          const bool mine = i < hits && q >= q0 && q < q1;
+          ks[u] = mine ? keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t i = b0 + 4 * ((u >> 2) * kBlock + threadIdx.x) + (u & 3);
           const int q = (int)(xs[u] & 1023u);
           const uint32_t slot = xs[u] >> 10;
-          if (q < q0 || q >= q1) continue;
+          if (i >= hits || q < q0 || q >= q1) continue;
           if (slot >= s_pre[q + 1] - s_pre[q]) {
             atomicOr(im.status, kStatusMismatch);
             continue;
           }
-          const uint64_t key = keys[i0 + u];
+          const uint64_t key = ks[u];
           if (!direct) {
             const uint32_t at = s_pre[q] - run_base + slot;
             s_keys[at] = key;
