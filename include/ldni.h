@@ -127,7 +127,8 @@ ldni_status ldni_trim(void);
  * caller-owned outputs, split at the point where the sample counts become
  * known.
  *   offsets   device u32 [w*w+1] per axis in the mask (entries of other axes
- *             are ignored and may be NULL); filled by begin.
+ *             are ignored and may be NULL), 16-byte aligned (written with
+ *             16-byte stores; LDNI_ERR_INVALID_ARG otherwise); filled by begin.
  *   n_samples HOST u64 [3]; begin writes the count of every axis (0 for
  *             axes not in the mask).
  *   plan      receives the state that finish needs (workspace on the device).

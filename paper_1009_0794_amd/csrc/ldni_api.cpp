@@ -363,8 +363,11 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   ldni_status st = validate(verts, n_verts, tris, n_tris, bbox, w, axis_mask);
   if (st != LDNI_OK) return st;
   for (int a = 0; a < 3; ++a)
-    if ((axis_mask >> a) & 1u)
+    if ((axis_mask >> a) & 1u) {
       if (!offsets[a]) return fail(LDNI_ERR_INVALID_ARG, "NULL offsets buffer for a requested axis");
+      if (reinterpret_cast<uintptr_t>(offsets[a]) % 16 != 0)
+        return fail(LDNI_ERR_INVALID_ARG, "offsets buffer not 16-byte aligned");
+    }
   for (int a = 0; a < 3; ++a) n_samples[a] = 0;
   const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
 

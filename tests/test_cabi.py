@@ -143,3 +143,15 @@ def test_trim_with_nothing_cached(L):
     """ldni_trim releases the buffers kept between calls; with none kept it
     touches no device."""
     assert L.ldni_trim() == 0
+
+
+def test_begin_rejects_misaligned_offsets(L):
+    """Offsets are written with 16-byte stores: a buffer that is not 16-byte
+    aligned is refused before any device work."""
+    bb = (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1)
+    offs = (ctypes.c_void_p * 3)(0x1000 + 4, None, None)
+    plan = ctypes.c_void_p(7)
+    n = (ctypes.c_uint64 * 3)()
+    assert L.ldni_sample_begin(0x2000, 3, 0x3000, 1, bb, 8, 1, offs, None, ctypes.byref(plan), n) == 1
+    assert "aligned" in L.ldni_last_error().decode()
+    assert plan.value is None
