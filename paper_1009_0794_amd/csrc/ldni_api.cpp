@@ -596,6 +596,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     STEP(hipStreamSynchronize(stream), "synchronise");
     if (rb[0] & kStatusBadIndex) return bail(fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)"));
     if (rb[0] & kStatusNonFinite) return bail(fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate"));
+    if (rb[0] & kStatusMismatch) return bail(fail(LDNI_ERR_DEVICE, "tile lists disagree with their counts"));
     const uint64_t need = rb[rb_more];
     {
       const uint64_t demand = (uint64_t)rb[rb_more + 1] | ((uint64_t)rb[rb_more + 2] << 32);
@@ -1027,6 +1028,7 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
     const uint32_t* h = b->host_out;
     if (h[0] & kStatusBadIndex) return fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)");
     if (h[0] & kStatusNonFinite) return fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate");
+    if (h[0] & kStatusMismatch) return fail(LDNI_ERR_DEVICE, "tile lists disagree with their counts");
     bool regrow = false;
     const uint64_t entries = h[1];
     if (entries > b->list_cap) {

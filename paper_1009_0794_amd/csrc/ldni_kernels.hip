@@ -370,6 +370,15 @@ __device__ __forceinline__ bool covered(float au, float bu, float cu, float tav,
   return (s0 != 0) & (s0 == s1) & (s1 == s2);
 }
 
+// Rectangle of a tile-list entry; an entry that is not a triangle of the
+// mesh (the lists were not written as counted) raises the mismatch bit and
+// has no candidates.
+__device__ __forceinline__ Rect entry_rect(const Image& im, int32_t t) {
+  if ((uint32_t)t < (uint64_t)im.n_tris) return im.rect[t];
+  atomicOr(im.status, kStatusMismatch);
+  return Rect{0, 0, 0, 0};
+}
+
 struct NoChunkHook {
   __device__ void operator()(bool, int) const {}
 };
@@ -392,7 +401,7 @@ __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int 
     int nc = 0;
     if (k < m) {
       const int32_t t = im.tile_list[base + k];
-      const Rect r = im.rect[t];
+      const Rect r = entry_rect(im, t);
       const int px0 = max((int)r.i0, g.x0) - g.x0, px1 = min((int)r.i1, g.x0 + g.cw) - g.x0;
       const int py0 = max((int)r.j0, ya) - g.y0, py1 = min((int)r.j1, yb) - g.y0;
       int width = 1;
@@ -576,7 +585,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
     // clamped per thread so the sum fits 32 bits
     uint32_t cand = 0;
     for (uint32_t e = e_begin + threadIdx.x; e < e_end; e += kBlock) {
-      const Rect r = im.rect[im.tile_list[e]];
+      const Rect r = entry_rect(im, im.tile_list[e]);
       const int nx = min((int)r.i1, g.x0 + g.cw) - max((int)r.i0, g.x0);
       const int ny = min((int)r.j1, g.y0 + g.ch) - max((int)r.j0, g.y0);
       if (nx > 0 && ny > 0) cand = min(cand + (uint32_t)(nx * ny), region_max);
@@ -598,7 +607,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
       int nc = 0;
       if (k < m) {
         const int32_t t = im.tile_list[cbase + k];
-        const Rect r = im.rect[t];
+        const Rect r = entry_rect(im, t);
         const int px0 = max((int)r.i0, g.x0) - g.x0, px1 = min((int)r.i1, g.x0 + g.cw) - g.x0;
         const int py0 = max((int)r.j0, g.y0) - g.y0, py1 = min((int)r.j1, g.y0 + g.ch) - g.y0;
         int width = 1;
