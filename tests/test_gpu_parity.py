@@ -303,3 +303,41 @@ def test_staging_cap_follows_the_deepest_pixel(tile):
     assert int(np.diff(ref[2].offsets.astype(np.int64)).max()) == 300
     for call in range(3):
         compare(_run(v, f, BOX8, w), ref, BOX8, label=f"call {call}")
+
+
+def test_maximum_resolution_rows_sampled():
+    """w = 16384, the largest resolution: the icosphere along z, with the
+    oracle recomputing a band of rows through the centre and one near the
+    edge of the sphere."""
+    m = mg.c1_icosphere()
+    w = 16384
+    vt = torch.from_numpy(m.verts).to(DEV)
+    ft = torch.from_numpy(m.tris).to(DEV)
+    got = ldni.sample(vt, ft, m.bbox, w, "z")[2]
+    torch.cuda.synchronize()
+    for j0, j1 in ((8190, 8194), (1500, 1502)):
+        off = got.offsets[j0 * w:j1 * w + 1].cpu().numpy().view(np.uint32).astype(np.int64)
+        s0, s1 = int(off[0]), int(off[-1])
+        r = oracle.sample(m.verts, m.tris, m.bbox, w, axes="z", window=(0, w, j0, j1))[2]
+        rc = np.diff(r.offsets.astype(np.int64))[j0 * w:j1 * w]
+        assert np.array_equal(np.diff(off), rc)
+        assert np.array_equal(got.tri[s0:s1].cpu().numpy(), r.tri)
+        assert np.array_equal(got.depth[s0:s1].cpu().numpy().view(np.uint32), r.depth.view(np.uint32))
+        assert np.array_equal(got.normal[s0:s1].cpu().numpy().view(np.uint32), r.normal.view(np.uint32))
+    assert got.max_layers == 2
+
+
+def test_samples_beyond_32_bits_rejected():
+    """A stack of 2,100 boxes covering the whole image: 4,200 samples on each
+    of the 1,048,576 rays along z, 4.4 x 10^9 in all, more than the u32
+    offsets hold.  The call fails with LDNI_ERR_OVERFLOW and the library
+    keeps working."""
+    parts = [mg.box_mesh((0.01, 0.01, 0.5 + 0.003 * k), (7.99, 7.99, 0.5 + 0.003 * k + 0.0015))
+             for k in range(2100)]
+    v, f = mg.concat(parts)
+    with pytest.raises(ldni.LDNIError) as e:
+        _run(v, f, BOX8, 1024, "z")
+    assert e.value.code == 4
+    m = mg.c1_icosphere()
+    compare(_run(m.verts, m.tris, m.bbox, m.w), oracle.sample(m.verts, m.tris, m.bbox, m.w), m.bbox,
+            label="after overflow")
