@@ -402,10 +402,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if ((axis_mask >> a) & 1u) p->axis_of[nimg++] = a;
   const int64_t n_all = nimg * n_tiles;  // tiles of all images, numbered image after image
   size_t off = 0;
-  // status words, tile entry counts (all images, then their total) and
-  // scatter cursors are adjacent and cleared by one fill
+  // status words, tile entry counts (all images, then their total), tile
+  // candidate counts (16-byte aligned for the scan) and scatter cursors are
+  // adjacent and cleared by one fill
   const size_t o_status = off; off += 256;
   const size_t o_tcnt = off; off += sizeof(uint32_t) * (size_t)(n_all + 1);
+  const size_t o_treg = (off + 15) & ~(size_t)15; off = o_treg + sizeof(uint32_t) * (size_t)(n_all + 1);
   const size_t o_tcur = off; off += sizeof(uint32_t) * (size_t)n_all;
   const int64_t n_clear = (int64_t)(off / sizeof(uint32_t));
   off = align_up(off);
@@ -423,7 +425,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th, stage_layers) * (size_t)n_all);
   const size_t o_plan = off; off = align_up(off + sizeof(uint32_t) * (size_t)(2 * n_all + 1));
   const size_t o_scan = off;
-  off = align_up(off + std::max(scan_scratch_bytes(npix, nimg), scan_scratch_bytes(2 * n_all, 1)));
+  off = align_up(off + std::max({scan_scratch_bytes(npix, nimg), scan_scratch_bytes(2 * n_all, 1),
+                                  scan_scratch_bytes(n_all, 2)}));
 
   hipError_t e = cache_get(&p->ws, off, stream, &p->ws_bytes);
   if (e != hipSuccess) {
@@ -433,9 +436,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   }
   char* ws = static_cast<char*>(p->ws);
   // [0] status, [1..3] max layers, [12..13] write-pass work counters,
-  // [16..17] staging cursor (u64), [18] tiles to walk again
+  // [18] tiles to walk again
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + o_status);
-  unsigned long long* stage_cursor = reinterpret_cast<unsigned long long*>(status + 16);
   uint32_t* walk_count = status + 18;
 
   MeshSetup ms{};
@@ -475,12 +477,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.n_tris = n_tris;
     im.tile_cnt = reinterpret_cast<uint32_t*>(ws + o_tcnt) + k * n_tiles;
     im.tile_cur = reinterpret_cast<uint32_t*>(ws + o_tcur) + k * n_tiles;
+    im.tile_region = reinterpret_cast<uint32_t*>(ws + o_treg) + k * n_tiles;
     im.tile_list = nullptr;
     im.counts = reinterpret_cast<uint32_t*>(ws + o_counts[k]);
     im.max_layers = status + 1 + k;
     im.offsets = offsets[a];
     im.status = status;
-    im.stage_cursor = stage_cursor;
     im.tile_stage = reinterpret_cast<uint32_t*>(ws + o_tstage[k]);
     im.tile_hits = reinterpret_cast<uint32_t*>(ws + o_thits[k]);
     im.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
@@ -532,14 +534,17 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   } while (0)
 
   uint32_t* tile_cnt_all = reinterpret_cast<uint32_t*>(ws + o_tcnt);
+  uint32_t* tile_region_all = reinterpret_cast<uint32_t*>(ws + o_treg);
   uint32_t* tile_cur_all = reinterpret_cast<uint32_t*>(ws + o_tcur);
   STEP(launch_fill_u32(status, 0u, n_clear, stream), "fill");
-  // setup also counts every triangle's tiles
+  // setup also counts every triangle's tiles and their candidate pixels
   STEP(timed("setup", stream, [&] { return launch_setup(ms, set, stream); }), "setup kernel");
-  // one scan over the tile counts of all images: the images' lists follow
-  // each other in one array
+  // one scan over the tile counts of all images (the images' lists follow
+  // each other in one array), and over their candidate counts (the images'
+  // staging regions follow each other in the staging buffer)
   STEP(timed("scan_tiles", stream, [&] {
-         return launch_scan(tile_cnt_all, tile_cnt_all, n_all, scan_scratch, status, stream);
+         return launch_tile_scan(tile_cnt_all, tile_region_all, n_all, stage_layers * (uint32_t)(tw * th),
+                                 scan_scratch, status, stream);
        }), "tile scan");
   // Tile lists are sized from the largest entries-per-triangle ratio seen so
   // far; the scatter drops entries beyond the capacity and the call is redone
@@ -571,11 +576,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   gather_src[n_gather++] = status + 3;
   for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].offsets + npix;  // rb[4+k]
   const int rb_more = n_gather;
-  gather_src[n_gather++] = tile_cnt_all + n_all;  // list entries
-  gather_src[n_gather++] = status + 16;           // staging demand (u64)
-  gather_src[n_gather++] = status + 17;
-  gather_src[n_gather++] = status + 18;           // tiles to walk again
-  gather_src[n_gather++] = set.plan + 2 * n_all;  // place items
+  gather_src[n_gather++] = tile_cnt_all + n_all;     // list entries
+  gather_src[n_gather++] = tile_region_all + n_all;  // staging demand (saturated)
+  gather_src[n_gather++] = status + 18;              // tiles to walk again
+  gather_src[n_gather++] = set.plan + 2 * n_all;     // place items
   const uint32_t* counts_k[kMaxImages];
   uint32_t* offsets_k[kMaxImages];
   for (int k = 0; k < nimg; ++k) {
@@ -599,12 +603,12 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if (rb[0] & kStatusMismatch) return bail(fail(LDNI_ERR_DEVICE, "tile lists disagree with their counts"));
     const uint64_t need = rb[rb_more];
     {
-      const uint64_t demand = (uint64_t)rb[rb_more + 1] | ((uint64_t)rb[rb_more + 2] << 32);
+      const uint64_t demand = rb[rb_more + 1];
       uint32_t ml = 0;
       for (int k = 0; k < nimg; ++k) ml = std::max(ml, rb[1 + k]);
       stage_seen_record(stage_key, StageSeen{demand, ml});
-      p->n_walk = rb[rb_more + 3];
-      p->n_items = rb[rb_more + 4];
+      p->n_walk = rb[rb_more + 2];
+      p->n_items = rb[rb_more + 3];
     }
     if (n_tris > 0) {
       const double ratio = std::min(8.0, (double)need / ((double)n_tris * nimg) * 1.1);
@@ -616,10 +620,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if (attempt == 1) return bail(fail(LDNI_ERR_DEVICE, "tile list sizing failed"));
     cap = need;
     STEP(alloc_lists(cap), "tile list allocation");
-    // cursors, max layers, staging cursor and walk count start again
+    // cursors, max layers and walk count start again
     STEP(launch_fill_u32(tile_cur_all, 0u, n_all, stream), "fill");
     STEP(launch_fill_u32(status + 1, 0u, 3, stream), "fill");
-    STEP(launch_fill_u32(status + 16, 0u, 3, stream), "fill");
+    STEP(launch_fill_u32(walk_count, 0u, 1, stream), "fill");
   }
   if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more samples on one axis"));
   for (int k = 0; k < nimg; ++k) {
@@ -898,6 +902,7 @@ struct ldni_batch {
   uint32_t* offsets_arena = nullptr;
   uint32_t* counts_arena = nullptr;
   uint32_t* tile_arena = nullptr;
+  uint32_t* region_arena = nullptr;  // candidate counts -> staging regions (after tile_arena)
   uint32_t* cur_arena = nullptr;
   uint32_t* max_layers = nullptr;
   void* scan_scratch = nullptr;
@@ -964,12 +969,14 @@ hipError_t batch_upload(ldni_batch* b) {
 hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   hipError_t e;
 #define Q(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
-  Q(launch_fill_u32(b->dev.status, 0u, 20, s));  // status, work counters, staging cursor, walk count
+  Q(launch_fill_u32(b->dev.status, 0u, 20, s));  // status, work counters, walk count
   Q(launch_fill_u32(b->max_layers, 0u, b->n_img, s));
-  Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)b->total_tiles + 1, s));
+  // tile entry counts and (after them) candidate counts
+  Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)(b->region_arena - b->tile_arena) + (int64_t)b->total_tiles + 1, s));
   Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
-  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles
-  Q(launch_scan(b->tile_arena, b->tile_arena, (int64_t)b->total_tiles, b->scan_scratch, b->dev.status, s));
+  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles and candidates
+  Q(launch_tile_scan(b->tile_arena, b->region_arena, (int64_t)b->total_tiles,
+                     b->stage_layers * (uint32_t)(b->small ? 256 : 1024), b->scan_scratch, b->dev.status, s));
   Q(launch_batch_scatter(b->dev, b->bin_block_start.back(), s));
   Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, b->small, s));
   Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
@@ -1186,7 +1193,9 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const size_t o_soup = take(sizeof(float) * 9 * tris_total);
   const size_t o_tnorm = take(sizeof(float) * 3 * tris_total);
   const size_t o_rect = take(sizeof(Rect) * rect_total);
-  const size_t o_tile = take(sizeof(uint32_t) * (b->total_tiles + 1));
+  // tile entry counts, then (16-byte aligned) tile candidate counts
+  const uint64_t region_at = (b->total_tiles + 1 + 3) & ~(uint64_t)3;
+  const size_t o_tile = take(sizeof(uint32_t) * (region_at + b->total_tiles + 1));
   const size_t o_cur = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_counts = take(sizeof(uint32_t) * b->total_slots);
   const size_t o_offs = take(sizeof(uint32_t) * b->total_slots);
@@ -1203,8 +1212,9 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const size_t o_thits = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_walk = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_plan = take(sizeof(uint32_t) * (2 * b->total_tiles + 1));
-  const size_t o_scan = take(std::max(scan_scratch_bytes(2 * (int64_t)b->total_tiles),
-                                      scan_scratch_bytes((int64_t)b->total_slots)));
+  const size_t o_scan = take(std::max({scan_scratch_bytes(2 * (int64_t)b->total_tiles),
+                                       scan_scratch_bytes((int64_t)b->total_tiles, 2),
+                                       scan_scratch_bytes((int64_t)b->total_slots)}));
   e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(&b->ws, off);
   if (e != hipSuccess) {
     b->ws = nullptr;
@@ -1227,6 +1237,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   D.host_out = b->host_out;
   b->max_layers = reinterpret_cast<uint32_t*>(ws + o_ml);
   b->tile_arena = reinterpret_cast<uint32_t*>(ws + o_tile);
+  b->region_arena = b->tile_arena + region_at;
   b->cur_arena = reinterpret_cast<uint32_t*>(ws + o_cur);
   b->counts_arena = reinterpret_cast<uint32_t*>(ws + o_counts);
   b->offsets_arena = reinterpret_cast<uint32_t*>(ws + o_offs);
@@ -1235,7 +1246,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   D.plan = reinterpret_cast<uint32_t*>(ws + o_plan);
   D.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
   D.walk_count = D.status + 18;
-  D.stage_cursor = reinterpret_cast<unsigned long long*>(D.status + 16);
+  D.region_total = b->region_arena + b->total_tiles;
   D.place_cap = place_stage_cap(tile_pix);
   uint32_t* tstage = reinterpret_cast<uint32_t*>(ws + o_tstage);
   uint32_t* thits = reinterpret_cast<uint32_t*>(ws + o_thits);
@@ -1287,7 +1298,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.max_layers = b->max_layers + k;
     im.offsets = b->offsets_arena + b->seg_start[k];
     im.status = D.status;
-    im.stage_cursor = D.stage_cursor;
+    im.tile_region = b->region_arena + b->tile_start[k];
     im.tile_stage = tstage + b->tile_start[k];
     im.tile_hits = thits + b->tile_start[k];
     im.walk_list = D.walk_list;

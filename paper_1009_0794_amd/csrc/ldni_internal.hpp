@@ -54,13 +54,17 @@ struct Image {
   float* normal;      // [n][3]
   int32_t* tri;       // [n]
   uint32_t* status;   // shared status word
-  // Hits of the sampling pass, grouped by tile.  With stage_key null the
-  // count pass only counts and the write pass walks every tile again.
+  // Hits of the sampling pass, grouped by tile.  With stage_key null every
+  // tile with hits is walked again by the place pass.
   uint64_t* stage_key;               // (depth key, triangle) of each hit
   uint32_t* stage_qs;                // tile pixel | (slot within the pixel << 10)
-  unsigned long long* stage_cursor;  // bump allocator over the buffer (shared by the set)
-  uint64_t stage_cap;                // entries in the buffer
-  uint32_t stage_layers;             // a tile reserves at most this many entries per pixel
+  uint64_t stage_cap;                // entries in the buffer (below 2^32 - 1)
+  uint32_t stage_layers;             // a tile's region holds at most this many entries per pixel
+  // [n_tiles + 1] the tile's candidates, each triangle's rounded up to whole
+  // 4-entry groups (counted by setup); the region scan turns them into the
+  // tile's staging region [tile_region[t], tile_region[t + 1]) (capped at
+  // stage_layers entries per tile pixel, saturating at 2^32 - 1)
+  uint32_t* tile_region;
   uint32_t* tile_stage;              // [n_tiles] first entry of the tile's hits (a multiple
                                      // of 4; regions are whole 4-entry groups), or kNoStage
   uint32_t* tile_hits;               // [n_tiles] hits of the tile
@@ -156,7 +160,7 @@ struct BatchDevice {
   void* items;                      // place items
   uint32_t* walk_list;
   uint32_t* walk_count;
-  unsigned long long* stage_cursor;
+  const uint32_t* region_total;     // staging entries the regions of the batch ask for
   int32_t place_cap;
 };
 
@@ -216,5 +220,11 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scrat
 // (in place allowed); scratch: scan_scratch_bytes(n, nseg).
 hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
                                 void* scratch, uint32_t* status, hipStream_t s);
+// The tile scan: entry counts -> list offsets (as launch_scan), and in the
+// same launches candidate counts -> staging regions, each tile's count
+// capped at region_cap and the prefix saturating at 2^32 - 1 (in place
+// allowed; n + 1 slots each).  scratch: scan_scratch_bytes(n, 2).
+hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n, uint32_t region_cap,
+                            void* scratch, uint32_t* status, hipStream_t s);
 
 }  // namespace ldni

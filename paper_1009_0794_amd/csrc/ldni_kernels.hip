@@ -2,20 +2,23 @@
 //
 // Pipeline per call (every kernel covers all requested axes in one launch):
 //   setup      triangle-parallel: gather and validate vertices, float64 face
-//              normal, candidate pixel rectangle on each image
-//   bin_count  triangle-parallel: entries per screen tile (global atomics)
-//   scan       tile counts -> tile offsets
+//              normal, candidate pixel rectangle on each image, and the count
+//              of entries and candidate pixels of every screen tile it meets
+//   tile scan  entry counts -> tile-list offsets; candidate counts -> each
+//              tile's region of the staging buffer
 //   bin_scatter  triangle ids into per-tile lists
-//   count      one workgroup per tile: exact coverage test of every candidate
-//              (triangle, pixel centre), LDS per-pixel atomic counters ->
-//              counts[w*w] and the largest per-pixel count
+//   sample     one workgroup per tile: exact coverage test of every candidate
+//              (triangle, pixel centre); the hits' float64 depth, (depth,
+//              triangle) key and arrival slot in their pixel are staged in the
+//              tile's region, per-pixel counts -> counts[w*w]
 //   scan       counts -> offsets[w*w+1]
-//   write      one workgroup per tile: the same coverage test, float64 depth,
-//              (depth, triangle) keys staged in LDS at their pixel's slots,
-//              per-pixel sort, then contiguous row-range stores of depth,
-//              normal and triangle id.  A tile row whose samples do not fit
-//              in LDS is written straight to its output range and sorted
-//              there.
+//   plan       place items (a tile's pixels split into runs that fit in LDS)
+//   place      one workgroup per item: the staged keys of a run are put at
+//              their pixel slots in LDS, ranked within the pixel and stored as
+//              depth, normal and triangle id; a pixel deeper than LDS is
+//              stored unsorted and sorted in place
+//   walk       tiles whose hits did not fit their region: walked again and
+//              written directly
 // Nothing here is a dense contraction, so there is no MFMA: the work is
 // integer/FP64 ALU plus HBM traffic.
 #pragma clang fp contract(off)
@@ -249,12 +252,18 @@ __global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set
 // ---------------------------------------------------------------------------
 // Every (triangle, tile) pair of a wave is counted (or placed) with one
 // atomic per distinct tile of the wave: lanes that share the tile are peeled
-// off together and ranked by their lane order.  Mesh order is spatially
+// off together and ranked by their lane order.  Counting also adds up the
+// tile's candidate pixels, which size its staging region.  Mesh order is spatially
 // coherent for most meshes, so a wave typically touches a handful of tiles.
 // All 64 lanes of every wave must call this (t beyond the mesh = no tiles).
 template <bool kScatter>
 __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
   const int lane = threadIdx.x & 63;
+  // counting: per wave, the candidate sums of its group leaders (zero
+  // between uses)
+  __shared__ uint32_t s_acc[kBlock];
+  uint32_t* acc = s_acc + (threadIdx.x & ~63);
+  if (!kScatter) acc[lane] = 0u;
   int tx0 = 0, ty0 = 0, nx = 1, n = 0;
   if (live && r.i0 < r.i1 && r.j0 < r.j1) {
     tx0 = r.i0 / im.tw;
@@ -268,32 +277,53 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
   const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int q = 0; q < nmax; ++q) {
     int key = -1;
+    uint32_t cand = 0;  // counting: candidates in the tile, whole 4-entry groups
     if (q < n) {
       const int qy = q / nx;
-      key = (ty0 + qy) * im.ntx + tx0 + (q - qy * nx);
+      const int tx = tx0 + (q - qy * nx), ty = ty0 + qy;
+      key = ty * im.ntx + tx;
+      if (!kScatter) {
+        const int cx = min((int)r.i1, (tx + 1) * im.tw) - max((int)r.i0, tx * im.tw);
+        const int cy = min((int)r.j1, (ty + 1) * im.th) - max((int)r.j0, ty * im.th);
+        cand = ((uint32_t)(cx * cy) + 3u) & ~3u;
+      }
     }
-    // Peel the wave's distinct tiles; each group's leader issues one atomic.
-    // The scatter's atomics return the group's base: all of them are issued
-    // before any is waited for, and every lane then reads its leader's.
+    // Peel the wave's distinct tiles into groups with a leader each; the
+    // leaders then issue their atomics together (one instruction), and the
+    // scatter's return the group's base, which every lane reads from its
+    // leader.
     const uint32_t list_at = (kScatter && key >= 0) ? im.tile_cnt[key] : 0u;
     uint64_t pending = __ballot(key >= 0);
     int my_leader = 0;
-    uint32_t my_rank = 0, lead_base = 0;
+    uint32_t my_rank = 0, group = 0, lead_base = 0;
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
       const int k = __builtin_amdgcn_readfirstlane(__shfl(key, leader, 64));
       const uint64_t same = __ballot(key == k);
-      if (lane == leader) {
-        if (kScatter)
-          lead_base = atomicAdd(&im.tile_cur[k], (uint32_t)__popcll(same));
-        else
-          atomicAdd(&im.tile_cnt[k], (uint32_t)__popcll(same));
-      }
       if (key == k) {
         my_leader = leader;
         my_rank = (uint32_t)__popcll(same & lower);
+        group = (uint32_t)__popcll(same);
       }
       pending &= ~same;
+    }
+    if (kScatter && key >= 0 && my_leader == lane) lead_base = atomicAdd(&im.tile_cur[key], group);
+    if (!kScatter) {
+      // Each lane adds its candidates to its leader's slot; the leaders then
+      // add their group's entries and candidates to the tile.
+      if (key >= 0) atomicAdd(&acc[my_leader], cand);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (key >= 0 && my_leader == lane) {
+        const uint32_t c = acc[lane];
+        acc[lane] = 0u;
+        atomicAdd(&im.tile_cnt[key], group);
+        atomicAdd(&im.tile_region[key], c);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (kScatter) {
       const uint32_t base = (uint32_t)__shfl((int)lead_base, my_leader, 64);
@@ -528,9 +558,8 @@ struct SampleLds {
 // pixel) descriptor to its wave's list; after each window the wave takes its
 // hits 64 at a time, recomputes their edge functions, and computes depth,
 // key and arrival slot with every lane busy, storing them to consecutive
-// entries of the tile's staging region.  The region is reserved from the
-// tile's candidate count (pixels of the clipped rectangles), which bounds
-// its hits.
+// entries of the tile's staging region.  The region is sized by the tile's
+// candidate count (pixels of the clipped rectangles), which bounds its hits.
 template <int kTilePix>
 __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t* plan, uint32_t n_total,
                             int place_cap) {
@@ -542,7 +571,6 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   __shared__ ChunkLds<true> L;
   __shared__ Lds H;
   __shared__ uint32_t s_red[kWaves];
-  __shared__ uint32_t s_region[2];  // first entry, size
   __shared__ uint32_t s_fill;
 
   const TileGeom g = tile_geom(im, tile);
@@ -555,45 +583,17 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   for (int q = threadIdx.x; q <= g.ch; q += kBlock)
     s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
 
-  // Reserve the tile's region: its candidate count (rounded up to whole
-  // 4-entry groups so the write pass can read 16-byte vectors), capped at
-  // stage_layers per pixel.  One chunk of entries: its count comes with the
-  // chunk; more: the entries are counted first.
-  const uint32_t region_max = im.stage_layers * (uint32_t)npix;
-  auto reserve = [&](uint32_t cand) {
-    uint32_t size = min((min(cand, region_max) + 3u) & ~3u, region_max);
-    uint64_t base = 0;
-    if (size > 0 && im.stage_key != nullptr) {
-      base = atomicAdd(im.stage_cursor, (unsigned long long)size);
-      if (base + size > im.stage_cap) size = 0;  // no room left: walked again later
-    } else {
-      size = 0;
-    }
-    s_region[0] = (uint32_t)base;
-    s_region[1] = size;
-  };
+  // The tile's staging region comes from the tile scan (whole 4-entry
+  // groups, so the place pass reads 16-byte vectors); a region that ends
+  // beyond the buffer is not used and the tile is walked again.
   const uint64_t cap = im.list_cap;
   const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[tile], cap);
   const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[tile + 1], cap);
-  const bool one_chunk = e_end - e_begin <= (uint32_t)kBlock;
-  if (threadIdx.x == 0) {
-    s_fill = 0;
-    s_region[0] = 0;
-    s_region[1] = 0;
-  }
-  if (!one_chunk) {
-    // clamped per thread so the sum fits 32 bits
-    uint32_t cand = 0;
-    for (uint32_t e = e_begin + threadIdx.x; e < e_end; e += kBlock) {
-      const Rect r = entry_rect(im, im.tile_list[e]);
-      const int nx = min((int)r.i1, g.x0 + g.cw) - max((int)r.i0, g.x0);
-      const int ny = min((int)r.j1, g.y0 + g.ch) - max((int)r.j0, g.y0);
-      if (nx > 0 && ny > 0) cand = min(cand + (uint32_t)(nx * ny), region_max);
-    }
-    uint32_t total;
-    (void)block_exclusive_scan<uint32_t>(cand, s_red, total);
-    if (threadIdx.x == 0) reserve(total);
-  }
+  const uint32_t region_first = im.tile_region[tile];
+  const uint32_t region_end = im.tile_region[tile + 1];
+  const uint32_t region_size =
+      (im.stage_key != nullptr && region_end <= im.stage_cap) ? region_end - region_first : 0u;
+  if (threadIdx.x == 0) s_fill = 0;
   __syncthreads();
   const double lo_a = im.lo_a;
   const float inv_cw = 1.0f / (float)cw;
@@ -626,15 +626,11 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
       int total;
       const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
       if (k < m) L.start[k] = excl;
-      if (k == 0) {
-        L.start[m] = total;
-        if (cbase == e_begin && one_chunk) reserve((uint32_t)total);
-      }
+      if (k == 0) L.start[m] = total;
       __syncthreads();
     }
     const int total = L.start[m];
     const int run = min(max((total + kBlock - 1) / kBlock, 2), kMaxRun);
-    const uint32_t region_first = s_region[0], region_size = s_region[1];
 
     for (int wb = 0; wb < total; wb += kBlock * run) {
       // ---- walk: covered candidates append their descriptor
@@ -744,12 +740,12 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   if (threadIdx.x == 0) {
     if (mx > 0) atomicMax(im.max_layers, mx);
     const uint32_t hits = s_fill;
-    const bool staged = hits <= s_region[1];
+    const bool staged = hits <= region_size;
     im.tile_hits[tile] = hits;
     if (hits == 0) {
       im.tile_stage[tile] = 0;
     } else if (staged) {
-      im.tile_stage[tile] = s_region[0];
+      im.tile_stage[tile] = region_first;
     } else {
       im.tile_stage[tile] = kNoStage;
       im.walk_list[atomicAdd(im.walk_count, 1u)] = gtile;
@@ -1395,7 +1391,8 @@ __global__ void __launch_bounds__(kBlock) fill_u32_kernel(uint32_t* p, uint32_t 
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;  // 4096 values per workgroup
 
-__device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i, uint32_t v[16]) {
+__device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i, uint32_t cap,
+                                       uint32_t v[16]) {
   if (i + 16 <= n) {
     const uint4* p = reinterpret_cast<const uint4*>(in + i);
 #pragma unroll
@@ -1407,14 +1404,20 @@ __device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i,
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = (i + k < n) ? in[i + k] : 0u;
   }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = min(v[k], cap);
 }
 
 // Up to kMaxImages scans of n values each (input, output and where the
-// total goes per segment), nb workgroups per segment.
+// total goes per segment), nb workgroups per segment.  Every value is first
+// capped at the segment's cap; a saturating segment (bit in sat) clamps its
+// prefixes at 2^32 - 1 instead of raising the overflow bit.
 struct ScanSegs {
   const uint32_t* in[kMaxImages];
   uint32_t* out[kMaxImages];
   uint32_t* total[kMaxImages];
+  uint32_t cap[kMaxImages];
+  uint32_t sat;
   int64_t n;
   int64_t nb;
   int32_t nseg;
@@ -1426,7 +1429,7 @@ __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(ScanSegs sg, uint64
   const int64_t b = (int64_t)blockIdx.x - (int64_t)seg * sg.nb;
   const int64_t i = b * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[16];
-  load16(sg.in[seg], sg.n, i, v);
+  load16(sg.in[seg], sg.n, i, sg.cap[seg], v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
@@ -1451,8 +1454,9 @@ __global__ void __launch_bounds__(kBlock) scan_spine_kernel(ScanSegs sg, uint64_
     carry += total;
   }
   if (threadIdx.x == 0) {
-    *sg.total[blockIdx.x] = (uint32_t)carry;
-    if (carry > 0xffffffffull && status) atomicOr(status, kStatusOverflow);
+    const bool sat = (sg.sat >> blockIdx.x) & 1u;
+    *sg.total[blockIdx.x] = (uint32_t)min(carry, 0xffffffffull);
+    if (carry > 0xffffffffull && status && !sat) atomicOr(status, kStatusOverflow);
   }
 }
 
@@ -1464,16 +1468,17 @@ __global__ void __launch_bounds__(kBlock) scan_apply_kernel(ScanSegs sg, const u
   const int64_t n = sg.n;
   uint32_t* out = sg.out[seg];
   uint32_t v[16];
-  load16(sg.in[seg], n, i, v);
+  load16(sg.in[seg], n, i, sg.cap[seg], v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
   uint64_t total;
   uint64_t run = block_exclusive_scan<uint64_t>(s, s_w, total) + partial[blockIdx.x];
+  const uint64_t top = ((sg.sat >> seg) & 1u) ? 0xffffffffull : ~0ull;
   uint32_t o[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    o[k] = (uint32_t)run;
+    o[k] = (uint32_t)min(run, top);
     run += v[k];
   }
   if (i + 16 <= n) {
@@ -1613,7 +1618,7 @@ __global__ void __launch_bounds__(kBlock) scan_apply_segmented_kernel(
   __shared__ uint64_t s_w[kWaves];
   const int64_t i = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[16];
-  load16(in, n, i, v);
+  load16(in, n, i, 0xffffffffu, v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
@@ -1636,9 +1641,8 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
     B.host_out[0] = *B.status;
     B.host_out[1] = *B.tile_total;
     uint32_t* tail = B.host_out + 4 + 4 * (size_t)B.n_images;
-    const unsigned long long demand = *B.stage_cursor;
-    tail[0] = (uint32_t)demand;
-    tail[1] = (uint32_t)(demand >> 32);
+    tail[0] = *B.region_total;
+    tail[1] = 0u;
     tail[2] = *B.walk_count;
   }
   if (k < B.n_images) {
@@ -1870,6 +1874,7 @@ hipError_t launch_batch_pixel_scan(const BatchDevice& b, const uint32_t* counts,
   if (nb == 0 || b.n_images == 0) return hipSuccess;
   ScanSegs sg{};
   sg.in[0] = counts;
+  sg.cap[0] = 0xffffffffu;
   sg.n = n_slots;
   sg.nb = nb;
   sg.nseg = 1;
@@ -1896,6 +1901,15 @@ size_t scan_scratch_bytes(int64_t n, int nseg) {
   return (size_t)((nb > 0 ? nb : 1) * (nseg > 0 ? nseg : 1) + 2) * sizeof(uint64_t);
 }
 
+static hipError_t run_scan(const ScanSegs& sg, void* scratch, uint32_t* status, hipStream_t s) {
+  uint64_t* partial = static_cast<uint64_t*>(scratch);
+  const unsigned blocks = (unsigned)(sg.nb * sg.nseg);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kBlock), 0, s, sg, partial);
+  hipLaunchKernelGGL(scan_spine_kernel, dim3((unsigned)sg.nseg), dim3(kBlock), 0, s, sg, partial, status);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, sg, partial);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
                                 void* scratch, uint32_t* status, hipStream_t s) {
   if (nseg < 1 || nseg > kMaxImages) return hipErrorInvalidValue;
@@ -1911,16 +1925,34 @@ hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out,
     sg.in[k] = in[k];
     sg.out[k] = out[k];
     sg.total[k] = out[k] + n;
+    sg.cap[k] = 0xffffffffu;
   }
   sg.n = n;
   sg.nb = (n + kScanTile - 1) / kScanTile;
   sg.nseg = nseg;
-  uint64_t* partial = static_cast<uint64_t*>(scratch);
-  const unsigned blocks = (unsigned)(sg.nb * nseg);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(blocks), dim3(kBlock), 0, s, sg, partial);
-  hipLaunchKernelGGL(scan_spine_kernel, dim3((unsigned)nseg), dim3(kBlock), 0, s, sg, partial, status);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, sg, partial);
-  return hipGetLastError();
+  return run_scan(sg, scratch, status, s);
+}
+
+hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n, uint32_t region_cap,
+                            void* scratch, uint32_t* status, hipStream_t s) {
+  if (n <= 0) {
+    hipError_t e = launch_fill_u32(tile_cnt, 0u, 1, s);
+    return e != hipSuccess ? e : launch_fill_u32(tile_region, 0u, 1, s);
+  }
+  ScanSegs sg{};
+  sg.in[0] = tile_cnt;
+  sg.out[0] = tile_cnt;
+  sg.total[0] = tile_cnt + n;
+  sg.cap[0] = 0xffffffffu;
+  sg.in[1] = tile_region;
+  sg.out[1] = tile_region;
+  sg.total[1] = tile_region + n;
+  sg.cap[1] = region_cap;
+  sg.sat = 2u;
+  sg.n = n;
+  sg.nb = (n + kScanTile - 1) / kScanTile;
+  sg.nseg = 2;
+  return run_scan(sg, scratch, status, s);
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
