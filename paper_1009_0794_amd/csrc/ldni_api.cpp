@@ -556,13 +556,13 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   auto alloc_lists = [&](uint64_t c) -> hipError_t {
     cache_put(p->lists, p->lists_bytes, stream);
     p->lists = nullptr;
-    hipError_t ea = cache_get(&p->lists, sizeof(int32_t) * (size_t)c, stream, &p->lists_bytes);
+    hipError_t ea = cache_get(&p->lists, sizeof(int2) * (size_t)c, stream, &p->lists_bytes);
     if (ea != hipSuccess) {
       p->lists = nullptr;
       return ea;
     }
     for (int k = 0; k < nimg; ++k) {
-      set.img[k].tile_list = static_cast<int32_t*>(p->lists);
+      set.img[k].tile_list = static_cast<int2*>(p->lists);
       set.img[k].list_cap = c;
     }
     return hipSuccess;
@@ -942,7 +942,7 @@ void batch_destroy(ldni_batch* b) {
 // Points the image table at the current list and sample buffers and uploads it.
 hipError_t batch_upload(ldni_batch* b) {
   for (int k = 0; k < b->n_img; ++k) {
-    b->images_h[k].tile_list = static_cast<int32_t*>(b->lists);
+    b->images_h[k].tile_list = static_cast<int2*>(b->lists);
     b->images_h[k].list_cap = b->list_cap;
   }
   b->dev.list_cap = b->list_cap;
@@ -1039,7 +1039,7 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
     bool regrow = false;
     const uint64_t entries = h[1];
     if (entries > b->list_cap) {
-      ldni_status st = batch_grow(b, &b->lists, &b->list_cap, entries, sizeof(int32_t));
+      ldni_status st = batch_grow(b, &b->lists, &b->list_cap, entries, sizeof(int2));
       if (st != LDNI_OK) return st;
       regrow = true;
     }
@@ -1325,7 +1325,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   for (int k = 0; k < n_img; ++k)
     cap += (uint64_t)std::ceil((double)meshes[b->img_mesh[k]].n_tris * std::min(g_list_ratio.load(), 8.0)) +
            4 * (uint64_t)(b->tile_start[k + 1] - b->tile_start[k]);
-  ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, sizeof(int32_t));
+  ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, sizeof(int2));
   if (st != LDNI_OK) return bail(st);
   // staging: a first guess (24 entries per triangle plus one per pixel),
   // grown to the demand after the first run if it was short

@@ -44,7 +44,9 @@ struct Image {
   // workspace
   uint32_t* tile_cnt;   // [n_tiles + 1] entries per tile -> exclusive offsets
   uint32_t* tile_cur;   // [n_tiles] scatter cursors
-  int32_t* tile_list;   // triangle ids grouped by tile
+  int2* tile_list;      // entries grouped by tile: (triangle id, its candidate
+                        // rectangle in the tile: x0 | y0 << 8 | (width - 1) << 16
+                        // | (height - 1) << 24, tile-local pixels)
   uint64_t list_cap;    // capacity of tile_list (entries beyond it are dropped)
   uint32_t* counts;     // [w*w] samples per pixel
   uint32_t* max_layers; // [1]

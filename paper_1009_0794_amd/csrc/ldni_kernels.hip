@@ -278,15 +278,19 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
   for (int q = 0; q < nmax; ++q) {
     int key = -1;
     uint32_t cand = 0;  // counting: candidates in the tile, whole 4-entry groups
+    uint32_t geom = 0;  // scatter: the rectangle in the tile (tile-list entry layout)
     if (q < n) {
       const int qy = q / nx;
       const int tx = tx0 + (q - qy * nx), ty = ty0 + qy;
       key = ty * im.ntx + tx;
-      if (!kScatter) {
-        const int cx = min((int)r.i1, (tx + 1) * im.tw) - max((int)r.i0, tx * im.tw);
-        const int cy = min((int)r.j1, (ty + 1) * im.th) - max((int)r.j0, ty * im.th);
-        cand = ((uint32_t)(cx * cy) + 3u) & ~3u;
-      }
+      const int x0 = tx * im.tw, y0 = ty * im.th;
+      const int lx0 = max((int)r.i0, x0) - x0, lx1 = min((int)r.i1, x0 + im.tw) - x0;
+      const int ly0 = max((int)r.j0, y0) - y0, ly1 = min((int)r.j1, y0 + im.th) - y0;
+      if (kScatter)
+        geom = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 - 1) << 16) |
+               ((uint32_t)(ly1 - ly0 - 1) << 24);
+      else
+        cand = ((uint32_t)((lx1 - lx0) * (ly1 - ly0)) + 3u) & ~3u;
     }
     // Peel the wave's distinct tiles into groups with a leader each; the
     // leaders then issue their atomics together (one instruction), and the
@@ -329,7 +333,7 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
       const uint32_t base = (uint32_t)__shfl((int)lead_base, my_leader, 64);
       if (key >= 0) {
         const uint64_t pos = (uint64_t)list_at + base + my_rank;
-        if (pos < im.list_cap) im.tile_list[pos] = (int32_t)t;
+        if (pos < im.list_cap) im.tile_list[pos] = make_int2((int32_t)t, (int32_t)geom);
       }
     }
   }
@@ -400,13 +404,28 @@ __device__ __forceinline__ bool covered(float au, float bu, float cu, float tav,
   return (s0 != 0) & (s0 == s1) & (s1 == s2);
 }
 
-// Rectangle of a tile-list entry; an entry that is not a triangle of the
-// mesh (the lists were not written as counted) raises the mismatch bit and
-// has no candidates.
-__device__ __forceinline__ Rect entry_rect(const Image& im, int32_t t) {
-  if ((uint32_t)t < (uint64_t)im.n_tris) return im.rect[t];
-  atomicOr(im.status, kStatusMismatch);
-  return Rect{0, 0, 0, 0};
+// Candidate rectangle of a tile-list entry in tile pixels, rows [y0, y1)
+// and columns [x0, x0 + width).  An entry that is not a triangle of the mesh
+// or does not fit the tile (the lists were not written as counted) raises the
+// mismatch bit and has no candidates (y1 = y0).
+struct EntryRect {
+  int x0, y0, width, y1;
+};
+__device__ __forceinline__ EntryRect entry_rect(const Image& im, const TileGeom& g, int2 ent) {
+  const uint32_t gm = (uint32_t)ent.y;
+  EntryRect r;
+  r.x0 = gm & 255;
+  r.y0 = (gm >> 8) & 255;
+  r.width = ((gm >> 16) & 255) + 1;
+  r.y1 = r.y0 + (int)(gm >> 24) + 1;
+  if ((uint32_t)ent.x >= (uint64_t)im.n_tris || r.x0 + r.width > g.cw || r.y1 > g.ch) {
+    atomicOr(im.status, kStatusMismatch);
+    r.x0 = 0;
+    r.y0 = 0;
+    r.width = 1;
+    r.y1 = 0;
+  }
+  return r;
 }
 
 struct NoChunkHook {
@@ -424,22 +443,18 @@ __device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int 
   const uint64_t cap = im.list_cap;
   const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[g.tile], cap);
   const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[g.tile + 1], cap);
-  const int ya = g.y0 + r0, yb = g.y0 + r1;
   for (uint32_t base = e_begin; base < e_end; base += kBlock) {
     const int m = (int)min((uint32_t)kBlock, e_end - base);
     const int k = threadIdx.x;
     int nc = 0;
     if (k < m) {
-      const int32_t t = im.tile_list[base + k];
-      const Rect r = entry_rect(im, t);
-      const int px0 = max((int)r.i0, g.x0) - g.x0, px1 = min((int)r.i1, g.x0 + g.cw) - g.x0;
-      const int py0 = max((int)r.j0, ya) - g.y0, py1 = min((int)r.j1, yb) - g.y0;
-      int width = 1;
-      if (px1 > px0 && py1 > py0) {
-        width = px1 - px0;
-        nc = width * (py1 - py0);
-      }
-      L.geom[k] = px0 | (max(py0, 0) << 8) | ((width - 1) << 16);
+      const int2 ent = im.tile_list[base + k];
+      const int32_t t = ent.x;
+      const EntryRect r = entry_rect(im, g, ent);
+      const int py0 = max(r.y0, r0), py1 = min(r.y1, r1);
+      const int width = r.width;
+      if (py1 > py0) nc = width * (py1 - py0);
+      L.geom[k] = r.x0 | (max(py0, 0) << 8) | ((width - 1) << 16);
       if (nc > 0) {  // vertex data only for entries with candidates in these rows
         const float* s = im.soup + 9 * (int64_t)t;
         L.ab[k] = make_float4(s[im.u], s[im.v], s[3 + im.u], s[3 + im.v]);
@@ -606,16 +621,11 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
       const int k = threadIdx.x;
       int nc = 0;
       if (k < m) {
-        const int32_t t = im.tile_list[cbase + k];
-        const Rect r = entry_rect(im, t);
-        const int px0 = max((int)r.i0, g.x0) - g.x0, px1 = min((int)r.i1, g.x0 + g.cw) - g.x0;
-        const int py0 = max((int)r.j0, g.y0) - g.y0, py1 = min((int)r.j1, g.y0 + g.ch) - g.y0;
-        int width = 1;
-        if (px1 > px0 && py1 > py0) {
-          width = px1 - px0;
-          nc = width * (py1 - py0);
-        }
-        L.geom[k] = px0 | (max(py0, 0) << 8) | ((width - 1) << 16);
+        const int2 ent = im.tile_list[cbase + k];
+        const int32_t t = ent.x;
+        const EntryRect r = entry_rect(im, g, ent);
+        nc = r.width * (r.y1 - r.y0);
+        L.geom[k] = r.x0 | (r.y0 << 8) | ((r.width - 1) << 16);
         if (nc > 0) {
           const float* sp = im.soup + 9 * (int64_t)t;
           L.ab[k] = make_float4(sp[im.u], sp[im.v], sp[3 + im.u], sp[3 + im.v]);
