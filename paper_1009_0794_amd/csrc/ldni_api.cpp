@@ -19,6 +19,35 @@
 
 using namespace ldni;
 
+namespace ldni {
+
+// The centre c_i = f32(lo + (i + 0.5) h) (float64 arithmetic, then rounded)
+// differs from the real lo + (i + 0.5) h by at most 2^-24 (1 + 2^-26) M with
+// M = |lo| + (w + 1) h, and t carries a relative float64 error of a few
+// 2^-53, i.e. below 2^-48 (w + 1) pixels.  Twice the sum, in pixels, is the
+// slack.
+void finish_image_geometry(Image& im) {
+  auto slack = [&](double lo, double h) {
+    if (!(h > 0.0)) return HUGE_VAL;
+    const double m = std::fabs(lo) + ((double)im.w + 1.0) * h;
+    return 2.0 * (std::ldexp(m, -24) * (1.0 + std::ldexp(1.0, -26)) / h + std::ldexp((double)im.w + 1.0, -48));
+  };
+  auto shift = [](int n) {
+    if (n <= 0 || (n & (n - 1)) != 0) return -1;
+    int s = 0;
+    while ((1 << s) < n) ++s;
+    return s;
+  };
+  im.inv_h_u = 1.0 / im.h_u;
+  im.inv_h_v = 1.0 / im.h_v;
+  im.slack_u = slack(im.lo_u, im.h_u);
+  im.slack_v = slack(im.lo_v, im.h_v);
+  im.tw_shift = shift(im.tw);
+  im.th_shift = shift(im.th);
+}
+
+}  // namespace ldni
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -463,11 +492,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.h_u = ((double)bbox[3 + im.u] - (double)bbox[im.u]) / (double)w;
     im.lo_v = (double)bbox[im.v];
     im.h_v = ((double)bbox[3 + im.v] - (double)bbox[im.v]) / (double)w;
-    im.inv_h_u = 1.0 / im.h_u;
-    im.inv_h_v = 1.0 / im.h_v;
     im.lo_a = (double)bbox[a];
     im.tw = tw;
     im.th = th;
+    finish_image_geometry(im);
     im.ntx = ntx;
     im.nty = nty;
     im.soup = ms.soup;
@@ -1280,10 +1308,9 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.h_u = ((double)d.bbox[3 + im.u] - (double)d.bbox[im.u]) / (double)d.w;
     im.lo_v = (double)d.bbox[im.v];
     im.h_v = ((double)d.bbox[3 + im.v] - (double)d.bbox[im.v]) / (double)d.w;
-    im.inv_h_u = 1.0 / im.h_u;
-    im.inv_h_v = 1.0 / im.h_v;
     im.lo_a = (double)d.bbox[a];
     tile_shape(d.w, d.n_tris, d.tile_w, d.tile_h, &im.tw, &im.th);
+    finish_image_geometry(im);
     im.ntx = (d.w + im.tw - 1) / im.tw;
     im.nty = (d.w + im.th - 1) / im.th;
     im.soup = bm.m.soup;

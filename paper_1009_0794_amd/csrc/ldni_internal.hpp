@@ -32,9 +32,14 @@ struct Image {
   double lo_u, h_u;  // pixel centre c_u[i] = f32(lo_u + (i + 0.5) * h_u)
   double lo_v, h_v;
   double inv_h_u, inv_h_v;  // 1 / h (first estimates of pixel indices only)
+  // An estimate t = (x - lo) / h - 0.5 farther than this from every integer
+  // gives the first centre at or above x as ceil(t), float32 rounding of the
+  // centres included; nearer, the centres are compared one by one.
+  double slack_u, slack_v;
   double lo_a;       // depth origin
   // tiling
   int32_t tw, th;    // tile shape in pixels
+  int32_t tw_shift, th_shift;  // log2 of tw, th when a power of two, else -1
   int32_t ntx, nty;  // tiles along u and v
   // mesh (shared by the images of one mesh)
   const float* soup;   // [T][9] vertex coordinates A,B,C (x,y,z each)
@@ -104,6 +109,10 @@ struct MeshSetup {
   Rect* rect[kMaxImages];
   uint32_t* status;
 };
+
+// Fills the derived fields of an image (inverse steps, centre slack, tile
+// shifts) from w, the tile shape and lo/h of both image axes.
+void finish_image_geometry(Image& im);
 
 // ---- launchers (ldni_kernels.hip) ----
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);

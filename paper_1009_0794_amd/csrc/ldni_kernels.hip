@@ -49,9 +49,14 @@ __device__ __forceinline__ float pixel_centre(double lo, double h, int i) {
 }
 
 // Smallest i in [0, w] whose centre is >= x (centres are non-decreasing in i).
-// The float64 estimate is corrected against the exact float32 centres.
-__device__ int first_centre_at_or_above(double lo, double h, double inv_h, int w, float x) {
-  double t = ((double)x - lo) * inv_h - 0.5;
+// The float64 estimate is exact when it is farther than slack from every
+// integer; otherwise it is corrected against the exact float32 centres.
+__device__ int first_centre_at_or_above(double lo, double h, double inv_h, double slack, int w, float x) {
+  const double t = ((double)x - lo) * inv_h - 0.5;
+  if (t > 0.0 && t < (double)w) {
+    const double c = ceil(t);
+    if (c - t > slack && c - t < 1.0 - slack) return (int)c;
+  }
   int i;
   if (!(t > 0.0)) i = 0;
   else if (t >= (double)w) i = w;
@@ -228,10 +233,10 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
     const float vmin = fminf(fminf(P[im.v], P[3 + im.v]), P[6 + im.v]);
     const float vmax = fmaxf(fmaxf(P[im.v], P[3 + im.v]), P[6 + im.v]);
     Rect r;
-    const int i0 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.w, umin);
-    const int i1 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.w, umax);
-    const int j0 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.w, vmin);
-    const int j1 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.w, vmax);
+    const int i0 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.slack_u, im.w, umin);
+    const int i1 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.slack_u, im.w, umax);
+    const int j0 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.slack_v, im.w, vmin);
+    const int j1 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.slack_v, im.w, vmax);
     if (i0 < i1 && j0 < j1) {
       r.i0 = (int16_t)i0; r.i1 = (int16_t)i1; r.j0 = (int16_t)j0; r.j1 = (int16_t)j1;
     } else {
@@ -264,24 +269,28 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
   __shared__ uint32_t s_acc[kBlock];
   uint32_t* acc = s_acc + (threadIdx.x & ~63);
   if (!kScatter) acc[lane] = 0u;
+  // tile of a pixel column / row (shifts for the usual power-of-two shapes)
+  auto tile_x = [&](int i) { return im.tw_shift >= 0 ? i >> im.tw_shift : i / im.tw; };
+  auto tile_y = [&](int j) { return im.th_shift >= 0 ? j >> im.th_shift : j / im.th; };
   int tx0 = 0, ty0 = 0, nx = 1, n = 0;
   if (live && r.i0 < r.i1 && r.j0 < r.j1) {
-    tx0 = r.i0 / im.tw;
-    ty0 = r.j0 / im.th;
-    nx = (r.i1 - 1) / im.tw - tx0 + 1;
-    n = nx * ((r.j1 - 1) / im.th - ty0 + 1);
+    tx0 = tile_x(r.i0);
+    ty0 = tile_y(r.j0);
+    nx = tile_x(r.i1 - 1) - tx0 + 1;
+    n = nx * (tile_y(r.j1 - 1) - ty0 + 1);
   }
-  int nmax = n;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, __shfl_xor(nmax, d, 64));
   const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int q = 0; q < nmax; ++q) {
+  int qx = 0, qy = 0;  // tile q of the triangle, q = qy * nx + qx
+  for (int q = 0; __ballot(q < n) != 0; ++q) {  // while any lane has tiles left
     int key = -1;
     uint32_t cand = 0;  // counting: candidates in the tile, whole 4-entry groups
     uint32_t geom = 0;  // scatter: the rectangle in the tile (tile-list entry layout)
     if (q < n) {
-      const int qy = q / nx;
-      const int tx = tx0 + (q - qy * nx), ty = ty0 + qy;
+      const int tx = tx0 + qx, ty = ty0 + qy;
+      if (++qx == nx) {
+        qx = 0;
+        ++qy;
+      }
       key = ty * im.ntx + tx;
       const int x0 = tx * im.tw, y0 = ty * im.th;
       const int lx0 = max((int)r.i0, x0) - x0, lx1 = min((int)r.i1, x0 + im.tw) - x0;
@@ -302,7 +311,7 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
     uint32_t my_rank = 0, group = 0, lead_base = 0;
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int k = __builtin_amdgcn_readfirstlane(__shfl(key, leader, 64));
+      const int k = __builtin_amdgcn_readlane(key, leader);  // leader is wave-uniform
       const uint64_t same = __ballot(key == k);
       if (key == k) {
         my_leader = leader;
