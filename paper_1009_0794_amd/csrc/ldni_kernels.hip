@@ -601,6 +601,26 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   const int npix = g.cw * g.ch;
   const int cw = g.cw;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t cap = im.list_cap;
+  const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[tile], cap);
+  const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[tile + 1], cap);
+
+  if (e_begin == e_end) {
+    // no triangle meets the tile: zero counts, no hits, nothing to place
+    for (int q = threadIdx.x; q < npix; q += kBlock) {
+      const int py = q / cw, px = q - py * cw;
+      im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = 0u;
+    }
+    if (threadIdx.x == 0) {
+      im.tile_hits[tile] = 0u;
+      im.tile_stage[tile] = 0u;
+      if (plan) {
+        plan[gtile] = 0u;
+        plan[n_total + gtile] = 0u;
+      }
+    }
+    return;
+  }
 
   for (int q = threadIdx.x; q < npix; q += kBlock) s_cnt[q] = 0;
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
@@ -610,9 +630,6 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   // The tile's staging region comes from the tile scan (whole 4-entry
   // groups, so the place pass reads 16-byte vectors); a region that ends
   // beyond the buffer is not used and the tile is walked again.
-  const uint64_t cap = im.list_cap;
-  const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[tile], cap);
-  const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[tile + 1], cap);
   const uint32_t region_first = im.tile_region[tile];
   const uint32_t region_end = im.tile_region[tile + 1];
   const uint32_t region_size =
