@@ -518,14 +518,16 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     set.tile_start[k + 1] = set.tile_start[k] + (uint32_t)n_tiles;
   }
   // Staging buffer for the hits of the sampling pass: what the last call of
-  // the same shape asked for, else a first guess (24 entries per triangle
-  // plus four per pixel).  A tile that finds no room is walked again by the
-  // write pass, so a short buffer costs time, never results.  Never more than
-  // stage_layers entries per pixel, which is all the tiles can ask for.
+  // the same shape asked for (the candidate total of its tile scan), else a
+  // first guess (16 entries per triangle and image, which covers small
+  // triangles' rectangles rounded to 4-entry groups, plus four per pixel for
+  // large ones).  A tile whose region does not fit is walked again by the
+  // place pass, so a short buffer costs time, never results.  Never more
+  // than stage_layers entries per pixel, which is all the tiles can ask for.
   {
     const double px = (double)npix * nimg;
     const double want = have_seen ? (double)seen.demand * 1.1 + 65536.0
-                                  : 24.0 * (double)n_tris + 4.0 * px + 65536.0;
+                                  : 16.0 * (double)n_tris * nimg + 4.0 * px + 65536.0;
     const double most = std::min((double)stage_layers * px + 65536.0, (double)kMaxStageEntries);
     uint64_t stage_cap = (uint64_t)std::min(want, most);
     // test hook: a smaller buffer (0: none) forces tiles onto the walk path
@@ -1354,7 +1356,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
            4 * (uint64_t)(b->tile_start[k + 1] - b->tile_start[k]);
   ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, sizeof(int2));
   if (st != LDNI_OK) return bail(st);
-  // staging: a first guess (24 entries per triangle plus one per pixel),
+  // staging: a first guess (24 entries per triangle and image plus one per pixel),
   // grown to the demand after the first run if it was short
   {
     uint64_t guess = 65536;
