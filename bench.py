@@ -306,13 +306,84 @@ def measure_fwd_bwd(ldni, torch, mg, reps):
     }
 
 
+def measure_boolean(ldni, torch, mg, reps):
+    """Boolean operations (Sec. 4.1, small interval removal Sec. 4.1.1) of two
+    seeded scenes sampled on one grid (scene64 seeds 1 and 7, w = 2048): one
+    step is the union, intersection and difference on all three axes through
+    the C ABI (nine calls, results freed)."""
+    meshes = [mg.c3_scene64(seed=1), mg.c3_scene64(seed=7)]
+    L = []
+    for m in meshes:
+        v = torch.from_numpy(m.verts).cuda()
+        f = torch.from_numpy(m.tris).cuda()
+        L.append(ldni.sample(v, f, m.bbox, m.w, "xyz"))
+    del meshes
+    w = L[0][0].w
+    npix = w * w
+    ops = ("union", "intersection", "difference")
+    n_out, n_in = 0, 0
+    for op in ops:
+        for a in range(3):
+            r = ldni.ldni_boolean(L[0][a], L[1][a], op)
+            n_out += int(r.view(a).n_samples)
+            n_in += L[0][a].n + L[1][a].n
+            r.free()
+
+    def step():
+        for op in ops:
+            for a in range(3):
+                ldni.ldni_boolean(L[0][a], L[1][a], op).free()
+
+    for _ in range(2):
+        step()
+    with Timer(torch) as t:
+        for _ in range(reps):
+            step()
+    ms = t.ms / reps
+    ldni.profile_enable(True)
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ldni.profile_enable(False)
+    ks = ldni.profile_read()
+    calls = 9
+    # algorithmic bytes: both inputs' offsets and depths, the kept samples'
+    # normal and id, the result's offsets and samples
+    alg = calls * 12 * (npix + 1) + 4 * n_in + 36 * n_out
+    kern = {k: round(v[1] / reps, 4) for k, v in ks.items() if k.startswith("boolean")}
+    # the count pass alone must read both inputs' offsets and depths and
+    # write the counts; the write pass also the kept samples and the result
+    cnt_bytes = calls * 12 * (npix + 1) + 4 * n_in
+    wr_bytes = calls * 16 * (npix + 1) + 4 * n_in + 36 * n_out
+    def roof(name, b):
+        if name not in ks or ks[name][1] <= 0:
+            return None
+        gbs = b / (ks[name][1] / reps / 1e3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": b}
+    return {
+        "workload": "boolean-2048",
+        "description": "union, intersection and difference of scene64 (seed 1) and scene64 (seed 7) "
+                       "LDNIs at w=2048, 3 axes each",
+        "input_samples_per_step": n_in, "output_samples_per_step": n_out,
+        "ms_per_step": round(ms, 4),
+        "value": n_in / (ms / 1e3), "unit": "input samples/s",
+        "path_roofline": {"algorithmic_bytes_per_step": alg,
+                          "achieved_GBps": round(alg / (ms / 1e3) / 1e9, 1),
+                          "frac_of_hbm_peak": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "count_roofline": roof("boolean_count", cnt_bytes),
+        "write_roofline": roof("boolean_write", wr_bytes),
+        "kernels_ms_per_step": kern,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
-                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd"],
+                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd", "boolean-2048"],
                     help="measure one part only (default: the headline plus every part)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -387,6 +458,13 @@ def main():
                          "config": {"workload": "flower-512 forward+backward",
                                     "parallelism": "single GPU"}})
         line["fwd_bwd"] = rf
+    if args.workload in (None, "boolean-2048"):
+        ro = measure_boolean(ldni, torch, mg, reps=max(2, args.steps // 4))
+        if args.workload == "boolean-2048":
+            line.update({"value": round(ro["value"], 1), "ms_per_step": ro["ms_per_step"],
+                         "config": {"workload": "boolean-2048", "description": ro["description"],
+                                    "parallelism": "single GPU"}})
+        line["boolean"] = ro
     print(json.dumps(line), flush=True)
 
 

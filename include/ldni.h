@@ -173,6 +173,40 @@ ldni_status ldni_backward(const float *verts, int64_t n_verts, const int32_t *tr
                           const ldni_axis_view views[3], const float *const grad_depth[3],
                           const float *const grad_normal[3], float *grad_verts, void *hip_stream);
 
+/*
+ * ldni_boolean -- Boolean operation of two solids given as LDNIs of one axis
+ * sampled on the same grid (same box and w), Sec. 4.1 and Fig. 5: in every
+ * pixel a solid's samples, read as consecutive (enter, exit) pairs, bound its
+ * 1D volumes, and the result keeps the volumes where the operation holds
+ *   LDNI_UNION         inside A or inside B,
+ *   LDNI_INTERSECTION  inside A and inside B,
+ *   LDNI_DIFFERENCE    inside A and not inside B (end points that come from
+ *                      B get their normal reversed);
+ * then every volume thinner than eps is removed (small interval removal,
+ * Sec. 4.1.1; the paper uses eps = 1e-5).
+ * Readings fixed here: an unpaired last sample of a pixel (odd count) bounds
+ * nothing and is ignored; volumes that touch merge, so the result never
+ * holds a zero-thickness gap or sliver (thickness (double)exit -
+ * (double)enter must be > 0 and >= eps); an end point at depth d is A's first
+ * sample at d if A has one, else B's first sample at d.
+ *   a, b    HOST views (ldni_axis_view) of the two inputs: w, n_samples and
+ *           device offsets/depth/normal/tri as a sampling result lays them
+ *           out (per pixel ascending depth).  Offsets must be a prefix of the
+ *           samples (non-decreasing, at most n_samples); the call fails with
+ *           LDNI_ERR_INVALID_ARG when the device finds they are not.
+ *   op      LDNI_UNION, LDNI_INTERSECTION or LDNI_DIFFERENCE.
+ *   eps     finite, >= 0.
+ *   axis    0..2: which view of *out holds the result (the others are empty).
+ *   out     a new result owned by the caller (ldni_free); samples are copies
+ *           of input samples (a B normal negated for the difference), and
+ *           tri holds A's triangle id t as t and B's as -1 - t.
+ * One host synchronisation (the result size); inputs must stay valid until
+ * the work queued on hip_stream has run.
+ */
+enum { LDNI_UNION = 0, LDNI_INTERSECTION = 1, LDNI_DIFFERENCE = 2 };
+ldni_status ldni_boolean(const ldni_axis_view *a, const ldni_axis_view *b, int32_t op, float eps,
+                         int32_t axis, void *hip_stream, ldni_result **out);
+
 /* Largest per-pixel count of each axis of a plan (after begin). */
 ldni_status ldni_plan_max_layers(const ldni_plan *plan, uint32_t max_layers[3]);
 

@@ -22,7 +22,8 @@ from ._lib import LDNIError
 __all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ldni_free", "ldni_trim",
            "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
            "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read",
-           "ldni_backward", "sample_diff", "LDNISample", "Batch", "sample_batch"]
+           "ldni_backward", "sample_diff", "LDNISample", "Batch", "sample_batch", "ldni_boolean",
+           "boolean", "BOOLEAN_OPS"]
 
 AXES = "xyz"
 library_path = _lib.LIB_PATH
@@ -307,6 +308,32 @@ def ldni_sample(verts, tris, bbox, w: int, axes="xyz", stream=None) -> Result:
                                       tris.shape[0], _bbox(bbox), int(w), axis_mask(axes), st,
                                       ctypes.byref(h)))
     return Result(h)
+
+
+BOOLEAN_OPS = {"union": 0, "intersection": 1, "difference": 2}
+
+
+def ldni_boolean(a: LDNI, b: LDNI, op, eps: float = 1e-5, stream=None) -> Result:
+    """The C ABI ``ldni_boolean``: Boolean operation (Sec. 4.1, small interval
+    removal Sec. 4.1.1) of two LDNIs of one axis sampled on the same grid; the
+    library owns the result, whose view ``a.axis`` holds it."""
+    if isinstance(op, str):
+        op = BOOLEAN_OPS[op]
+    h = ctypes.c_void_p()
+    st = _stream(a.depth.device) if stream is None else ctypes.c_void_p(stream)
+    va, vb = _view(a), _view(b)
+    _lib.check(_lib.lib().ldni_boolean(ctypes.byref(va), ctypes.byref(vb), int(op), float(eps),
+                                       int(a.axis), st, ctypes.byref(h)))
+    return Result(h)
+
+
+def boolean(a: LDNI, b: LDNI, op, eps: float = 1e-5) -> LDNI:
+    """``ldni_boolean`` with the result copied into new torch tensors."""
+    r = ldni_boolean(a, b, op, eps)
+    try:
+        return _copy_view(r.view(a.axis), a.axis, a.depth.device)
+    finally:
+        r.free()
 
 
 def _copy_view(v: _lib.AxisView, axis: int, device) -> LDNI:

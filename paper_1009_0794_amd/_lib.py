@@ -95,6 +95,9 @@ def lib():
     L.ldni_batch_axis.restype = st
     L.ldni_batch_free.argtypes = [vp]
     L.ldni_batch_free.restype = None
+    L.ldni_boolean.argtypes = [ctypes.POINTER(AxisView), ctypes.POINTER(AxisView), i32, ctypes.c_float, i32,
+                               vp, ctypes.POINTER(vp)]
+    L.ldni_boolean.restype = st
     L.ldni_profile_enable.argtypes = [ctypes.c_int]
     L.ldni_profile_enable.restype = st
     L.ldni_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -129,4 +132,5 @@ def exported_symbols():
             "ldni_sample_finish", "ldni_plan_free", "ldni_plan_max_layers",
             "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
-            "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch"]
+            "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch",
+            "ldni_boolean"]

@@ -508,7 +508,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.tile_region = reinterpret_cast<uint32_t*>(ws + o_treg) + k * n_tiles;
     im.tile_list = nullptr;
     im.counts = reinterpret_cast<uint32_t*>(ws + o_counts[k]);
-    im.max_layers = status + 1 + k;
+    im.max_layers = nullptr;  // the pixel scan writes status[1 + k]
     im.offsets = offsets[a];
     im.status = status;
     im.tile_stage = reinterpret_cast<uint32_t*>(ws + o_tstage[k]);
@@ -612,15 +612,17 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   gather_src[n_gather++] = set.plan + 2 * n_all;     // place items
   const uint32_t* counts_k[kMaxImages];
   uint32_t* offsets_k[kMaxImages];
+  uint32_t* max_k[kMaxImages];  // largest count of each image
   for (int k = 0; k < nimg; ++k) {
     counts_k[k] = set.img[k].counts;
     offsets_k[k] = set.img[k].offsets;
+    max_k[k] = status + 1 + k;
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
     STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
     STEP(timed("sample", stream, [&] { return launch_sample(set, stream); }), "sampling kernel");
     STEP(timed("scan_pixels", stream, [&] {
-           return launch_scan_segments(counts_k, offsets_k, nimg, npix, scan_scratch, status, stream);
+           return launch_scan_segments(counts_k, offsets_k, nimg, npix, scan_scratch, status, stream, max_k);
          }), "pixel scan");
     STEP(timed("plan_items", stream, [&] {
            return launch_plan_items(set, p->items, scan_scratch, status, stream);
@@ -892,6 +894,110 @@ ldni_status ldni_trim(void) {
   }
   if (have_cur) (void)hipSetDevice(cur);
   return ok ? LDNI_OK : fail(LDNI_ERR_DEVICE, "releasing cached buffers");
+}
+
+ldni_status ldni_boolean(const ldni_axis_view* a, const ldni_axis_view* b, int32_t op, float eps,
+                         int32_t axis, void* hip_stream, ldni_result** out) {
+  if (out) *out = nullptr;
+  if (!out || !a || !b) return fail(LDNI_ERR_INVALID_ARG, "NULL argument");
+  if (op < LDNI_UNION || op > LDNI_DIFFERENCE)
+    return fail(LDNI_ERR_INVALID_ARG, "op must be LDNI_UNION, LDNI_INTERSECTION or LDNI_DIFFERENCE");
+  if (axis < 0 || axis > 2) return fail(LDNI_ERR_INVALID_ARG, "axis must be 0, 1 or 2");
+  if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(LDNI_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (a->w < 1 || a->w > 16384 || a->w != b->w)
+    return fail(LDNI_ERR_INVALID_ARG, "both views need the same w in [1, 16384]");
+  for (const ldni_axis_view* v : {a, b}) {
+    if (!v->offsets) return fail(LDNI_ERR_INVALID_ARG, "NULL offsets");
+    if (v->n_samples > 0 && (!v->depth || !v->normal || !v->tri))
+      return fail(LDNI_ERR_INVALID_ARG, "NULL sample array of a view with samples");
+    if (v->n_samples > 0xffffffffull) return fail(LDNI_ERR_INVALID_ARG, "a view has 2^32 or more samples");
+  }
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  prepare_pool(device);
+  uint32_t* rb = pinned_readback();
+  if (!rb) return fail(LDNI_ERR_OUT_OF_MEMORY, "pinned readback buffer");
+  const int32_t w = a->w;
+  const int64_t npix = (int64_t)w * w;
+
+  ldni_result* r = new (std::nothrow) ldni_result();
+  if (!r) return fail(LDNI_ERR_OUT_OF_MEMORY, "result");
+  std::memset(r->view, 0, sizeof(r->view));
+  r->stream = stream;
+  hipError_t e = cache_get(&r->offsets_buf, sizeof(uint32_t) * (size_t)(npix + 1), stream, &r->offsets_bytes);
+  if (e != hipSuccess) {
+    r->offsets_buf = nullptr;
+    ldni_free(r);
+    return hip_fail(e, "offsets allocation");
+  }
+  // workspace: status words ([0] status, [1] max layers), scan partials, the
+  // kept samples' sources (one word per input sample)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  const size_t o_refs = align_up(256 + scan_scratch_bytes(npix, 1));
+  e = cache_get(&ws, o_refs + sizeof(uint32_t) * (size_t)(a->n_samples + b->n_samples), stream, &ws_bytes);
+  if (e != hipSuccess) {
+    ldni_free(r);
+    return hip_fail(e, "workspace allocation");
+  }
+  auto bail = [&](ldni_status st) {
+    cache_put(ws, ws_bytes, stream);
+    ldni_free(r);
+    return st;
+  };
+  uint32_t* status = static_cast<uint32_t*>(ws);
+  uint32_t* counts = static_cast<uint32_t*>(r->offsets_buf);
+  BooleanArgs g{};
+  g.a = AxisArrays{a->n_samples, static_cast<const uint32_t*>(a->offsets), static_cast<const float*>(a->depth),
+                   static_cast<const float*>(a->normal), static_cast<const int32_t*>(a->tri)};
+  g.b = AxisArrays{b->n_samples, static_cast<const uint32_t*>(b->offsets), static_cast<const float*>(b->depth),
+                   static_cast<const float*>(b->normal), static_cast<const int32_t*>(b->tri)};
+  g.npix = npix;
+  g.op = op;
+  g.eps = (double)eps;
+  g.counts = counts;
+  g.refs = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + o_refs);
+  g.status = status;
+#define BSTEP(expr, what)                                  \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return bail(hip_fail(e_, what)); \
+  } while (0)
+  BSTEP(launch_fill_u32(status, 0u, 64, stream), "fill");
+  BSTEP(timed("boolean_count", stream, [&] { return launch_boolean(g, false, stream); }), "Boolean count kernel");
+  BSTEP(timed("boolean_scan", stream, [&] {
+          return launch_scan(counts, counts, npix, static_cast<char*>(ws) + 256, status, stream, status + 1);
+        }), "Boolean scan");
+  const uint32_t* src[3] = {status, status + 1, counts + npix};
+  BSTEP(launch_gather(src, 3, rb, stream), "readback");
+  BSTEP(hipStreamSynchronize(stream), "synchronise");
+  if (rb[0] & kStatusMismatch) return bail(fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples"));
+  if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more result samples"));
+  const uint64_t n = rb[2];
+  size_t o_normal = align_up(sizeof(float) * n), o_tri = align_up(o_normal + sizeof(float) * 3 * n);
+  e = cache_get(&r->samples_buf, o_tri + sizeof(int32_t) * n, stream, &r->samples_bytes);
+  if (e != hipSuccess) {
+    r->samples_buf = nullptr;
+    return bail(hip_fail(e, "sample allocation"));
+  }
+  char* sb = static_cast<char*>(r->samples_buf);
+  g.out_depth = reinterpret_cast<float*>(sb);
+  g.out_normal = reinterpret_cast<float*>(sb + o_normal);
+  g.out_tri = reinterpret_cast<int32_t*>(sb + o_tri);
+  BSTEP(timed("boolean_write", stream, [&] { return launch_boolean(g, true, stream); }), "Boolean write kernel");
+#undef BSTEP
+  cache_put(ws, ws_bytes, stream);
+  ldni_axis_view& v = r->view[axis];
+  v.w = w;
+  v.max_layers = rb[1];
+  v.n_samples = n;
+  v.offsets = counts;
+  v.depth = g.out_depth;
+  v.normal = g.out_normal;
+  v.tri = g.out_tri;
+  *out = r;
+  return LDNI_OK;
 }
 
 void ldni_free(ldni_result* r) {

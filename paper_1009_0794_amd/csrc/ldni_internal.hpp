@@ -54,7 +54,8 @@ struct Image {
                         // | (height - 1) << 24, tile-local pixels)
   uint64_t list_cap;    // capacity of tile_list (entries beyond it are dropped)
   uint32_t* counts;     // [w*w] samples per pixel
-  uint32_t* max_layers; // [1]
+  uint32_t* max_layers; // [1] largest per-pixel count (atomic max per tile), or null
+                        // when the pixel scan takes it
   // outputs
   uint32_t* offsets;  // [w*w + 1]
   float* depth;       // [n]
@@ -217,6 +218,30 @@ struct BackwardArgs {
 };
 hipError_t launch_backward(const BackwardArgs& args, hipStream_t s);
 
+// ---- Boolean operations on two LDNIs of one axis (ldni_boolean.hip) ----
+constexpr int kBoolUnion = 0, kBoolIntersection = 1, kBoolDifference = 2;
+struct AxisArrays {
+  uint64_t n;               // samples
+  const uint32_t* offsets;  // [npix + 1]
+  const float* depth;
+  const float* normal;      // [n][3]
+  const int32_t* tri;
+};
+struct BooleanArgs {
+  AxisArrays a, b;
+  int64_t npix;
+  int32_t op;
+  double eps;             // volumes thinner than this are removed
+  uint32_t* counts;       // [npix + 1]: kept samples per pixel (count pass),
+                          // scanned in place into the result offsets (write pass)
+  uint32_t* refs;         // [a.n + b.n]: sources of the kept samples (count pass)
+  uint32_t* status;       // kStatusMismatch: offsets of an input out of order
+  float* out_depth;
+  float* out_normal;
+  int32_t* out_tri;
+};
+hipError_t launch_boolean(const BooleanArgs& g, bool write, hipStream_t s);
+
 // Copies n (<= 16) device words into pinned, device-visible host memory.
 // Copies n <= kMaxGather scattered device words to pinned host memory.
 constexpr int kMaxGather = 32;
@@ -224,13 +249,16 @@ hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, 
 
 // Exclusive scan of n u32 values into out[0..n] (out[n] = total).  Totals of
 // 2^32 or more raise kStatusOverflow.  scratch: scan_scratch_bytes(n, 1).
+// max_out (if given) receives the largest value.
 size_t scan_scratch_bytes(int64_t n, int nseg = 1);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
-                       uint32_t* status, hipStream_t s);
+                       uint32_t* status, hipStream_t s, uint32_t* max_out = nullptr);
 // nseg <= kMaxImages such scans of n values each, in one set of launches
-// (in place allowed); scratch: scan_scratch_bytes(n, nseg).
+// (in place allowed); scratch: scan_scratch_bytes(n, nseg); max_out[k] as
+// above per segment.
 hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
-                                void* scratch, uint32_t* status, hipStream_t s);
+                                void* scratch, uint32_t* status, hipStream_t s,
+                                uint32_t* const* max_out = nullptr);
 // The tile scan: entry counts -> list offsets (as launch_scan), and in the
 // same launches candidate counts -> staging regions, each tile's count
 // capped at region_cap and the prefix saturating at 2^32 - 1 (in place

@@ -772,9 +772,11 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
     mx = max(mx, c);
     im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = c;
   }
-  mx = block_max(mx, s_red);
+  // (the single-mesh path takes the largest count from the pixel scan instead
+  // of one same-address atomic per tile)
+  if (im.max_layers != nullptr) mx = block_max(mx, s_red);
   if (threadIdx.x == 0) {
-    if (mx > 0) atomicMax(im.max_layers, mx);
+    if (im.max_layers != nullptr && mx > 0) atomicMax(im.max_layers, mx);
     const uint32_t hits = s_fill;
     const bool staged = hits <= region_size;
     im.tile_hits[tile] = hits;
@@ -1452,6 +1454,7 @@ struct ScanSegs {
   const uint32_t* in[kMaxImages];
   uint32_t* out[kMaxImages];
   uint32_t* total[kMaxImages];
+  uint32_t* max_out[kMaxImages];  // largest value of the segment, or null
   uint32_t cap[kMaxImages];
   uint32_t sat;
   int64_t n;
@@ -1467,11 +1470,20 @@ __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(ScanSegs sg, uint64
   uint32_t v[16];
   load16(sg.in[seg], sg.n, i, sg.cap[seg], v);
   uint64_t s = 0;
+  uint32_t m = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) s += v[k];
+  for (int k = 0; k < 16; ++k) {
+    s += v[k];
+    m = max(m, v[k]);
+  }
   uint64_t total;
   block_exclusive_scan<uint64_t>(s, s_w, total);
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
+  if (sg.max_out[seg] != nullptr) {  // the spine takes the largest of these
+    __shared__ uint32_t s_m[kWaves];
+    m = block_max(m, s_m);
+    if (threadIdx.x == 0) partial[(int64_t)sg.nb * sg.nseg + 2 + blockIdx.x] = m;
+  }
 }
 
 // One workgroup per segment: exclusive scan of its per-tile partial sums,
@@ -1479,15 +1491,24 @@ __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(ScanSegs sg, uint64
 __global__ void __launch_bounds__(kBlock) scan_spine_kernel(ScanSegs sg, uint64_t* partial,
                                                              uint32_t* status) {
   __shared__ uint64_t s_w[kWaves];
+  __shared__ uint32_t s_m[kWaves];
   uint64_t* part = partial + (int64_t)blockIdx.x * sg.nb;
+  const uint64_t* pmax = partial + (int64_t)sg.nb * sg.nseg + 2 + (int64_t)blockIdx.x * sg.nb;
+  const bool want_max = sg.max_out[blockIdx.x] != nullptr;
   uint64_t carry = 0;
+  uint32_t m = 0;
   for (int64_t base = 0; base < sg.nb; base += kBlock) {
     const int64_t q = base + threadIdx.x;
     const uint64_t x = q < sg.nb ? part[q] : 0;
+    if (want_max && q < sg.nb) m = max(m, (uint32_t)pmax[q]);
     uint64_t total;
     const uint64_t e = block_exclusive_scan<uint64_t>(x, s_w, total);
     if (q < sg.nb) part[q] = carry + e;
     carry += total;
+  }
+  if (want_max) {
+    m = block_max(m, s_m);
+    if (threadIdx.x == 0) *sg.max_out[blockIdx.x] = m;
   }
   if (threadIdx.x == 0) {
     const bool sat = (sg.sat >> blockIdx.x) & 1u;
@@ -1932,9 +1953,10 @@ hipError_t launch_batch_finish_counts(const BatchDevice& b, hipStream_t s) {
   return hipGetLastError();
 }
 
+// partial sums of the workgroups, two spare words, then their largest values
 size_t scan_scratch_bytes(int64_t n, int nseg) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  return (size_t)((nb > 0 ? nb : 1) * (nseg > 0 ? nseg : 1) + 2) * sizeof(uint64_t);
+  return (size_t)(2 * (nb > 0 ? nb : 1) * (nseg > 0 ? nseg : 1) + 2) * sizeof(uint64_t);
 }
 
 static hipError_t run_scan(const ScanSegs& sg, void* scratch, uint32_t* status, hipStream_t s) {
@@ -1947,7 +1969,7 @@ static hipError_t run_scan(const ScanSegs& sg, void* scratch, uint32_t* status, 
 }
 
 hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
-                                void* scratch, uint32_t* status, hipStream_t s) {
+                                void* scratch, uint32_t* status, hipStream_t s, uint32_t* const* max_out) {
   if (nseg < 1 || nseg > kMaxImages) return hipErrorInvalidValue;
   if (n <= 0) {
     for (int k = 0; k < nseg; ++k) {
@@ -1961,6 +1983,7 @@ hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out,
     sg.in[k] = in[k];
     sg.out[k] = out[k];
     sg.total[k] = out[k] + n;
+    sg.max_out[k] = max_out ? max_out[k] : nullptr;
     sg.cap[k] = 0xffffffffu;
   }
   sg.n = n;
@@ -1992,8 +2015,8 @@ hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scratch,
-                       uint32_t* status, hipStream_t s) {
-  return launch_scan_segments(&in, &out, 1, n, scratch, status, s);
+                       uint32_t* status, hipStream_t s, uint32_t* max_out) {
+  return launch_scan_segments(&in, &out, 1, n, scratch, status, s, max_out ? &max_out : nullptr);
 }
 
 }  // namespace ldni

@@ -155,3 +155,33 @@ def test_begin_rejects_misaligned_offsets(L):
     assert L.ldni_sample_begin(0x2000, 3, 0x3000, 1, bb, 8, 1, offs, None, ctypes.byref(plan), n) == 1
     assert "aligned" in L.ldni_last_error().decode()
     assert plan.value is None
+
+
+def _bool_call(L, a=True, b=True, op=0, eps=1e-5, axis=0, wa=8, wb=8, offsets=True, n=0, samples=True):
+    from paper_1009_0794_amd import _lib
+    def view(w):
+        v = _lib.AxisView()
+        v.w, v.n_samples = w, n
+        v.offsets = 4096 if offsets else None
+        if samples:
+            v.depth = v.normal = v.tri = 8192
+        return v
+    va, vb = view(wa), view(wb)
+    out = ctypes.c_void_p(123)
+    rc = L.ldni_boolean(ctypes.byref(va) if a else None, ctypes.byref(vb) if b else None, op, eps,
+                        axis, None, ctypes.byref(out))
+    return rc, out.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(a=False), dict(b=False), dict(op=-1), dict(op=3), dict(eps=-1e-5), dict(eps=float("nan")),
+    dict(eps=float("inf")), dict(axis=3), dict(axis=-1), dict(wa=8, wb=9), dict(wa=0, wb=0),
+    dict(wa=16385, wb=16385), dict(offsets=False), dict(n=5, samples=False), dict(n=2 ** 32),
+])
+def test_boolean_invalid_arguments_rejected_on_host(L, kw):
+    """ldni_boolean (Sec. 4.1) checks its arguments before any device work
+    (the fake device pointers here are never dereferenced)."""
+    rc, out = _bool_call(L, **kw)
+    assert rc == 1
+    assert out is None
+    assert L.ldni_last_error().decode()

@@ -1,0 +1,179 @@
+"""Parity of the HIP Boolean operations (Sec. 4.1; small interval removal,
+Sec. 4.1.1) with the CPU oracle.  The results are copies of input samples,
+so offsets, depths, normals and ids must match bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import boolean as ob
+import paper_1009_0794_amd as ldni
+from paper_1009_0794_amd import meshgen as mg
+from paper_1009_0794_amd._lib import LDNIError
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+BBOX = [-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]
+OPS = ("union", "intersection", "difference")
+
+
+def _to_gpu(axis, a: oracle.AxisLDNI) -> ldni.LDNI:
+    cnt = np.diff(a.offsets.astype(np.int64))
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    return ldni.LDNI(axis, a.w, int(cnt.max()) if cnt.size else 0, t(a.offsets.view(np.int32)),
+                     t(a.depth.astype(np.float32)), t(a.normal.astype(np.float32).reshape(-1, 3)),
+                     t(a.tri.astype(np.int32)))
+
+
+def _to_cpu(g: ldni.LDNI) -> oracle.AxisLDNI:
+    return oracle.AxisLDNI(w=g.w, offsets=g.offsets.cpu().numpy().view(np.uint32),
+                           depth=g.depth.cpu().numpy(), normal=g.normal.cpu().numpy(),
+                           tri=g.tri.cpu().numpy())
+
+
+def _same(got: ldni.LDNI, ref: oracle.AxisLDNI, label):
+    off = got.offsets.cpu().numpy().view(np.uint32)
+    assert np.array_equal(off, ref.offsets), f"{label}: offsets"
+    assert np.array_equal(got.depth.cpu().numpy().view(np.uint32), ref.depth.view(np.uint32)), f"{label}: depth"
+    assert np.array_equal(got.normal.cpu().numpy().view(np.uint32).reshape(-1, 3),
+                          ref.normal.view(np.uint32).reshape(-1, 3)), f"{label}: normal"
+    assert np.array_equal(got.tri.cpu().numpy(), ref.tri), f"{label}: tri"
+    cnt = np.diff(off.astype(np.int64))
+    assert got.max_layers == (int(cnt.max()) if cnt.size else 0), f"{label}: max layers"
+
+
+def _random_ldni(rng, w, levels=24, max_n=9):
+    """Sorted small-integer depths (many ties within and across solids), odd
+    counts and empty pixels included; random unit normals and ids."""
+    cnt = rng.integers(0, max_n, w * w)
+    cnt[rng.random(w * w) < 0.2] = 0
+    offsets = np.zeros(w * w + 1, np.uint32)
+    offsets[1:] = np.cumsum(cnt)
+    depth = np.concatenate([np.sort(rng.integers(0, levels, c)).astype(np.float32) * np.float32(0.125)
+                            for c in cnt] + [np.zeros(0, np.float32)])
+    n = int(offsets[-1])
+    nrm = rng.normal(size=(n, 3)).astype(np.float32)
+    return oracle.AxisLDNI(w=w, offsets=offsets, depth=depth, normal=nrm,
+                           tri=rng.integers(0, 1 << 30, n).astype(np.int32))
+
+
+@pytest.mark.parametrize("seed,w", [(0, 1), (1, 37), (2, 64)])
+def test_random_lists_match_oracle(seed, w):
+    rng = np.random.default_rng(seed)
+    a, b = _random_ldni(rng, w), _random_ldni(rng, w)
+    ga, gb = _to_gpu(1, a), _to_gpu(1, b)
+    for op in OPS:
+        for eps in (0.0, 1e-5, 0.3):
+            got = ldni.boolean(ga, gb, op, eps)
+            torch.cuda.synchronize()
+            assert got.axis == 1
+            _same(got, ob.boolean(a, b, op, eps), f"w={w} {op} eps={eps}")
+
+
+def test_empty_inputs():
+    rng = np.random.default_rng(5)
+    a = _random_ldni(rng, 16)
+    z = oracle.AxisLDNI(w=16, offsets=np.zeros(257, np.uint32), depth=np.zeros(0, np.float32),
+                        normal=np.zeros((0, 3), np.float32), tri=np.zeros(0, np.int32))
+    ga, gz = _to_gpu(0, a), _to_gpu(0, z)
+    for op in OPS:
+        _same(ldni.boolean(ga, gz, op), ob.boolean(a, z, op), f"A {op} empty")
+        _same(ldni.boolean(gz, ga, op), ob.boolean(z, a, op), f"empty {op} A")
+        assert ldni.boolean(gz, gz, op).depth.numel() == 0
+
+
+def _meshes():
+    va, fa = mg.icosphere(3, radius=0.7)
+    vb, fb = mg.torus(48, 24, 0.5, 0.22, center=(0.3, 0.1, 0.05))
+    return (va, fa), (vb, fb)
+
+
+def _sample(v, f, w):
+    vt = torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(DEV)
+    ft = torch.from_numpy(np.ascontiguousarray(f, np.int32)).to(DEV)
+    out = ldni.sample(vt, ft, BBOX, w, "xyz")
+    torch.cuda.synchronize()
+    return out
+
+
+def test_sampled_solids_match_oracle():
+    (va, fa), (vb, fb) = _meshes()
+    A, B = _sample(va, fa, 96), _sample(vb, fb, 96)
+    for axis in range(3):
+        a, b = _to_cpu(A[axis]), _to_cpu(B[axis])
+        for op in OPS:
+            got = ldni.boolean(A[axis], B[axis], op)
+            assert got.depth.numel() > 0
+            _same(got, ob.boolean(a, b, op), f"axis {axis} {op}")
+
+
+def test_intersection_minus_a_is_empty():
+    """Sec. 4.1.1: on one grid, (A n B) - A is empty, and (A u B) n A has
+    exactly A's depths."""
+    (va, fa), (vb, fb) = _meshes()
+    A, B = _sample(va, fa, 128), _sample(vb, fb, 128)
+    for axis in range(3):
+        inter = ldni.boolean(A[axis], B[axis], "intersection")
+        assert inter.depth.numel() > 0
+        assert ldni.boolean(inter, A[axis], "difference").depth.numel() == 0
+        ua = ldni.boolean(ldni.boolean(A[axis], B[axis], "union"), A[axis], "intersection")
+        assert torch.equal(ua.offsets, A[axis].offsets)
+        assert torch.equal(ua.depth, A[axis].depth)
+
+
+def test_large_grid_band_matches_oracle():
+    """Two different seeded scenes at w = 2048 (the largest workload's grid):
+    a band of rows against the oracle, and every pixel's result sorted with
+    an even count."""
+    A = _sample(*_scene(1), 2048)
+    B = _sample(*_scene(7), 2048)
+    w = 2048
+    for axis, op in ((0, "union"), (1, "intersection"), (2, "difference")):
+        got = ldni.boolean(A[axis], B[axis], op)
+        off = got.offsets.cpu().numpy().view(np.uint32).astype(np.int64)
+        cnt = np.diff(off)
+        assert (cnt % 2 == 0).all()
+        dep = got.depth.cpu().numpy()
+        if dep.size > 1:
+            d = np.diff(dep)
+            first = np.zeros(dep.size, bool)
+            first[off[:-1][cnt > 0]] = True
+            assert (d[~first[1:]] > 0).all()  # strictly increasing inside a pixel
+        rows = slice(1000 * w, 1008 * w)  # 8 rows: 128 x 128 pixels
+        a, b = _band(_to_cpu(A[axis]), rows), _band(_to_cpu(B[axis]), rows)
+        ref = ob.boolean(a, b, op)
+        band = _band(_to_cpu(got), rows)
+        for name in ("offsets", "depth", "tri"):
+            assert np.array_equal(getattr(band, name), getattr(ref, name)), f"axis {axis} {op}: {name}"
+        assert np.array_equal(band.normal.view(np.uint32), ref.normal.view(np.uint32))
+
+
+def _scene(seed):
+    m = mg.c3_scene64(seed=seed)
+    return m.verts, m.tris
+
+
+def _band(x: oracle.AxisLDNI, rows: slice) -> oracle.AxisLDNI:
+    """Pixels [rows.start, rows.stop) as an LDNI of their own (the operation
+    is per pixel, so a band of n = m*m pixels can stand as an m x m grid)."""
+    o = x.offsets.astype(np.int64)
+    s, e = int(o[rows.start]), int(o[rows.stop])
+    n = rows.stop - rows.start
+    m = int(round(np.sqrt(n)))
+    assert m * m == n
+    return oracle.AxisLDNI(w=m, offsets=(o[rows.start:rows.stop + 1] - s).astype(np.uint32),
+                           depth=x.depth[s:e], normal=x.normal[s:e].reshape(-1, 3), tri=x.tri[s:e])
+
+
+def test_bad_offsets_rejected():
+    rng = np.random.default_rng(3)
+    a = _random_ldni(rng, 8)
+    ga = _to_gpu(2, a)
+    bad = ldni.LDNI(2, 8, ga.max_layers, ga.offsets.clone(), ga.depth, ga.normal, ga.tri)
+    bad.offsets[5] = bad.offsets[6] + 3  # decreasing offsets
+    with pytest.raises(LDNIError) as e:
+        ldni.boolean(ga, bad, "union")
+    assert e.value.code == 1
+    # a well-formed call afterwards still works
+    _same(ldni.boolean(ga, ga, "union"), ob.boolean(a, a, "union"), "after error")
