@@ -509,6 +509,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.tile_list = nullptr;
     im.counts = reinterpret_cast<uint32_t*>(ws + o_counts[k]);
     im.max_layers = nullptr;  // the pixel scan writes status[1 + k]
+    im.tile_max = nullptr;
     im.offsets = offsets[a];
     im.status = status;
     im.tile_stage = reinterpret_cast<uint32_t*>(ws + o_tstage[k]);
@@ -1346,6 +1347,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const int tile_pix = b->small ? 256 : 1024;
   const size_t o_tstage = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_thits = take(sizeof(uint32_t) * b->total_tiles);
+  const size_t o_tmax = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_walk = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_plan = take(sizeof(uint32_t) * (2 * b->total_tiles + 1));
   const size_t o_scan = take(std::max({scan_scratch_bytes(2 * (int64_t)b->total_tiles),
@@ -1386,6 +1388,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   D.place_cap = place_stage_cap(tile_pix);
   uint32_t* tstage = reinterpret_cast<uint32_t*>(ws + o_tstage);
   uint32_t* thits = reinterpret_cast<uint32_t*>(ws + o_thits);
+  uint32_t* tmax = reinterpret_cast<uint32_t*>(ws + o_tmax);
+  D.tile_max = tmax;
 
   b->meshes_h.assign(n_meshes, BatchMesh{});
   b->images_h.assign(n_img, Image{});
@@ -1436,6 +1440,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.tile_region = b->region_arena + b->tile_start[k];
     im.tile_stage = tstage + b->tile_start[k];
     im.tile_hits = thits + b->tile_start[k];
+    im.tile_max = tmax + b->tile_start[k];
     im.walk_list = D.walk_list;
     im.walk_count = D.walk_count;
   }

@@ -54,8 +54,9 @@ struct Image {
                         // | (height - 1) << 24, tile-local pixels)
   uint64_t list_cap;    // capacity of tile_list (entries beyond it are dropped)
   uint32_t* counts;     // [w*w] samples per pixel
-  uint32_t* max_layers; // [1] largest per-pixel count (atomic max per tile), or null
-                        // when the pixel scan takes it
+  uint32_t* max_layers; // [1] largest per-pixel count (atomic max per tile unless
+                        // tile_max is given), or null when the pixel scan takes it
+  uint32_t* tile_max;   // [n_tiles] largest count of each tile, or null
   // outputs
   uint32_t* offsets;  // [w*w + 1]
   float* depth;       // [n]
@@ -153,6 +154,7 @@ struct BatchDevice {
   const uint32_t* tri_block_start;  // [n_meshes+1] setup workgroups per mesh (prefix)
   const uint32_t* bin_block_start;  // [n_images+1] binning workgroups per image (prefix)
   const uint32_t* tile_start;       // [n_images+1] tiles per image (prefix)
+  const uint32_t* tile_max;         // [total tiles] largest count of each tile
   const uint64_t* seg_start;        // [n_images+1] first slot of each image in counts/offsets
   uint64_t* sample_base;            // [n_images] first sample of each image in the outputs
   uint32_t* work;                   // [2] work counters of the persistent kernels

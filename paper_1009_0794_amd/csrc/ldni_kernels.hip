@@ -614,6 +614,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
     if (threadIdx.x == 0) {
       im.tile_hits[tile] = 0u;
       im.tile_stage[tile] = 0u;
+      if (im.tile_max) im.tile_max[tile] = 0u;
       if (plan) {
         plan[gtile] = 0u;
         plan[n_total + gtile] = 0u;
@@ -772,11 +773,13 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
     mx = max(mx, c);
     im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = c;
   }
-  // (the single-mesh path takes the largest count from the pixel scan instead
-  // of one same-address atomic per tile)
-  if (im.max_layers != nullptr) mx = block_max(mx, s_red);
+  // The largest count: per tile for a later reduction (batches), else one
+  // atomic per tile if asked (the single-mesh path takes it from the pixel
+  // scan): atomics from every tile to one address would queue up.
+  if (im.tile_max != nullptr || im.max_layers != nullptr) mx = block_max(mx, s_red);
   if (threadIdx.x == 0) {
-    if (im.max_layers != nullptr && mx > 0) atomicMax(im.max_layers, mx);
+    if (im.tile_max != nullptr) im.tile_max[tile] = mx;
+    else if (im.max_layers != nullptr && mx > 0) atomicMax(im.max_layers, mx);
     const uint32_t hits = s_fill;
     const bool staged = hits <= region_size;
     im.tile_hits[tile] = hits;
@@ -1690,10 +1693,20 @@ __global__ void __launch_bounds__(kBlock) scan_apply_segmented_kernel(
   }
 }
 
-// One thread per image: sample count, placement in the output arena (or
-// the capacity flag), host summary.
+// One workgroup per image: its largest count (from its tiles' largest),
+// sample count, placement in the output arena (or the capacity flag), host
+// summary.
 __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice B) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  __shared__ uint32_t s_m[kWaves];
+  const int k = blockIdx.x;
+  if (k >= B.n_images) return;
+  Image& im = B.images[k];
+  uint32_t m = 0;
+  for (uint32_t t = B.tile_start[k] + threadIdx.x; t < B.tile_start[k + 1]; t += kBlock)
+    m = max(m, B.tile_max[t]);
+  m = block_max(m, s_m);
+  if (threadIdx.x != 0) return;
+  *im.max_layers = m;
   if (k == 0) {
     B.host_out[0] = *B.status;
     B.host_out[1] = *B.tile_total;
@@ -1702,8 +1715,7 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
     tail[1] = 0u;
     tail[2] = *B.walk_count;
   }
-  if (k < B.n_images) {
-    Image& im = B.images[k];
+  {
     const uint64_t n = im.offsets[(size_t)im.w * im.w];
     const uint64_t base = B.sample_base[k];
     const bool fits = base + n <= B.sample_cap && (uint64_t)*B.tile_total <= B.list_cap;
@@ -1714,7 +1726,7 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
     h[0] = (uint32_t)n;
     h[1] = (uint32_t)base;
     h[2] = (uint32_t)(base >> 32);
-    h[3] = *im.max_layers;  // the host compares n and base with the capacities
+    h[3] = m;  // the host compares n and base with the capacities
   }
   __threadfence_system();
 }
@@ -1948,8 +1960,8 @@ hipError_t launch_batch_pixel_scan(const BatchDevice& b, const uint32_t* counts,
 }
 
 hipError_t launch_batch_finish_counts(const BatchDevice& b, hipStream_t s) {
-  hipLaunchKernelGGL(batch_finish_counts_kernel, dim3(grid_for(b.n_images > 0 ? b.n_images : 1, kBlock)),
-                     dim3(kBlock), 0, s, b);
+  if (b.n_images == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_finish_counts_kernel, dim3((unsigned)b.n_images), dim3(kBlock), 0, s, b);
   return hipGetLastError();
 }
 
