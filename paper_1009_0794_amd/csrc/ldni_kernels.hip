@@ -1672,20 +1672,38 @@ __global__ void __launch_bounds__(kBlock) segment_base_kernel(const uint32_t* in
   if (threadIdx.x == 0) seg_base[blockIdx.x] = partial[b] + total;
 }
 
+// The workgroup finds the segment of its first value once; a thread whose 16
+// values lie in one segment stores them as four 16-byte vectors.
 __global__ void __launch_bounds__(kBlock) scan_apply_segmented_kernel(
     const uint32_t* in, int64_t n, const uint64_t* partial, const uint64_t* seg_start,
     const uint64_t* seg_base, int n_seg, uint32_t* out) {
   __shared__ uint64_t s_w[kWaves];
+  __shared__ int s_seg;
   const int64_t i = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  if (threadIdx.x == 0) s_seg = segment_of(seg_start, n_seg, (uint64_t)blockIdx.x * kScanTile);
   uint32_t v[16];
   load16(in, n, i, 0xffffffffu, v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
   uint64_t total;
-  uint64_t run = block_exclusive_scan<uint64_t>(s, s_w, total) + partial[blockIdx.x];
+  uint64_t run = block_exclusive_scan<uint64_t>(s, s_w, total) + partial[blockIdx.x];  // (barriers)
   if (i >= n) return;
-  int seg = segment_of(seg_start, n_seg, (uint64_t)i);
+  int seg = s_seg;
+  while (seg + 1 < n_seg && seg_start[seg + 1] <= (uint64_t)i) ++seg;
+  if (i + 16 <= n && (seg + 1 >= n_seg || seg_start[seg + 1] >= (uint64_t)(i + 16))) {
+    const uint64_t base = seg_base[seg];
+    uint32_t o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      o[k] = (uint32_t)(run - base);
+      run += v[k];
+    }
+    uint4* p = reinterpret_cast<uint4*>(out + i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    return;
+  }
   for (int k = 0; k < 16 && i + k < n; ++k) {
     while (seg + 1 < n_seg && seg_start[seg + 1] <= (uint64_t)(i + k)) ++seg;
     out[i + k] = (uint32_t)(run - seg_base[seg]);
