@@ -209,6 +209,27 @@ def measure_plain(ldni, torch, mesh, steps, warmup, workload):
     }
 
 
+def measure_rgb8(ldni, torch, mesh, steps):
+    """The approximate normal output (Sec. 3, 8 bits per component, one packed
+    word per sample) against float normals through the same torch-output
+    call (ldni_sample_begin/finish)."""
+    verts = torch.from_numpy(mesh.verts).cuda()
+    tris = torch.from_numpy(mesh.tris).cuda()
+    out = {}
+    for kind in ("f32", "rgb8"):
+        for _ in range(2):
+            ldni.sample(verts, tris, mesh.bbox, mesh.w, "xyz", normals=kind)
+        ldni.profile_enable(True)
+        with Timer(torch) as t:
+            for _ in range(steps):
+                ldni.sample(verts, tris, mesh.bbox, mesh.w, "xyz", normals=kind)
+        ldni.profile_enable(False)
+        ks = ldni.profile_read()
+        out[kind] = {"ms_per_step": round(t.ms / steps, 4),
+                     "place_ms": round(ks["place"][1] / steps, 4) if "place" in ks else None}
+    return {"bytes_per_sample": {"f32": 20, "rgb8": 12}, **out}
+
+
 def measure_batch(ldni, torch, mg, reps):
     """256 seeded meshes, each at its own w: one graph replay vs 256 plain
     ldni_sample calls on one stream."""
@@ -432,6 +453,7 @@ def main():
                                 "parallelism": "single GPU"},
                      "roofline": r["roofline"], "path_roofline": r["path_roofline"],
                      "kernels_ms_per_step": r["kernels_ms_per_step"]})
+        line["normal_rgb8"] = measure_rgb8(ldni, torch, mesh, max(2, args.steps // 2))
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_seconds)
         del mesh

@@ -144,6 +144,21 @@ ldni_status ldni_sample_begin(const float *verts, int64_t n_verts, const int32_t
                               uint64_t n_samples[3]);
 ldni_status ldni_sample_finish(ldni_plan *plan, float *const depth[3], float *const normal[3],
                                int32_t *const tri[3]);
+/*
+ * ldni_sample_finish_rgb8 -- ldni_sample_finish with the paper's approximate
+ * normal sampling (Sec. 3, "Approximate Surface Normal Sampling"; the
+ * accuracy trade-off under "Balance between time and accuracy"): each
+ * component c of a sample's unit normal is stored as the 8-bit colour of
+ * (c + 1) / 2, b = floor((c + 1) * 127.5 + 0.5) clamped to [0, 255]
+ * (float64 operations in that order), packed as x | y << 8 | z << 16 in one
+ * 32-bit word per sample (decode: c ~ b / 127.5 - 1, within 1/255).  Depth,
+ * triangle id, order and counts are those of ldni_sample_finish.
+ *   normal_rgb8  HOST array of 3 device u32 [n] pointers (entries of axes not
+ *                in the mask ignored).  Same ownership and errors as
+ *                ldni_sample_finish; the plan is released either way.
+ */
+ldni_status ldni_sample_finish_rgb8(ldni_plan *plan, float *const depth[3], uint32_t *const normal_rgb8[3],
+                                    int32_t *const tri[3]);
 void ldni_plan_free(ldni_plan *plan);
 
 /*

@@ -111,26 +111,33 @@ def ldni_sample_begin(verts, tris, bbox, w, axes="xyz"):
     return plan, offs, [int(x) for x in n]
 
 
-def ldni_sample_finish(plan, depth, normal, tri):
+def ldni_sample_finish(plan, depth, normal, tri, rgb8=False):
     """Second half: writes the samples into the given tensors (dicts by axis)
-    and releases the plan."""
+    and releases the plan.  With rgb8, ``normal`` holds int32 [n] tensors that
+    receive the 8-bit normal codes (``ldni_sample_finish_rgb8``)."""
     L = _lib.lib()
     d, nm, t = (ctypes.c_void_p * 3)(), (ctypes.c_void_p * 3)(), (ctypes.c_void_p * 3)()
     for a in depth:
         d[a], nm[a], t[a] = depth[a].data_ptr(), normal[a].data_ptr(), tri[a].data_ptr()
-    _lib.check(L.ldni_sample_finish(plan, d, nm, t))
+    fn = L.ldni_sample_finish_rgb8 if rgb8 else L.ldni_sample_finish
+    _lib.check(fn(plan, d, nm, t))
 
 
 def ldni_plan_free(plan):
     _lib.lib().ldni_plan_free(plan)
 
 
-def sample(verts, tris, bbox, w: int, axes="xyz") -> Dict[int, LDNI]:
+def sample(verts, tris, bbox, w: int, axes="xyz", normals="f32") -> Dict[int, LDNI]:
     """LDNIs of a mesh as torch tensors on the mesh's device.
 
     verts float32 [V,3] and tris int32 [T,3] (counter-clockwise seen from
     outside) on a HIP device; bbox = (xlo, ylo, zlo, xhi, yhi, zhi) on the host;
-    returns ``{axis: LDNI}`` for the requested axes."""
+    returns ``{axis: LDNI}`` for the requested axes.  normals="rgb8" stores the
+    paper's approximate normals: ``normal`` is then an int32 [n] tensor of
+    packed 8-bit codes (x | y << 8 | z << 16, component ~ byte / 127.5 - 1)."""
+    if normals not in ("f32", "rgb8"):
+        raise ValueError("normals must be 'f32' or 'rgb8'")
+    rgb8 = normals == "rgb8"
     torch = _torch()
     verts, tris = _check_mesh(verts, tris)
     plan, offs, n = ldni_sample_begin(verts, tris, bbox, w, axes)
@@ -142,12 +149,13 @@ def sample(verts, tris, bbox, w: int, axes="xyz") -> Dict[int, LDNI]:
         depth, normal, tri = {}, {}, {}
         for a in offs:
             depth[a] = torch.empty(n[a], dtype=torch.float32, device=dev)
-            normal[a] = torch.empty((n[a], 3), dtype=torch.float32, device=dev)
+            normal[a] = (torch.empty(n[a], dtype=torch.int32, device=dev) if rgb8 else
+                         torch.empty((n[a], 3), dtype=torch.float32, device=dev))
             tri[a] = torch.empty(n[a], dtype=torch.int32, device=dev)
     except BaseException:
         ldni_plan_free(plan)
         raise
-    ldni_sample_finish(plan, depth, normal, tri)
+    ldni_sample_finish(plan, depth, normal, tri, rgb8=rgb8)
     return {a: LDNI(a, int(w), int(ml[a]), offs[a], depth[a], normal[a], tri[a]) for a in offs}
 
 

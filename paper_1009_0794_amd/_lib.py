@@ -72,6 +72,8 @@ def lib():
     L.ldni_sample_begin.restype = st
     L.ldni_sample_finish.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
     L.ldni_sample_finish.restype = st
+    L.ldni_sample_finish_rgb8.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.ldni_sample_finish_rgb8.restype = st
     L.ldni_plan_free.argtypes = [vp]
     L.ldni_plan_free.restype = None
     L.ldni_plan_max_layers.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
@@ -133,4 +135,4 @@ def exported_symbols():
             "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
             "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch",
-            "ldni_boolean"]
+            "ldni_boolean", "ldni_sample_finish_rgb8"]

@@ -676,21 +676,29 @@ ldni_status ldni_plan_max_layers(const ldni_plan* plan, uint32_t max_layers[3]) 
   return LDNI_OK;
 }
 
-ldni_status ldni_sample_finish(ldni_plan* p, float* const depth[3], float* const normal[3],
-                               int32_t* const tri[3]) {
+}  // extern "C"
+
+namespace {
+
+// Second half of a call: the place pass into the caller's buffers (float
+// normals, or 8-bit codes when rgb8 is given), then the plan is released.
+ldni_status finish_plan(ldni_plan* p, float* const depth[3], float* const normal[3],
+                        uint32_t* const rgb8[3], int32_t* const tri[3]) {
   if (!p) return fail(LDNI_ERR_INVALID_ARG, "NULL plan");
-  if (!depth || !normal || !tri) {
+  if (!depth || !(normal || rgb8) || !tri) {
     release_plan(p);
     return fail(LDNI_ERR_INVALID_ARG, "NULL output array");
   }
   for (int k = 0; k < p->set.n; ++k) {
     const int a = p->axis_of[k];
-    if (p->n[a] > 0 && (!depth[a] || !normal[a] || !tri[a])) {
+    const bool have_normal = rgb8 ? rgb8[a] != nullptr : normal[a] != nullptr;
+    if (p->n[a] > 0 && (!depth[a] || !have_normal || !tri[a])) {
       release_plan(p);
       return fail(LDNI_ERR_INVALID_ARG, "NULL output buffer for an axis with samples");
     }
     p->set.img[k].depth = depth[a];
-    p->set.img[k].normal = normal[a];
+    p->set.img[k].normal = rgb8 ? nullptr : normal[a];
+    p->set.img[k].normal_rgb8 = rgb8 ? rgb8[a] : nullptr;
     p->set.img[k].tri = tri[a];
   }
   hipError_t e = hipSuccess;
@@ -701,6 +709,28 @@ ldni_status ldni_sample_finish(ldni_plan* p, float* const depth[3], float* const
   release_plan(p);
   if (e != hipSuccess) return hip_fail(e, "write kernel");
   return LDNI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ldni_status ldni_sample_finish(ldni_plan* p, float* const depth[3], float* const normal[3],
+                               int32_t* const tri[3]) {
+  if (!normal) {
+    release_plan(p);
+    return fail(LDNI_ERR_INVALID_ARG, "NULL output array");
+  }
+  return finish_plan(p, depth, normal, nullptr, tri);
+}
+
+ldni_status ldni_sample_finish_rgb8(ldni_plan* p, float* const depth[3], uint32_t* const normal_rgb8[3],
+                                    int32_t* const tri[3]) {
+  if (!normal_rgb8) {
+    release_plan(p);
+    return fail(LDNI_ERR_INVALID_ARG, "NULL output array");
+  }
+  return finish_plan(p, depth, nullptr, normal_rgb8, tri);
 }
 
 void ldni_plan_free(ldni_plan* plan) { release_plan(plan); }

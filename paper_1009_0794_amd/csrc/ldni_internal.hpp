@@ -60,7 +60,8 @@ struct Image {
   // outputs
   uint32_t* offsets;  // [w*w + 1]
   float* depth;       // [n]
-  float* normal;      // [n][3]
+  float* normal;      // [n][3] (unused when normal_rgb8 is set)
+  uint32_t* normal_rgb8;  // [n] 8-bit normal codes, or null for float normals
   int32_t* tri;       // [n]
   uint32_t* status;   // shared status word
   // Hits of the sampling pass, grouped by tile.  With stage_key null every

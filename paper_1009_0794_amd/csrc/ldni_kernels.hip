@@ -81,6 +81,30 @@ __device__ __forceinline__ int orient(float pu, float pv, float qu, float qv, do
   return s;
 }
 
+// Approximate normal sampling (Sec. 3): each component c of the unit normal
+// becomes one byte, the 8-bit colour (c + 1) / 2 rounded to nearest,
+// floor((c + 1) * 127.5 + 0.5) clamped to [0, 255] with float64 operations in
+// that order; x | y << 8 | z << 16.
+__device__ __forceinline__ uint32_t encode_rgb8(float x, float y, float z) {
+  auto q = [](float c) -> uint32_t {
+    const double t = floor(((double)c + 1.0) * 127.5 + 0.5);
+    return (uint32_t)fmin(fmax(t, 0.0), 255.0);
+  };
+  return q(x) | (q(y) << 8) | (q(z) << 16);
+}
+
+// The normal of output sample o, as three floats or as its 8-bit code.
+__device__ __forceinline__ void store_normal(const Image& im, size_t o, float x, float y, float z) {
+  if (im.normal_rgb8 != nullptr) {
+    im.normal_rgb8[o] = encode_rgb8(x, y, z);
+  } else {
+    float* dst = im.normal + 3 * o;
+    dst[0] = x;
+    dst[1] = y;
+    dst[2] = z;
+  }
+}
+
 // (depth, triangle) as one unsigned key whose order is depth, then id.
 __device__ __forceinline__ uint64_t sample_key(float d, int32_t t) {
   uint32_t b = __float_as_uint(d);
@@ -847,10 +871,7 @@ __device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t
       const size_t o = (size_t)s_off[q] + rank;
       im.depth[o] = key_depth(key[u]);
       im.tri[o] = (int32_t)(uint32_t)key[u];
-      float* dst = im.normal + 3 * o;
-      dst[0] = nx[u];
-      dst[1] = ny[u];
-      dst[2] = nz[u];
+      store_normal(im, o, nx[u], ny[u], nz[u]);
     }
   }
 }
@@ -922,10 +943,7 @@ __device__ void finish_deep_pixel(const Image& im, size_t o, uint32_t n) {
   for (uint32_t s2 = threadIdx.x; s2 < n; s2 += kBlock) {
     const int32_t t = im.tri[o + s2];
     const float* nrm = im.tnorm + 3 * (int64_t)t;
-    float* dst = im.normal + 3 * (o + s2);
-    dst[0] = nrm[0];
-    dst[1] = nrm[1];
-    dst[2] = nrm[2];
+    store_normal(im, o + s2, nrm[0], nrm[1], nrm[2]);
   }
 }
 

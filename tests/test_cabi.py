@@ -185,3 +185,11 @@ def test_boolean_invalid_arguments_rejected_on_host(L, kw):
     assert rc == 1
     assert out is None
     assert L.ldni_last_error().decode()
+
+
+def test_finish_rgb8_rejects_null_plan(L):
+    """ldni_sample_finish_rgb8 (Sec. 3 approximate normals) checks its
+    arguments on the host."""
+    arr = (ctypes.c_void_p * 3)()
+    assert L.ldni_sample_finish_rgb8(None, arr, arr, arr) == 1
+    assert L.ldni_sample_finish_rgb8(None, None, None, None) == 1

@@ -1,0 +1,78 @@
+"""The approximate (8-bit) normal output (Sec. 3, approximate surface normal
+sampling; ldni_sample_finish_rgb8) against the oracle: codes bit for bit,
+and depth, ids and counts identical to the float-normal output."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import normal_codec as nc
+import paper_1009_0794_amd as ldni
+from paper_1009_0794_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype)).to(DEV)
+
+
+@pytest.mark.parametrize("name,w", [("c1_icosphere", 131), ("c2_flower", 512)])
+def test_codes_match_oracle(name, w):
+    m = getattr(mg, name)()
+    v, f = _dev(m.verts, np.float32), _dev(m.tris, np.int32)
+    f32 = ldni.sample(v, f, m.bbox, w, "xyz")
+    r8 = ldni.sample(v, f, m.bbox, w, "xyz", normals="rgb8")
+    torch.cuda.synchronize()
+    ref = oracle.sample(m.verts, m.tris, m.bbox, w, axes="xyz") if w <= 131 else None
+    for a in range(3):
+        assert r8[a].normal.dtype == torch.int32 and r8[a].normal.dim() == 1
+        assert torch.equal(r8[a].offsets, f32[a].offsets)
+        assert torch.equal(r8[a].depth, f32[a].depth)
+        assert torch.equal(r8[a].tri, f32[a].tri)
+        codes = r8[a].normal.cpu().numpy().view(np.uint32)
+        assert np.array_equal(codes, nc.encode(f32[a].normal.cpu().numpy()))
+        if ref is not None:
+            assert np.array_equal(codes, nc.encode(ref[a].normal))
+        # the decoded normal is within half a step of the float one
+        err = np.abs(nc.decode(codes) - f32[a].normal.cpu().numpy().astype(np.float64))
+        assert err.max() <= 1.0 / 255.0 + 1e-7
+
+
+BOX8 = (0.0, 0.0, 0.0, 8.0, 8.0, 8.0)
+
+
+def _pair(v, f, bbox, w, axes="xyz"):
+    vt, ft = _dev(v, np.float32), _dev(f, np.int32)
+    out = (ldni.sample(vt, ft, bbox, w, axes), ldni.sample(vt, ft, bbox, w, axes, normals="rgb8"))
+    torch.cuda.synchronize()
+    return out
+
+
+def _same_codes(f32, r8):
+    for a in f32:
+        assert torch.equal(r8[a].offsets, f32[a].offsets)
+        assert torch.equal(r8[a].depth, f32[a].depth)
+        assert torch.equal(r8[a].tri, f32[a].tri)
+        assert np.array_equal(r8[a].normal.cpu().numpy().view(np.uint32),
+                              nc.encode(f32[a].normal.cpu().numpy()))
+
+
+def test_pixel_deeper_than_lds_stage():
+    """The 4,200-sample pixels of a stack of thin boxes are written to their
+    output ranges and sorted there; their codes come from that path."""
+    parts = [mg.box_mesh((3.2, 3.2, 0.5 + 0.003 * k), (4.8, 4.8, 0.5 + 0.003 * k + 0.0015))
+             for k in range(2100)]
+    v, f = mg.concat(parts)
+    _same_codes(*_pair(v, f, BOX8, 8, "z"))
+
+
+@pytest.mark.parametrize("entries", ["0", "60000"])
+def test_tiles_walked_again(entries, monkeypatch):
+    """With no staging buffer or a short one, tiles are walked again by the
+    place pass; their codes are those of the float normals."""
+    m = mg.c2_flower()
+    monkeypatch.setenv("LDNI_STAGE_ENTRIES", entries)
+    _same_codes(*_pair(m.verts, m.tris, m.bbox, 160))
