@@ -398,13 +398,59 @@ def measure_boolean(ldni, torch, mg, reps):
     }
 
 
+def measure_nodes(ldni, torch, mg, reps):
+    """Grid-node classification (Definition 3; Sec. 5.1 step 1) of the scene64
+    LDNIs at w = 2048: one step is one ldni_classify_nodes call over all
+    2048^3 nodes (the bit volume, 1 GiB, written in full)."""
+    m = mg.c3_scene64(seed=1)
+    v = torch.from_numpy(m.verts).cuda()
+    f = torch.from_numpy(m.tris).cuda()
+    L = ldni.sample(v, f, m.bbox, m.w, "xyz")
+    del v, f
+    w = m.w
+    bits = torch.empty(ldni.node_words(w), dtype=torch.int32, device="cuda")
+    _, n_in, n_split = ldni.classify_nodes([L[0], L[1], L[2]], m.bbox, bits)
+    for _ in range(2):
+        ldni.classify_nodes([L[0], L[1], L[2]], m.bbox, bits)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            ldni.classify_nodes([L[0], L[1], L[2]], m.bbox, bits)
+    ms = t.ms / reps
+    ldni.profile_enable(True)
+    for _ in range(reps):
+        ldni.classify_nodes([L[0], L[1], L[2]], m.bbox, bits)
+    torch.cuda.synchronize()
+    ldni.profile_enable(False)
+    ks = ldni.profile_read()
+    # algorithmic bytes: each LDNI's offsets and depths read once, the bit
+    # volume written once
+    n_samples = sum(L[a].n for a in range(3))
+    alg = 3 * 4 * (w * w + 1) + 4 * n_samples + 4 * bits.numel()
+    roof = None
+    if "classify_nodes" in ks and ks["classify_nodes"][1] > 0:
+        k_ms = ks["classify_nodes"][1] / reps
+        gbs = alg / (k_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "classify_nodes", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(k_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": alg}
+    return {
+        "workload": "nodes-2048",
+        "description": "inside/outside of the 2048^3 grid nodes of the scene64 (seed 1) LDNIs by the "
+                       "two-of-three vote",
+        "nodes_per_step": w ** 3, "input_samples": n_samples, "nodes_inside": n_in,
+        "nodes_with_split_votes": n_split,
+        "ms_per_step": round(ms, 4), "value": w ** 3 / (ms / 1e3), "unit": "nodes/s",
+        "roofline": roof,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
-                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd", "boolean-2048"],
+                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd", "boolean-2048", "nodes-2048"],
                     help="measure one part only (default: the headline plus every part)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -487,6 +533,13 @@ def main():
                          "config": {"workload": "boolean-2048", "description": ro["description"],
                                     "parallelism": "single GPU"}})
         line["boolean"] = ro
+    if args.workload in (None, "nodes-2048"):
+        rn = measure_nodes(ldni, torch, mg, reps=max(2, args.steps // 4))
+        if args.workload == "nodes-2048":
+            line.update({"value": round(rn["value"], 1), "unit": rn["unit"], "ms_per_step": rn["ms_per_step"],
+                         "config": {"workload": "nodes-2048", "description": rn["description"],
+                                    "parallelism": "single GPU"}})
+        line["nodes"] = rn
     print(json.dumps(line), flush=True)
 
 

@@ -222,6 +222,41 @@ enum { LDNI_UNION = 0, LDNI_INTERSECTION = 1, LDNI_DIFFERENCE = 2 };
 ldni_status ldni_boolean(const ldni_axis_view *a, const ldni_axis_view *b, int32_t op, float eps,
                          int32_t axis, void *hip_stream, ldni_result **out);
 
+/*
+ * ldni_classify_nodes -- inside/outside of the w x w x w grid nodes where the
+ * rays of the three LDNIs of one solid meet (Definition 3; Sec. 5.1, step 1
+ * of the contouring algorithm).  Along each of its three rays a node is
+ * inside when it lies in one of the ray's volumes (from a sample of odd rank
+ * to the next, Sec. 2 after Proposition 1); the node is classified inside
+ * when at least two of its three LDNIs say so.
+ * Readings fixed here: node (i, j, k) lies at the pixel centres
+ * (c_x[i], c_y[j], c_z[k]) (the Centres convention above) and its depth on
+ * the a-LDNI is f32(c_a - lo_a) in float64, the depth a sample exactly there
+ * would get; along a ray it is inside when an odd number of the ray's
+ * samples have depth <= its depth (half-open volumes [enter, exit); an
+ * unpaired last sample of an odd count is ignored).
+ *   views   HOST array of the x-, y- and z-LDNI views (ldni_result_axis
+ *           order), one w; offsets and depth are read (depth ascending per
+ *           pixel, as sampled); offsets must be a prefix of the samples
+ *           (non-decreasing, at most n_samples), else LDNI_ERR_INVALID_ARG
+ *           (found on the device; bits are then unspecified).
+ *   bbox    HOST f32 box the views were sampled with (as ldni_sample).
+ *   bits    device u32 [n_words], caller-owned, fully written: nb^3 bricks
+ *           of 32 x 32 x 32 nodes, nb = ceil(w/32); brick (i/32, j/32, k/32)
+ *           starts at word ((k/32 * nb + j/32) * nb + i/32) * 1024; inside a
+ *           brick word (k%32)*32 + (j%32) holds nodes i/32*32 .. +31 of row
+ *           (j, k), node i in bit i%32.  Bits of nodes beyond w are zero.
+ *   n_words at least ldni_node_words(w).
+ *   stats   HOST u64 [2] or NULL: nodes inside, and nodes whose three
+ *           votes are not all equal (the disagreements the vote repairs).
+ * One host synchronisation (the totals and the status).
+ */
+ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[6], uint32_t *bits,
+                                uint64_t n_words, uint64_t stats[2], void *hip_stream);
+
+/* Words of the bit volume of ldni_classify_nodes at resolution w (1..16384). */
+ldni_status ldni_node_words(int32_t w, uint64_t *n_words);
+
 /* Largest per-pixel count of each axis of a plan (after begin). */
 ldni_status ldni_plan_max_layers(const ldni_plan *plan, uint32_t max_layers[3]);
 

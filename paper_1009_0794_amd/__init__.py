@@ -23,7 +23,7 @@ __all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ld
            "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
            "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read",
            "ldni_backward", "sample_diff", "LDNISample", "Batch", "sample_batch", "ldni_boolean",
-           "boolean", "BOOLEAN_OPS"]
+           "boolean", "BOOLEAN_OPS", "ldni_classify_nodes", "classify_nodes", "node_words"]
 
 AXES = "xyz"
 library_path = _lib.LIB_PATH
@@ -342,6 +342,40 @@ def boolean(a: LDNI, b: LDNI, op, eps: float = 1e-5) -> LDNI:
         return _copy_view(r.view(a.axis), a.axis, a.depth.device)
     finally:
         r.free()
+
+
+def node_words(w: int) -> int:
+    """``ldni_node_words``: 32-bit words of the node bit volume at resolution w."""
+    n = ctypes.c_uint64()
+    _lib.check(_lib.lib().ldni_node_words(int(w), ctypes.byref(n)))
+    return int(n.value)
+
+
+def ldni_classify_nodes(ldnis, bbox, bits=None):
+    """The C ABI ``ldni_classify_nodes`` (Definition 3; Sec. 5.1 step 1): the
+    inside/outside bit of every node of the w^3 grid where the rays of the
+    x-, y- and z-LDNI (``ldnis[0..2]``, sampled with ``bbox``) meet, by a
+    two-of-three vote.  ``bits`` (int32 device tensor of ``node_words(w)``
+    words, allocated if None) receives 32^3-node bricks; returns (bits,
+    nodes inside, nodes whose three votes differ)."""
+    torch = _torch()
+    L = [ldnis[a] for a in range(3)]
+    w = int(L[0].w)
+    n = node_words(w)
+    dev = L[0].depth.device
+    if bits is None:
+        bits = torch.empty(n, dtype=torch.int32, device=dev)
+    elif bits.dtype != torch.int32 or not bits.is_contiguous() or bits.numel() < n or bits.device != dev:
+        raise ValueError(f"bits must be a contiguous int32 tensor of at least {n} words on {dev}")
+    views = (_lib.AxisView * 3)(*[_view(l) for l in L])
+    bb = (ctypes.c_float * 6)(*[float(x) for x in bbox])
+    stats = (ctypes.c_uint64 * 2)()
+    _lib.check(_lib.lib().ldni_classify_nodes(views, bb, ctypes.c_void_p(bits.data_ptr()), n, stats,
+                                              _stream(dev)))
+    return bits, int(stats[0]), int(stats[1])
+
+
+classify_nodes = ldni_classify_nodes
 
 
 def _copy_view(v: _lib.AxisView, axis: int, device) -> LDNI:

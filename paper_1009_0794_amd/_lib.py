@@ -100,6 +100,11 @@ def lib():
     L.ldni_boolean.argtypes = [ctypes.POINTER(AxisView), ctypes.POINTER(AxisView), i32, ctypes.c_float, i32,
                                vp, ctypes.POINTER(vp)]
     L.ldni_boolean.restype = st
+    L.ldni_classify_nodes.argtypes = [ctypes.POINTER(AxisView), ctypes.POINTER(ctypes.c_float), vp,
+                                      ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), vp]
+    L.ldni_classify_nodes.restype = st
+    L.ldni_node_words.argtypes = [i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.ldni_node_words.restype = st
     L.ldni_profile_enable.argtypes = [ctypes.c_int]
     L.ldni_profile_enable.restype = st
     L.ldni_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -135,4 +140,4 @@ def exported_symbols():
             "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
             "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch",
-            "ldni_boolean", "ldni_sample_finish_rgb8"]
+            "ldni_boolean", "ldni_sample_finish_rgb8", "ldni_classify_nodes", "ldni_node_words"]

@@ -1031,6 +1031,92 @@ ldni_status ldni_boolean(const ldni_axis_view* a, const ldni_axis_view* b, int32
   return LDNI_OK;
 }
 
+ldni_status ldni_node_words(int32_t w, uint64_t* n_words) {
+  if (!n_words) return fail(LDNI_ERR_INVALID_ARG, "NULL n_words");
+  *n_words = 0;
+  if (w < 1 || w > 16384) return fail(LDNI_ERR_INVALID_ARG, "w must be in [1, 16384]");
+  const uint64_t nb = (uint64_t)(w + 31) / 32;
+  *n_words = nb * nb * nb * 1024;
+  return LDNI_OK;
+}
+
+ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[6], uint32_t* bits,
+                                uint64_t n_words, uint64_t stats[2], void* hip_stream) {
+  if (!views || !bbox || !bits) return fail(LDNI_ERR_INVALID_ARG, "NULL argument");
+  const int32_t w = views[0].w;
+  if (w < 1 || w > 16384 || views[1].w != w || views[2].w != w)
+    return fail(LDNI_ERR_INVALID_ARG, "the three views need the same w in [1, 16384]");
+  for (int d = 0; d < 3; ++d) {
+    if (!std::isfinite(bbox[d]) || !std::isfinite(bbox[3 + d]))
+      return fail(LDNI_ERR_INVALID_ARG, "bbox must be finite");
+    if (!(bbox[d] < bbox[3 + d])) return fail(LDNI_ERR_INVALID_ARG, "bbox needs lo < hi on every axis");
+    const ldni_axis_view& v = views[d];
+    if (!v.offsets) return fail(LDNI_ERR_INVALID_ARG, "NULL offsets");
+    if (v.n_samples > 0 && !v.depth) return fail(LDNI_ERR_INVALID_ARG, "NULL depth of a view with samples");
+    if (v.n_samples > 0xffffffffull) return fail(LDNI_ERR_INVALID_ARG, "a view has 2^32 or more samples");
+  }
+  uint64_t need = 0;
+  (void)ldni_node_words(w, &need);
+  if (n_words < need) return fail(LDNI_ERR_INVALID_ARG, "bits holds fewer words than ldni_node_words(w)");
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  prepare_pool(device);
+  uint32_t* rb = pinned_readback();
+  if (!rb) return fail(LDNI_ERR_OUT_OF_MEMORY, "pinned readback buffer");
+  // workspace: [0] status word, [64..80) the two totals, [256..) per-workgroup
+  // sums, then the span ranks of the y- and z-rays
+  const uint32_t n_wg = node_workgroups(w);
+  const int32_t n_spans = (w + 63) / 64;
+  const size_t o_ranks = align_up(256 + 16 * (size_t)n_wg);
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipError_t e = cache_get(&ws, o_ranks + 2 * (size_t)(n_spans + 1) * (size_t)w * (size_t)w, stream, &ws_bytes);
+  if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+  char* wb = static_cast<char*>(ws);
+  NodeArgs g{};
+  for (int d = 0; d < 3; ++d) {
+    const ldni_axis_view& v = views[d];
+    g.axis[d] = AxisArrays{v.n_samples, v.offsets, v.depth, nullptr, nullptr};
+    g.lo[d] = (double)bbox[d];
+    g.h[d] = ((double)bbox[3 + d] - (double)bbox[d]) / (double)w;
+  }
+  g.w = w;
+  g.nb = (w + 31) / 32;
+  g.bits = bits;
+  g.status = reinterpret_cast<uint32_t*>(wb);
+  g.stats = reinterpret_cast<uint64_t*>(wb + 64);
+  g.partial = reinterpret_cast<uint64_t*>(wb + 256);
+  g.ranks = reinterpret_cast<uint8_t*>(wb + o_ranks);
+  g.n_spans = n_spans;
+  auto run = [&]() -> ldni_status {
+#define NSTEP(expr, what)                       \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+    NSTEP(launch_fill_u32(g.status, 0u, 1, stream), "fill");
+    NSTEP(timed("node_ranks", stream, [&] { return launch_node_ranks(g, stream); }), "rank kernel");
+    NSTEP(timed("classify_nodes", stream, [&] { return launch_classify_nodes(g, stream); }), "classify kernel");
+    NSTEP(launch_node_stats(g, stream), "node totals");
+    const uint32_t* words = reinterpret_cast<const uint32_t*>(g.stats);
+    const uint32_t* src[5] = {g.status, words, words + 1, words + 2, words + 3};
+    NSTEP(launch_gather(src, 5, rb, stream), "readback");
+    NSTEP(hipStreamSynchronize(stream), "synchronise");
+#undef NSTEP
+    if (rb[0] & kStatusMismatch)
+      return fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples");
+    if (stats) {
+      stats[0] = (uint64_t)rb[1] | ((uint64_t)rb[2] << 32);
+      stats[1] = (uint64_t)rb[3] | ((uint64_t)rb[4] << 32);
+    }
+    return LDNI_OK;
+  };
+  const ldni_status st = run();
+  cache_put(ws, ws_bytes, stream);
+  return st;
+}
+
 void ldni_free(ldni_result* r) {
   if (!r) return;
   cache_put(r->samples_buf, r->samples_bytes, r->stream);

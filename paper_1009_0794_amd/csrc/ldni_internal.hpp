@@ -246,6 +246,27 @@ struct BooleanArgs {
 hipError_t launch_boolean(const BooleanArgs& g, bool write, hipStream_t s);
 
 // Copies n (<= 16) device words into pinned, device-visible host memory.
+// Grid-node classification of three LDNIs of one box and resolution
+// (ldni_nodes.hip).  axis[a] is the a-LDNI; lo/h the node origin and
+// spacing per world axis; bits holds nb^3 bricks of 1024 words (nb =
+// ceil(w/32)); partial 2 words per workgroup (node_workgroups); stats[0..1]
+// = nodes inside, nodes whose three votes differ.
+struct NodeArgs {
+  AxisArrays axis[3];
+  int32_t w, nb;
+  double lo[3], h[3];
+  uint32_t* bits;
+  uint32_t* status;   // kStatusMismatch: offsets of an input out of order
+  uint64_t* partial;
+  uint64_t* stats;
+  uint8_t* ranks;     // 2 * (n_spans + 1) * w * w bytes (launch_node_ranks)
+  int32_t n_spans;    // ceil(w / 64)
+};
+uint32_t node_workgroups(int32_t w);
+hipError_t launch_node_ranks(const NodeArgs& g, hipStream_t s);
+hipError_t launch_classify_nodes(const NodeArgs& g, hipStream_t s);
+hipError_t launch_node_stats(const NodeArgs& g, hipStream_t s);
+
 // Copies n <= kMaxGather scattered device words to pinned host memory.
 constexpr int kMaxGather = 32;
 hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, hipStream_t s);

@@ -193,3 +193,46 @@ def test_finish_rgb8_rejects_null_plan(L):
     arr = (ctypes.c_void_p * 3)()
     assert L.ldni_sample_finish_rgb8(None, arr, arr, arr) == 1
     assert L.ldni_sample_finish_rgb8(None, None, None, None) == 1
+
+
+def _nodes_call(L, views=True, ws=(8, 8, 8), offsets=True, n=0, depth=True, bbox=(0, 0, 0, 1, 1, 1),
+                bits=True, n_words=None):
+    from paper_1009_0794_amd import _lib
+    arr = (_lib.AxisView * 3)()
+    for a in range(3):
+        arr[a].w, arr[a].n_samples = ws[a], n
+        arr[a].offsets = 4096 if offsets else None
+        arr[a].depth = 8192 if depth else None
+    bb = (ctypes.c_float * 6)(*bbox)
+    need = ctypes.c_uint64()
+    L.ldni_node_words(max(1, min(ws[0], 16384)), ctypes.byref(need))
+    nw = need.value if n_words is None else n_words
+    stats = (ctypes.c_uint64 * 2)(7, 7)
+    rc = L.ldni_classify_nodes(arr if views else None, bb, 0x10000 if bits else None, nw, stats, None)
+    return rc, list(stats)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(views=False), dict(bits=False), dict(ws=(8, 8, 9)), dict(ws=(0, 0, 0)),
+    dict(ws=(16385, 16385, 16385)), dict(offsets=False), dict(n=5, depth=False), dict(n=2 ** 32),
+    dict(bbox=(0, 0, 0, 1, 0, 1)), dict(bbox=(0, 0, float("nan"), 1, 1, 1)),
+    dict(bbox=(0, 0, 0, 1, 1, float("inf"))), dict(n_words=1024 - 1),
+])
+def test_classify_nodes_invalid_arguments_rejected_on_host(L, kw):
+    """ldni_classify_nodes (Definition 3; Sec. 5.1 step 1) checks its
+    arguments before any device work (the fake device pointers here are
+    never dereferenced) and leaves the totals untouched."""
+    rc, stats = _nodes_call(L, **kw)
+    assert rc == 1
+    assert stats == [7, 7]
+    assert L.ldni_last_error().decode()
+
+
+def test_node_words(L):
+    """Bricks of 32^3 nodes, 1024 words each, ceil(w/32) per axis."""
+    n = ctypes.c_uint64()
+    for w, nb in ((1, 1), (32, 1), (33, 2), (2048, 64), (16384, 512)):
+        assert L.ldni_node_words(w, ctypes.byref(n)) == 0
+        assert n.value == nb ** 3 * 1024
+    assert L.ldni_node_words(0, ctypes.byref(n)) == 1 and n.value == 0
+    assert L.ldni_node_words(8, None) == 1
