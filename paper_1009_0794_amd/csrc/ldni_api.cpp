@@ -1034,7 +1034,7 @@ ldni_status ldni_boolean(const ldni_axis_view* a, const ldni_axis_view* b, int32
 ldni_status ldni_node_words(int32_t w, uint64_t* n_words) {
   if (!n_words) return fail(LDNI_ERR_INVALID_ARG, "NULL n_words");
   *n_words = 0;
-  if (w < 1 || w > 16384) return fail(LDNI_ERR_INVALID_ARG, "w must be in [1, 16384]");
+  if (w < 1 || w > 8192) return fail(LDNI_ERR_INVALID_ARG, "w must be in [1, 8192]");
   const uint64_t nb = (uint64_t)(w + 31) / 32;
   *n_words = nb * nb * nb * 1024;
   return LDNI_OK;
@@ -1044,8 +1044,8 @@ ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[
                                 uint64_t n_words, uint64_t stats[2], void* hip_stream) {
   if (!views || !bbox || !bits) return fail(LDNI_ERR_INVALID_ARG, "NULL argument");
   const int32_t w = views[0].w;
-  if (w < 1 || w > 16384 || views[1].w != w || views[2].w != w)
-    return fail(LDNI_ERR_INVALID_ARG, "the three views need the same w in [1, 16384]");
+  if (w < 1 || w > 8192 || views[1].w != w || views[2].w != w)
+    return fail(LDNI_ERR_INVALID_ARG, "the three views need the same w in [1, 8192]");
   for (int d = 0; d < 3; ++d) {
     if (!std::isfinite(bbox[d]) || !std::isfinite(bbox[3 + d]))
       return fail(LDNI_ERR_INVALID_ARG, "bbox must be finite");
@@ -1065,13 +1065,13 @@ ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[
   uint32_t* rb = pinned_readback();
   if (!rb) return fail(LDNI_ERR_OUT_OF_MEMORY, "pinned readback buffer");
   // workspace: [0] status word, [64..80) the two totals, [256..) per-workgroup
-  // sums, then the span ranks of the y- and z-rays
+  // sums, then the span codes of the three axes
   const uint32_t n_wg = node_workgroups(w);
   const int32_t n_spans = (w + 63) / 64;
-  const size_t o_ranks = align_up(256 + 16 * (size_t)n_wg);
+  const size_t o_codes = align_up(256 + 16 * (size_t)n_wg);
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  hipError_t e = cache_get(&ws, o_ranks + 2 * (size_t)(n_spans + 1) * (size_t)w * (size_t)w, stream, &ws_bytes);
+  hipError_t e = cache_get(&ws, o_codes + node_code_bytes(w), stream, &ws_bytes);
   if (e != hipSuccess) return hip_fail(e, "workspace allocation");
   char* wb = static_cast<char*>(ws);
   NodeArgs g{};
@@ -1087,7 +1087,7 @@ ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[
   g.status = reinterpret_cast<uint32_t*>(wb);
   g.stats = reinterpret_cast<uint64_t*>(wb + 64);
   g.partial = reinterpret_cast<uint64_t*>(wb + 256);
-  g.ranks = reinterpret_cast<uint8_t*>(wb + o_ranks);
+  g.codes = reinterpret_cast<uint16_t*>(wb + o_codes);
   g.n_spans = n_spans;
   auto run = [&]() -> ldni_status {
 #define NSTEP(expr, what)                       \
@@ -1096,7 +1096,7 @@ ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
     NSTEP(launch_fill_u32(g.status, 0u, 1, stream), "fill");
-    NSTEP(timed("node_ranks", stream, [&] { return launch_node_ranks(g, stream); }), "rank kernel");
+    NSTEP(timed("node_codes", stream, [&] { return launch_node_codes(g, stream); }), "span code kernel");
     NSTEP(timed("classify_nodes", stream, [&] { return launch_classify_nodes(g, stream); }), "classify kernel");
     NSTEP(launch_node_stats(g, stream), "node totals");
     const uint32_t* words = reinterpret_cast<const uint32_t*>(g.stats);

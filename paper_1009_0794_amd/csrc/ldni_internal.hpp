@@ -259,11 +259,12 @@ struct NodeArgs {
   uint32_t* status;   // kStatusMismatch: offsets of an input out of order
   uint64_t* partial;
   uint64_t* stats;
-  uint8_t* ranks;     // 2 * (n_spans + 1) * w * w bytes (launch_node_ranks)
+  uint16_t* codes;    // node_code_bytes(w): span codes of the three axes (launch_node_codes)
   int32_t n_spans;    // ceil(w / 64)
 };
 uint32_t node_workgroups(int32_t w);
-hipError_t launch_node_ranks(const NodeArgs& g, hipStream_t s);
+size_t node_code_bytes(int32_t w);
+hipError_t launch_node_codes(const NodeArgs& g, hipStream_t s);
 hipError_t launch_classify_nodes(const NodeArgs& g, hipStream_t s);
 hipError_t launch_node_stats(const NodeArgs& g, hipStream_t s);
 

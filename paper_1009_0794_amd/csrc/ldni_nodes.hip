@@ -48,7 +48,6 @@ constexpr int kRow = 33;      // LDS stride of a 32-word bit matrix (no bank con
 constexpr int kVoteBlock = 512;  // threads of a classification workgroup
 constexpr int kXRays = kSpan * kSpan / kVoteBlock;       // 8 x-rays per thread
 constexpr int kVisits = kStep * kSpan / kVoteBlock;      // 4 y- and 4 z-spans per thread per step
-constexpr int kMaxSpans = 16384 / kSpan;
 
 // Depth of node t on an axis with origin lo and pixel size h; nodes past the
 // grid get +inf so that the tables stay sorted.
@@ -118,54 +117,130 @@ __device__ __forceinline__ void transpose32(uint32_t* row) {
   for (int i = 0; i < 32; ++i) row[i] = a[i];
 }
 
-// Ranks of the spans of every y- and z-ray: for span s (nodes 64 s .. 64 s + 63
-// along the ray) the number of the ray's paired samples at or before the
-// span's first node, i.e. the parity of that node and the position of the
-// first sample that can fall inside the span; entry n_spans holds the
-// paired count.  One byte each, 255 meaning 255 or more.  ranks[f][s][p]:
-// f = 0 for the y-LDNI, 1 for the z-LDNI, p the pixel.  One thread per ray.
-__global__ __launch_bounds__(kNodeBlock) void node_ranks_kernel(NodeArgs g) {
-  __shared__ float s_start[2][kMaxSpans + 1];
-  const int S = g.n_spans;
-  for (int q = threadIdx.x; q < 2 * (S + 1); q += kNodeBlock) {
-    const int f = q / (S + 1), s = q - f * (S + 1);
-    s_start[f][s] = s < S ? node_depth(g.lo[1 + f], g.h[1 + f], s * kSpan, g.w) : __int_as_float(0x7f800000);
-  }
+// Span codes.  For every ray of the three LDNIs and every span of 64 nodes
+// along it (span s holds nodes 64 s .. 64 s + 63), one 16-bit code:
+//   bit 12      parity of the ray's paired samples at or before the span's
+//               first node (inside at that node),
+//   bits 0..5   t1, bits 6..11 t2: the samples after the first node and at or
+//               before the span's last node flip the nodes from position
+//               t (1..63) on; 0 means none,
+//   bit 13      more than two such samples: bits 0..11 then hold the number
+//               of the ray's paired samples before them (4095: that many or
+//               more), and the vote pass walks the span's samples.
+// Codes are grouped so that one step of one vote workgroup reads 4096
+// consecutive codes per axis (index = block * 4096 + v):
+//   x-ray (j, k), span s along i:  block ((s*S + k/64)*S + j/64),  v = (k%64)*64 + j%64
+//   y-ray (i, k), span s along j:  block ((s*S + k/64)*S + i/64),  v = (i%64)*64 + k%64
+//   z-ray (i, j), span s along k:  block ((s*S + j/64)*S + i/64),  v = (j%64)*64 + i%64
+// with S = ceil(w/64) spans per axis; one axis's codes fill S^3 * 4096 words.
+constexpr uint32_t kCodeParity = 1u << 12;
+constexpr uint32_t kCodeWalk = 1u << 13;
+constexpr uint32_t kRankMax = 4095u;  // bits 0..11 of a walk code: samples before the span (4095: or more)
+
+__device__ __forceinline__ size_t code_index(int f, int iu, int iv, int s, int S) {
+  // (iu, iv) = pixel of the f-LDNI; the frame is cyclic: x (j, k), y (k, i), z (i, j)
+  const int a = f == 1 ? iv : iu;  // the coordinate whose 64-block is the inner block index
+  const int b = f == 1 ? iu : iv;  // the other one (outer block index, and the row of v)
+  // x: a = j, b = k -> v = (k%64)*64 + j%64, block (s, k/64, j/64)
+  // y: a = i, b = k -> v = (i%64)*64 + k%64, block (s, k/64, i/64)
+  // z: a = i, b = j -> v = (j%64)*64 + i%64, block (s, j/64, i/64)
+  const size_t block = ((size_t)s * S + (b >> 6)) * S + (a >> 6);
+  const uint32_t v = f == 1 ? (uint32_t)((a & 63) * 64 + (b & 63)) : (uint32_t)((b & 63) * 64 + (a & 63));
+  return block * 4096 + v;
+}
+
+// One thread per ray: walks the ray's paired samples once and writes the
+// code of each of its spans.  Grid (ceil(w*w/256), 3): blockIdx.y is the axis.
+__global__ __launch_bounds__(kNodeBlock) void node_codes_kernel(NodeArgs g) {
+  extern __shared__ float s_t[];  // the w node depths along this axis
+  const int f = blockIdx.y;
+  const int w = g.w, S = g.n_spans;
+  for (int t = threadIdx.x; t < w; t += kNodeBlock) s_t[t] = node_depth(g.lo[f], g.h[f], t, w);
   __syncthreads();
-  const int64_t npix = (int64_t)g.w * g.w;
-  const int64_t t = (int64_t)blockIdx.x * kNodeBlock + threadIdx.x;
-  if (t >= 2 * npix) return;
-  const int f = t >= npix ? 1 : 0;
-  const size_t p = (size_t)(t - f * npix);
-  const AxisArrays& ax = g.axis[1 + f];
-  uint8_t* R = g.ranks + (size_t)f * (size_t)(S + 1) * (size_t)npix + p;
+  const size_t npix = (size_t)w * w;
+  const size_t p = (size_t)blockIdx.x * kNodeBlock + threadIdx.x;
+  if (p >= npix) return;
+  const int iu = (int)(p % (size_t)w), iv = (int)(p / (size_t)w);
+  const AxisArrays& ax = g.axis[f];
+  uint16_t* C = g.codes + (size_t)f * ((size_t)S * S * S * 4096);
   const uint32_t o0 = ax.offsets[p], o1 = ax.offsets[p + 1];
   uint32_t cnt = 0;
   if (o1 < o0 || (uint64_t)o1 > ax.n) atomicOr(g.status, kStatusMismatch);
   else cnt = (o1 - o0) & ~1u;
-  uint32_t q = 0;
-  float d = cnt > 0 ? ax.depth[o0] : 0.0f;
-  for (int s = 0; s <= S; ++s) {
-    const float T = s_start[f][s];
-    while (q < cnt && d <= T) {
-      ++q;
-      d = q < cnt ? ax.depth[o0 + q] : 0.0f;
+  // the samples are read four at a time (independent loads), q indexes them
+  const float* dep = ax.depth + o0;
+  float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f;
+  auto fill = [&](uint32_t from) {
+    if (from < cnt) b0 = dep[from];
+    if (from + 1 < cnt) b1 = dep[from + 1];
+    if (from + 2 < cnt) b2 = dep[from + 2];
+    if (from + 3 < cnt) b3 = dep[from + 3];
+  };
+  uint32_t q = 0, parity = 0;
+  fill(0);
+  float d = b0;
+  auto next = [&]() {
+    ++q;
+    if ((q & 3u) == 0) fill(q);
+    const uint32_t r = q & 3u;
+    d = r == 0 ? b0 : r == 1 ? b1 : r == 2 ? b2 : b3;
+  };
+  // consecutive spans of one ray are S*S blocks apart
+  uint16_t* c = C + code_index(f, iu, iv, 0, S);
+  const size_t span_step = (size_t)S * S * 4096;
+  for (int s = 0; s < S; ++s, c += span_step) {
+    const int base = s * kSpan, last = min(base + kSpan - 1, w - 1);
+    const float t_first = s_t[base], t_last = s_t[last];
+    while (q < cnt && d <= t_first) {
+      parity ^= 1u;
+      next();
     }
-    R[(size_t)s * npix] = (uint8_t)(q < 255u ? q : 255u);
+    uint32_t code = parity ? kCodeParity : 0u;
+    if (q < cnt && d <= t_last) {
+      const uint32_t rank = q;
+      int n_t = 0;
+      do {
+        // d lies after node base and at or before node last: it flips nodes c.. (c in 1..last-base)
+        int lo = 1, hi = last - base;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_t[base + mid] < d) lo = mid + 1; else hi = mid;
+        }
+        if (n_t == 0) code |= (uint32_t)lo;
+        else if (n_t == 1) code |= (uint32_t)lo << 6;
+        ++n_t;
+        parity ^= 1u;
+        next();
+      } while (q < cnt && d <= t_last);
+      // more than two: the code keeps the rank of the span's first sample instead
+      if (n_t > 2) code = (code & kCodeParity) | kCodeWalk | (rank < kRankMax ? rank : kRankMax);
+    }
+    *c = (uint16_t)code;
   }
 }
 
-// Inside mask of a span from its ranks: the parity at its first node, then a
-// toggle at each sample inside it (samples o0 + ra .. o0 + rb - 1 are the
-// ones after the first node and at or before the next span's first node).
-// Saturated ranks walk the ray from its start instead.
-__device__ __forceinline__ uint64_t span_from_ranks(const AxisArrays& ax, size_t p, uint32_t o0, uint32_t ra,
-                                                    uint32_t rb, const float* T, float t_first, float t_last,
-                                                    bool& bad) {
-  if (ra == 255u || rb == 255u) return span_mask(ax, p, T, t_first, t_last, bad);
-  uint64_t m = (ra & 1u) ? ~0ull : 0ull;
-  for (uint32_t q = o0 + ra; q < o0 + rb; ++q) {
-    const float s = ax.depth[q];
+// The rare span with more than two samples inside: from its code's rank, the
+// parity at its first node and a walk over its own samples (from the ray's
+// start when the rank saturated).
+__device__ __forceinline__ uint64_t span_walk(const AxisArrays* ax, size_t p, uint32_t code, const float* T,
+                                              uint32_t* bad) {
+  const uint32_t rank = code & kRankMax;
+  if (rank == kRankMax) {
+    bool b = false;
+    const uint64_t m = span_mask(*ax, p, T, T[0], T[kSpan - 1], b);
+    if (b) *bad = 1u;
+    return m;
+  }
+  const uint32_t o0 = ax->offsets[p], o1 = ax->offsets[p + 1];
+  if (o1 < o0 || (uint64_t)o1 > ax->n) {
+    *bad = 1u;
+    return 0;
+  }
+  const uint32_t end = o0 + ((o1 - o0) & ~1u);
+  const float t_first = T[0], t_last = T[kSpan - 1];
+  uint64_t m = (code & kCodeParity) ? ~0ull : 0ull;
+  for (uint32_t q = o0 + rank; q < end; ++q) {
+    const float s = ax->depth[q];
     if (!(s <= t_last)) break;
     const int c = s <= t_first ? 0 : count_below<kSpan>(T, s);
     m ^= c >= 64 ? 0ull : (~0ull << c);
@@ -173,198 +248,137 @@ __device__ __forceinline__ uint64_t span_from_ranks(const AxisArrays& ax, size_t
   return m;
 }
 
+// Inside mask of a span from its code (bit t = node t of the span).
+__device__ __forceinline__ uint64_t decode_span(uint32_t code) {
+  uint64_t m = (code & kCodeParity) ? ~0ull : 0ull;
+  const uint32_t t1 = code & 63u, t2 = (code >> 6) & 63u;
+  if (t1) m ^= ~0ull << t1;
+  if (t2) m ^= ~0ull << t2;
+  return m;
+}
+
+__device__ __forceinline__ uint32_t code_at(const uint4& c, int m) {
+  const uint32_t word = m < 2 ? c.x : m < 4 ? c.y : m < 6 ? c.z : c.w;
+  return (m & 1) ? word >> 16 : word & 0xffffu;
+}
+
+// LDS bit matrices of one step: y matrix (k, j-half, i-half) and z matrix
+// (j, k-half, i-half), 32 rows of kRow words.
+__device__ __forceinline__ int ymat(int kl, int jh, int ih) { return (ih * 2 + jh) * kSpan + kl; }
+__device__ __forceinline__ int zmat(int jl, int kh, int ih) { return 4 * kSpan + (ih * 2 + kh) * kSpan + jl; }
+
+// The vote.  A workgroup owns the 64 x 64 rows (j, k) of one block and walks
+// along i one span (two bricks) per step.  Thread t handles the 8 consecutive
+// codes v = 8t .. 8t + 7 of each axis (one 16-byte load each, issued a step
+// ahead).
 __global__ __launch_bounds__(kVoteBlock, 4) void classify_nodes_kernel(NodeArgs g) {
-  __shared__ float s_tx[2][kStep];  // node depths of the current and the next step along i
-  __shared__ float s_ty[kSpan];
-  __shared__ float s_tz[kSpan];
-  __shared__ uint32_t s_y[2 * kSpan * kRow];  // matrix (k, j-half): rows i, bits j; then rows j, bits i
-  __shared__ uint32_t s_z[2 * kSpan * kRow];  // matrix (j, k-half): rows i, bits k; then rows k, bits i
+  __shared__ uint32_t s_m[8 * kSpan * kRow];  // 256 y and 256 z matrices
+  __shared__ float s_ty[kSpan], s_tz[kSpan];
+  __shared__ float s_tx[2][kSpan];  // node depths of the current and the next span along i
   __shared__ uint64_t s_sum[2][kVoteBlock / 64];
 
   const int tid = threadIdx.x;
-  const int w = g.w, nb = g.nb;
-  const int blocks_j = (nb + 1) >> 1;
-  const int bj0 = 2 * (int)(blockIdx.x % blocks_j), bk0 = 2 * (int)(blockIdx.x / blocks_j);
-  const int j0 = bj0 * kStep, k0 = bk0 * kStep;
+  const int w = g.w, nb = g.nb, S = g.n_spans;
+  const int J = (int)(blockIdx.x % S), K = (int)(blockIdx.x / S);
+  const int j0 = J * kSpan, k0 = K * kSpan;
   const AxisArrays& X = g.axis[0];
   const AxisArrays& Y = g.axis[1];
   const AxisArrays& Z = g.axis[2];
-  const size_t npix = (size_t)w * w;
-  // ranks of this block's span along j (y-rays) and along k (z-rays)
-  const uint8_t* ry = g.ranks + (size_t)(j0 / kSpan) * npix;
-  const uint8_t* rz = g.ranks + (size_t)(g.n_spans + 1) * npix + (size_t)(k0 / kSpan) * npix;
-  bool bad = false;
+  const size_t per_axis = (size_t)S * S * S * 4096;
+  // x codes of this block: v = kl*64 + jl; thread t takes jl = t % 64 and kl = (t / 64)*8 + m
+  const uint16_t* cx = g.codes + ((size_t)K * S + J) * 4096 + (size_t)(tid >> 6) * 512 + (tid & 63);
+  const uint4* cy = reinterpret_cast<const uint4*>(g.codes + per_axis) + ((size_t)J * S + K) * S * 512 + tid;
+  const uint4* cz = reinterpret_cast<const uint4*>(g.codes + 2 * per_axis) + ((size_t)K * S + J) * S * 512 + tid;
+  const size_t x_step = (size_t)S * S * 4096;  // codes per x span step
 
   if (tid < kSpan) s_ty[tid] = node_depth(g.lo[1], g.h[1], j0 + tid, w);
   else if (tid < 2 * kSpan) s_tz[tid - kSpan] = node_depth(g.lo[2], g.h[2], k0 + tid - kSpan, w);
-  else if (tid < 2 * kSpan + kStep) s_tx[0][tid - 2 * kSpan] = node_depth(g.lo[0], g.h[0], tid - 2 * kSpan, w);
-
-  // x-ray states: ray r = tid + 512 m is row (j0 + r % 64, k0 + r / 64); the
-  // depth of its next sample is kept loaded
-  uint32_t xq[kXRays], xe[kXRays];
-  float xs[kXRays];
-  uint32_t xpar = 0;
+  else if (tid < 3 * kSpan) s_tx[0][tid - 2 * kSpan] = node_depth(g.lo[0], g.h[0], tid - 2 * kSpan, w);
+  // this thread's rays: 8 consecutive v = 8 tid + m
+  const int hi6 = tid >> 3, lo6 = (tid & 7) * 8;  // v / 64, v % 64 - m
+  uint32_t nx[8];
 #pragma unroll
-  for (int m = 0; m < kXRays; ++m) {
-    const int r = tid + kVoteBlock * m;
-    const int j = j0 + (r & (kSpan - 1)), k = k0 + (r >> 6);
-    xq[m] = xe[m] = 0;
-    xs[m] = 0.0f;
-    if (j < w && k < w) {
-      const size_t p = (size_t)k * w + j;
-      const uint32_t o0 = X.offsets[p], o1 = X.offsets[p + 1];
-      if (o1 < o0 || (uint64_t)o1 > X.n) {
-        bad = true;
-      } else {
-        xq[m] = o0;
-        xe[m] = o0 + ((o1 - o0) & ~1u);
-        if (o0 < xe[m]) xs[m] = X.depth[o0];
-      }
-    }
-  }
+  for (int m = 0; m < 8; ++m) nx[m] = cx[m * 64];
+  uint4 ny = cy[0], nz = cz[0];
   __syncthreads();
-  const float ty_first = s_ty[0], ty_last = s_ty[kSpan - 1];
-  const float tz_first = s_tz[0], tz_last = s_tz[kSpan - 1];
   uint32_t n_inside = 0, n_split = 0;
+  uint32_t bad = 0;
 
-  for (int bi = 0; bi < nb; ++bi) {
-    const int i0 = bi * kStep;
-    const float* TX = s_tx[bi & 1];
-    const float tx_first = TX[0], tx_last = TX[kStep - 1];
-    // (1) offsets and ranks of the step's spans: y-rays (i, k) along j,
-    // z-rays (i, j) along k; all issued before any is used
-    uint32_t vo[2 * kVisits], vr[2 * kVisits];
+  for (int it = 0; it < S; ++it) {
+    uint32_t ux[8];
 #pragma unroll
-    for (int m = 0; m < kVisits; ++m) {
-      const int v = tid + kVoteBlock * m;
-      const int i_y = i0 + (v >> 6), k = k0 + (v & (kSpan - 1));
-      const int i_z = i0 + (v & (kStep - 1)), j = j0 + (v >> 5);
-      vo[m] = vr[m] = vo[kVisits + m] = vr[kVisits + m] = 0;
-      if (i_y < w && k < w) {
-        const size_t p = (size_t)i_y * w + k;
-        vo[m] = Y.offsets[p];
-        vr[m] = (uint32_t)ry[p] | ((uint32_t)ry[npix + p] << 8);
-      }
-      if (i_z < w && j < w) {
-        const size_t p = (size_t)j * w + i_z;
-        vo[kVisits + m] = Z.offsets[p];
-        vr[kVisits + m] = (uint32_t)rz[p] | ((uint32_t)rz[npix + p] << 8);
-      }
+    for (int m = 0; m < 8; ++m) ux[m] = nx[m];
+    const uint4 uy = ny, uz = nz;
+    if (it + 1 < S) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) nx[m] = cx[(size_t)(it + 1) * x_step + m * 64];
+      ny = cy[(size_t)(it + 1) * 512];
+      nz = cz[(size_t)(it + 1) * 512];
     }
-    // (2) x-rays, first round: the kept depths decide; the next samples'
-    // loads are issued without waiting
-    uint32_t xw[kXRays];
-    bool more = false;
-#pragma unroll
-    for (int m = 0; m < kXRays; ++m) {
-      xw[m] = ((xpar >> m) & 1u) ? 0xffffffffu : 0u;
-      if (xq[m] < xe[m] && xs[m] <= tx_last) {
-        const float sd = xs[m];
-        const int c = sd <= tx_first ? 0 : count_below<kStep>(TX, sd);
-        xw[m] ^= c >= 32 ? 0u : (0xffffffffu << c);
-        xpar ^= 1u << m;
-        ++xq[m];
-        xs[m] = xq[m] < xe[m] ? X.depth[xq[m]] : 0.0f;
-        more = true;
-      }
-    }
-    // (3) spans: the parity at the first node goes to LDS; the first sample
-    // that may lie inside has its load issued now
-    uint32_t vq[2 * kVisits], vn[2 * kVisits];
-    float vd[2 * kVisits];
-#pragma unroll
-    for (int m = 0; m < 2 * kVisits; ++m) {
-      const bool is_y = m < kVisits;
-      const int v = tid + kVoteBlock * (is_y ? m : m - kVisits);
-      const AxisArrays& A = is_y ? Y : Z;
-      const uint32_t ra = vr[m] & 255u, rb = vr[m] >> 8;
-      uint32_t* row = is_y ? s_y + (2 * (v & (kSpan - 1))) * kRow + (v >> 6)
-                           : s_z + (2 * (v >> 5)) * kRow + (v & (kStep - 1));
-      uint64_t mask = 0;
-      vn[m] = 0;
-      vq[m] = 0;
-      vd[m] = 0.0f;
-      if (ra == 255u || rb == 255u) {  // saturated ranks: walk from the ray's start
-        const int i = i0 + (is_y ? (v >> 6) : (v & (kStep - 1)));
-        const int o = is_y ? k0 + (v & (kSpan - 1)) : j0 + (v >> 5);
-        if (i < w && o < w) {
-          const size_t p = is_y ? (size_t)i * w + o : (size_t)o * w + i;
-          mask = is_y ? span_mask(Y, p, s_ty, ty_first, ty_last, bad) : span_mask(Z, p, s_tz, tz_first, tz_last, bad);
+    const int i0 = it * kSpan;
+    const float* TX = s_tx[it & 1];
+    // y spans: v = il*64 + kl (il = hi6, kl = lo6 + m); z spans: v = jl*64 + il (jl = hi6, il = lo6 + m)
+#pragma unroll 1
+    for (int m = 0; m < 8; ++m) {
+      {
+        const int il = hi6, kl = lo6 + m;
+        const int i = i0 + il, k = k0 + kl;
+        uint64_t mk = 0;
+        if (i < w && k < w) {
+          const uint32_t c = code_at(uy, m);
+          mk = (c & kCodeWalk) ? span_walk(&Y, (size_t)i * w + k, c, s_ty, &bad) : decode_span(c);
         }
-      } else {
-        mask = (ra & 1u) ? ~0ull : 0ull;
-        vq[m] = vo[m] + ra;
-        vn[m] = rb - ra;
-        if (vn[m] > 0) vd[m] = A.depth[vq[m]];
+        s_m[ymat(kl, 0, il >> 5) * kRow + (il & 31)] = (uint32_t)mk;
+        s_m[ymat(kl, 1, il >> 5) * kRow + (il & 31)] = (uint32_t)(mk >> 32);
       }
-      row[0] = (uint32_t)mask;
-      row[kRow] = (uint32_t)(mask >> 32);
-    }
-    // (4) x-rays, further rounds (two or more samples of a ray in one step)
-    while (more) {
-      more = false;
-#pragma unroll
-      for (int m = 0; m < kXRays; ++m) {
-        if (xq[m] < xe[m] && xs[m] <= tx_last) {
-          const float sd = xs[m];
-          const int c = sd <= tx_first ? 0 : count_below<kStep>(TX, sd);
-          xw[m] ^= c >= 32 ? 0u : (0xffffffffu << c);
-          xpar ^= 1u << m;
-          ++xq[m];
-          xs[m] = xq[m] < xe[m] ? X.depth[xq[m]] : 0.0f;
-          more = true;
+      {
+        const int jl = hi6, il = lo6 + m;
+        const int i = i0 + il, j = j0 + jl;
+        uint64_t mk = 0;
+        if (i < w && j < w) {
+          const uint32_t c = code_at(uz, m);
+          mk = (c & kCodeWalk) ? span_walk(&Z, (size_t)j * w + i, c, s_tz, &bad) : decode_span(c);
         }
+        s_m[zmat(jl, 0, il >> 5) * kRow + (il & 31)] = (uint32_t)mk;
+        s_m[zmat(jl, 1, il >> 5) * kRow + (il & 31)] = (uint32_t)(mk >> 32);
       }
-    }
-    // (5) spans: toggles of the samples inside (each thread owns its LDS words)
-#pragma unroll
-    for (int m = 0; m < 2 * kVisits; ++m) {
-      if (vn[m] == 0) continue;
-      const bool is_y = m < kVisits;
-      const int v = tid + kVoteBlock * (is_y ? m : m - kVisits);
-      const AxisArrays& A = is_y ? Y : Z;
-      const float* T = is_y ? s_ty : s_tz;
-      const float t_first = is_y ? ty_first : tz_first, t_last = is_y ? ty_last : tz_last;
-      uint32_t* row = is_y ? s_y + (2 * (v & (kSpan - 1))) * kRow + (v >> 6)
-                           : s_z + (2 * (v >> 5)) * kRow + (v & (kStep - 1));
-      uint64_t mask = (uint64_t)row[0] | ((uint64_t)row[kRow] << 32);
-      while (vn[m] > 0) {
-        const float sd = vd[m];
-        if (!(sd <= t_last)) break;
-        const int c = sd <= t_first ? 0 : count_below<kSpan>(T, sd);
-        mask ^= c >= 64 ? 0ull : (~0ull << c);
-        ++vq[m];
-        --vn[m];
-        if (vn[m] > 0) vd[m] = A.depth[vq[m]];
-      }
-      row[0] = (uint32_t)mask;
-      row[kRow] = (uint32_t)(mask >> 32);
     }
     __syncthreads();
-    // (6) one 32 x 32 transpose per thread of the first half: 128 y matrices,
-    // then 128 z matrices; the second half prepares the next step's depths
-    if (tid < 4 * kSpan) transpose32(tid < 2 * kSpan ? s_y + tid * kRow : s_z + (tid - 2 * kSpan) * kRow);
-    else if (tid < 4 * kSpan + kStep) s_tx[(bi + 1) & 1][tid - 4 * kSpan] = node_depth(g.lo[0], g.h[0], i0 + kStep + tid - 4 * kSpan, w);
+    // one 32 x 32 transpose per thread; a spare wave fills the next span's depths
+    transpose32(s_m + tid * kRow);
     __syncthreads();
-    // (7) majority of the three words, stored to the brick
-    const uint32_t valid = (w - i0 >= 32) ? 0xffffffffu : ((1u << (w - i0)) - 1u);
+    if (tid >= kVoteBlock - kSpan)
+      s_tx[(it + 1) & 1][tid - (kVoteBlock - kSpan)] = node_depth(g.lo[0], g.h[0], i0 + kSpan + tid - (kVoteBlock - kSpan), w);
+    // majority of the three words: x-ray (jl, kl), jl = t % 64, kl = (t / 64)*8 + m;
+    // a wave stores 64 consecutive words of two brick rows per instruction
+    const int jl = tid & 63, j = j0 + jl;
+#pragma unroll 1
+    for (int m = 0; m < 8; ++m) {
+      const int kl = (tid >> 6) * 8 + m, k = k0 + kl;
+      uint64_t xm = 0;
+      if (j < w && k < w) {
+        const uint32_t c = ux[m];
+        xm = (c & kCodeWalk) ? span_walk(&X, (size_t)k * w + j, c, TX, &bad) : decode_span(c);
+      }
+      const int bj = 2 * J + (jl >> 5), bk = 2 * K + (kl >> 5);
 #pragma unroll
-    for (int m = 0; m < kXRays; ++m) {
-      const int r = tid + kVoteBlock * m;
-      const int jl = r & (kSpan - 1), kl = r >> 6;
-      const uint32_t xw_ = xw[m];
-      const uint32_t yw = s_y[(2 * kl + (jl >> 5)) * kRow + (jl & 31)];
-      const uint32_t zw = s_z[(2 * jl + (kl >> 5)) * kRow + (kl & 31)];
-      const uint32_t in = ((xw_ & yw) | (xw_ & zw) | (yw & zw)) & valid;
-      const uint32_t split = ((xw_ | yw | zw) & ~(xw_ & yw & zw)) & valid;
-      const int bj = bj0 + (jl >> 5), bk = bk0 + (kl >> 5);
-      if (bj < nb && bk < nb) {
-        g.bits[(((size_t)bk * nb + bj) * nb + bi) * 1024 + (kl & 31) * 32 + (jl & 31)] = in;
+      for (int ih = 0; ih < 2; ++ih) {
+        const uint32_t xw = (uint32_t)(xm >> (32 * ih));
+        const uint32_t yw = s_m[ymat(kl, jl >> 5, ih) * kRow + (jl & 31)];
+        const uint32_t zw = s_m[zmat(jl, kl >> 5, ih) * kRow + (kl & 31)];
+        const int ib = i0 + 32 * ih;
+        // rows past the grid hold no node (their y or z words may carry fill bits)
+        const uint32_t row = (ib >= w || j >= w || k >= w) ? 0u
+                             : (w - ib >= 32) ? 0xffffffffu : ((1u << (w - ib)) - 1u);
+        const uint32_t in = ((xw & yw) | (xw & zw) | (yw & zw)) & row;
         n_inside += __popc(in);
-        n_split += __popc(split);
+        n_split += __popc(((xw | yw | zw) & ~(xw & yw & zw)) & row);
+        const int bi = 2 * it + ih;
+        if (bi < nb && bj < nb && bk < nb)
+          g.bits[(((size_t)bk * nb + bj) * nb + bi) * 1024 + (kl & 31) * 32 + (jl & 31)] = in;
       }
     }
-    __syncthreads();  // the next step rewrites s_y and s_z
+    __syncthreads();  // the next step rewrites the matrices
   }
 
   if (bad) atomicOr(g.status, kStatusMismatch);
@@ -420,15 +434,19 @@ __global__ __launch_bounds__(kNodeBlock) void node_stats_kernel(const uint64_t* 
 }  // namespace
 
 uint32_t node_workgroups(int32_t w) {
-  const uint32_t nb = (uint32_t)((w + kStep - 1) / kStep);
-  const uint32_t per = (nb + 1) / 2;
-  return per * per;
+  const uint32_t S = (uint32_t)((w + kSpan - 1) / kSpan);
+  return S * S;
 }
 
-hipError_t launch_node_ranks(const NodeArgs& g, hipStream_t s) {
-  const int64_t rays = 2 * (int64_t)g.w * g.w;
-  hipLaunchKernelGGL(node_ranks_kernel, dim3((unsigned)((rays + kNodeBlock - 1) / kNodeBlock)), dim3(kNodeBlock), 0,
-                     s, g);
+size_t node_code_bytes(int32_t w) {
+  const size_t S = (size_t)((w + kSpan - 1) / kSpan);
+  return 3 * S * S * S * 4096 * sizeof(uint16_t);
+}
+
+hipError_t launch_node_codes(const NodeArgs& g, hipStream_t s) {
+  const int64_t npix = (int64_t)g.w * g.w;
+  hipLaunchKernelGGL(node_codes_kernel, dim3((unsigned)((npix + kNodeBlock - 1) / kNodeBlock), 3), dim3(kNodeBlock),
+                     sizeof(float) * (size_t)g.w, s, g);
   return hipGetLastError();
 }
 
