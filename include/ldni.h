@@ -236,7 +236,7 @@ ldni_status ldni_boolean(const ldni_axis_view *a, const ldni_axis_view *b, int32
  * samples have depth <= its depth (half-open volumes [enter, exit); an
  * unpaired last sample of an odd count is ignored).
  *   views   HOST array of the x-, y- and z-LDNI views (ldni_result_axis
- *           order), one w; offsets and depth are read (depth ascending per
+ *           order), one w in 1..8192; offsets and depth are read (depth ascending per
  *           pixel, as sampled); offsets must be a prefix of the samples
  *           (non-decreasing, at most n_samples), else LDNI_ERR_INVALID_ARG
  *           (found on the device; bits are then unspecified).
@@ -249,12 +249,14 @@ ldni_status ldni_boolean(const ldni_axis_view *a, const ldni_axis_view *b, int32
  *   n_words at least ldni_node_words(w).
  *   stats   HOST u64 [2] or NULL: nodes inside, and nodes whose three
  *           votes are not all equal (the disagreements the vote repairs).
+ * Workspace: about 3 w^3 / 32 bytes (w = 2048: 0.8 GB) of span codes from
+ * the stream-ordered pool, kept for reuse like the other calls' buffers.
  * One host synchronisation (the totals and the status).
  */
 ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[6], uint32_t *bits,
                                 uint64_t n_words, uint64_t stats[2], void *hip_stream);
 
-/* Words of the bit volume of ldni_classify_nodes at resolution w (1..16384). */
+/* Words of the bit volume of ldni_classify_nodes at resolution w (1..8192). */
 ldni_status ldni_node_words(int32_t w, uint64_t *n_words);
 
 /* Largest per-pixel count of each axis of a plan (after begin). */

@@ -214,7 +214,7 @@ def _nodes_call(L, views=True, ws=(8, 8, 8), offsets=True, n=0, depth=True, bbox
 
 @pytest.mark.parametrize("kw", [
     dict(views=False), dict(bits=False), dict(ws=(8, 8, 9)), dict(ws=(0, 0, 0)),
-    dict(ws=(16385, 16385, 16385)), dict(offsets=False), dict(n=5, depth=False), dict(n=2 ** 32),
+    dict(ws=(8193, 8193, 8193)), dict(offsets=False), dict(n=5, depth=False), dict(n=2 ** 32),
     dict(bbox=(0, 0, 0, 1, 0, 1)), dict(bbox=(0, 0, float("nan"), 1, 1, 1)),
     dict(bbox=(0, 0, 0, 1, 1, float("inf"))), dict(n_words=1024 - 1),
 ])
@@ -231,8 +231,9 @@ def test_classify_nodes_invalid_arguments_rejected_on_host(L, kw):
 def test_node_words(L):
     """Bricks of 32^3 nodes, 1024 words each, ceil(w/32) per axis."""
     n = ctypes.c_uint64()
-    for w, nb in ((1, 1), (32, 1), (33, 2), (2048, 64), (16384, 512)):
+    for w, nb in ((1, 1), (32, 1), (33, 2), (2048, 64), (8192, 256)):
         assert L.ldni_node_words(w, ctypes.byref(n)) == 0
         assert n.value == nb ** 3 * 1024
     assert L.ldni_node_words(0, ctypes.byref(n)) == 1 and n.value == 0
+    assert L.ldni_node_words(8193, ctypes.byref(n)) == 1 and n.value == 0
     assert L.ldni_node_words(8, None) == 1
