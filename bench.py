@@ -433,6 +433,7 @@ def measure_nodes(ldni, torch, mg, reps):
         roof = {"bound": "hbm", "kernel": "classify_nodes", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(k_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": alg}
+    kern = {k: round(v[1] / reps, 4) for k, v in ks.items() if k in ("node_codes", "classify_nodes")}
     return {
         "workload": "nodes-2048",
         "description": "inside/outside of the 2048^3 grid nodes of the scene64 (seed 1) LDNIs by the "
@@ -441,6 +442,10 @@ def measure_nodes(ldni, torch, mg, reps):
         "nodes_with_split_votes": n_split,
         "ms_per_step": round(ms, 4), "value": w ** 3 / (ms / 1e3), "unit": "nodes/s",
         "roofline": roof,
+        "path_roofline": {"algorithmic_bytes_per_step": alg,
+                          "achieved_GBps": round(alg / (ms / 1e3) / 1e9, 1),
+                          "frac_of_hbm_peak": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms_per_step": kern,
     }
 
 
