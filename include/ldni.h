@@ -259,6 +259,42 @@ ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[
 /* Words of the bit volume of ldni_classify_nodes at resolution w (1..8192). */
 ldni_status ldni_node_words(int32_t w, uint64_t *n_words);
 
+/*
+ * ldni_offset -- offset of a solid given by its three LDNIs by a distance r
+ * (Sec. 4.2): the Minkowski sum with a sphere of radius r, approximated by
+ * uniting the solid with a sphere centred at every sample of its LDNIs, each
+ * sphere sampled on the same grid (r > 0); an inner offset (r < 0) subtracts
+ * spheres of radius |r| instead.  The Boolean operations are those of Sec.
+ * 4.1 with the small interval removal of Sec. 4.1.1.
+ * Readings fixed here: the spheres of all samples of the three LDNIs are
+ * applied at once; the centre of a sample of the a-LDNI at pixel (i, j) is
+ * (lo_a + depth, c_u[i], c_v[j]) in float64 (placed by axis); a sphere hits
+ * a ray when rho^2 < r^2 (float64, rho the distance of the centre from the
+ * ray), at centre -/+ sqrt(r^2 - rho^2), depths rounded to float32, normal
+ * (x - centre)/|r| in float64 rounded to float32 (negated for r < 0); per
+ * ray, events of equal float32 depth form one group, the solid's state after
+ * a group is the parity of its (paired) samples so far, the spheres' state is
+ * whether one is entered and not left; a group that changes the result
+ * contributes its first event: the solid's samples by index, then spheres by
+ * generating sample, an enter before its exit; volumes with (double)exit -
+ * (double)enter <= 0 or < eps are removed.  Generating samples are numbered
+ * over the x-, y-, z-view in storage order; a result sample from the sphere
+ * of sample g has tri = -1 - g, one from the solid keeps its id.
+ *   views   HOST array of the x-, y- and z-LDNI (ldni_result_axis order), one
+ *           w; offsets must be a prefix of the samples (else
+ *           LDNI_ERR_INVALID_ARG, found on the device); fewer than 2^30
+ *           samples in all.
+ *   bbox    HOST f32 box the views were sampled with.
+ *   r       finite, not zero (world units).
+ *   eps     finite, >= 0 (the paper uses 1e-5).
+ *   out     a new three-axis result owned by the caller (ldni_free).
+ * A ray may meet at most 1024 events (its paired samples plus two per sphere
+ * that hits it); more fail with LDNI_ERR_OVERFLOW.  Two host
+ * synchronisations (the tile-list size, the result size).
+ */
+ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], float r, float eps,
+                        void *hip_stream, ldni_result **out);
+
 /* Largest per-pixel count of each axis of a plan (after begin). */
 ldni_status ldni_plan_max_layers(const ldni_plan *plan, uint32_t max_layers[3]);
 

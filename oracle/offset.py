@@ -176,3 +176,25 @@ def offset(L, bbox, w, r, eps=1e-5):
                           normal=np.asarray(nrm, np.float32).reshape(n, 3),
                           tri=np.asarray(tri, np.int32).reshape(n))
     return res
+
+
+def offset_rays(L, bbox, w, r, axis, pixels, eps=1e-5):
+    """The same result on chosen rays only: for each pixel of ``pixels`` on
+    the ``axis``-LDNI, a list of (depth, normal, id)."""
+    union = r > 0
+    rr = abs(float(np.float32(r)))
+    b = bbox_f32(bbox)
+    centres = sphere_centres(L, bbox, w)
+    a = axis
+    u, v = (a + 1) % 3, (a + 2) % 3
+    cu, cv = _centres(b[u], b[3 + u], w), _centres(b[v], b[3 + v], w)
+    srt = np.argsort(centres[:, u], kind="stable")
+    order = (srt, centres[srt, u])
+    ax = L[a]
+    out = []
+    for p in pixels:
+        p = int(p)
+        o0, o1 = int(ax.offsets[p]), int(ax.offsets[p + 1])
+        ev = _ray_events(a, cu[p % w], cv[p // w], centres, rr, b[a], union, order)
+        out.append(offset_pixel(ax.depth[o0:o1], ax.normal[o0:o1], ax.tri[o0:o1], ev, union, eps))
+    return out

@@ -23,7 +23,8 @@ __all__ = ["LDNI", "LDNIError", "sample", "ldni_sample", "ldni_result_axis", "ld
            "ldni_sample_begin", "ldni_sample_finish", "ldni_plan_free", "ldni_status_string",
            "set_tile_shape", "axis_mask", "library_path", "profile_enable", "profile_read",
            "ldni_backward", "sample_diff", "LDNISample", "Batch", "sample_batch", "ldni_boolean",
-           "boolean", "BOOLEAN_OPS", "ldni_classify_nodes", "classify_nodes", "node_words"]
+           "boolean", "BOOLEAN_OPS", "ldni_classify_nodes", "classify_nodes", "node_words",
+           "ldni_offset", "offset"]
 
 AXES = "xyz"
 library_path = _lib.LIB_PATH
@@ -376,6 +377,30 @@ def ldni_classify_nodes(ldnis, bbox, bits=None):
 
 
 classify_nodes = ldni_classify_nodes
+
+
+def ldni_offset(ldnis, bbox, r: float, eps: float = 1e-5) -> Result:
+    """The C ABI ``ldni_offset`` (Sec. 4.2): the solid whose x-, y-, z-LDNIs are
+    ``ldnis[0..2]`` (sampled with ``bbox``) offset by r, as the union with a
+    sphere of radius r at every sample (r < 0: their difference); the library
+    owns the three-axis result."""
+    L = [ldnis[a] for a in range(3)]
+    views = (_lib.AxisView * 3)(*[_view(l) for l in L])
+    bb = (ctypes.c_float * 6)(*[float(x) for x in bbox])
+    h = ctypes.c_void_p()
+    _lib.check(_lib.lib().ldni_offset(views, bb, float(r), float(eps), _stream(L[0].depth.device),
+                                      ctypes.byref(h)))
+    return Result(h)
+
+
+def offset(ldnis, bbox, r: float, eps: float = 1e-5) -> Dict[int, LDNI]:
+    """``ldni_offset`` with the three axes copied into new torch tensors."""
+    dev = ldnis[0].depth.device
+    res = ldni_offset(ldnis, bbox, r, eps)
+    try:
+        return {a: _copy_view(res.view(a), a, dev) for a in range(3)}
+    finally:
+        res.free()
 
 
 def _copy_view(v: _lib.AxisView, axis: int, device) -> LDNI:

@@ -105,6 +105,9 @@ def lib():
     L.ldni_classify_nodes.restype = st
     L.ldni_node_words.argtypes = [i32, ctypes.POINTER(ctypes.c_uint64)]
     L.ldni_node_words.restype = st
+    L.ldni_offset.argtypes = [ctypes.POINTER(AxisView), ctypes.POINTER(ctypes.c_float), ctypes.c_float,
+                              ctypes.c_float, vp, ctypes.POINTER(vp)]
+    L.ldni_offset.restype = st
     L.ldni_profile_enable.argtypes = [ctypes.c_int]
     L.ldni_profile_enable.restype = st
     L.ldni_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -140,4 +143,5 @@ def exported_symbols():
             "ldni_status_string", "ldni_last_error", "ldni_set_tile_shape",
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
             "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch",
-            "ldni_boolean", "ldni_sample_finish_rgb8", "ldni_classify_nodes", "ldni_node_words"]
+            "ldni_boolean", "ldni_sample_finish_rgb8", "ldni_classify_nodes", "ldni_node_words",
+            "ldni_offset"]

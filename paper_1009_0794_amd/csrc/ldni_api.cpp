@@ -1117,6 +1117,176 @@ ldni_status ldni_classify_nodes(const ldni_axis_view views[3], const float bbox[
   return st;
 }
 
+ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], float r, float eps, void* hip_stream,
+                        ldni_result** out) {
+  if (out) *out = nullptr;
+  if (!out || !views || !bbox) return fail(LDNI_ERR_INVALID_ARG, "NULL argument");
+  if (!std::isfinite(r) || r == 0.0f) return fail(LDNI_ERR_INVALID_ARG, "r must be finite and not zero");
+  if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(LDNI_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  const int32_t w = views[0].w;
+  if (w < 1 || w > 16384 || views[1].w != w || views[2].w != w)
+    return fail(LDNI_ERR_INVALID_ARG, "the three views need the same w in [1, 16384]");
+  uint64_t n_total = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (!std::isfinite(bbox[d]) || !std::isfinite(bbox[3 + d]))
+      return fail(LDNI_ERR_INVALID_ARG, "bbox must be finite");
+    if (!(bbox[d] < bbox[3 + d])) return fail(LDNI_ERR_INVALID_ARG, "bbox needs lo < hi on every axis");
+    const ldni_axis_view& v = views[d];
+    if (!v.offsets) return fail(LDNI_ERR_INVALID_ARG, "NULL offsets");
+    if (v.n_samples > 0 && (!v.depth || !v.normal || !v.tri))
+      return fail(LDNI_ERR_INVALID_ARG, "NULL sample array of a view with samples");
+    if (v.n_samples > 0xffffffffull) return fail(LDNI_ERR_INVALID_ARG, "a view has 2^32 or more samples");
+    n_total += v.n_samples;
+  }
+  if (n_total >= kMaxSpheres) return fail(LDNI_ERR_INVALID_ARG, "2^30 or more samples in the three views");
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  prepare_pool(device);
+  uint32_t* rb = pinned_readback();
+  if (!rb) return fail(LDNI_ERR_OUT_OF_MEMORY, "pinned readback buffer");
+  const int64_t npix = (int64_t)w * w;
+  const int32_t tiles_x = (w + 7) / 8;
+  const uint32_t tiles_axis = (uint32_t)tiles_x * (uint32_t)tiles_x;
+  const int64_t n_tiles = 3 * (int64_t)tiles_axis;
+
+  ldni_result* res = new (std::nothrow) ldni_result();
+  if (!res) return fail(LDNI_ERR_OUT_OF_MEMORY, "result");
+  std::memset(res->view, 0, sizeof(res->view));
+  res->stream = stream;
+  hipError_t e = cache_get(&res->offsets_buf, 3 * sizeof(uint32_t) * (size_t)(npix + 1), stream, &res->offsets_bytes);
+  if (e != hipSuccess) {
+    res->offsets_buf = nullptr;
+    ldni_free(res);
+    return hip_fail(e, "offsets allocation");
+  }
+  // workspace: status, tile counts and cursors, tile starts, scan scratch, centres
+  const size_t o_count = 256;
+  const size_t o_cursor = align_up(o_count + sizeof(uint32_t) * (size_t)n_tiles);
+  const size_t o_start = align_up(o_cursor + sizeof(uint32_t) * (size_t)n_tiles);
+  const size_t o_scratch = align_up(o_start + sizeof(uint32_t) * (size_t)(n_tiles + 1));
+  const size_t scratch = std::max(scan_scratch_bytes(n_tiles, 1), scan_scratch_bytes(npix, 3));
+  const size_t o_centres = align_up(o_scratch + scratch);
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  e = cache_get(&ws, o_centres + 3 * sizeof(double) * (size_t)std::max<uint64_t>(n_total, 1), stream, &ws_bytes);
+  if (e != hipSuccess) {
+    ldni_free(res);
+    return hip_fail(e, "workspace allocation");
+  }
+  void* list = nullptr;
+  size_t list_bytes = 0;
+  auto bail = [&](ldni_status st) {
+    cache_put(list, list_bytes, stream);
+    cache_put(ws, ws_bytes, stream);
+    ldni_free(res);
+    return st;
+  };
+  char* wb = static_cast<char*>(ws);
+  OffsetArgs g{};
+  uint64_t base = 0;
+  for (int d = 0; d < 3; ++d) {
+    const ldni_axis_view& v = views[d];
+    g.in[d] = AxisArrays{v.n_samples, v.offsets, v.depth, v.normal, v.tri};
+    g.lo[d] = (double)bbox[d];
+    g.h[d] = ((double)bbox[3 + d] - (double)bbox[d]) / (double)w;
+    g.base[d] = base;
+    base += v.n_samples;
+    g.counts[d] = static_cast<uint32_t*>(res->offsets_buf) + d * (npix + 1);
+    g.out_offsets[d] = g.counts[d];
+  }
+  g.w = w;
+  g.tiles_x = tiles_x;
+  g.tiles_per_axis = tiles_axis;
+  g.n_spheres = (uint32_t)n_total;
+  g.r = std::fabs((double)r);
+  g.eps = (double)eps;
+  g.union_op = r > 0.0f ? 1 : 0;
+  g.status = reinterpret_cast<uint32_t*>(wb);
+  g.tile_count = reinterpret_cast<uint32_t*>(wb + o_count);
+  g.tile_cursor = reinterpret_cast<uint32_t*>(wb + o_cursor);
+  g.tile_start = reinterpret_cast<uint32_t*>(wb + o_start);
+  g.centres = reinterpret_cast<double*>(wb + o_centres);
+  void* scr = wb + o_scratch;
+#define OSTEP(expr, what)                                  \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return bail(hip_fail(e_, what)); \
+  } while (0)
+  OSTEP(launch_fill_u32(g.status, 0u, 64, stream), "fill");
+  OSTEP(launch_fill_u32(g.tile_count, 0u, 2 * n_tiles + 64, stream), "fill");  // counts and cursors
+  OSTEP(timed("offset_centres", stream, [&] { return launch_offset_centres(g, stream); }), "centre kernel");
+  OSTEP(timed("offset_bin", stream, [&] { return launch_offset_bin(g, false, stream); }), "binning kernel");
+  OSTEP(launch_scan(g.tile_count, g.tile_start, n_tiles, scr, g.status, stream), "tile scan");
+  {
+    const uint32_t* src[2] = {g.status, g.tile_start + n_tiles};
+    OSTEP(launch_gather(src, 2, rb, stream), "readback");
+    OSTEP(hipStreamSynchronize(stream), "synchronise");
+  }
+  if (rb[0] & kStatusMismatch)
+    return bail(fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples"));
+  if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more tile-list entries"));
+  e = cache_get(&list, sizeof(uint32_t) * (size_t)std::max<uint32_t>(rb[1], 1), stream, &list_bytes);
+  if (e != hipSuccess) {
+    list = nullptr;
+    return bail(hip_fail(e, "tile list allocation"));
+  }
+  g.list = static_cast<uint32_t*>(list);
+  OSTEP(timed("offset_bin", stream, [&] { return launch_offset_bin(g, true, stream); }), "binning kernel");
+  OSTEP(timed("offset_count", stream, [&] { return launch_offset_rays(g, false, stream); }), "offset count kernel");
+  uint32_t* max_slot = g.status + 8;  // [8..10]: largest count per axis
+  uint32_t* maxes[3] = {max_slot, max_slot + 1, max_slot + 2};
+  OSTEP(launch_scan_segments(g.counts, g.counts, 3, npix, scr, g.status, stream, maxes), "offset scan");
+  {
+    const uint32_t* src[7] = {g.status, g.counts[0] + npix, g.counts[1] + npix, g.counts[2] + npix,
+                              maxes[0], maxes[1], maxes[2]};
+    OSTEP(launch_gather(src, 7, rb, stream), "readback");
+    OSTEP(hipStreamSynchronize(stream), "synchronise");
+  }
+  if (rb[0] & kStatusMismatch)
+    return bail(fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples"));
+  if (rb[0] & kStatusOutFull)
+    return bail(fail(LDNI_ERR_OVERFLOW, "a ray has more than 896 events at one depth or more than 512 end "
+                                        "points before small volumes are removed"));
+  if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more result samples on one axis"));
+  const uint64_t n_out[3] = {rb[1], rb[2], rb[3]};
+  const uint32_t max_layers[3] = {rb[4], rb[5], rb[6]};
+  size_t o_ax[3][3], total = 0;
+  for (int d = 0; d < 3; ++d) {
+    o_ax[d][0] = total;
+    o_ax[d][1] = align_up(o_ax[d][0] + sizeof(float) * n_out[d]);
+    o_ax[d][2] = align_up(o_ax[d][1] + 3 * sizeof(float) * n_out[d]);
+    total = align_up(o_ax[d][2] + sizeof(int32_t) * n_out[d]);
+  }
+  e = cache_get(&res->samples_buf, std::max<size_t>(total, 256), stream, &res->samples_bytes);
+  if (e != hipSuccess) {
+    res->samples_buf = nullptr;
+    return bail(hip_fail(e, "sample allocation"));
+  }
+  char* sb = static_cast<char*>(res->samples_buf);
+  for (int d = 0; d < 3; ++d) {
+    g.out_depth[d] = reinterpret_cast<float*>(sb + o_ax[d][0]);
+    g.out_normal[d] = reinterpret_cast<float*>(sb + o_ax[d][1]);
+    g.out_tri[d] = reinterpret_cast<int32_t*>(sb + o_ax[d][2]);
+  }
+  OSTEP(timed("offset_write", stream, [&] { return launch_offset_rays(g, true, stream); }), "offset write kernel");
+#undef OSTEP
+  cache_put(list, list_bytes, stream);
+  cache_put(ws, ws_bytes, stream);
+  for (int d = 0; d < 3; ++d) {
+    ldni_axis_view& v = res->view[d];
+    v.w = w;
+    v.max_layers = max_layers[d];
+    v.n_samples = n_out[d];
+    v.offsets = g.counts[d];
+    v.depth = g.out_depth[d];
+    v.normal = g.out_normal[d];
+    v.tri = g.out_tri[d];
+  }
+  *out = res;
+  return LDNI_OK;
+}
+
 void ldni_free(ldni_result* r) {
   if (!r) return;
   cache_put(r->samples_buf, r->samples_bytes, r->stream);

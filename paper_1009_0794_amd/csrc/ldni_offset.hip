@@ -1,0 +1,423 @@
+// ldni_offset.hip -- gfx950 kernels offsetting a solid given by its LDNIs.
+//
+// Sec. 4.2 approximates the offset of a solid H by a distance r by the
+// Minkowski sum of H with a sphere of radius r: a sphere is centred at every
+// depth-normal sample of H's LDNIs, sampled into LDNIs on the same grid, and
+// united with H (an inner offset, r < 0, subtracts spheres of radius |r|),
+// with the Boolean operations of Sec. 4.1 and the small interval removal of
+// Sec. 4.1.1.
+//
+// Fixed readings: the spheres of all samples of the three LDNIs are applied
+// at once; a sphere hits a ray when rho^2 < r^2 (float64), at centre -/+
+// sqrt(r^2 - rho^2); per ray the events are H's paired samples and the
+// spheres' chord ends; events of equal float32 depth form one group, after
+// which H's state is the parity of its samples so far and the spheres' state
+// is "some sphere entered and not left"; a group that changes the result
+// (H or S, resp. H and not S) contributes its first event (H's samples by
+// index, then spheres by generating sample, enter before exit); volumes with
+// (double)exit - (double)enter <= 0 or < eps are removed.  Generating samples
+// are numbered over the x-, y-, z-LDNI in storage order; a sphere's sample
+// gets id -1 - g.
+//
+// Passes: the sphere centres (one thread per pixel); binning of the spheres
+// into 8 x 8 pixel tiles of every image (count, scan, scatter); then one wave
+// per ray, twice (count, write): the ray's events go to a wave-private LDS
+// buffer as 64-bit keys (orderable depth, order), window by window in depth
+// when they do not fit, a bitonic sort orders them, and a sweep in chunks of
+// 64 (wave prefix sums of H's parity and of the open spheres, group starts by
+// a max-scan) finds the result's end points.
+// Nothing is a contraction: the work is the exact chord tests and the sorts.
+#pragma clang fp contract(off)
+
+#include "ldni_internal.hpp"
+
+namespace ldni {
+namespace {
+
+constexpr int kOffBlock = 256;  // four waves, one ray each at a time
+constexpr int kOffWaves = kOffBlock / 64;
+constexpr uint32_t kSphereOrder = 0x80000000u;
+
+__device__ __forceinline__ uint32_t orderable(float d) {
+  uint32_t u = __float_as_uint(d);
+  if (u == 0x80000000u) u = 0u;  // -0 groups with +0
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ double centre_of(const OffsetArgs& g, int b, int i) {
+  return (double)(float)(g.lo[b] + ((double)i + 0.5) * g.h[b]);
+}
+
+// Centres of the spheres: one thread per pixel of each LDNI writes the
+// centres of the pixel's samples (world order) at the sample's number.
+__global__ __launch_bounds__(kOffBlock) void offset_centres_kernel(OffsetArgs g) {
+  const int64_t npix = (int64_t)g.w * g.w;
+  const int64_t t = (int64_t)blockIdx.x * kOffBlock + threadIdx.x;
+  if (t >= 3 * npix) return;
+  const int a = (int)(t / npix);
+  const int64_t p = t - a * npix;
+  const int u = (a + 1) % 3, v = (a + 2) % 3;
+  const AxisArrays& ax = g.in[a];
+  const uint32_t o0 = ax.offsets[p], o1 = ax.offsets[p + 1];
+  if (o1 < o0 || (uint64_t)o1 > ax.n) {
+    atomicOr(g.status, kStatusMismatch);
+    return;
+  }
+  const double cu = centre_of(g, u, (int)(p % g.w)), cv = centre_of(g, v, (int)(p / g.w));
+  for (uint32_t q = o0; q < o1; ++q) {
+    double* c = g.centres + 3 * (g.base[a] + q);
+    c[a] = g.lo[a] + (double)ax.depth[q];
+    c[u] = cu;
+    c[v] = cv;
+  }
+}
+
+// Pixel range [i0, i1] of an image axis whose centres may lie within r of x
+// (one pixel of margin for the rounding of the centres); i0 > i1 if none.
+__device__ __forceinline__ void pixel_range(const OffsetArgs& g, int b, double x, int& i0, int& i1) {
+  const double t0 = (x - g.r - g.lo[b]) / g.h[b] - 0.5, t1 = (x + g.r - g.lo[b]) / g.h[b] - 0.5;
+  const double f0 = floor(t0) - 1.0, f1 = ceil(t1) + 1.0;
+  i0 = f0 < 0.0 ? 0 : f0 > (double)(g.w - 1) ? g.w : (int)f0;
+  i1 = f1 < 0.0 ? -1 : f1 > (double)(g.w - 1) ? g.w - 1 : (int)f1;
+}
+
+// Binning: for sphere s and image a, the tiles its pixel range covers; count
+// (kScatter false) or write the sphere into the tiles' lists.
+template <bool kScatter>
+__global__ __launch_bounds__(kOffBlock) void offset_bin_kernel(OffsetArgs g) {
+  const int64_t t = (int64_t)blockIdx.x * kOffBlock + threadIdx.x;
+  if (t >= 3 * (int64_t)g.n_spheres) return;
+  const int a = (int)(t / g.n_spheres);
+  const uint32_t s = (uint32_t)(t - (int64_t)a * g.n_spheres);
+  const int u = (a + 1) % 3, v = (a + 2) % 3;
+  const double* c = g.centres + 3 * (size_t)s;
+  int iu0, iu1, iv0, iv1;
+  pixel_range(g, u, c[u], iu0, iu1);
+  pixel_range(g, v, c[v], iv0, iv1);
+  if (iu0 > iu1 || iv0 > iv1) return;
+  const int tx0 = iu0 >> 3, tx1 = iu1 >> 3, ty0 = iv0 >> 3, ty1 = iv1 >> 3;
+  const uint32_t tiles = (uint32_t)a * g.tiles_per_axis;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const uint32_t tile = tiles + (uint32_t)(ty * g.tiles_x + tx);
+      if (kScatter) g.list[g.tile_start[tile] + atomicAdd(&g.tile_cursor[tile], 1u)] = s;
+      else atomicAdd(&g.tile_count[tile], 1u);
+    }
+}
+
+// One event's world-order normal and depth for a sphere g on the ray of axis
+// a through (cu, cv) (exactly the arithmetic of the hit test).
+struct SphereHit {
+  float depth;
+  float n[3];
+};
+__device__ __forceinline__ SphereHit sphere_sample(const OffsetArgs& g, int a, double cu, double cv, uint32_t s,
+                                                   bool is_exit) {
+  const int u = (a + 1) % 3, v = (a + 2) % 3;
+  const double* c = g.centres + 3 * (size_t)s;
+  const double du = cu - c[u], dv = cv - c[v];
+  const double rho2 = du * du + dv * dv;
+  const double t = sqrt(g.r * g.r - rho2);
+  const double z = is_exit ? c[a] + t : c[a] - t;
+  const double sign = g.union_op ? 1.0 : -1.0;
+  SphereHit h;
+  h.depth = (float)(z - g.lo[a]);
+  h.n[u] = (float)(sign * (du / g.r));
+  h.n[v] = (float)(sign * (dv / g.r));
+  h.n[a] = (float)(sign * ((z - c[a]) / g.r));
+  return h;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive wave prefix sum.
+__device__ __forceinline__ int wave_scan_add(int x) {
+  const int lane = (int)lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int wave_scan_max(int x) {
+  const int lane = (int)lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x = max(x, y);
+  }
+  return x;
+}
+
+// Bitonic sort of key[0..n) ascending by one wave (padded with ~0 to a power
+// of two of at least 64, within the buffer).
+__device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
+  const uint32_t lane = lane_id();
+  uint32_t n2 = 64;
+  while (n2 < n) n2 <<= 1;
+  for (uint32_t k = n + lane; k < n2; k += 64) key[k] = ~0ull;
+  wave_sync();
+  for (uint32_t size = 2; size <= n2; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t q = lane; q < n2 / 2; q += 64) {
+        const uint32_t lo = 2 * q - (q & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = key[lo], y = key[hi];
+        if ((x > y) == up) {
+          key[lo] = y;
+          key[hi] = x;
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// The per-ray pass: counts (kWrite false) or writes the ray's result.  The
+// ray's events are taken in windows of depth: a window collects the events
+// at or after its lower depth bound into a buffer of kOffsetBuf keys; when a
+// chunk would not fit, the buffer is sorted and cut back to the events
+// before the depth of its kOffsetKeep-th smallest, which becomes the
+// window's (exclusive) upper bound.  Windows end between groups of equal
+// depth, and the sweep carries H's parity, the open spheres and the result
+// state from one window to the next.
+template <bool kWrite>
+__global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
+  __shared__ uint64_t s_key[kOffWaves][kOffsetBuf];
+  __shared__ uint64_t s_emit[kOffWaves][kOffsetEmit];
+  __shared__ uint32_t s_rbit[kOffWaves][kOffsetBuf / 32];
+
+  const int wv = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const int64_t npix = (int64_t)g.w * g.w;
+  const int64_t ray = (int64_t)blockIdx.x * kOffWaves + wv;
+  if (ray >= 3 * npix) return;
+  const int a = (int)(ray / npix);
+  const int64_t p = ray - a * npix;
+  const int u = (a + 1) % 3, v = (a + 2) % 3;
+  const int iu = (int)(p % g.w), iv = (int)(p / g.w);
+  const double cu = centre_of(g, u, iu), cv = centre_of(g, v, iv);
+  uint64_t* key = s_key[wv];
+  uint64_t* emit = s_emit[wv];
+  uint32_t* rbit = s_rbit[wv];
+  const AxisArrays& H = g.in[a];
+
+  const uint32_t o0 = H.offsets[p], o1 = H.offsets[p + 1];
+  uint32_t nh = 0;
+  if (o1 < o0 || (uint64_t)o1 > H.n) {
+    if (lane == 0) atomicOr(g.status, kStatusMismatch);
+  } else {
+    nh = (o1 - o0) & ~1u;
+  }
+  const uint32_t tile = (uint32_t)a * g.tiles_per_axis + (uint32_t)((iv >> 3) * g.tiles_x + (iu >> 3));
+  const uint32_t l0 = g.tile_start[tile], l1 = g.tile_start[tile + 1];
+  const double r2 = g.r * g.r;
+
+  uint32_t lower = 0;        // window: orderable depth >= lower ...
+  bool more = true;          // ... and, if bounded, < upper
+  int carry_h = 0, carry_s = 0;
+  bool prev_res = false;
+  uint32_t n_emit = 0;
+  bool failed = false;
+  while (more && !failed) {
+    uint32_t upper = 0;
+    bool bounded = false;
+    uint32_t n = 0;
+    // append up to two events per lane (keys k0, k1; has0, has1) after filtering
+    auto append = [&](uint64_t k0, bool has0, uint64_t k1, bool has1) {
+      auto in_window = [&](uint64_t k) {
+        const uint32_t d = (uint32_t)(k >> 32);
+        return d >= lower && (!bounded || d < upper);
+      };
+      bool h0 = has0 && in_window(k0), h1 = has1 && in_window(k1);
+      uint32_t c = (h0 ? 1u : 0u) + (h1 ? 1u : 0u);
+      uint32_t total = (uint32_t)__popcll(__ballot(h0)) + (uint32_t)__popcll(__ballot(h1));
+      if (n + total > (uint32_t)kOffsetBuf) {
+        wave_sort(key, n);
+        const uint32_t cut = (uint32_t)(key[kOffsetKeep] >> 32);
+        // events before the cut depth stay: the first index whose depth is >= cut
+        uint32_t m = 0;
+        for (uint32_t q0 = 0; q0 < (uint32_t)kOffsetKeep + 1; q0 += 64) {
+          const uint32_t q = q0 + lane;
+          m += (uint32_t)__popcll(__ballot(q <= (uint32_t)kOffsetKeep && (uint32_t)(key[q] >> 32) < cut));
+        }
+        bounded = true;
+        upper = cut;
+        n = m;
+        if (m == 0) failed = true;  // one group of equal depth larger than a window
+        h0 = has0 && in_window(k0);
+        h1 = has1 && in_window(k1);
+        c = (h0 ? 1u : 0u) + (h1 ? 1u : 0u);
+        wave_sync();
+      }
+      const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+      const uint64_t below = (1ull << lane) - 1ull;
+      (void)c;
+      uint32_t pos = n + (uint32_t)__popcll(m0 & below) + (uint32_t)__popcll(m1 & below);
+      if (h0) key[pos++] = k0;
+      if (h1) key[pos] = k1;
+      n += (uint32_t)__popcll(m0) + (uint32_t)__popcll(m1);
+    };
+    for (uint32_t k0 = 0; k0 < nh && !failed; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      const bool has = k < nh;
+      const uint64_t kk = has ? (((uint64_t)orderable(H.depth[o0 + k]) << 32) | k) : 0ull;
+      append(kk, has, 0ull, false);
+    }
+    for (uint32_t base = l0; base < l1 && !failed; base += 64) {
+      const uint32_t e = base + lane;
+      bool hit = false;
+      uint64_t ka = 0, kb = 0;
+      if (e < l1) {
+        const uint32_t sph = g.list[e];
+        const double* c = g.centres + 3 * (size_t)sph;
+        const double du = cu - c[u], dv = cv - c[v];
+        const double rho2 = du * du + dv * dv;
+        if (rho2 < r2) {
+          hit = true;
+          const double t = sqrt(r2 - rho2), za = c[a];
+          const float d0 = (float)((za - t) - g.lo[a]), d1 = (float)((za + t) - g.lo[a]);
+          ka = ((uint64_t)orderable(d0) << 32) | kSphereOrder | (sph << 1);
+          kb = ((uint64_t)orderable(d1) << 32) | kSphereOrder | (sph << 1) | 1u;
+        }
+      }
+      append(ka, hit, kb, hit);
+    }
+    if (failed) break;
+    wave_sync();
+    if (n > 0) {
+      wave_sort(key, n);
+      // sweep: per event H's parity and the open spheres after it; at the
+      // last event of each group the result state against the one after the
+      // previous group; a change emits the group's first event
+      int carry_first = -1;
+      const bool window_prev = prev_res;  // result state before this window
+      for (uint32_t c0 = 0; c0 < n; c0 += 64) {
+        const uint32_t q = c0 + lane;
+        const bool valid = q < n;
+        const uint64_t kq = valid ? key[q] : ~0ull;
+        const bool is_h = valid && !(kq & kSphereOrder);
+        const int ph = carry_h + wave_scan_add(is_h ? 1 : 0);
+        const int ps = carry_s + wave_scan_add((valid && !is_h) ? ((kq & 1u) ? -1 : 1) : 0);
+        const uint32_t dq = (uint32_t)(kq >> 32);
+        const bool first = valid && (q == 0 || (uint32_t)(key[q - 1] >> 32) != dq);
+        const bool last = valid && (q + 1 == n || (uint32_t)(key[q + 1] >> 32) != dq);
+        const int fq = max(carry_first, wave_scan_max(first ? (int)q : -1));
+        const bool res = g.union_op ? ((ph & 1) != 0 || ps > 0) : ((ph & 1) != 0 && ps <= 0);
+        const uint64_t rm = __ballot(valid && res);
+        if (lane == 0) rbit[c0 >> 5] = (uint32_t)rm;
+        if (lane == 32) rbit[(c0 >> 5) + 1] = (uint32_t)(rm >> 32);
+        wave_sync();
+        bool e = false;
+        if (last) {
+          const bool prev = fq > 0 ? ((rbit[(fq - 1) >> 5] >> ((fq - 1) & 31)) & 1u) != 0 : window_prev;
+          e = prev != res;
+        }
+        const uint64_t em = __ballot(e);
+        const uint32_t ne = (uint32_t)__popcll(em);
+        if (n_emit + ne > (uint32_t)kOffsetEmit) {
+          failed = true;
+          break;
+        }
+        if (e) emit[n_emit + (uint32_t)__popcll(em & ((1ull << lane) - 1ull))] = key[fq];
+        n_emit += ne;
+        carry_h = __shfl(ph, 63);
+        carry_s = __shfl(ps, 63);
+        carry_first = __shfl(fq, 63);
+        // state after the last event so far (after the window: the next one's start)
+        const int last_q = (int)min(c0 + 63, n - 1);
+        const uint64_t rm_last = __shfl(rm, 0);
+        prev_res = ((rm_last >> (last_q - (int)c0)) & 1ull) != 0;
+      }
+      wave_sync();
+    }
+    more = bounded;
+    lower = upper;
+  }
+  if (failed) {
+    if (lane == 0) atomicOr(g.status, kStatusOutFull);
+    if (!kWrite && lane == 0) g.counts[a][p] = 0;
+    return;
+  }
+  // small interval removal over the end-point pairs, then count or write
+  const uint32_t pairs = n_emit / 2;
+  uint32_t kept = 0;
+  const uint32_t out = kWrite ? g.out_offsets[a][p] : 0u;
+  auto depth_of = [&](uint64_t k) -> float {
+    if (!(k & kSphereOrder)) return H.depth[o0 + (uint32_t)(k & 0x7fffffffu)];
+    return sphere_sample(g, a, cu, cv, (uint32_t)((k & 0x7fffffffu) >> 1), (k & 1u) != 0).depth;
+  };
+  for (uint32_t m0 = 0; m0 < pairs; m0 += 64) {
+    const uint32_t m = m0 + lane;
+    bool keep = false;
+    uint64_t ea = 0, eb = 0;
+    if (m < pairs) {
+      ea = emit[2 * m];
+      eb = emit[2 * m + 1];
+      const double th = (double)depth_of(eb) - (double)depth_of(ea);
+      keep = th > 0.0 && th >= g.eps;
+    }
+    const uint64_t km = __ballot(keep);
+    if (kWrite && keep) {
+      const uint32_t pos = out + 2 * (kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull)));
+      for (int z = 0; z < 2; ++z) {
+        const uint64_t k = z ? eb : ea;
+        const size_t o = (size_t)pos + z;
+        if (!(k & kSphereOrder)) {
+          const uint32_t hq = o0 + (uint32_t)(k & 0x7fffffffu);
+          g.out_depth[a][o] = H.depth[hq];
+          g.out_normal[a][3 * o] = H.normal[3 * (size_t)hq];
+          g.out_normal[a][3 * o + 1] = H.normal[3 * (size_t)hq + 1];
+          g.out_normal[a][3 * o + 2] = H.normal[3 * (size_t)hq + 2];
+          g.out_tri[a][o] = H.tri[hq];
+        } else {
+          const uint32_t sph = (uint32_t)((k & 0x7fffffffu) >> 1);
+          const SphereHit h = sphere_sample(g, a, cu, cv, sph, (k & 1u) != 0);
+          g.out_depth[a][o] = h.depth;
+          g.out_normal[a][3 * o] = h.n[0];
+          g.out_normal[a][3 * o + 1] = h.n[1];
+          g.out_normal[a][3 * o + 2] = h.n[2];
+          g.out_tri[a][o] = -1 - (int32_t)sph;
+        }
+      }
+    }
+    kept += (uint32_t)__popcll(km);
+  }
+  if (!kWrite && lane == 0) g.counts[a][p] = 2 * kept;
+}
+
+}  // namespace
+
+hipError_t launch_offset_centres(const OffsetArgs& g, hipStream_t s) {
+  const int64_t n = 3 * (int64_t)g.w * g.w;
+  hipLaunchKernelGGL(offset_centres_kernel, dim3((unsigned)((n + kOffBlock - 1) / kOffBlock)), dim3(kOffBlock), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_offset_bin(const OffsetArgs& g, bool scatter, hipStream_t s) {
+  const int64_t n = 3 * (int64_t)g.n_spheres;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kOffBlock - 1) / kOffBlock));
+  if (scatter) hipLaunchKernelGGL(offset_bin_kernel<true>, grid, dim3(kOffBlock), 0, s, g);
+  else hipLaunchKernelGGL(offset_bin_kernel<false>, grid, dim3(kOffBlock), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_offset_rays(const OffsetArgs& g, bool write, hipStream_t s) {
+  const int64_t rays = 3 * (int64_t)g.w * g.w;
+  const dim3 grid((unsigned)((rays + kOffWaves - 1) / kOffWaves));
+  if (write) hipLaunchKernelGGL(offset_ray_kernel<true>, grid, dim3(kOffBlock), 0, s, g);
+  else hipLaunchKernelGGL(offset_ray_kernel<false>, grid, dim3(kOffBlock), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace ldni

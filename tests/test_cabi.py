@@ -237,3 +237,33 @@ def test_node_words(L):
     assert L.ldni_node_words(0, ctypes.byref(n)) == 1 and n.value == 0
     assert L.ldni_node_words(8193, ctypes.byref(n)) == 1 and n.value == 0
     assert L.ldni_node_words(8, None) == 1
+
+
+def _offset_call(L, views=True, ws=(8, 8, 8), offsets=True, n=0, arrays=True, bbox=(0, 0, 0, 1, 1, 1),
+                 r=0.1, eps=1e-5, out=True):
+    from paper_1009_0794_amd import _lib
+    arr = (_lib.AxisView * 3)()
+    for a in range(3):
+        arr[a].w, arr[a].n_samples = ws[a], n
+        arr[a].offsets = 4096 if offsets else None
+        if arrays:
+            arr[a].depth = arr[a].normal = arr[a].tri = 8192
+    bb = (ctypes.c_float * 6)(*bbox)
+    res = ctypes.c_void_p(123)
+    rc = L.ldni_offset(arr if views else None, bb, r, eps, None, ctypes.byref(res) if out else None)
+    return rc, res.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(views=False), dict(out=False), dict(r=0.0), dict(r=float("nan")), dict(r=float("inf")),
+    dict(eps=-1.0), dict(eps=float("nan")), dict(ws=(8, 9, 8)), dict(ws=(0, 0, 0)),
+    dict(ws=(16385, 16385, 16385)), dict(offsets=False), dict(n=5, arrays=False), dict(n=2 ** 32),
+    dict(n=2 ** 29), dict(bbox=(0, 0, 0, 1, 1, 0)), dict(bbox=(0, float("inf"), 0, 1, 1, 1)),
+])
+def test_offset_invalid_arguments_rejected_on_host(L, kw):
+    """ldni_offset (Sec. 4.2) checks its arguments before any device work
+    (the fake device pointers here are never dereferenced)."""
+    rc, res = _offset_call(L, **kw)
+    assert rc == 1
+    assert res is None or not kw.get("out", True)
+    assert L.ldni_last_error().decode()

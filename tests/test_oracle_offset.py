@@ -249,3 +249,16 @@ def test_tangent_sphere_is_no_event():
     # ray (4, 4): its samples 0.75 and 1.25 (g = 2, 3) grow to [0.5, 1.5]; the spheres of
     # g = 0, 1 at pixel (3, 4) are tangent to it at depths 0.5 and 1.0
     assert [(float(x), int(t)) for x, t in zip(res.depth[s], res.tri[s])] == [(0.5, -3), (1.5, -4)]
+
+
+def test_offset_rays_matches_full():
+    w = 10
+    L = _solid(w)
+    full = oo.offset(L, BBOX, w, 0.21)
+    pix = [0, 17, 45, 46, 99]
+    for a in range(3):
+        got = oo.offset_rays(L, BBOX, w, 0.21, a, pix)
+        for p, res in zip(pix, got):
+            s = slice(int(full[a].offsets[p]), int(full[a].offsets[p + 1]))
+            assert [float(d) for d, _, _ in res] == full[a].depth[s].tolist()
+            assert [t for _, _, t in res] == full[a].tri[s].tolist()
