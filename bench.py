@@ -449,13 +449,66 @@ def measure_nodes(ldni, torch, mg, reps):
     }
 
 
+def measure_offset(ldni, torch, mg, reps):
+    """Offsetting (Sec. 4.2) of the flower (the C2 mesh) sampled at w = 128
+    (the paper's offsetting resolution) and w = 256: one step is an outer and
+    an inner offset by two pixels (r = +2h, -2h), each a full ldni_offset
+    call on resident LDNIs, results freed."""
+    m = mg.c2_flower()
+    v = torch.from_numpy(m.verts).cuda()
+    f = torch.from_numpy(m.tris).cuda()
+    out = {}
+    for w in (128, 256):
+        L = ldni.sample(v, f, m.bbox, w, "xyz")
+        h = (m.bbox[3] - m.bbox[0]) / w
+        n_in = sum(L[a].n for a in range(3))
+        n_out = 0
+        for r in (2 * h, -2 * h):
+            res = ldni.ldni_offset(L, m.bbox, r)
+            n_out += sum(int(res.view(a).n_samples) for a in range(3))
+            res.free()
+
+        def step():
+            for r in (2 * h, -2 * h):
+                ldni.ldni_offset(L, m.bbox, r).free()
+
+        step()
+        with Timer(torch) as t:
+            for _ in range(reps):
+                step()
+        ms = t.ms / reps
+        ldni.profile_enable(True)
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        ldni.profile_enable(False)
+        ks = ldni.profile_read()
+        kern = {k: round(val[1] / reps, 4) for k, val in ks.items() if k.startswith("offset")}
+        # algorithmic bytes: the three LDNIs read (offsets, depth, normal, id), the results written
+        alg = 2 * (3 * 4 * (w * w + 1) + 20 * n_in) + 3 * 4 * 2 * (w * w + 1) + 20 * n_out
+        out[f"flower-{w}"] = {
+            "w": w, "r_pixels": 2, "input_samples": n_in, "output_samples_per_step": n_out,
+            "ms_per_step": round(ms, 4), "ms_per_offset": round(ms / 2, 4),
+            "value": 2 * n_in / (ms / 1e3), "unit": "input samples offset/s",
+            "path_roofline": {"algorithmic_bytes_per_step": alg,
+                              "achieved_GBps": round(alg / (ms / 1e3) / 1e9, 1),
+                              "frac_of_hbm_peak": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5)},
+            "kernels_ms_per_step": kern,
+        }
+        del L
+    out["description"] = ("outer and inner offset (r = +2h, -2h) of the flower mesh's LDNIs: union with "
+                          "(difference of) a sphere at every sample, all three axes")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
-                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd", "boolean-2048", "nodes-2048"],
+                    choices=sorted(PLAIN) + ["batch256", "flower-512-fwdbwd", "boolean-2048", "nodes-2048",
+                                                "offset-flower"],
                     help="measure one part only (default: the headline plus every part)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -545,6 +598,14 @@ def main():
                          "config": {"workload": "nodes-2048", "description": rn["description"],
                                     "parallelism": "single GPU"}})
         line["nodes"] = rn
+    if args.workload in (None, "offset-flower"):
+        rf2 = measure_offset(ldni, torch, mg, reps=max(2, args.steps // 4))
+        if args.workload == "offset-flower":
+            line.update({"value": round(rf2["flower-256"]["value"], 1), "unit": rf2["flower-256"]["unit"],
+                         "ms_per_step": rf2["flower-256"]["ms_per_step"],
+                         "config": {"workload": "offset-flower-256", "description": rf2["description"],
+                                    "parallelism": "single GPU"}})
+        line["offset"] = rf2
     print(json.dumps(line), flush=True)
 
 
