@@ -1146,9 +1146,7 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   uint32_t* rb = pinned_readback();
   if (!rb) return fail(LDNI_ERR_OUT_OF_MEMORY, "pinned readback buffer");
   const int64_t npix = (int64_t)w * w;
-  const int32_t tiles_x = (w + 7) / 8;
-  const uint32_t tiles_axis = (uint32_t)tiles_x * (uint32_t)tiles_x;
-  const int64_t n_tiles = 3 * (int64_t)tiles_axis;
+  const int64_t n_rays = 3 * npix;
 
   ldni_result* res = new (std::nothrow) ldni_result();
   if (!res) return fail(LDNI_ERR_OUT_OF_MEMORY, "result");
@@ -1160,16 +1158,20 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
     ldni_free(res);
     return hip_fail(e, "offsets allocation");
   }
-  // workspace: status, tile counts and cursors, tile starts, scan scratch, centres
+  // workspace: status, ray counts and cursors, ray starts, scan scratch, centres
   const size_t o_count = 256;
-  const size_t o_cursor = align_up(o_count + sizeof(uint32_t) * (size_t)n_tiles);
-  const size_t o_start = align_up(o_cursor + sizeof(uint32_t) * (size_t)n_tiles);
-  const size_t o_scratch = align_up(o_start + sizeof(uint32_t) * (size_t)(n_tiles + 1));
-  const size_t scratch = std::max(scan_scratch_bytes(n_tiles, 1), scan_scratch_bytes(npix, 3));
+  const size_t o_cursor = align_up(o_count + sizeof(uint32_t) * (size_t)n_rays);
+  const size_t o_start = align_up(o_cursor + sizeof(uint32_t) * (size_t)n_rays);
+  const size_t o_scratch = align_up(o_start + sizeof(uint32_t) * (size_t)(n_rays + 1));
+  const size_t scratch = std::max(scan_scratch_bytes(n_rays, 1), scan_scratch_bytes(npix, 3));
   const size_t o_centres = align_up(o_scratch + scratch);
+  // the end points the count pass keeps for the write pass (when this stays modest)
+  const size_t saved_bytes = sizeof(uint64_t) * kOffsetSaved * 3 * (size_t)npix;
+  const bool use_saved = saved_bytes <= ((size_t)1 << 30);
+  const size_t o_saved = align_up(o_centres + 3 * sizeof(double) * (size_t)std::max<uint64_t>(n_total, 1));
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  e = cache_get(&ws, o_centres + 3 * sizeof(double) * (size_t)std::max<uint64_t>(n_total, 1), stream, &ws_bytes);
+  e = cache_get(&ws, o_saved + (use_saved ? saved_bytes : 0), stream, &ws_bytes);
   if (e != hipSuccess) {
     ldni_free(res);
     return hip_fail(e, "workspace allocation");
@@ -1196,17 +1198,16 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
     g.out_offsets[d] = g.counts[d];
   }
   g.w = w;
-  g.tiles_x = tiles_x;
-  g.tiles_per_axis = tiles_axis;
   g.n_spheres = (uint32_t)n_total;
   g.r = std::fabs((double)r);
   g.eps = (double)eps;
   g.union_op = r > 0.0f ? 1 : 0;
   g.status = reinterpret_cast<uint32_t*>(wb);
-  g.tile_count = reinterpret_cast<uint32_t*>(wb + o_count);
-  g.tile_cursor = reinterpret_cast<uint32_t*>(wb + o_cursor);
-  g.tile_start = reinterpret_cast<uint32_t*>(wb + o_start);
+  g.ray_count = reinterpret_cast<uint32_t*>(wb + o_count);
+  g.ray_cursor = reinterpret_cast<uint32_t*>(wb + o_cursor);
+  g.ray_start = reinterpret_cast<uint32_t*>(wb + o_start);
   g.centres = reinterpret_cast<double*>(wb + o_centres);
+  g.saved = use_saved ? reinterpret_cast<uint64_t*>(wb + o_saved) : nullptr;
   void* scr = wb + o_scratch;
 #define OSTEP(expr, what)                                  \
   do {                                                     \
@@ -1214,22 +1215,22 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
     if (e_ != hipSuccess) return bail(hip_fail(e_, what)); \
   } while (0)
   OSTEP(launch_fill_u32(g.status, 0u, 64, stream), "fill");
-  OSTEP(launch_fill_u32(g.tile_count, 0u, 2 * n_tiles + 64, stream), "fill");  // counts and cursors
+  OSTEP(launch_fill_u32(g.ray_count, 0u, 2 * n_rays + 64, stream), "fill");  // counts and cursors
   OSTEP(timed("offset_centres", stream, [&] { return launch_offset_centres(g, stream); }), "centre kernel");
   OSTEP(timed("offset_bin", stream, [&] { return launch_offset_bin(g, false, stream); }), "binning kernel");
-  OSTEP(launch_scan(g.tile_count, g.tile_start, n_tiles, scr, g.status, stream), "tile scan");
+  OSTEP(launch_scan(g.ray_count, g.ray_start, n_rays, scr, g.status, stream), "ray list scan");
   {
-    const uint32_t* src[2] = {g.status, g.tile_start + n_tiles};
+    const uint32_t* src[2] = {g.status, g.ray_start + n_rays};
     OSTEP(launch_gather(src, 2, rb, stream), "readback");
     OSTEP(hipStreamSynchronize(stream), "synchronise");
   }
   if (rb[0] & kStatusMismatch)
     return bail(fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples"));
-  if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more tile-list entries"));
+  if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more sphere hits on the rays"));
   e = cache_get(&list, sizeof(uint32_t) * (size_t)std::max<uint32_t>(rb[1], 1), stream, &list_bytes);
   if (e != hipSuccess) {
     list = nullptr;
-    return bail(hip_fail(e, "tile list allocation"));
+    return bail(hip_fail(e, "ray list allocation"));
   }
   g.list = static_cast<uint32_t*>(list);
   OSTEP(timed("offset_bin", stream, [&] { return launch_offset_bin(g, true, stream); }), "binning kernel");

@@ -271,29 +271,31 @@ hipError_t launch_node_stats(const NodeArgs& g, hipStream_t s);
 // Offsetting (ldni_offset.hip): the three input LDNIs, their box (lo, h per
 // world axis), |r| and eps, the sphere centres (3 doubles per sample,
 // numbered over x, y, z with base[a] the first number of axis a), the
-// binning of spheres into 8 x 8 pixel tiles of each image (tile_count,
-// scanned into tile_start[3 * tiles_per_axis + 1], tile_cursor, list), the
+// binning of spheres into the lists of the rays they hit (ray_count over the
+// 3 w^2 rays, scanned into ray_start[3 w^2 + 1], ray_cursor, list), the
 // per-ray result counts (scanned in place into the output offsets) and the
 // output arrays of the write pass.
 constexpr int kOffsetBuf = 1024;              // events of one depth window of one ray, in LDS
 constexpr int kOffsetKeep = 896;              // a full window is cut back to fewer events than this
 constexpr int kOffsetEmit = 512;              // end points of one ray's result before small volumes go
+constexpr int kOffsetSaved = 16;              // end points per ray kept by the count pass for the write pass
 constexpr uint32_t kMaxSpheres = 1u << 30;    // sphere numbers fit 30 bits of the sort key
 struct OffsetArgs {
   AxisArrays in[3];
-  int32_t w, tiles_x;
-  uint32_t tiles_per_axis, n_spheres;
+  int32_t w;
+  uint32_t n_spheres;
   uint64_t base[3];
   double lo[3], h[3];
   double r, eps;
   int32_t union_op;
   double* centres;
-  uint32_t *tile_count, *tile_start, *tile_cursor, *list;
+  uint32_t *ray_count, *ray_start, *ray_cursor, *list;
   uint32_t* counts[3];
   const uint32_t* out_offsets[3];
   float* out_depth[3];
   float* out_normal[3];
   int32_t* out_tri[3];
+  uint64_t* saved;   // [3 * w * w][kOffsetSaved] kept end-point keys, or null (the write pass recomputes)
   uint32_t* status;  // kStatusMismatch: bad input offsets; kStatusOutFull: a ray's window or end points overflow
 };
 hipError_t launch_offset_centres(const OffsetArgs& g, hipStream_t s);

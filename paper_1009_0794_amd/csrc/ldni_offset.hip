@@ -20,7 +20,7 @@
 // gets id -1 - g.
 //
 // Passes: the sphere centres (one thread per pixel); binning of the spheres
-// into 8 x 8 pixel tiles of every image (count, scan, scatter); then one wave
+// into the lists of the rays they hit (count, scan, scatter); then one wave
 // per ray, twice (count, write): the ray's events go to a wave-private LDS
 // buffer as 64-bit keys (orderable depth, order), window by window in depth
 // when they do not fit, a bitonic sort orders them, and a sweep in chunks of
@@ -81,28 +81,63 @@ __device__ __forceinline__ void pixel_range(const OffsetArgs& g, int b, double x
   i1 = f1 < 0.0 ? -1 : f1 > (double)(g.w - 1) ? g.w - 1 : (int)f1;
 }
 
-// Binning: for sphere s and image a, the tiles its pixel range covers; count
-// (kScatter false) or write the sphere into the tiles' lists.
+// Binning: for sphere s and image a, the rays of the pixels in its range
+// that the sphere hits (rho^2 < r^2, the test of the ray pass); count
+// (kScatter false) or write the sphere into those rays' lists.  Neighbouring
+// samples (neighbouring threads) mostly hit the same rays, so the lanes of a
+// wave that hold the same ray add to its counter with one atomic, issued by
+// the first of them.
 template <bool kScatter>
 __global__ __launch_bounds__(kOffBlock) void offset_bin_kernel(OffsetArgs g) {
   const int64_t t = (int64_t)blockIdx.x * kOffBlock + threadIdx.x;
-  if (t >= 3 * (int64_t)g.n_spheres) return;
-  const int a = (int)(t / g.n_spheres);
-  const uint32_t s = (uint32_t)(t - (int64_t)a * g.n_spheres);
-  const int u = (a + 1) % 3, v = (a + 2) % 3;
-  const double* c = g.centres + 3 * (size_t)s;
-  int iu0, iu1, iv0, iv1;
-  pixel_range(g, u, c[u], iu0, iu1);
-  pixel_range(g, v, c[v], iv0, iv1);
-  if (iu0 > iu1 || iv0 > iv1) return;
-  const int tx0 = iu0 >> 3, tx1 = iu1 >> 3, ty0 = iv0 >> 3, ty1 = iv1 >> 3;
-  const uint32_t tiles = (uint32_t)a * g.tiles_per_axis;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const uint32_t tile = tiles + (uint32_t)(ty * g.tiles_x + tx);
-      if (kScatter) g.list[g.tile_start[tile] + atomicAdd(&g.tile_cursor[tile], 1u)] = s;
-      else atomicAdd(&g.tile_count[tile], 1u);
+  const uint32_t lane = __lane_id();
+  int a = 0, u = 0, v = 0, ni = 0, n_my = 0, iu0 = 0, iv0 = 0;
+  uint32_t s = 0;
+  double pu = 0.0, pv = 0.0;
+  if (t < 3 * (int64_t)g.n_spheres) {
+    a = (int)(t / g.n_spheres);
+    s = (uint32_t)(t - (int64_t)a * g.n_spheres);
+    u = (a + 1) % 3;
+    v = (a + 2) % 3;
+    const double* c = g.centres + 3 * (size_t)s;
+    pu = c[u];
+    pv = c[v];
+    int iu1, iv1;
+    pixel_range(g, u, pu, iu0, iu1);
+    pixel_range(g, v, pv, iv0, iv1);
+    if (iu0 <= iu1 && iv0 <= iv1) {
+      ni = iu1 - iu0 + 1;
+      n_my = ni * (iv1 - iv0 + 1);
     }
+  }
+  const double r2 = g.r * g.r;
+  const int64_t npix = (int64_t)g.w * g.w;
+  // the j-th pixel of every lane's range, j = 0, 1, ... while any lane has one
+  for (int j = 0; __ballot(j < n_my) != 0; ++j) {
+    uint32_t my = 0xffffffffu;
+    if (j < n_my) {
+      const int iu = iu0 + j % ni, iv = iv0 + j / ni;
+      const double du = centre_of(g, u, iu) - pu, dv = centre_of(g, v, iv) - pv;
+      if (du * du + dv * dv < r2) my = (uint32_t)(a * npix + (int64_t)iv * g.w + iu);
+    }
+    uint64_t pending = __ballot(my != 0xffffffffu);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t ray = __shfl(my, leader);
+      const uint64_t same = __ballot(my == ray);
+      uint32_t base = 0;
+      if ((int)lane == leader) {
+        if (kScatter) base = atomicAdd(&g.ray_cursor[ray], (uint32_t)__popcll(same));
+        else atomicAdd(&g.ray_count[ray], (uint32_t)__popcll(same));
+      }
+      if (kScatter) {
+        base = __shfl(base, leader);
+        if (my == ray) g.list[g.ray_start[ray] + base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull))] = s;
+      }
+      if (my == ray) my = 0xffffffffu;
+      pending &= ~same;
+    }
+  }
 }
 
 // One event's world-order normal and depth for a sphere g on the ray of axis
@@ -182,6 +217,56 @@ __device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
   }
 }
 
+// The orderable depth of the event of the given rank (0-based) among
+// key[0..n) by one wave: a radix select over the 32 depth bits, five bits a
+// pass, with a 32-bin histogram in hist.
+__device__ __forceinline__ uint32_t select_depth(const uint64_t* key, uint32_t n, uint32_t rank, uint32_t* hist) {
+  const uint32_t lane = lane_id();
+  uint32_t prefix = 0, mask = 0;
+  for (int hi = 32; hi > 0; hi -= 5) {
+    const int lo = hi > 5 ? hi - 5 : 0;
+    const uint32_t digit_mask = (1u << (hi - lo)) - 1u;
+    if (lane < 32) hist[lane] = 0;
+    wave_sync();
+    for (uint32_t q = lane; q < n; q += 64) {
+      const uint32_t d = (uint32_t)(key[q] >> 32);
+      if ((d & mask) == prefix) atomicAdd(&hist[(d >> lo) & digit_mask], 1u);
+    }
+    wave_sync();
+    const uint32_t c = lane < 32 ? hist[lane] : 0u;
+    const uint32_t cum = (uint32_t)wave_scan_add((int)c);
+    const uint64_t over = __ballot(cum > rank);
+    const int bucket = __ffsll((unsigned long long)over) - 1;
+    rank -= __shfl(cum - c, bucket);
+    prefix |= (uint32_t)bucket << lo;
+    mask |= digit_mask << lo;
+    wave_sync();
+  }
+  return prefix;
+}
+
+// Writes the result sample of event key k (a sample of the solid, or a
+// sphere's chord end) of ray (a, p) at output position o.
+__device__ __forceinline__ void write_event(const OffsetArgs& g, int a, int64_t p, double cu, double cv, uint64_t k,
+                                            size_t o) {
+  if (!(k & kSphereOrder)) {
+    const uint32_t hq = g.in[a].offsets[p] + (uint32_t)(k & 0x7fffffffu);
+    g.out_depth[a][o] = g.in[a].depth[hq];
+    g.out_normal[a][3 * o] = g.in[a].normal[3 * (size_t)hq];
+    g.out_normal[a][3 * o + 1] = g.in[a].normal[3 * (size_t)hq + 1];
+    g.out_normal[a][3 * o + 2] = g.in[a].normal[3 * (size_t)hq + 2];
+    g.out_tri[a][o] = g.in[a].tri[hq];
+  } else {
+    const uint32_t sph = (uint32_t)((k & 0x7fffffffu) >> 1);
+    const SphereHit h = sphere_sample(g, a, cu, cv, sph, (k & 1u) != 0);
+    g.out_depth[a][o] = h.depth;
+    g.out_normal[a][3 * o] = h.n[0];
+    g.out_normal[a][3 * o + 1] = h.n[1];
+    g.out_normal[a][3 * o + 2] = h.n[2];
+    g.out_tri[a][o] = -1 - (int32_t)sph;
+  }
+}
+
 // The per-ray pass: counts (kWrite false) or writes the ray's result.  The
 // ray's events are taken in windows of depth: a window collects the events
 // at or after its lower depth bound into a buffer of kOffsetBuf keys; when a
@@ -211,6 +296,15 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   uint32_t* rbit = s_rbit[wv];
   const AxisArrays& H = g.in[a];
 
+  if (kWrite) {
+    // a ray whose end points the count pass kept: expand them
+    const uint32_t out0 = g.out_offsets[a][p], cnt = g.out_offsets[a][p + 1] - out0;
+    if (cnt == 0) return;
+    if (g.saved && cnt <= (uint32_t)kOffsetSaved) {
+      if (lane < cnt) write_event(g, a, p, cu, cv, g.saved[(size_t)ray * kOffsetSaved + lane], (size_t)out0 + lane);
+      return;
+    }
+  }
   const uint32_t o0 = H.offsets[p], o1 = H.offsets[p + 1];
   uint32_t nh = 0;
   if (o1 < o0 || (uint64_t)o1 > H.n) {
@@ -218,8 +312,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   } else {
     nh = (o1 - o0) & ~1u;
   }
-  const uint32_t tile = (uint32_t)a * g.tiles_per_axis + (uint32_t)((iv >> 3) * g.tiles_x + (iu >> 3));
-  const uint32_t l0 = g.tile_start[tile], l1 = g.tile_start[tile + 1];
+  const uint32_t l0 = g.ray_start[ray], l1 = g.ray_start[ray + 1];
   const double r2 = g.r * g.r;
 
   uint32_t lower = 0;        // window: orderable depth >= lower ...
@@ -242,13 +335,17 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       uint32_t c = (h0 ? 1u : 0u) + (h1 ? 1u : 0u);
       uint32_t total = (uint32_t)__popcll(__ballot(h0)) + (uint32_t)__popcll(__ballot(h1));
       if (n + total > (uint32_t)kOffsetBuf) {
-        wave_sort(key, n);
-        const uint32_t cut = (uint32_t)(key[kOffsetKeep] >> 32);
-        // events before the cut depth stay: the first index whose depth is >= cut
+        // the depth of the kOffsetKeep-th smallest event becomes the bound;
+        // the events before it are compacted to the front (unsorted)
+        const uint32_t cut = select_depth(key, n, (uint32_t)kOffsetKeep, rbit);
         uint32_t m = 0;
-        for (uint32_t q0 = 0; q0 < (uint32_t)kOffsetKeep + 1; q0 += 64) {
-          const uint32_t q = q0 + lane;
-          m += (uint32_t)__popcll(__ballot(q <= (uint32_t)kOffsetKeep && (uint32_t)(key[q] >> 32) < cut));
+        for (uint32_t c0 = 0; c0 < n; c0 += 64) {
+          const uint32_t q = c0 + lane;
+          const uint64_t kq = q < n ? key[q] : 0ull;
+          const bool keep = q < n && (uint32_t)(kq >> 32) < cut;
+          const uint64_t bal = __ballot(keep);
+          if (keep) key[m + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = kq;
+          m += (uint32_t)__popcll(bal);
         }
         bounded = true;
         upper = cut;
@@ -273,19 +370,39 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       const uint64_t kk = has ? (((uint64_t)orderable(H.depth[o0 + k]) << 32) | k) : 0ull;
       append(kk, has, 0ull, false);
     }
+    // the ray's spheres, 64 at a time; loads run ahead (list entries two
+    // chunks, centres one chunk) so that a chunk's tests do not wait for them
+    uint32_t sph1 = 0, sph2 = 0;
+    double cu1 = 0.0, cv1 = 0.0, ca1 = 0.0;
+    if (l0 + lane < l1) {
+      sph1 = g.list[l0 + lane];
+      const double* c = g.centres + 3 * (size_t)sph1;
+      cu1 = c[u];
+      cv1 = c[v];
+      ca1 = c[a];
+    }
+    if (l0 + 64 + lane < l1) sph2 = g.list[l0 + 64 + lane];
     for (uint32_t base = l0; base < l1 && !failed; base += 64) {
       const uint32_t e = base + lane;
+      const uint32_t sph = sph1;
+      const double pu = cu1, pv = cv1, pa = ca1;
+      if (e + 64 < l1) {
+        const double* c = g.centres + 3 * (size_t)sph2;
+        cu1 = c[u];
+        cv1 = c[v];
+        ca1 = c[a];
+      }
+      sph1 = sph2;
+      if (e + 128 < l1) sph2 = g.list[e + 128];
       bool hit = false;
       uint64_t ka = 0, kb = 0;
       if (e < l1) {
-        const uint32_t sph = g.list[e];
-        const double* c = g.centres + 3 * (size_t)sph;
-        const double du = cu - c[u], dv = cv - c[v];
+        const double du = cu - pu, dv = cv - pv;
         const double rho2 = du * du + dv * dv;
         if (rho2 < r2) {
           hit = true;
-          const double t = sqrt(r2 - rho2), za = c[a];
-          const float d0 = (float)((za - t) - g.lo[a]), d1 = (float)((za + t) - g.lo[a]);
+          const double t = sqrt(r2 - rho2);
+          const float d0 = (float)((pa - t) - g.lo[a]), d1 = (float)((pa + t) - g.lo[a]);
           ka = ((uint64_t)orderable(d0) << 32) | kSphereOrder | (sph << 1);
           kb = ((uint64_t)orderable(d1) << 32) | kSphereOrder | (sph << 1) | 1u;
         }
@@ -367,28 +484,14 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       keep = th > 0.0 && th >= g.eps;
     }
     const uint64_t km = __ballot(keep);
+    const uint32_t rank = kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull));
     if (kWrite && keep) {
-      const uint32_t pos = out + 2 * (kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull)));
-      for (int z = 0; z < 2; ++z) {
-        const uint64_t k = z ? eb : ea;
-        const size_t o = (size_t)pos + z;
-        if (!(k & kSphereOrder)) {
-          const uint32_t hq = o0 + (uint32_t)(k & 0x7fffffffu);
-          g.out_depth[a][o] = H.depth[hq];
-          g.out_normal[a][3 * o] = H.normal[3 * (size_t)hq];
-          g.out_normal[a][3 * o + 1] = H.normal[3 * (size_t)hq + 1];
-          g.out_normal[a][3 * o + 2] = H.normal[3 * (size_t)hq + 2];
-          g.out_tri[a][o] = H.tri[hq];
-        } else {
-          const uint32_t sph = (uint32_t)((k & 0x7fffffffu) >> 1);
-          const SphereHit h = sphere_sample(g, a, cu, cv, sph, (k & 1u) != 0);
-          g.out_depth[a][o] = h.depth;
-          g.out_normal[a][3 * o] = h.n[0];
-          g.out_normal[a][3 * o + 1] = h.n[1];
-          g.out_normal[a][3 * o + 2] = h.n[2];
-          g.out_tri[a][o] = -1 - (int32_t)sph;
-        }
-      }
+      write_event(g, a, p, cu, cv, ea, (size_t)out + 2 * rank);
+      write_event(g, a, p, cu, cv, eb, (size_t)out + 2 * rank + 1);
+    }
+    if (!kWrite && keep && g.saved && 2 * rank + 1 < (uint32_t)kOffsetSaved) {
+      g.saved[(size_t)ray * kOffsetSaved + 2 * rank] = ea;
+      g.saved[(size_t)ray * kOffsetSaved + 2 * rank + 1] = eb;
     }
     kept += (uint32_t)__popcll(km);
   }
