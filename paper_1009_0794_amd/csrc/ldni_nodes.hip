@@ -350,32 +350,44 @@ __global__ __launch_bounds__(kVoteBlock, 4) void classify_nodes_kernel(NodeArgs 
     if (tid >= kVoteBlock - kSpan)
       s_tx[(it + 1) & 1][tid - (kVoteBlock - kSpan)] = node_depth(g.lo[0], g.h[0], i0 + kSpan + tid - (kVoteBlock - kSpan), w);
     // majority of the three words: x-ray (jl, kl), jl = t % 64, kl = (t / 64)*8 + m;
-    // a wave stores 64 consecutive words of two brick rows per instruction
+    // a wave stores 64 consecutive words of two brick rows per instruction.
+    // For m = 0..7 the y word moves by one matrix (kRow words), the z word by
+    // one row and the output by one brick row (32 words).
     const int jl = tid & 63, j = j0 + jl;
+    const int kl0 = (tid >> 6) * 8;
+    const uint32_t* yp = s_m + ymat(kl0, jl >> 5, 0) * kRow + (jl & 31);
+    const uint32_t* zp = s_m + zmat(jl, kl0 >> 5, 0) * kRow + (kl0 & 31);
+    constexpr int kYHalf = 2 * kSpan * kRow;  // the i-half step of a y matrix index (ih * 2 * 64 matrices)
+    const int bj = 2 * J + (jl >> 5), bk = 2 * K + (kl0 >> 5);
+    uint32_t valid[2];
+#pragma unroll
+    for (int ih = 0; ih < 2; ++ih) {
+      const int ib = i0 + 32 * ih;
+      valid[ih] = (ib >= w || j >= w) ? 0u : (w - ib >= 32) ? 0xffffffffu : ((1u << (w - ib)) - 1u);
+    }
+    const bool store[2] = {2 * it < nb && bj < nb && bk < nb, 2 * it + 1 < nb && bj < nb && bk < nb};
+    uint32_t* op[2] = {g.bits + (((size_t)bk * nb + bj) * nb + 2 * it) * 1024 + (kl0 & 31) * 32 + (jl & 31),
+                       g.bits + (((size_t)bk * nb + bj) * nb + 2 * it + 1) * 1024 + (kl0 & 31) * 32 + (jl & 31)};
 #pragma unroll 1
     for (int m = 0; m < 8; ++m) {
-      const int kl = (tid >> 6) * 8 + m, k = k0 + kl;
+      const int k = k0 + kl0 + m;
       uint64_t xm = 0;
       if (j < w && k < w) {
         const uint32_t c = ux[m];
         xm = (c & kCodeWalk) ? span_walk(&X, (size_t)k * w + j, c, TX, &bad) : decode_span(c);
       }
-      const int bj = 2 * J + (jl >> 5), bk = 2 * K + (kl >> 5);
+      const bool krow = k < w;
 #pragma unroll
       for (int ih = 0; ih < 2; ++ih) {
         const uint32_t xw = (uint32_t)(xm >> (32 * ih));
-        const uint32_t yw = s_m[ymat(kl, jl >> 5, ih) * kRow + (jl & 31)];
-        const uint32_t zw = s_m[zmat(jl, kl >> 5, ih) * kRow + (kl & 31)];
-        const int ib = i0 + 32 * ih;
+        const uint32_t yw = yp[m * kRow + ih * kYHalf];
+        const uint32_t zw = zp[m + ih * kYHalf];
         // rows past the grid hold no node (their y or z words may carry fill bits)
-        const uint32_t row = (ib >= w || j >= w || k >= w) ? 0u
-                             : (w - ib >= 32) ? 0xffffffffu : ((1u << (w - ib)) - 1u);
+        const uint32_t row = krow ? valid[ih] : 0u;
         const uint32_t in = ((xw & yw) | (xw & zw) | (yw & zw)) & row;
         n_inside += __popc(in);
         n_split += __popc(((xw | yw | zw) & ~(xw & yw & zw)) & row);
-        const int bi = 2 * it + ih;
-        if (bi < nb && bj < nb && bk < nb)
-          g.bits[(((size_t)bk * nb + bj) * nb + bi) * 1024 + (kl & 31) * 32 + (jl & 31)] = in;
+        if (store[ih]) op[ih][m * 32] = in;
       }
     }
     __syncthreads();  // the next step rewrites the matrices
