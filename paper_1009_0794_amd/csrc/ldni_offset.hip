@@ -219,7 +219,9 @@ __device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
 
 // The orderable depth of the event of the given rank (0-based) among
 // key[0..n) by one wave: a radix select over the 32 depth bits, five bits a
-// pass, with a 32-bin histogram in hist.
+// pass, with a 32-bin histogram in hist (32 words; the ray pass lends it
+// the wave's state bits, which hold kOffsetBuf / 32 words).
+static_assert(kOffsetBuf / 32 >= 32, "the radix select's 32-bin histogram must fit the wave's state bits");
 __device__ __forceinline__ uint32_t select_depth(const uint64_t* key, uint32_t n, uint32_t rank, uint32_t* hist) {
   const uint32_t lane = lane_id();
   uint32_t prefix = 0, mask = 0;
@@ -296,12 +298,15 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   uint32_t* rbit = s_rbit[wv];
   const AxisArrays& H = g.in[a];
 
+  // the write pass's slot of the ray: out .. out + cnt
+  uint32_t out = 0, cnt = 0;
   if (kWrite) {
-    // a ray whose end points the count pass kept: expand them
-    const uint32_t out0 = g.out_offsets[a][p], cnt = g.out_offsets[a][p + 1] - out0;
+    out = g.out_offsets[a][p];
+    cnt = g.out_offsets[a][p + 1] - out;
     if (cnt == 0) return;
+    // a ray whose end points the count pass kept: expand them
     if (g.saved && cnt <= (uint32_t)kOffsetSaved) {
-      if (lane < cnt) write_event(g, a, p, cu, cv, g.saved[(size_t)ray * kOffsetSaved + lane], (size_t)out0 + lane);
+      if (lane < cnt) write_event(g, a, p, cu, cv, g.saved[(size_t)ray * kOffsetSaved + lane], (size_t)out + lane);
       return;
     }
   }
@@ -468,7 +473,6 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   // small interval removal over the end-point pairs, then count or write
   const uint32_t pairs = n_emit / 2;
   uint32_t kept = 0;
-  const uint32_t out = kWrite ? g.out_offsets[a][p] : 0u;
   auto depth_of = [&](uint64_t k) -> float {
     if (!(k & kSphereOrder)) return H.depth[o0 + (uint32_t)(k & 0x7fffffffu)];
     return sphere_sample(g, a, cu, cv, (uint32_t)((k & 0x7fffffffu) >> 1), (k & 1u) != 0).depth;
@@ -485,7 +489,9 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
     }
     const uint64_t km = __ballot(keep);
     const uint32_t rank = kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull));
-    if (kWrite && keep) {
+    // the sweep is deterministic, so the write pass keeps what the count
+    // pass counted; the bound only keeps a disagreement inside the slot
+    if (kWrite && keep && 2 * rank + 1 < cnt) {
       write_event(g, a, p, cu, cv, ea, (size_t)out + 2 * rank);
       write_event(g, a, p, cu, cv, eb, (size_t)out + 2 * rank + 1);
     }
