@@ -47,20 +47,21 @@ PLAIN = {
 }
 
 
-def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1009_0794_amd", "csrc", "ldni_kernels.hip")
+def kernel_source_hash(source: str = "ldni_kernels.hip") -> str:
+    p = os.path.join(ROOT, "paper_1009_0794_amd", "csrc", source)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary,
-    or None if there is none or the kernel source changed since."""
+def read_traffic(workload: str, kernel: str, source: str = "ldni_kernels.hip"):
+    """HBM bytes per launch of ``kernel`` (defined in ``source``) from the
+    committed counter summary, or None if there is none or the kernel source
+    changed since."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    if not m or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash(source):
         return None
     m = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
@@ -380,8 +381,12 @@ def measure_boolean(ldni, torch, mg, reps):
         if name not in ks or ks[name][1] <= 0:
             return None
         gbs = b / (ks[name][1] / reps / 1e3) / 1e9
+        # counter bytes per launch (the nine calls of a step average out
+        # over whole steps) times the launches of a step
+        per_launch = read_traffic("boolean-2048", name, "ldni_boolean.hip")
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": b}
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": b,
+                "traffic_per_step": calls * per_launch if per_launch is not None else None}
     return {
         "workload": "boolean-2048",
         "description": "union, intersection and difference of scene64 (seed 1) and scene64 (seed 7) "
@@ -431,8 +436,9 @@ def measure_nodes(ldni, torch, mg, reps):
         k_ms = ks["classify_nodes"][1] / reps
         gbs = alg / (k_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "classify_nodes", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(k_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": alg}
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic("nodes-2048", "classify_nodes", "ldni_nodes.hip"),
+                "avg_launch_us": round(k_ms * 1e3, 2), "algorithmic_bytes_per_launch": alg}
     kern = {k: round(v[1] / reps, 4) for k, v in ks.items() if k in ("node_codes", "classify_nodes")}
     return {
         "workload": "nodes-2048",

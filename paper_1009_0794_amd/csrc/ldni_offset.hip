@@ -337,7 +337,6 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
         return d >= lower && (!bounded || d < upper);
       };
       bool h0 = has0 && in_window(k0), h1 = has1 && in_window(k1);
-      uint32_t c = (h0 ? 1u : 0u) + (h1 ? 1u : 0u);
       uint32_t total = (uint32_t)__popcll(__ballot(h0)) + (uint32_t)__popcll(__ballot(h1));
       if (n + total > (uint32_t)kOffsetBuf) {
         // the depth of the kOffsetKeep-th smallest event becomes the bound;
@@ -358,12 +357,10 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
         if (m == 0) failed = true;  // one group of equal depth larger than a window
         h0 = has0 && in_window(k0);
         h1 = has1 && in_window(k1);
-        c = (h0 ? 1u : 0u) + (h1 ? 1u : 0u);
         wave_sync();
       }
       const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
       const uint64_t below = (1ull << lane) - 1ull;
-      (void)c;
       uint32_t pos = n + (uint32_t)__popcll(m0 & below) + (uint32_t)__popcll(m1 & below);
       if (h0) key[pos++] = k0;
       if (h1) key[pos] = k1;
