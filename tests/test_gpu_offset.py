@@ -97,17 +97,18 @@ def test_random_lists_match_oracle(seed, w, r):
         _same(got[a], ref[a], f"seed {seed} axis {a}")
 
 
-def test_flower_sampled_rays():
+@pytest.mark.parametrize("w,r_pix", [(128, 2.5), (128, 2.0), (256, 2.0)])
+def test_flower_sampled_rays(w, r_pix):
     """C2's flower mesh sampled at w = 128 (the paper's offsetting
-    resolution) and offset by 2.5 pixels out and in: 600 random rays of each
-    axis against the oracle."""
+    resolution) and 256, offset out and in by 2.5 and 2 pixels (2 pixels at
+    both sizes is the timed workload): 600 random rays of each axis against
+    the oracle."""
     m = mg.c2_flower()
-    w = 128
     L = oracle.sample(m.verts, m.tris, m.bbox, w, axes="xyz")
     G = {a: _to_gpu(a, L[a]) for a in range(3)}
     h = (m.bbox[3] - m.bbox[0]) / w
     rng = np.random.default_rng(2)
-    for r in (2.5 * h, -2.5 * h):
+    for r in (r_pix * h, -r_pix * h):
         got = ldni.offset(G, m.bbox, r)
         for a in range(3):
             off = got[a].offsets.cpu().numpy().view(np.uint32).astype(np.int64)
