@@ -13,7 +13,7 @@ segments of A are sliced by the samples of B that fall inside them; then
 Sec. 4.1.1 then removes every resulting 1D volume thinner than eps
 (eps = 1e-5 in the paper, for single-precision depths).
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
   R1  A pixel with an odd sample count: its last, unpaired sample bounds no
       segment and is ignored.
   R2  Result pieces that touch (one ends at the depth where the next starts)

@@ -13,7 +13,7 @@ Proposition 1).  Numerical error and degenerate configurations can make the
 three rays disagree, so a node is classified inside when at least two of
 its three LDNIs place it inside.
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
   G1  Node (i, j, k) lies at the pixel centres (c_x[i], c_y[j], c_z[k]) of
       the sampler, c[t] = f32(lo + (t + 0.5) * (hi - lo) / w) in float64.
       Its depth on the a-LDNI is f32(c_a - lo_a) (float64 difference, one

@@ -7,7 +7,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 
 The paper renders the three components of the unit normal as an RGB colour
 with one byte per component, so a component c in [-1, 1] is stored with a
-resolution of 256 levels.  Reading fixed here (listed in the design doc): the
+resolution of 256 levels.  Reading fixed here: the
 colour is (c + 1) / 2 and the byte its 8-bit unsigned-normalised value rounded
 to nearest, b = floor((c + 1) * 127.5 + 0.5) clamped to [0, 255], evaluated
 with float64 operations in that order (exact for |c| >= 2^-29; a smaller c

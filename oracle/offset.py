@@ -11,7 +11,7 @@ inner offset, r < 0, every S of radius |r| is subtracted from H).  The
 Boolean operations are those of Sec. 4.1 with small interval removal
 (Sec. 4.1.1).
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
   OF1  The spheres sit at every sample of all three LDNIs.  The centre of a
        sample of the a-LDNI at pixel (iu, iv) is the point whose a-coordinate
        is lo_a + depth and whose other two coordinates are the pixel centres
