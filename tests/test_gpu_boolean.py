@@ -123,13 +123,14 @@ def test_intersection_minus_a_is_empty():
 
 
 def test_large_grid_band_matches_oracle():
-    """Two different seeded scenes at w = 2048 (the largest workload's grid):
-    a band of rows against the oracle, and every pixel's result sorted with
-    an even count."""
+    """Two different seeded scenes at w = 2048 (the timed workload: all three
+    operations on all three axes): a band of rows through the 32-layer
+    centre against the oracle, and every pixel's result sorted with an even
+    count."""
     A = _sample(*_scene(1), 2048)
     B = _sample(*_scene(7), 2048)
     w = 2048
-    for axis, op in ((0, "union"), (1, "intersection"), (2, "difference")):
+    for axis, op in [(a, o) for a in range(3) for o in ("union", "intersection", "difference")]:
         got = ldni.boolean(A[axis], B[axis], op)
         off = got.offsets.cpu().numpy().view(np.uint32).astype(np.int64)
         cnt = np.diff(off)
