@@ -106,3 +106,44 @@ def test_batch_reports_device_errors():
         ldni.sample_batch([(good[0], good[1], (0, 0, 0, 8, 8, 8), 8),
                            (badd[0], badd[1], (0, 0, 0, 8, 8, 8), 16)])
     assert e.value.code == 2
+
+
+def test_full_batch256_rows_against_oracle():
+    """The timed batch at full size: the 256 seeded meshes (log-uniform
+    triangle counts, each at its own w, tile shapes from the tuned table) in
+    one graph.  Every pixel count is even (the meshes are closed); for six
+    meshes (the largest w, the most triangles and four seeded picks) an
+    8-row band through the middle of every axis equals the oracle bit for
+    bit; a second replay writes the same bytes."""
+    meshes = mg.c4_batch256()
+    dev = [_dev(m.verts, m.tris) for m in meshes]
+    b = ldni.sample_batch([(v, f, m.bbox, m.w) for (v, f), m in zip(dev, meshes)], "xyz")
+    for k in range(len(meshes)):
+        for a in range(3):
+            off = b.to_torch(k, a).offsets.to(torch.int64) & 0xFFFFFFFF
+            assert bool(((off[1:] - off[:-1]) % 2 == 0).all()), f"mesh {k} axis {a}: odd count"
+    rng = np.random.default_rng(3)
+    picks = {int(np.argmax([m.w for m in meshes])), int(np.argmax([m.n_tris for m in meshes]))}
+    picks |= {int(k) for k in rng.choice(len(meshes), 4, replace=False)}
+    first = {}
+    for k in sorted(picks):
+        m = meshes[k]
+        j0, j1 = max(m.w // 2 - 4, 0), min(m.w // 2 + 4, m.w)
+        for a in range(3):
+            off, dep, nrm, tri = _np(b.to_torch(k, a))
+            first[(k, a)] = [x.copy() for x in (off, dep, nrm, tri)]
+            cnt = np.diff(off.astype(np.int64))
+            r = oracle.sample(m.verts, m.tris, m.bbox, m.w, axes=[a], window=(0, m.w, j0, j1))[a]
+            rc = np.diff(r.offsets.astype(np.int64))
+            s0, s1 = int(off[j0 * m.w]), int(off[j1 * m.w])
+            label = f"mesh {k} (w {m.w}, {m.n_tris} triangles) axis {a}"
+            assert np.array_equal(cnt[j0 * m.w:j1 * m.w], rc[j0 * m.w:j1 * m.w]), label
+            assert np.array_equal(tri[s0:s1], r.tri), label
+            assert np.array_equal(dep[s0:s1].view(np.uint32), r.depth.view(np.uint32)), label
+            assert np.array_equal(nrm[s0:s1].view(np.uint32), r.normal.view(np.uint32)), label
+    b.run()
+    torch.cuda.synchronize()
+    for (k, a), want in first.items():
+        for x, y in zip(_np(b.to_torch(k, a)), want):
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), f"replay: mesh {k} axis {a}"
+    b.free()
