@@ -206,7 +206,8 @@ def test_tiny_radius_keeps_the_solid():
 
 def test_pixel_rules_by_hand():
     """OF3 on hand-made events: H's samples win ties, then the sphere of the
-    smaller generating sample; touching volumes merge; thin volumes go."""
+    smaller generating sample, a sphere's enter before its exit; touching
+    volumes merge; volumes thinner than eps go, one exactly eps thick stays."""
     n = lambda *v: np.array(v, np.float32)
     hd, hn, ht = np.array([1.0, 2.0], np.float32), np.array([[0, 0, -1], [0, 0, 1]], np.float32), [10, 11]
     ev = [(np.float32(1.0), 5, 0, n(1, 0, 0)), (np.float32(1.5), 5, 1, n(0, 1, 0)),
@@ -229,6 +230,16 @@ def test_pixel_rules_by_hand():
            (np.float32(8.0), 1, 0, n(1, 0, 0)), (np.float32(9.0), 1, 1, n(1, 0, 0))]
     got = oo.offset_pixel(n(1.0, 2.0, 7.0), np.zeros((3, 3), np.float32), [1, 2, 3], ev3, True, 1e-5)
     assert [(float(d), t) for d, _, t in got] == [(1.0, 1), (2.0, 2), (8.0, -2), (9.0, -2)]
+    # a volume exactly eps thick stays (Sec. 4.1.1 removes only thinner ones)
+    got = oo.offset_pixel(n(0.5, 0.75), np.zeros((2, 3), np.float32), [1, 2], [], True, 0.25)
+    assert [(float(d), t) for d, _, t in got] == [(0.5, 1), (0.75, 2)]
+    # a sphere whose chord rounds to one depth enters before it exits: in a
+    # group where sphere 1 also enters, the end point is sphere 0's enter
+    ev4 = [(np.float32(1.0), 0, 1, n(0, 0, 1)), (np.float32(1.0), 0, 0, n(0, 0, -1)),
+           (np.float32(1.0), 1, 0, n(1, 0, 0)), (np.float32(2.0), 1, 1, n(0, 1, 0))]
+    got = oo.offset_pixel(np.zeros(0, np.float32), np.zeros((0, 3), np.float32), [], ev4, True, 1e-5)
+    assert [(float(d), tuple(float(c) for c in nr), t) for d, nr, t in got] == \
+        [(1.0, (0.0, 0.0, -1.0), -1), (2.0, (0.0, 1.0, 0.0), -2)]
 
 
 def test_tangent_sphere_is_no_event():
