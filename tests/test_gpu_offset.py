@@ -85,14 +85,16 @@ def _random_axis(rng, w, n_max=7):
                            tri=rng.integers(0, 1 << 30, n).astype(np.int32))
 
 
-@pytest.mark.parametrize("seed,w,r", [(0, 1, 0.3), (1, 9, 0.25), (2, 12, -0.2), (3, 12, 0.125)])
-def test_random_lists_match_oracle(seed, w, r):
+@pytest.mark.parametrize("seed,w,r,eps", [(0, 1, 0.3, 1e-5), (1, 9, 0.25, 1e-5), (2, 12, -0.2, 1e-5),
+                                          (3, 12, 0.125, 1e-5), (4, 12, -0.125, 0.25), (5, 9, 0.25, 0.125)])
+def test_random_lists_match_oracle(seed, w, r, eps):
     """Ties between samples and chord ends on a dyadic grid (r = 1/8 and 1/4
-    put chord ends on sample depths), odd counts, empty pixels."""
+    put chord ends on sample depths), odd counts, empty pixels; eps on the
+    same grid, so volumes exactly eps thick (kept) and thinner ones meet."""
     rng = np.random.default_rng(seed)
     L = {a: _random_axis(rng, w) for a in range(3)}
-    ref = oo.offset(L, BBOX, w, r)
-    got = ldni.offset({a: _to_gpu(a, L[a]) for a in range(3)}, BBOX, r)
+    ref = oo.offset(L, BBOX, w, r, eps)
+    got = ldni.offset({a: _to_gpu(a, L[a]) for a in range(3)}, BBOX, r, eps)
     for a in range(3):
         _same(got[a], ref[a], f"seed {seed} axis {a}")
 
