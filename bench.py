@@ -324,7 +324,12 @@ def measure_fwd_bwd(ldni, torch, mg, reps):
         "value": samples / ((ms_f + ms_b) / 1e3),
         "backward_roofline": {"bound": "hbm", "algorithmic_bytes": bwd_bytes,
                               "achieved_GBps": round(bwd_bytes / (kb[1] / kb[0] / 1e3) / 1e9, 2)
-                              if kb[1] > 0 else None},
+                              if kb[1] > 0 else None,
+                              "peak": HBM_PEAK_GBS,
+                              "frac": round(bwd_bytes / (kb[1] / kb[0] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                              if kb[1] > 0 else None,
+                              # counter bytes of one call (both backward kernels)
+                              "traffic": read_traffic("flower-512-fwdbwd", "backward")},
     }
 
 
