@@ -43,11 +43,10 @@ namespace {
 
 constexpr int kNodeBlock = 256;
 constexpr int kSpan = 64;     // nodes of a workgroup's block along j and along k
-constexpr int kStep = 32;     // nodes along i per step (one brick)
+// a vote step covers 2 x 32 nodes along i (two bricks) for the block's 64 x 64 (j, k) nodes
 constexpr int kRow = 33;      // LDS stride of a 32-word bit matrix (no bank conflicts)
 constexpr int kVoteBlock = 512;  // threads of a classification workgroup
-constexpr int kXRays = kSpan * kSpan / kVoteBlock;       // 8 x-rays per thread
-constexpr int kVisits = kStep * kSpan / kVoteBlock;      // 4 y- and 4 z-spans per thread per step
+static_assert(kSpan * kSpan / kVoteBlock == 8, "the vote kernel gives each thread 8 x-rays of its block");
 
 // Depth of node t on an axis with origin lo and pixel size h; nodes past the
 // grid get +inf so that the tables stay sorted.
