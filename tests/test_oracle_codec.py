@@ -47,3 +47,12 @@ def test_matches_exact_rational_rounding():
             assert g == min(max(int(want), 0), 255), x
         else:
             assert g == 128, x
+
+
+def test_components_beyond_the_unit_range_clamp():
+    """The reading clamps the byte to [0, 255]: components a little beyond
+    +-1 (a normal that is not quite unit length) still give 255 and 0, and so
+    do components far outside."""
+    c = np.array([1.0, 1.003, 1.004, 1.5, 7.0, -1.0, -1.004, -1.5, -7.0], np.float32)
+    got = nc.encode(np.stack([c, c, c], axis=1)) & 255
+    assert got.tolist() == [255, 255, 255, 255, 255, 0, 0, 0, 0]
