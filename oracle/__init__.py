@@ -22,6 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldni_oracle.c")
+_SRC_BOOL = os.path.join(_HERE, "boolean_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libldni_oracle.so")
 _lib = None
 
@@ -35,7 +36,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-            "-Wall", "-o", tmp, _SRC, "-lpthread", "-lm"])
+            "-Wall", "-o", tmp, _SRC, _SRC_BOOL, "-lpthread", "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -60,7 +61,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                                                          os.path.getmtime(_SRC_BOOL)):
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
@@ -77,6 +79,14 @@ def _load():
     lib.oracle_backward_axis.restype = ctypes.c_int
     lib.oracle_pixel_centres.argtypes = [vp, i32, ctypes.c_int, vp, vp]
     lib.oracle_pixel_centres.restype = ctypes.c_int
+    pu32, pf32, pi32 = (ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float),
+                        ctypes.POINTER(ctypes.c_int32))
+    lib.oracle_boolean.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double,
+                                   ctypes.POINTER(pu32), ctypes.POINTER(pf32), ctypes.POINTER(pf32),
+                                   ctypes.POINTER(pi32), ctypes.POINTER(ctypes.c_uint64)]
+    lib.oracle_boolean.restype = ctypes.c_int
+    lib.oracle_boolean_free.argtypes = [pu32, pf32, pf32, pi32]
+    lib.oracle_boolean_free.restype = None
     _lib = lib
     return lib
 

@@ -26,6 +26,10 @@ Readings where the paper is silent:
   R5  Output triangle ids: A's id t stays t; B's id t becomes -1 - t.
 Depths, normals and ids of kept samples are copies of the inputs (a B
 normal reversed for the difference), so results are exact.
+
+``boolean`` loops over pixels in Python (small grids); ``boolean_c`` runs the
+same steps in plain C (``boolean_oracle.c``) for whole large images.  The
+pins run on both.
 """
 from __future__ import annotations
 
@@ -121,3 +125,39 @@ def boolean(a: AxisLDNI, b: AxisLDNI, op, eps=1e-5) -> AxisLDNI:
                     depth=np.asarray(depth, dtype=np.float32).reshape(n),
                     normal=np.asarray(normal, dtype=np.float32).reshape(n, 3),
                     tri=np.asarray(tri, dtype=np.int32).reshape(n))
+
+
+def boolean_c(a: AxisLDNI, b: AxisLDNI, op, eps=1e-5) -> AxisLDNI:
+    """``boolean`` evaluated by the plain C restatement of the same steps."""
+    import ctypes
+
+    from . import _load
+    if isinstance(op, str):
+        op = OPS[op]
+    if a.w != b.w:
+        raise ValueError("both LDNIs must have the same resolution")
+    lib = _load()
+    w = a.w
+    arrs = []
+    for x in (a, b):
+        arrs += [np.ascontiguousarray(x.offsets, np.uint32), np.ascontiguousarray(x.depth, np.float32),
+                 np.ascontiguousarray(np.asarray(x.normal, np.float32).reshape(-1, 3)),
+                 np.ascontiguousarray(x.tri, np.int32)]
+    po = ctypes.POINTER(ctypes.c_uint32)()
+    pd = ctypes.POINTER(ctypes.c_float)()
+    pn = ctypes.POINTER(ctypes.c_float)()
+    pt = ctypes.POINTER(ctypes.c_int32)()
+    n = ctypes.c_uint64()
+    rc = lib.oracle_boolean(w * w, *[q.ctypes.data for q in arrs], int(op), float(eps), ctypes.byref(po),
+                            ctypes.byref(pd), ctypes.byref(pn), ctypes.byref(pt), ctypes.byref(n))
+    if rc != 0:
+        raise RuntimeError(f"oracle_boolean failed ({rc})")
+    k = int(n.value)
+    try:
+        res = AxisLDNI(w=w, offsets=np.ctypeslib.as_array(po, (w * w + 1,)).copy(),
+                       depth=np.ctypeslib.as_array(pd, (max(k, 1),))[:k].copy(),
+                       normal=np.ctypeslib.as_array(pn, (max(k, 1) * 3,))[:3 * k].reshape(k, 3).copy(),
+                       tri=np.ctypeslib.as_array(pt, (max(k, 1),))[:k].copy())
+    finally:
+        lib.oracle_boolean_free(po, pd, pn, pt)
+    return res

@@ -155,3 +155,36 @@ def test_intersection_minus_a_is_empty_on_one_grid():
         for p in range(24 * 24):
             got = list(ua.depth[ua.offsets[p]:ua.offsets[p + 1]])
             assert got == list(a.depth[a.offsets[p]:a.offsets[p + 1]])
+
+
+def _pixel_c(da, db, op, eps):
+    """One pixel through the C restatement (boolean_c) as a 1 x 1 LDNI."""
+    def one(d):
+        n = len(d)
+        return oracle.AxisLDNI(w=1, offsets=np.array([0, n], np.uint32), depth=np.asarray(d, np.float32),
+                               normal=np.tile(np.float32([0, 0, 1]), (n, 1)),
+                               tri=np.arange(n, dtype=np.int32))
+    r = ob.boolean_c(one(da), one(db), op, eps)
+    # source of each result sample: A's ids are 0..na-1, B's become -1 - j
+    return [(0, int(t), False) if t >= 0 else (1, int(-1 - t), op == ob.DIFFERENCE) for t in r.tri], r
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_c_oracle_matches_point_membership(seed):
+    """The C restatement used for whole large images, pinned the same way as
+    the Python one: result end points against point membership between
+    consecutive distinct depths, and the end-point sample rule; the normal
+    of an end point from B is reversed only in the difference."""
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(300):
+        da = np.sort(rng.integers(0, 12, rng.integers(0, 9))).astype(np.float32)
+        db = np.sort(rng.integers(0, 12, rng.integers(0, 9))).astype(np.float32)
+        for op in OPS:
+            for eps in (0.0, 1.5, 4.0):
+                res, r = _pixel_c(da, db, op, eps)
+                got = _depths(da, db, res)
+                assert got == _brute(da, db, op, eps), (da, db, op, eps)
+                assert res == [_rule_ref(da, db, z, op) for z in got]
+                assert list(r.depth) == got
+                for (solid, _, rev), nz in zip(res, r.normal[:, 2]):
+                    assert nz == (-1.0 if rev else 1.0)
