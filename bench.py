@@ -2,7 +2,7 @@
 """Throughput of LDNI sampling on one MI355X.
 
 Headline step: one pass of the sampling path (triangle setup, tile binning,
-sampling pass, scans, place + per-pixel sort, all three axes) over the scene64 mesh
+count pass, scans, write pass with the per-pixel sort, all three axes) over the scene64 mesh
 (2,152,448 triangles, w=2048) through the C ABI call ``ldni_sample``
 (library-owned outputs from the stream-ordered pool) followed by
 ``ldni_free``.  Inputs are resident in HBM before the timed region starts.
@@ -26,15 +26,17 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CUs x 2.4 GHz x 64 lanes x 2 flops per FMA)
-# algorithmic arithmetic of the sampling pass: per candidate pixel the exact
-# coverage test (6 translations into the ray frame, 3 edge functions of one
-# product and one fused multiply-add); per hit the barycentric depth
-# (2 adds for the denominator, 5 for the numerator, divide, add, subtract)
+# algorithmic arithmetic per sample: the exact coverage test of its pixel
+# centre (6 translations into the ray frame, 3 edge functions of one product
+# and one fused multiply-add) and its barycentric depth (2 adds for the
+# denominator, 5 for the numerator, divide, add, subtract)
 FLOPS_PER_CANDIDATE = 15
 FLOPS_PER_HIT = 10
 METRIC = "LDNI samples written/sec (3 axes) at w=512/2048; batched vs plain; fwd+bwd"
@@ -77,39 +79,34 @@ def kernel_alg_bytes(name, mesh, samples):
     """The share of the algorithmic bytes each kernel moves (per step)."""
     return {"setup": 12 * mesh.n_verts + 12 * mesh.n_tris,
             "scan_pixels": 3 * 4 * (mesh.w * mesh.w + 1),
-            "place": 16 * samples, "write": 16 * samples}.get(name)
+            "write": 16 * samples}.get(name)
 
 
-def candidate_count(mesh, axes=(0, 1, 2)) -> int:
-    """Candidate pixels of the sampling pass: for every triangle and axis, the
-    pixels of its rectangle (centres c with min <= c < max in both image
-    coordinates, centres rounded to float32 as the sampler does)."""
-    import numpy as np
-    lo = np.asarray(mesh.bbox[:3], np.float64)
-    hi = np.asarray(mesh.bbox[3:], np.float64)
-    P = mesh.verts[mesh.tris]  # (T, 3, 3) float32
-    total = 0
-    for a in axes:
-        ext = []
-        for d in ((a + 1) % 3, (a + 2) % 3):
-            h = (hi[d] - lo[d]) / mesh.w
-            c = (lo[d] + (np.arange(mesh.w, dtype=np.float64) + 0.5) * h).astype(np.float32)
-            mn = P[:, :, d].min(axis=1)
-            mx = P[:, :, d].max(axis=1)
-            ext.append(np.searchsorted(c, mx, "left").astype(np.int64)
-                       - np.searchsorted(c, mn, "left").astype(np.int64))
-        total += int((np.maximum(ext[0], 0) * np.maximum(ext[1], 0)).sum())
-    return total
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(mesh, seconds: float):
-    """The oracle on the same workload, all three axes, repeated until about
-    ``seconds`` of CPU work; its mean rate."""
-    import oracle
+def oracle_threads() -> int:
     threads = os.cpu_count() or 1
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         threads = min(threads, int(env))
+    return threads
+
+
+def cpu_baseline(mesh, seconds: float):
+    """The oracle on the same workload, all three axes, repeated until about
+    ``seconds`` of CPU work, on the host's threads; its mean rate.  Also the
+    oracle on one thread over a band of rows (the same per-pixel work, so
+    its rate per sample carries over)."""
+    import oracle
+    threads = oracle_threads()
     samples, passes = 0, 0
     t0 = time.perf_counter()
     while True:
@@ -120,9 +117,53 @@ def cpu_baseline(mesh, seconds: float):
         elapsed = time.perf_counter() - t0
         if elapsed >= seconds or passes >= 20:
             break
+    # single thread: rows [w/2 - w/16, w/2 + w/16) of every axis (through the
+    # densest part of the scene)
+    j0, j1 = mesh.w // 2 - mesh.w // 16, mesh.w // 2 + mesh.w // 16
+    t1 = time.perf_counter()
+    r1 = oracle.sample(mesh.verts, mesh.tris, mesh.bbox, mesh.w, axes="xyz", nthreads=1,
+                       window=(0, mesh.w, j0, j1))
+    one = sum(r1[a].n for a in range(3))
+    el1 = time.perf_counter() - t1
     return {"value": samples / elapsed, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"the whole workload (3 axes, culled mode) {passes} time(s): "
-                      f"{samples} samples in {elapsed:.1f} s"}
+                      f"{samples} samples in {elapsed:.1f} s on {threads} threads",
+            "single_thread": {"value": one / el1, "unit": "samples/s",
+                              "sample": f"rows [{j0}, {j1}) of each axis, culled mode: {one} samples "
+                                        f"in {el1:.1f} s"}}
+
+
+def oracle_c1_seconds():
+    """The C1 icosphere (w = 128, 3 axes) on the oracle: the literal
+    brute-force mode (every pixel x every triangle) and the culled mode, one
+    thread and all threads."""
+    import oracle
+    from paper_1009_0794_amd import meshgen as mg
+    m = mg.c1_icosphere()
+    out = {}
+    for mode, brute in (("brute", True), ("culled", False)):
+        for nt in (1, oracle_threads()):
+            t0 = time.perf_counter()
+            r = oracle.sample(m.verts, m.tris, m.bbox, m.w, axes="xyz", brute=brute, nthreads=nt)
+            out[f"{mode}_{nt}_threads_s"] = round(time.perf_counter() - t0, 4)
+    out["samples"] = sum(r[a].n for a in range(3))
+    return out
+
+
+def copy_bandwidth(torch, mib: int = 1024, reps: int = 10):
+    """Device-to-device copy of ``mib`` MiB (read + write counted): the HBM
+    ceiling a plain copy kernel reaches on this GPU."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            dst.copy_(src)
+    gbs = 2 * (mib << 20) * reps / (t.ms / 1e3) / 1e9
+    del src, dst
+    return {"bytes_per_copy": 2 * (mib << 20), "GBps": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 class Timer:
@@ -157,13 +198,19 @@ def measure_plain(ldni, torch, mesh, steps, warmup, workload):
 
     for _ in range(max(1, warmup)):
         n_axis, max_layers = step()
-    # the timed steps run without per-launch events; a second pass of the
-    # same steps records an event pair around every kernel launch on the
-    # library's stream for the per-kernel durations
+    # the timed steps run without per-launch events; a second pass times
+    # every step on its own (percentiles), a third records an event pair
+    # around every kernel launch on the library's stream for the per-kernel
+    # durations
     with Timer(torch) as t:
         for _ in range(steps):
             n_axis, max_layers = step()
     ms_step = t.ms / steps
+    per_step = []
+    for _ in range(steps):
+        with Timer(torch) as ts:
+            step()
+        per_step.append(ts.ms)
     ldni.profile_enable(True)
     with Timer(torch) as tp:
         for _ in range(steps):
@@ -171,37 +218,39 @@ def measure_plain(ldni, torch, mesh, steps, warmup, workload):
     ldni.profile_enable(False)
     kstats = ldni.profile_read()
     samples = sum(n_axis)
-    dom_name, (dom_launches, dom_ms) = max(kstats.items(), key=lambda kv: kv[1][1])
-    per_step = max(1, dom_launches // steps)
-    avg_s = dom_ms / dom_launches / 1e3
-    if dom_name == "sample":
-        # arithmetic-bound: algorithmic flops against the vector FP64 peak
-        cand = candidate_count(mesh)
-        flops = (FLOPS_PER_CANDIDATE * cand + FLOPS_PER_HIT * samples) / per_step
-        achieved = flops / avg_s / 1e12
-        roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3),
-                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                    "traffic": read_traffic(workload, dom_name),
-                    "avg_launch_us": round(avg_s * 1e6, 2),
-                    "algorithmic_flops_per_launch": flops, "candidates_per_step": cand}
-    else:
-        alg = kernel_alg_bytes(dom_name, mesh, samples)
-        alg_launch = alg / per_step if alg is not None else None
-        achieved = alg_launch / avg_s / 1e9 if alg_launch else 0.0
-        roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": read_traffic(workload, dom_name),
-                    "avg_launch_us": round(avg_s * 1e6, 2),
-                    "algorithmic_bytes_per_launch": alg_launch}
     b = fwd_bytes(mesh, samples)
+    dom_name, (dom_launches, dom_ms) = max(kstats.items(), key=lambda kv: kv[1][1])
+    launches_per_step = max(1, dom_launches // steps)
+    avg_s = dom_ms / dom_launches / 1e3
+    # the measurement's roofline: the step's algorithmic bytes (mesh read
+    # once, offsets and (depth, normal) samples written once) over the
+    # dominant kernel's time per step, against the HBM peak
+    dom_step_s = avg_s * launches_per_step
+    achieved = b / dom_step_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic(workload, dom_name),
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches_per_step": launches_per_step,
+                "algorithmic_bytes_per_step": b,
+                "path": {"achieved": round(b / (ms_step / 1e3) / 1e9, 2),
+                         "frac": round(b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    # arithmetic of the same kernel against the vector FP64 peak: per sample
+    # the exact coverage test and the barycentric depth
+    flops = (FLOPS_PER_CANDIDATE + FLOPS_PER_HIT) * samples
+    alu = {"bound": "alu", "kernel": dom_name, "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+           "achieved": round(flops / dom_step_s / 1e12, 3),
+           "frac": round(flops / dom_step_s / 1e12 / FP64_PEAK_TFLOPS, 4),
+           "algorithmic_flops_per_step": flops}
+    q = np.percentile(per_step, [10, 50, 90])
     return {
         "value": samples / (ms_step / 1e3),
         "ms_per_step": ms_step,
+        "step_ms_p10_p50_p90": [round(float(x), 4) for x in q],
         "samples_per_step": samples,
         "samples_per_axis": n_axis,
         "max_layers": max_layers,
         "roofline": roofline,
+        "alu_roofline": alu,
         "path_roofline": {"algorithmic_bytes_per_step": b,
                           "achieved_GBps": round(b / (ms_step / 1e3) / 1e9, 2),
                           "frac_of_hbm_peak": round(b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
@@ -227,7 +276,7 @@ def measure_rgb8(ldni, torch, mesh, steps):
         ldni.profile_enable(False)
         ks = ldni.profile_read()
         out[kind] = {"ms_per_step": round(t.ms / steps, 4),
-                     "place_ms": round(ks["place"][1] / steps, 4) if "place" in ks else None}
+                     "write_ms": round(ks["write"][1] / steps, 4) if "write" in ks else None}
     return {"bytes_per_sample": {"f32": 20, "rgb8": 12}, **out}
 
 
@@ -569,16 +618,29 @@ def main():
                                 "samples_per_step": r["samples_per_step"],
                                 "samples_per_axis": r["samples_per_axis"], "max_layers": r["max_layers"],
                                 "parallelism": "single GPU"},
-                     "roofline": r["roofline"], "path_roofline": r["path_roofline"],
+                     "step_ms_p10_p50_p90": r["step_ms_p10_p50_p90"],
+                     "roofline": r["roofline"], "alu_roofline": r["alu_roofline"],
+                     "path_roofline": r["path_roofline"],
                      "kernels_ms_per_step": r["kernels_ms_per_step"]})
+        line["hbm_copy_probe"] = copy_bandwidth(torch)
         line["normal_rgb8"] = measure_rgb8(ldni, torch, mesh, max(2, args.steps // 2))
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_seconds)
         del mesh
     if args.workload is None:
+        c1 = mg.c1_icosphere()
+        r1 = measure_plain(ldni, torch, c1, args.steps, args.warmup, "icosphere-128")
+        line["icosphere_128"] = {"value": round(r1["value"], 1), "ms_per_step": round(r1["ms_per_step"], 4),
+                                 "step_ms_p10_p50_p90": r1["step_ms_p10_p50_p90"],
+                                 "samples_per_step": r1["samples_per_step"],
+                                 "path_roofline": r1["path_roofline"],
+                                 "kernels_ms_per_step": r1["kernels_ms_per_step"]}
+        if not args.no_cpu_baseline:
+            line["icosphere_128"]["oracle_seconds"] = oracle_c1_seconds()
         fl = mg.c2_flower()
         r2 = measure_plain(ldni, torch, fl, args.steps, args.warmup, "flower-512")
         line["flower_512"] = {"value": round(r2["value"], 1), "ms_per_step": round(r2["ms_per_step"], 4),
+                              "step_ms_p10_p50_p90": r2["step_ms_p10_p50_p90"],
                               "samples_per_step": r2["samples_per_step"],
                               "path_roofline": r2["path_roofline"], "roofline": r2["roofline"],
                               "kernels_ms_per_step": r2["kernels_ms_per_step"]}

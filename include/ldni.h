@@ -100,19 +100,28 @@ typedef struct ldni_plan ldni_plan;     /* opaque; a sampling call split in two 
  *             from the stream-ordered pool of the current device); release it
  *             with ldni_free.  Axes not in the mask have empty views.
  * One host synchronisation per call (a second only when a first estimate of
- * the tile-list size was too small).  n_tris == 0 is valid (no samples).
+ * the tile-list size was too small): the per-axis sample counts, after the
+ * count pass.  The write pass then runs behind the call on hip_stream; the
+ * result's first ldni_result_axis waits for it and reports LDNI_ERR_DEVICE if
+ * it disagreed with the count pass.  n_tris == 0 is valid (no samples).
  */
 ldni_status ldni_sample(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                         const float bbox[6], int32_t w, uint32_t axis_mask, void *hip_stream,
                         ldni_result **out);
 
-/* View of axis 0 (x), 1 (y) or 2 (z).  LDNI_ERR_INVALID_ARG for a NULL
- * result or view, or an axis outside 0..2. */
+/* View of axis 0 (x), 1 (y) or 2 (z): one of the three LDNIs of
+ * Definition 3, each an LDI whose depths carry unit normals (Definitions 1
+ * and 2).  LDNI_ERR_INVALID_ARG for a NULL result or view, or an axis
+ * outside 0..2.  The first call on a result waits for the kernels that
+ * wrote it; LDNI_ERR_DEVICE (here and in every later call on the result)
+ * when a write pass stored more or fewer samples of a pixel than its count
+ * pass counted -- the result must then not be used. */
 ldni_status ldni_result_axis(const ldni_result *r, int axis, ldni_axis_view *view);
 
-/* Release a result (NULL-safe).  Its buffers are kept by the library for
- * later calls on the stream the result was made on (reused in that stream's
- * order, like hipFreeAsync), which must still exist. */
+/* Release a result -- the LDNIs of Definition 3 it holds (NULL-safe).  Its
+ * buffers are kept by the library for later calls on the stream the result
+ * was made on (reused in that stream's order, like hipFreeAsync), which must
+ * still exist.  A result whose kernels may still run is waited for first. */
 void ldni_free(ldni_result *r);
 
 /* Device memory the library keeps between calls: the buffers of released
@@ -134,7 +143,8 @@ ldni_status ldni_trim(void);
  *   plan      receives the state that finish needs (workspace on the device).
  * Then finish writes, for every axis in the mask, depth f32 [n], normal f32
  * [n][3] and tri i32 [n] into caller device buffers of at least n_samples[a]
- * elements, and releases the plan whether or not it succeeds.  A plan not
+ * elements, waits for the write pass (LDNI_ERR_DEVICE if it disagreed with
+ * the count pass), and releases the plan whether or not it succeeds.  A plan not
  * finished must be released with ldni_plan_free.  verts/tris must stay
  * unchanged until finish returns.
  */
@@ -302,7 +312,10 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
 /* Largest per-pixel count of each axis of a plan (after begin). */
 ldni_status ldni_plan_max_layers(const ldni_plan *plan, uint32_t max_layers[3]);
 
-/* Status name ("LDNI_OK", ...), never NULL. */
+/* Status name ("LDNI_OK", ...), never NULL.  The statuses enforce the input
+ * contract of Sec. 2: triangles of a polygonal mesh whose indices name
+ * vertices (Remark 2), finite coordinates, and the limits above; a closed,
+ * non-self-intersecting mesh (Definition 4) is assumed, not checked. */
 const char *ldni_status_string(ldni_status s);
 
 /* Thread-local detail of the last error ("" if none). */
@@ -357,7 +370,11 @@ ldni_status ldni_batch_axis(const ldni_batch *b, int32_t mesh, int axis, ldni_ax
 
 void ldni_batch_free(ldni_batch *b); /* NULL-safe; synchronous */
 
-/* ldni_batch_create under the name of the batched entry point. */
+/* ldni_batch_create under the name of the batched entry point: Definitions
+ * 1-3 applied mesh by mesh, every mesh's geometry sent to the device once
+ * and kept (as Sec. 3 keeps it in a display list).  The results come as one
+ * ldni_batch handle, not one ldni_result per mesh: ldni_batch_axis gives
+ * each mesh's views, valid until the next run or ldni_batch_free. */
 ldni_status ldni_sample_batch(int32_t n_meshes, const ldni_mesh_desc *meshes, uint32_t axis_mask,
                               void *hip_stream, ldni_batch **out);
 
@@ -378,6 +395,24 @@ typedef struct {
 
 ldni_status ldni_profile_enable(int enable);
 ldni_status ldni_profile_read(ldni_kernel_stat *stats, int32_t max, int32_t *n);
+
+/*
+ * Self-test of the sampling kernels' candidate pruning, run on the host (no
+ * GPU work).  The kernels test only the pixels of each triangle row that lie
+ * in a conservative column span (bounded by the edge lines with margins for
+ * float32 translation and rounding), and the count pass counts the pixels
+ * of an inner span (the same bounds moved inward) as hits without testing
+ * them; this generates n_cases seeded triangles on seeded grids -- random,
+ * on pixel-centre lattices, with edges nearly parallel to the rows,
+ * slivers, tiny and huge ones, boxes far from the origin -- and checks every
+ * pixel centre of each triangle's candidate rectangle with the exact
+ * coverage test of Definition 1 (the Hits convention above).  counts (HOST
+ * u64 [4]) receives: hits outside their row's span plus inner-span pixels
+ * that miss (0 for a sound pruning), hits, pixels inside the spans, pixels
+ * inside the inner spans.  LDNI_ERR_INVALID_ARG for a NULL counts or
+ * n_cases < 0.
+ */
+ldni_status ldni_span_selftest(uint64_t seed, int64_t n_cases, uint64_t counts[4]);
 
 #ifdef __cplusplus
 }

@@ -200,9 +200,9 @@ def ldni_backward(verts, tris, bbox, w: int, ldnis: Dict[int, LDNI], grad_depth=
     if not (grad_verts.is_contiguous() and grad_verts.dtype == torch.float32
             and tuple(grad_verts.shape) == tuple(verts.shape)):
         raise ValueError("grad_verts must be a contiguous float32 tensor shaped like verts")
-    _lib.check(_lib.lib().ldni_backward(verts.data_ptr(), verts.shape[0], tris.data_ptr(),
-                                        tris.shape[0], _bbox(bbox), int(w), mask, views, gd, gn,
-                                        grad_verts.data_ptr(), _stream(verts.device)))
+    fn = _lib.lib().ldni_backward
+    _lib.check(fn(verts.data_ptr(), verts.shape[0], tris.data_ptr(), tris.shape[0], _bbox(bbox), int(w), mask,
+                  views, gd, gn, grad_verts.data_ptr(), _stream(verts.device)))
     return grad_verts
 
 

@@ -238,7 +238,10 @@ __global__ void __launch_bounds__(kBoolBlock) boolean_write_kernel(BooleanArgs g
   const int64_t p0 = ((int64_t)blockIdx.x * kBoolWaves + wave) * 64;
   if (p0 >= g.npix) return;
   const WavePixels w = wave_pixels(g, p0, false);
-  if (!w.ok) return;  // the call fails; nothing was counted
+  if (!w.ok) {  // inputs that changed between the passes: the call fails
+    if (lane == 0) atomicOr(g.status, kStatusMismatch);
+    return;
+  }
   uint32_t* so = s_o[wave];
   const uint32_t o = w.live ? g.counts[w.p] : 0u;
   const uint32_t R1 = g.counts[p0 + w.nlive];
@@ -272,7 +275,10 @@ __global__ void __launch_bounds__(kBoolBlock) boolean_write_kernel(BooleanArgs g
       const uint32_t k = k0 + (uint32_t)lane + 64u * u;
       if (!any[u]) continue;
       const uint64_t si = (uint64_t)base[u] + src[u];
-      if (si >= (from_b[u] ? g.b.n : g.a.n)) continue;  // (inputs changed between the passes)
+      if (si >= (from_b[u] ? g.b.n : g.a.n)) {  // inputs changed between the passes
+        atomicOr(g.status, kStatusMismatch);
+        continue;
+      }
       put(g, k, from_b[u], si);
     }
   }

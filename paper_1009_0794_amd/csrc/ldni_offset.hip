@@ -463,7 +463,9 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
     lower = upper;
   }
   if (failed) {
-    if (lane == 0) atomicOr(g.status, kStatusOutFull);
+    // the count pass flags the ray as too full for the call; in the write
+    // pass (the count pass kept this ray) it is a disagreement of the passes
+    if (lane == 0) atomicOr(g.status, kWrite ? kStatusMismatch : kStatusOutFull);
     if (!kWrite && lane == 0) g.counts[a][p] = 0;
     return;
   }
@@ -487,7 +489,8 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
     const uint64_t km = __ballot(keep);
     const uint32_t rank = kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull));
     // the sweep is deterministic, so the write pass keeps what the count
-    // pass counted; the bound only keeps a disagreement inside the slot
+    // pass counted; a disagreement (checked below) never writes outside the
+    // ray's slot
     if (kWrite && keep && 2 * rank + 1 < cnt) {
       write_event(g, a, p, cu, cv, ea, (size_t)out + 2 * rank);
       write_event(g, a, p, cu, cv, eb, (size_t)out + 2 * rank + 1);
@@ -499,6 +502,9 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
     kept += (uint32_t)__popcll(km);
   }
   if (!kWrite && lane == 0) g.counts[a][p] = 2 * kept;
+  // more or fewer end points than the count pass kept: slots unwritten or
+  // surplus ones dropped, so the call fails
+  if (kWrite && lane == 0 && 2 * kept != cnt) atomicOr(g.status, kStatusMismatch);
 }
 
 }  // namespace
