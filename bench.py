@@ -2,7 +2,8 @@
 """Throughput of LDNI sampling on one MI355X.
 
 Headline step: one pass of the sampling path (triangle setup, tile binning,
-count pass, scans, write pass with the per-pixel sort, all three axes) over the scene64 mesh
+sampling pass, scans, place pass with the per-pixel sort, all three axes)
+over the scene64 mesh
 (2,152,448 triangles, w=2048) through the C ABI call ``ldni_sample``
 (library-owned outputs from the stream-ordered pool) followed by
 ``ldni_free``.  Inputs are resident in HBM before the timed region starts.
@@ -33,10 +34,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CUs x 2.4 GHz x 64 lanes x 2 flops per FMA)
-# algorithmic arithmetic per sample: the exact coverage test of its pixel
-# centre (6 translations into the ray frame, 3 edge functions of one product
-# and one fused multiply-add) and its barycentric depth (2 adds for the
-# denominator, 5 for the numerator, divide, add, subtract)
+# algorithmic arithmetic of the sampling pass: per candidate pixel the exact
+# coverage test (6 translations into the ray frame, 3 edge functions of one
+# product and one fused multiply-add); per hit the barycentric depth
+# (2 adds for the denominator, 5 for the numerator, divide, add, subtract)
 FLOPS_PER_CANDIDATE = 15
 FLOPS_PER_HIT = 10
 METRIC = "LDNI samples written/sec (3 axes) at w=512/2048; batched vs plain; fwd+bwd"
@@ -79,7 +80,28 @@ def kernel_alg_bytes(name, mesh, samples):
     """The share of the algorithmic bytes each kernel moves (per step)."""
     return {"setup": 12 * mesh.n_verts + 12 * mesh.n_tris,
             "scan_pixels": 3 * 4 * (mesh.w * mesh.w + 1),
-            "write": 16 * samples}.get(name)
+            "place": 16 * samples}.get(name)
+
+
+def candidate_count(mesh, axes=(0, 1, 2)) -> int:
+    """Candidate pixels of the sampling pass: for every triangle and axis, the
+    pixels of its rectangle (centres c with min <= c < max in both image
+    coordinates, centres rounded to float32 as the sampler does)."""
+    lo = np.asarray(mesh.bbox[:3], np.float64)
+    hi = np.asarray(mesh.bbox[3:], np.float64)
+    P = mesh.verts[mesh.tris]  # (T, 3, 3) float32
+    total = 0
+    for a in axes:
+        ext = []
+        for d in ((a + 1) % 3, (a + 2) % 3):
+            h = (hi[d] - lo[d]) / mesh.w
+            c = (lo[d] + (np.arange(mesh.w, dtype=np.float64) + 0.5) * h).astype(np.float32)
+            mn = P[:, :, d].min(axis=1)
+            mx = P[:, :, d].max(axis=1)
+            ext.append(np.searchsorted(c, mx, "left").astype(np.int64)
+                       - np.searchsorted(c, mn, "left").astype(np.int64))
+        total += int((np.maximum(ext[0], 0) * np.maximum(ext[1], 0)).sum())
+    return total
 
 
 def cpu_model() -> str:
@@ -234,13 +256,15 @@ def measure_plain(ldni, torch, mesh, steps, warmup, workload):
                 "algorithmic_bytes_per_step": b,
                 "path": {"achieved": round(b / (ms_step / 1e3) / 1e9, 2),
                          "frac": round(b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
-    # arithmetic of the same kernel against the vector FP64 peak: per sample
-    # the exact coverage test and the barycentric depth
-    flops = (FLOPS_PER_CANDIDATE + FLOPS_PER_HIT) * samples
-    alu = {"bound": "alu", "kernel": dom_name, "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-           "achieved": round(flops / dom_step_s / 1e12, 3),
-           "frac": round(flops / dom_step_s / 1e12 / FP64_PEAK_TFLOPS, 4),
-           "algorithmic_flops_per_step": flops}
+    # arithmetic of the sampling pass against the vector FP64 peak: per
+    # candidate pixel the exact coverage test, per hit the barycentric depth
+    cand = candidate_count(mesh)
+    flops = FLOPS_PER_CANDIDATE * cand + FLOPS_PER_HIT * samples
+    sample_s = kstats["sample"][1] / steps / 1e3 if "sample" in kstats else dom_step_s
+    alu = {"bound": "alu", "kernel": "sample", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+           "achieved": round(flops / sample_s / 1e12, 3),
+           "frac": round(flops / sample_s / 1e12 / FP64_PEAK_TFLOPS, 4),
+           "algorithmic_flops_per_step": flops, "candidates_per_step": cand}
     q = np.percentile(per_step, [10, 50, 90])
     return {
         "value": samples / (ms_step / 1e3),
@@ -276,7 +300,7 @@ def measure_rgb8(ldni, torch, mesh, steps):
         ldni.profile_enable(False)
         ks = ldni.profile_read()
         out[kind] = {"ms_per_step": round(t.ms / steps, 4),
-                     "write_ms": round(ks["write"][1] / steps, 4) if "write" in ks else None}
+                     "place_ms": round(ks["place"][1] / steps, 4) if "place" in ks else None}
     return {"bytes_per_sample": {"f32": 20, "rgb8": 12}, **out}
 
 

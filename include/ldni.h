@@ -396,23 +396,6 @@ typedef struct {
 ldni_status ldni_profile_enable(int enable);
 ldni_status ldni_profile_read(ldni_kernel_stat *stats, int32_t max, int32_t *n);
 
-/*
- * Self-test of the sampling kernels' candidate pruning, run on the host (no
- * GPU work).  The kernels test only the pixels of each triangle row that lie
- * in a conservative column span (bounded by the edge lines with margins for
- * float32 translation and rounding), and the count pass counts the pixels
- * of an inner span (the same bounds moved inward) as hits without testing
- * them; this generates n_cases seeded triangles on seeded grids -- random,
- * on pixel-centre lattices, with edges nearly parallel to the rows,
- * slivers, tiny and huge ones, boxes far from the origin -- and checks every
- * pixel centre of each triangle's candidate rectangle with the exact
- * coverage test of Definition 1 (the Hits convention above).  counts (HOST
- * u64 [4]) receives: hits outside their row's span plus inner-span pixels
- * that miss (0 for a sound pruning), hits, pixels inside the spans, pixels
- * inside the inner spans.  LDNI_ERR_INVALID_ARG for a NULL counts or
- * n_cases < 0.
- */
-ldni_status ldni_span_selftest(uint64_t seed, int64_t n_cases, uint64_t counts[4]);
 
 #ifdef __cplusplus
 }

@@ -112,8 +112,6 @@ def lib():
     L.ldni_profile_enable.restype = st
     L.ldni_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
     L.ldni_profile_read.restype = st
-    L.ldni_span_selftest.argtypes = [ctypes.c_uint64, i64, ctypes.POINTER(ctypes.c_uint64)]
-    L.ldni_span_selftest.restype = st
     _lib = L
     return L
 
@@ -146,4 +144,4 @@ def exported_symbols():
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
             "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch",
             "ldni_boolean", "ldni_sample_finish_rgb8", "ldni_classify_nodes", "ldni_node_words",
-            "ldni_offset", "ldni_span_selftest"]
+            "ldni_offset"]

@@ -16,7 +16,6 @@
 
 #include "../../include/ldni.h"
 #include "ldni_internal.hpp"
-#include "ldni_span.hpp"
 
 using namespace ldni;
 
@@ -41,15 +40,6 @@ void finish_image_geometry(Image& im) {
   };
   im.inv_h_u = 1.0 / im.h_u;
   im.inv_h_v = 1.0 / im.h_v;
-  // Span columns: t = (x - c_0) * inv_hf_u, with every centre within
-  // 2^-24 |c| of the real one and c_0 the same, plus float32 rounding of
-  // the subtraction and product over at most ~2^10 pixels: 2^-22 max|c| / h
-  // covers the centres, 2^-13 pixels the rest.
-  im.inv_hf_u = (float)im.inv_h_u;
-  {
-    const double cmax = std::max(std::fabs(im.lo_u), std::fabs(im.lo_u + (double)im.w * im.h_u));
-    im.span_slack = (float)(std::ldexp(cmax / im.h_u, -22) + std::ldexp(1.0, -13));
-  }
   im.slack_u = slack(im.lo_u, im.h_u);
   im.slack_v = slack(im.lo_v, im.h_v);
   im.tw_shift = shift(im.tw);
@@ -83,6 +73,50 @@ void tile_shape(int32_t w, int64_t n_tris, int req_w, int req_h, int* tw, int* t
 }
 // largest (tile-list entries / triangles) seen, with headroom
 std::atomic<double> g_list_ratio{2.0};
+// Staging buffers hold fewer than 2^32 entries (tile regions start at 32-bit
+// entry indices); batch_grow adds up to 1/16 + 1024 to what it is asked for.
+constexpr uint64_t kMaxStageEntries = 0xf0000000ull;
+
+// Staging entries the sampling pass asked for in recent calls, keyed by the
+// call's shape: a repeated call on the same mesh gets what the last one
+// needed (plus headroom for moved vertices).
+struct StageKey {
+  int64_t n_verts, n_tris;
+  int32_t w, tw, th;
+  uint32_t mask;
+  bool operator==(const StageKey& o) const {
+    return n_verts == o.n_verts && n_tris == o.n_tris && w == o.w && tw == o.tw && th == o.th &&
+           mask == o.mask;
+  }
+};
+struct StageSeen {
+  uint64_t demand;      // staging entries asked for
+  uint32_t max_layers;  // deepest pixel
+};
+std::mutex g_stage_mu;
+std::vector<std::pair<StageKey, StageSeen>> g_stage_seen;  // most recent last
+constexpr size_t kStageMemory = 1024;
+
+bool stage_seen_lookup(const StageKey& k, StageSeen* seen) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  for (size_t i = g_stage_seen.size(); i-- > 0;)
+    if (g_stage_seen[i].first == k) {
+      *seen = g_stage_seen[i].second;
+      return true;
+    }
+  return false;
+}
+
+void stage_seen_record(const StageKey& k, StageSeen seen) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  for (size_t i = 0; i < g_stage_seen.size(); ++i)
+    if (g_stage_seen[i].first == k) {
+      g_stage_seen.erase(g_stage_seen.begin() + i);
+      break;
+    }
+  if (g_stage_seen.size() >= kStageMemory) g_stage_seen.erase(g_stage_seen.begin());
+  g_stage_seen.emplace_back(k, seen);
+}
 
 ldni_status fail(ldni_status s, const std::string& msg) {
   g_last_error = msg;
@@ -333,10 +367,15 @@ struct ldni_plan {
   int axis_of[kMaxImages] = {0, 0, 0};  // image k samples axis axis_of[k]
   void* ws = nullptr;     // workspace
   size_t ws_bytes = 0;
-  void* lists = nullptr;  // tile-list entries
+  void* lists = nullptr;  // tile lists
   size_t lists_bytes = 0;
-  uint32_t n_items = 0;   // write items
-  uint32_t* status = nullptr;
+  uint32_t* write_counter = nullptr;
+  void* items = nullptr;  // place-pass work items
+  uint32_t n_items = 0;
+  void* stage = nullptr;  // hits staged by the sampling pass
+  size_t stage_bytes = 0;
+  uint32_t n_walk = 0;    // tiles the write pass walks again
+  uint32_t* status = nullptr;  // the call's device status word
   uint64_t n[3] = {0, 0, 0};
   uint32_t max_layers[3] = {0, 0, 0};
 };
@@ -360,6 +399,7 @@ namespace {
 void release_plan(ldni_plan* p) {
   if (!p) return;
   cache_put(p->lists, p->lists_bytes, p->stream);
+  cache_put(p->stage, p->stage_bytes, p->stream);
   cache_put(p->ws, p->ws_bytes, p->stream);
   delete p;
 }
@@ -482,29 +522,43 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   const int64_t n_tiles = (int64_t)ntx * nty;
   const int64_t npix = (int64_t)w * w;
 
+  // what the last call of this shape needed (staging entries, deepest pixel)
+  const StageKey stage_key{n_verts, n_tris, w, tw, th, axis_mask};
+  StageSeen seen{0, 0};
+  const bool have_seen = stage_seen_lookup(stage_key, &seen);
+  const uint32_t stage_layers = stage_layers_for(seen.max_layers);
+
   // ---- workspace layout ----
   int nimg = 0;
   for (int a = 0; a < 3; ++a)
     if ((axis_mask >> a) & 1u) p->axis_of[nimg++] = a;
   const int64_t n_all = nimg * n_tiles;  // tiles of all images, numbered image after image
   size_t off = 0;
-  // status words, tile entry counts (all images, then their total) and
-  // scatter cursors are adjacent and cleared by one fill
+  // status words, tile entry counts (all images, then their total), tile
+  // candidate counts (16-byte aligned for the scan) and scatter cursors are
+  // adjacent and cleared by one fill
   const size_t o_status = off; off += 256;
   const size_t o_tcnt = off; off += sizeof(uint32_t) * (size_t)(n_all + 1);
+  const size_t o_treg = (off + 15) & ~(size_t)15; off = o_treg + sizeof(uint32_t) * (size_t)(n_all + 1);
   const size_t o_tcur = off; off += sizeof(uint32_t) * (size_t)n_all;
   const int64_t n_clear = (int64_t)(off / sizeof(uint32_t));
   off = align_up(off);
-  const size_t o_tnorm = off; off = align_up(off + sizeof(float) * 3 * (size_t)n_tris);
-  size_t o_counts[kMaxImages], o_thits[kMaxImages];
+  const size_t o_soup = off; off = align_up(off + sizeof(float) * 9 * (size_t)n_tris);
+  const size_t o_tnorm = off; off = align_up(off + sizeof(float4) * (size_t)n_tris);
+  size_t o_rect[kMaxImages], o_counts[kMaxImages], o_tstage[kMaxImages], o_thits[kMaxImages];
   for (int k = 0; k < nimg; ++k) {
+    o_rect[k] = off; off = align_up(off + sizeof(Rect) * (size_t)n_tris);
     o_counts[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)npix);
+    o_tstage[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
     o_thits[k] = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_tiles);
   }
+  const size_t o_walk = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_all);
+  const size_t o_items = off;
+  off = align_up(off + 16 * (size_t)max_place_items_per_tile(tw * th, stage_layers) * (size_t)n_all);
   const size_t o_plan = off; off = align_up(off + sizeof(uint32_t) * (size_t)(2 * n_all + 1));
   const size_t o_scan = off;
   off = align_up(off + std::max({scan_scratch_bytes(npix, nimg), scan_scratch_bytes(2 * n_all, 1),
-                                  scan_scratch_bytes(n_all, 1)}));
+                                  scan_scratch_bytes(n_all, 2)}));
 
   hipError_t e = cache_get(&p->ws, off, stream, &p->ws_bytes);
   if (e != hipSuccess) {
@@ -513,16 +567,19 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     return hip_fail(e, "workspace allocation");
   }
   char* ws = static_cast<char*>(p->ws);
-  // [0] status, [1..3] max layers
+  // [0] status, [1..3] max layers, [12..13] write-pass work counters,
+  // [18] tiles to walk again
   uint32_t* status = reinterpret_cast<uint32_t*>(ws + o_status);
   p->status = status;
+  uint32_t* walk_count = status + 18;
 
   MeshSetup ms{};
   ms.verts = verts;
   ms.n_verts = n_verts;
   ms.tris = tris;
   ms.n_tris = n_tris;
-  ms.tnorm = reinterpret_cast<float*>(ws + o_tnorm);
+  ms.soup = reinterpret_cast<float*>(ws + o_soup);
+  ms.tnorm = reinterpret_cast<float4*>(ws + o_tnorm);
   ms.status = status;
 
   ImageSet& set = p->set;
@@ -545,25 +602,61 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     finish_image_geometry(im);
     im.ntx = ntx;
     im.nty = nty;
-    im.verts = verts;
-    im.n_verts = n_verts;
-    im.tris = tris;
+    im.soup = ms.soup;
     im.tnorm = ms.tnorm;
+    im.rect = reinterpret_cast<const Rect*>(ws + o_rect[k]);
+    ms.rect[k] = reinterpret_cast<Rect*>(ws + o_rect[k]);
     im.n_tris = n_tris;
     im.tile_cnt = reinterpret_cast<uint32_t*>(ws + o_tcnt) + k * n_tiles;
     im.tile_cur = reinterpret_cast<uint32_t*>(ws + o_tcur) + k * n_tiles;
-    im.ent_uv = nullptr;
-    im.ent_z = nullptr;
+    im.tile_region = reinterpret_cast<uint32_t*>(ws + o_treg) + k * n_tiles;
+    im.tile_list = nullptr;
     im.counts = reinterpret_cast<uint32_t*>(ws + o_counts[k]);
     im.max_layers = nullptr;  // the pixel scan writes status[1 + k]
     im.tile_max = nullptr;
-    im.tile_hits = reinterpret_cast<uint32_t*>(ws + o_thits[k]);
     im.offsets = offsets[a];
     im.status = status;
+    im.tile_stage = reinterpret_cast<uint32_t*>(ws + o_tstage[k]);
+    im.tile_hits = reinterpret_cast<uint32_t*>(ws + o_thits[k]);
+    im.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
+    im.walk_count = walk_count;
     set.tile_start[k + 1] = set.tile_start[k] + (uint32_t)n_tiles;
+  }
+  // Staging buffer for the hits of the sampling pass: what the last call of
+  // the same shape asked for (the candidate total of its tile scan), else a
+  // first guess (16 entries per triangle and image, which covers small
+  // triangles' rectangles rounded to 4-entry groups, plus four per pixel for
+  // large ones).  A tile whose region does not fit is walked again by the
+  // place pass, so a short buffer costs time, never results.  Never more
+  // than stage_layers entries per pixel, which is all the tiles can ask for.
+  {
+    const double px = (double)npix * nimg;
+    const double want = have_seen ? (double)seen.demand * 1.1 + 65536.0
+                                  : 16.0 * (double)n_tris * nimg + 4.0 * px + 65536.0;
+    const double most = std::min((double)stage_layers * px + 65536.0, (double)kMaxStageEntries);
+    uint64_t stage_cap = (uint64_t)std::min(want, most);
+    // test hook: a smaller buffer (0: none) forces tiles onto the walk path
+    if (const char* env = std::getenv("LDNI_STAGE_ENTRIES"))
+      stage_cap = std::min<uint64_t>(stage_cap, std::strtoull(env, nullptr, 10));
+    stage_cap &= ~(uint64_t)3;  // whole 4-entry groups: 16-byte aligned pixel/slot words
+    if (stage_cap == 0 ||
+        cache_get(&p->stage, stage_cap * (sizeof(uint64_t) + sizeof(uint32_t)), stream, &p->stage_bytes) !=
+            hipSuccess)
+      p->stage = nullptr;  // no staging: every tile with hits is walked again
+    for (int k = 0; k < nimg; ++k) {
+      Image& im = set.img[k];
+      im.stage_key = p->stage ? static_cast<uint64_t*>(p->stage) : nullptr;
+      im.stage_qs = p->stage ? reinterpret_cast<uint32_t*>(static_cast<uint64_t*>(p->stage) + stage_cap)
+                             : nullptr;
+      im.stage_cap = p->stage ? stage_cap : 0;
+      im.stage_layers = stage_layers;
+    }
   }
   void* scan_scratch = ws + o_scan;
   set.plan = reinterpret_cast<uint32_t*>(ws + o_plan);
+  set.place_cap = place_stage_cap(tw * th);
+  p->write_counter = status + 12;
+  p->items = ws + o_items;
 
   auto bail = [&](ldni_status s) {
     release_plan(p);
@@ -576,14 +669,17 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   } while (0)
 
   uint32_t* tile_cnt_all = reinterpret_cast<uint32_t*>(ws + o_tcnt);
+  uint32_t* tile_region_all = reinterpret_cast<uint32_t*>(ws + o_treg);
   uint32_t* tile_cur_all = reinterpret_cast<uint32_t*>(ws + o_tcur);
   STEP(launch_fill_u32(status, 0u, n_clear, stream), "fill");
-  // setup also counts every triangle's tiles
+  // setup also counts every triangle's tiles and their candidate pixels
   STEP(timed("setup", stream, [&] { return launch_setup(ms, set, stream); }), "setup kernel");
   // one scan over the tile counts of all images (the images' lists follow
-  // each other in one array)
+  // each other in one array), and over their candidate counts (the images'
+  // staging regions follow each other in the staging buffer)
   STEP(timed("scan_tiles", stream, [&] {
-         return launch_scan(tile_cnt_all, tile_cnt_all, n_all, scan_scratch, status, stream);
+         return launch_tile_scan(tile_cnt_all, tile_region_all, n_all, stage_layers * (uint32_t)(tw * th),
+                                 scan_scratch, status, stream);
        }), "tile scan");
   // Tile lists are sized from the largest entries-per-triangle ratio seen so
   // far; the scatter drops entries beyond the capacity and the call is redone
@@ -595,15 +691,13 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   auto alloc_lists = [&](uint64_t c) -> hipError_t {
     cache_put(p->lists, p->lists_bytes, stream);
     p->lists = nullptr;
-    // 48 bytes per entry: two float4 of image coordinates, one of axis coordinates
-    hipError_t ea = cache_get(&p->lists, 48 * (size_t)c, stream, &p->lists_bytes);
+    hipError_t ea = cache_get(&p->lists, sizeof(int2) * (size_t)c, stream, &p->lists_bytes);
     if (ea != hipSuccess) {
       p->lists = nullptr;
       return ea;
     }
     for (int k = 0; k < nimg; ++k) {
-      set.img[k].ent_uv = static_cast<float4*>(p->lists);
-      set.img[k].ent_z = static_cast<float4*>(p->lists) + 2 * c;
+      set.img[k].tile_list = static_cast<int2*>(p->lists);
       set.img[k].list_cap = c;
     }
     return hipSuccess;
@@ -617,8 +711,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   gather_src[n_gather++] = status + 3;
   for (int k = 0; k < nimg; ++k) gather_src[n_gather++] = set.img[k].offsets + npix;  // rb[4+k]
   const int rb_more = n_gather;
-  gather_src[n_gather++] = tile_cnt_all + n_all;  // list entries
-  gather_src[n_gather++] = set.plan + 2 * n_all;  // write items
+  gather_src[n_gather++] = tile_cnt_all + n_all;     // list entries
+  gather_src[n_gather++] = tile_region_all + n_all;  // staging demand (saturated)
+  gather_src[n_gather++] = status + 18;              // tiles to walk again
+  gather_src[n_gather++] = set.plan + 2 * n_all;     // place items
   const uint32_t* counts_k[kMaxImages];
   uint32_t* offsets_k[kMaxImages];
   uint32_t* max_k[kMaxImages];  // largest count of each image
@@ -628,21 +724,29 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     max_k[k] = status + 1 + k;
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
-    STEP(timed("scatter", stream, [&] { return launch_scatter(ms, set, stream); }), "scatter kernel");
-    STEP(timed("count", stream, [&] { return launch_count(set, stream); }), "count kernel");
+    STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
+    STEP(timed("sample", stream, [&] { return launch_sample(set, stream); }), "sampling kernel");
     STEP(timed("scan_pixels", stream, [&] {
            return launch_scan_segments(counts_k, offsets_k, nimg, npix, scan_scratch, status, stream, max_k);
          }), "pixel scan");
-    STEP(timed("scan_plan", stream, [&] { return launch_plan_scan(set, scan_scratch, status, stream); }),
-         "plan scan");
-    // the single readback: status, max layers, sample and entry totals, items
+    STEP(timed("plan_items", stream, [&] {
+           return launch_plan_items(set, p->items, scan_scratch, status, stream);
+         }), "place plan");
+    // the single readback: status, max layers, sample and entry totals
     STEP(launch_gather(gather_src, n_gather, rb, stream), "readback");
     STEP(hipStreamSynchronize(stream), "synchronise");
     if (rb[0] & kStatusBadIndex) return bail(fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)"));
     if (rb[0] & kStatusNonFinite) return bail(fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate"));
     if (rb[0] & kStatusMismatch) return bail(fail(LDNI_ERR_DEVICE, "tile lists disagree with their counts"));
     const uint64_t need = rb[rb_more];
-    p->n_items = rb[rb_more + 1];
+    {
+      const uint64_t demand = rb[rb_more + 1];
+      uint32_t ml = 0;
+      for (int k = 0; k < nimg; ++k) ml = std::max(ml, rb[1 + k]);
+      stage_seen_record(stage_key, StageSeen{demand, ml});
+      p->n_walk = rb[rb_more + 2];
+      p->n_items = rb[rb_more + 3];
+    }
     if (n_tris > 0) {
       const double ratio = std::min(8.0, (double)need / ((double)n_tris * nimg) * 1.1);
       double cur = g_list_ratio.load();
@@ -653,9 +757,10 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     if (attempt == 1) return bail(fail(LDNI_ERR_DEVICE, "tile list sizing failed"));
     cap = need;
     STEP(alloc_lists(cap), "tile list allocation");
-    // cursors and max layers start again
+    // cursors, max layers and walk count start again
     STEP(launch_fill_u32(tile_cur_all, 0u, n_all, stream), "fill");
     STEP(launch_fill_u32(status + 1, 0u, 3, stream), "fill");
+    STEP(launch_fill_u32(walk_count, 0u, 1, stream), "fill");
   }
   if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more samples on one axis"));
   for (int k = 0; k < nimg; ++k) {
@@ -679,9 +784,9 @@ ldni_status ldni_plan_max_layers(const ldni_plan* plan, uint32_t max_layers[3]) 
 
 namespace {
 
-// Second half of a call: the write pass into the caller's buffers (float
+// Second half of a call: the place pass into the caller's buffers (float
 // normals, or 8-bit codes when rgb8 is given), then the plan is released.
-// With owner, the result checks the write pass's status when it is first
+// With owner, the result checks the place pass's status when it is first
 // read; without, the call waits for it here.
 ldni_status finish_plan(ldni_plan* p, float* const depth[3], float* const normal[3],
                         uint32_t* const rgb8[3], int32_t* const tri[3], ldni_result* owner) {
@@ -703,19 +808,14 @@ ldni_status finish_plan(ldni_plan* p, float* const depth[3], float* const normal
     p->set.img[k].tri = tri[a];
   }
   hipError_t e = hipSuccess;
-  void* items = nullptr;
-  size_t items_bytes = 0;
-  if (p->n_items > 0) {
-    e = cache_get(&items, 8 * (size_t)p->n_items, p->stream, &items_bytes);
-    if (e == hipSuccess) e = timed("plan_items", p->stream, [&] { return launch_plan_items(p->set, items, p->stream); });
-    if (e == hipSuccess)
-      e = timed("write", p->stream, [&] { return launch_write(p->set, items, p->n_items, p->stream); });
-  }
+  if (p->n_tris > 0)
+    e = timed("place", p->stream, [&] {
+      return launch_place(p->set, p->items, p->n_items, p->write_counter, p->n_walk, p->stream);
+    });
   ldni_status st = LDNI_OK;
   if (e != hipSuccess) st = hip_fail(e, "write kernel");
   else if (owner) st = arm_status(owner, p->status, p->stream);
   else st = check_now(p->status, p->stream);
-  cache_put(items, items_bytes, p->stream);
   release_plan(p);
   return st;
 }
@@ -1353,23 +1453,27 @@ struct ldni_batch {
   int32_t n_img = 0;
   std::vector<ldni_mesh_desc> desc;
   std::vector<int32_t> img_mesh, img_axis;
-  std::vector<uint32_t> tri_block_start, tile_start;
+  std::vector<uint32_t> tri_block_start, bin_block_start, tile_start;
   std::vector<uint64_t> seg_start;
   hipStream_t cs = nullptr;  // private stream the graph is captured on
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  void* lists = nullptr;     // tile-list entries, 48 bytes each
+  void* lists = nullptr;
   uint64_t list_cap = 0;
   void* samples = nullptr;
   uint64_t sample_cap = 0;
-  void* items = nullptr;     // write items, 8 bytes each
+  void* stage = nullptr;  // hits staged by the sampling pass
+  uint64_t stage_cap = 0;
+  uint32_t stage_layers = 64;  // staging entries per tile pixel (grows with the deepest pixel)
+  void* items = nullptr;  // place items, sized for stage_layers
   uint64_t items_cap = 0;
-  bool small = true;         // every image's tiles have at most 256 pixels
+  bool small = true;      // every image's tiles have at most 256 pixels
   uint32_t* host_out = nullptr;
   BatchDevice dev{};
   uint32_t* offsets_arena = nullptr;
   uint32_t* counts_arena = nullptr;
   uint32_t* tile_arena = nullptr;
+  uint32_t* region_arena = nullptr;  // candidate counts -> staging regions (after tile_arena)
   uint32_t* cur_arena = nullptr;
   uint32_t* max_layers = nullptr;
   void* scan_scratch = nullptr;
@@ -1397,6 +1501,7 @@ void batch_destroy(ldni_batch* b) {
   batch_release_graph(b);
   if (b->cs) (void)hipStreamSynchronize(b->cs);
   if (b->samples) (void)hipFree(b->samples);
+  if (b->stage) (void)hipFree(b->stage);
   if (b->items) (void)hipFree(b->items);
   if (b->lists) (void)hipFree(b->lists);
   if (b->ws) (void)hipFree(b->ws);
@@ -1408,8 +1513,7 @@ void batch_destroy(ldni_batch* b) {
 // Points the image table at the current list and sample buffers and uploads it.
 hipError_t batch_upload(ldni_batch* b) {
   for (int k = 0; k < b->n_img; ++k) {
-    b->images_h[k].ent_uv = static_cast<float4*>(b->lists);
-    b->images_h[k].ent_z = static_cast<float4*>(b->lists) + 2 * b->list_cap;
+    b->images_h[k].tile_list = static_cast<int2*>(b->lists);
     b->images_h[k].list_cap = b->list_cap;
   }
   b->dev.list_cap = b->list_cap;
@@ -1418,8 +1522,15 @@ hipError_t batch_upload(ldni_batch* b) {
   b->dev.tri = b->samples ? reinterpret_cast<int32_t*>(static_cast<float*>(b->samples) + 4 * b->sample_cap)
                           : nullptr;
   b->dev.sample_cap = b->sample_cap;
+  for (int k = 0; k < b->n_img; ++k) {
+    Image& im = b->images_h[k];
+    im.stage_key = b->stage ? static_cast<uint64_t*>(b->stage) : nullptr;
+    im.stage_qs = b->stage ? reinterpret_cast<uint32_t*>(static_cast<uint64_t*>(b->stage) + b->stage_cap)
+                           : nullptr;
+    im.stage_cap = b->stage ? b->stage_cap : 0;
+    im.stage_layers = b->stage_layers;
+  }
   b->dev.items = b->items;
-  b->dev.items_cap = b->items_cap;
   hipError_t e = hipMemcpy(b->dev.images, b->images_h.data(), sizeof(Image) * b->n_img, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   return hipMemcpy(b->dev.meshes, b->meshes_h.data(), sizeof(BatchMesh) * b->n_meshes, hipMemcpyHostToDevice);
@@ -1429,18 +1540,20 @@ hipError_t batch_upload(ldni_batch* b) {
 hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   hipError_t e;
 #define Q(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
-  Q(launch_fill_u32(b->dev.status, 0u, 20, s));  // status, work counters
+  Q(launch_fill_u32(b->dev.status, 0u, 20, s));  // status, work counters, walk count
   Q(launch_fill_u32(b->max_layers, 0u, b->n_img, s));
-  Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)b->total_tiles + 1, s));
+  // tile entry counts and (after them) candidate counts
+  Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)(b->region_arena - b->tile_arena) + (int64_t)b->total_tiles + 1, s));
   Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
-  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles
-  Q(launch_scan(b->tile_arena, b->tile_arena, (int64_t)b->total_tiles, b->scan_scratch, b->dev.status, s));
-  Q(launch_batch_scatter(b->dev, b->tri_block_start.back(), s));
-  Q(launch_batch_count(b->dev, (uint32_t)b->total_tiles, b->small, s));
+  Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles and candidates
+  Q(launch_tile_scan(b->tile_arena, b->region_arena, (int64_t)b->total_tiles,
+                     b->stage_layers * (uint32_t)(b->small ? 256 : 1024), b->scan_scratch, b->dev.status, s));
+  Q(launch_batch_scatter(b->dev, b->bin_block_start.back(), s));
+  Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, b->small, s));
   Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
                             b->scan_scratch, s));
   Q(launch_batch_finish_counts(b->dev, s));
-  Q(launch_batch_write(b->dev, (uint32_t)b->total_tiles, b->small, b->scan_scratch, s));
+  Q(launch_batch_place(b->dev, (uint32_t)b->total_tiles, b->small, b->scan_scratch, s));
 #undef Q
   return hipSuccess;
 }
@@ -1462,11 +1575,8 @@ hipError_t batch_capture(ldni_batch* b) {
 }
 
 ldni_status batch_grow(ldni_batch* b, void** buf, uint64_t* cap, uint64_t need, size_t bytes_per) {
-  const uint64_t c = (need + need / 16 + 1024) & ~(uint64_t)3;
-  if (*buf) {
-    (void)hipStreamSynchronize(b->cs);
-    (void)hipFree(*buf);
-  }
+  const uint64_t c = (need + need / 16 + 1024) & ~(uint64_t)3;  // whole 4-entry groups
+  if (*buf) (void)hipFree(*buf);
   *buf = nullptr;
   hipError_t e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(buf, (size_t)c * bytes_per);
   if (e != hipSuccess) {
@@ -1485,7 +1595,7 @@ extern "C" {
 ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
   if (!b) return fail(LDNI_ERR_INVALID_ARG, "NULL batch");
   const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  for (int attempt = 0; attempt < 4; ++attempt) {
+  for (int attempt = 0; attempt < 3; ++attempt) {
     if (!b->exec) {
       hipError_t e = batch_upload(b);
       if (e == hipSuccess) e = batch_capture(b);
@@ -1496,19 +1606,14 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
     const uint32_t* h = b->host_out;
     if (h[0] & kStatusBadIndex) return fail(LDNI_ERR_INDEX, "triangle index outside [0, n_verts)");
     if (h[0] & kStatusNonFinite) return fail(LDNI_ERR_NONFINITE, "non-finite vertex coordinate");
+    if (h[0] & kStatusMismatch) return fail(LDNI_ERR_DEVICE, "tile lists disagree with their counts");
     bool regrow = false;
     const uint64_t entries = h[1];
     if (entries > b->list_cap) {
-      ldni_status st = batch_grow(b, &b->lists, &b->list_cap, entries, 48);
+      ldni_status st = batch_grow(b, &b->lists, &b->list_cap, entries, sizeof(int2));
       if (st != LDNI_OK) return st;
       regrow = true;
     }
-    if (regrow) {  // counts were made from truncated lists: sizes are not final
-      batch_release_graph(b);
-      continue;
-    }
-    // (entries within their capacity: the lists were written as counted)
-    if (h[0] & kStatusMismatch) return fail(LDNI_ERR_DEVICE, "the write pass disagreed with the count pass");
     uint64_t need = 0;
     for (int k = 0; k < b->n_img; ++k) {
       const uint32_t* r = h + 4 + 4 * (size_t)k;
@@ -1519,21 +1624,48 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
       b->ml[k] = r[3];
       need = std::max(need, base + n);
     }
-    bool again = false;
+    if (regrow) {  // counts were made from truncated lists: sizes are not final
+      batch_release_graph(b);
+      continue;
+    }
     if (need > b->sample_cap) {
       // 5 floats per sample: depth, normal[3], tri
       ldni_status st = batch_grow(b, &b->samples, &b->sample_cap, need, 5 * sizeof(float));
       if (st != LDNI_OK) return st;
-      again = true;
-    }
-    if ((uint64_t)h[2] > b->items_cap) {
-      ldni_status st = batch_grow(b, &b->items, &b->items_cap, h[2], 8);
-      if (st != LDNI_OK) return st;
-      again = true;
-    }
-    if (again) {
       batch_release_graph(b);
       continue;
+    }
+    // Tiles that found no room in the staging buffer were walked again, so
+    // the results stand; the buffer and the per-pixel cap grow for the next run.
+    uint32_t ml = 0;
+    for (int k = 0; k < b->n_img; ++k) ml = std::max(ml, b->ml[k]);
+    const uint32_t layers = stage_layers_for(ml);
+    if (layers > b->stage_layers) {
+      // a larger item buffer first; without one the batch keeps its cap
+      const uint64_t need_items =
+          (uint64_t)max_place_items_per_tile(b->small ? 256 : 1024, layers) * b->total_tiles;
+      void* grown = nullptr;
+      if (!env_fault("alloc") && hipMalloc(&grown, (size_t)need_items * 16) == hipSuccess) {
+        (void)hipStreamSynchronize(b->cs);
+        (void)hipFree(b->items);
+        b->items = grown;
+        b->items_cap = need_items;
+        b->stage_layers = layers;
+        batch_release_graph(b);
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    const uint32_t* tail = h + 4 + 4 * (size_t)b->n_img;
+    // (tile regions start at 32-bit entry indices)
+    const uint64_t demand = std::min<uint64_t>((uint64_t)tail[0] | ((uint64_t)tail[1] << 32), kMaxStageEntries);
+    if (demand > b->stage_cap) {
+      // 12 bytes per entry: key and pixel/slot
+      if (batch_grow(b, &b->stage, &b->stage_cap, demand, sizeof(uint64_t) + sizeof(uint32_t)) != LDNI_OK) {
+        b->stage = nullptr;  // no staging: every tile is walked again
+        b->stage_cap = 0;
+      }
+      batch_release_graph(b);
     }
     return LDNI_OK;
   }
@@ -1579,10 +1711,11 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
 
   // ---- tables ----
   b->tri_block_start.push_back(0);
+  b->bin_block_start.push_back(0);
   b->tile_start.push_back(0);
   b->seg_start.push_back(0);
-  uint64_t tris_total = 0;
-  std::vector<uint64_t> tri_off(n_meshes);
+  uint64_t tris_total = 0, rect_total = 0;
+  std::vector<uint64_t> tri_off(n_meshes), rect_off;
   for (int m = 0; m < n_meshes; ++m) {
     const ldni_mesh_desc& d = meshes[m];
     tri_off[m] = tris_total;
@@ -1596,6 +1729,9 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
       const uint64_t tiles = (uint64_t)((d.w + tw - 1) / tw) * ((d.w + th - 1) / th);
       b->img_mesh.push_back(m);
       b->img_axis.push_back(a);
+      rect_off.push_back(rect_total);
+      rect_total += (uint64_t)d.n_tris;
+      b->bin_block_start.push_back(b->bin_block_start.back() + tb);
       b->tile_start.push_back((uint32_t)(b->tile_start.back() + tiles));
       b->seg_start.push_back(b->seg_start.back() + (uint64_t)d.w * d.w + 1);
     }
@@ -1603,7 +1739,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   b->n_img = (int32_t)b->img_mesh.size();
   b->total_tiles = b->tile_start.back();
   b->total_slots = b->seg_start.back();
-  if (b->total_tiles >= 0x7fffffffull) return bail(fail(LDNI_ERR_INVALID_ARG, "too many tiles in one batch"));
+  if (b->total_tiles >= 0xffffffffull) return bail(fail(LDNI_ERR_INVALID_ARG, "too many tiles in one batch"));
   const int n_img = b->n_img;
   b->n.assign(n_img, 0);
   b->ml.assign(n_img, 0);
@@ -1620,12 +1756,17 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const size_t o_meshes = take(sizeof(BatchMesh) * n_meshes);
   const size_t o_images = take(sizeof(Image) * n_img);
   const size_t o_tbs = take(sizeof(uint32_t) * (n_meshes + 1));
+  const size_t o_bbs = take(sizeof(uint32_t) * (n_img + 1));
   const size_t o_ts = take(sizeof(uint32_t) * (n_img + 1));
   const size_t o_ss = take(sizeof(uint64_t) * (n_img + 1));
   const size_t o_sb = take(sizeof(uint64_t) * n_img);
   const size_t o_ml = take(sizeof(uint32_t) * n_img);
-  const size_t o_tnorm = take(sizeof(float) * 3 * tris_total);
-  const size_t o_tile = take(sizeof(uint32_t) * (b->total_tiles + 1));
+  const size_t o_soup = take(sizeof(float) * 9 * tris_total);
+  const size_t o_tnorm = take(sizeof(float4) * tris_total);
+  const size_t o_rect = take(sizeof(Rect) * rect_total);
+  // tile entry counts, then (16-byte aligned) tile candidate counts
+  const uint64_t region_at = (b->total_tiles + 1 + 3) & ~(uint64_t)3;
+  const size_t o_tile = take(sizeof(uint32_t) * (region_at + b->total_tiles + 1));
   const size_t o_cur = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_counts = take(sizeof(uint32_t) * b->total_slots);
   const size_t o_offs = take(sizeof(uint32_t) * b->total_slots);
@@ -1637,11 +1778,14 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
       tile_shape(meshes[m].w, meshes[m].n_tris, meshes[m].tile_w, meshes[m].tile_h, &tw, &th);
       b->small = b->small && tw * th <= 256;
     }
+  const int tile_pix = b->small ? 256 : 1024;
+  const size_t o_tstage = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_thits = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_tmax = take(sizeof(uint32_t) * b->total_tiles);
+  const size_t o_walk = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_plan = take(sizeof(uint32_t) * (2 * b->total_tiles + 1));
   const size_t o_scan = take(std::max({scan_scratch_bytes(2 * (int64_t)b->total_tiles),
-                                       scan_scratch_bytes((int64_t)b->total_tiles),
+                                       scan_scratch_bytes((int64_t)b->total_tiles, 2),
                                        scan_scratch_bytes((int64_t)b->total_slots)}));
   e = env_fault("alloc") ? hipErrorOutOfMemory : hipMalloc(&b->ws, off);
   if (e != hipSuccess) {
@@ -1658,32 +1802,42 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   D.images = reinterpret_cast<Image*>(ws + o_images);
   D.n_images = n_img;
   D.tri_block_start = reinterpret_cast<uint32_t*>(ws + o_tbs);
+  D.bin_block_start = reinterpret_cast<uint32_t*>(ws + o_bbs);
   D.tile_start = reinterpret_cast<uint32_t*>(ws + o_ts);
   D.seg_start = reinterpret_cast<uint64_t*>(ws + o_ss);
   D.sample_base = reinterpret_cast<uint64_t*>(ws + o_sb);
   D.host_out = b->host_out;
   b->max_layers = reinterpret_cast<uint32_t*>(ws + o_ml);
   b->tile_arena = reinterpret_cast<uint32_t*>(ws + o_tile);
+  b->region_arena = b->tile_arena + region_at;
   b->cur_arena = reinterpret_cast<uint32_t*>(ws + o_cur);
   b->counts_arena = reinterpret_cast<uint32_t*>(ws + o_counts);
   b->offsets_arena = reinterpret_cast<uint32_t*>(ws + o_offs);
   b->scan_scratch = ws + o_scan;
   D.tile_total = b->tile_arena + b->total_tiles;
   D.plan = reinterpret_cast<uint32_t*>(ws + o_plan);
+  D.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
+  D.walk_count = D.status + 18;
+  D.region_total = b->region_arena + b->total_tiles;
+  D.place_cap = place_stage_cap(tile_pix);
+  uint32_t* tstage = reinterpret_cast<uint32_t*>(ws + o_tstage);
   uint32_t* thits = reinterpret_cast<uint32_t*>(ws + o_thits);
   uint32_t* tmax = reinterpret_cast<uint32_t*>(ws + o_tmax);
   D.tile_max = tmax;
 
   b->meshes_h.assign(n_meshes, BatchMesh{});
   b->images_h.assign(n_img, Image{});
-  float* tnorm = reinterpret_cast<float*>(ws + o_tnorm);
+  float* soup = reinterpret_cast<float*>(ws + o_soup);
+  float4* tnorm = reinterpret_cast<float4*>(ws + o_tnorm);
+  Rect* rect = reinterpret_cast<Rect*>(ws + o_rect);
   for (int m = 0; m < n_meshes; ++m) {
     BatchMesh& bm = b->meshes_h[m];
     bm.m.verts = meshes[m].verts;
     bm.m.n_verts = meshes[m].n_verts;
     bm.m.tris = meshes[m].tris;
     bm.m.n_tris = meshes[m].n_tris;
-    bm.m.tnorm = tnorm + 3 * tri_off[m];
+    bm.m.soup = soup + 9 * tri_off[m];
+    bm.m.tnorm = tnorm + tri_off[m];
     bm.m.status = D.status;
     bm.nimg = 0;
   }
@@ -1705,10 +1859,10 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     finish_image_geometry(im);
     im.ntx = (d.w + im.tw - 1) / im.tw;
     im.nty = (d.w + im.th - 1) / im.th;
-    im.verts = d.verts;
-    im.n_verts = d.n_verts;
-    im.tris = d.tris;
+    im.soup = bm.m.soup;
     im.tnorm = bm.m.tnorm;
+    im.rect = rect + rect_off[k];
+    bm.m.rect[bm.nimg] = rect + rect_off[k];
     bm.img[bm.nimg++] = k;
     im.n_tris = d.n_tris;
     im.tile_cnt = b->tile_arena + b->tile_start[k];
@@ -1717,11 +1871,18 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.max_layers = b->max_layers + k;
     im.offsets = b->offsets_arena + b->seg_start[k];
     im.status = D.status;
+    im.tile_region = b->region_arena + b->tile_start[k];
+    im.tile_stage = tstage + b->tile_start[k];
     im.tile_hits = thits + b->tile_start[k];
     im.tile_max = tmax + b->tile_start[k];
+    im.walk_list = D.walk_list;
+    im.walk_count = D.walk_count;
   }
   e = hipMemcpy(const_cast<uint32_t*>(D.tri_block_start), b->tri_block_start.data(),
                 sizeof(uint32_t) * (n_meshes + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(const_cast<uint32_t*>(D.bin_block_start), b->bin_block_start.data(),
+                  sizeof(uint32_t) * (n_img + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(const_cast<uint32_t*>(D.tile_start), b->tile_start.data(), sizeof(uint32_t) * (n_img + 1),
                   hipMemcpyHostToDevice);
@@ -1733,15 +1894,29 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   if (e == hipSuccess) e = hipStreamSynchronize(b->cs);
   if (e != hipSuccess) return bail(hip_fail(e, "batch tables"));
 
-  // tile lists sized like the single-mesh path; outputs and items sized by
-  // the first run
+  // tile lists sized like the single-mesh path; outputs sized by the first run
   uint64_t cap = 1024;
   for (int k = 0; k < n_img; ++k)
     cap += (uint64_t)std::ceil((double)meshes[b->img_mesh[k]].n_tris * std::min(g_list_ratio.load(), 8.0)) +
            4 * (uint64_t)(b->tile_start[k + 1] - b->tile_start[k]);
-  ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, 48);
+  ldni_status st = batch_grow(b, &b->lists, &b->list_cap, cap, sizeof(int2));
   if (st != LDNI_OK) return bail(st);
-  st = batch_grow(b, &b->items, &b->items_cap, 2 * b->total_tiles, 8);
+  // staging: a first guess (24 entries per triangle and image plus one per pixel),
+  // grown to the demand after the first run if it was short
+  {
+    uint64_t guess = 65536;
+    for (int k = 0; k < n_img; ++k)
+      guess += 24 * (uint64_t)meshes[b->img_mesh[k]].n_tris +
+               (uint64_t)meshes[b->img_mesh[k]].w * meshes[b->img_mesh[k]].w;
+    guess = std::min<uint64_t>(guess, kMaxStageEntries);
+    if (batch_grow(b, &b->stage, &b->stage_cap, guess, sizeof(uint64_t) + sizeof(uint32_t)) != LDNI_OK) {
+      b->stage = nullptr;
+      b->stage_cap = 0;
+    }
+  }
+  st = batch_grow(b, &b->items, &b->items_cap,
+                  (uint64_t)max_place_items_per_tile(b->small ? 256 : 1024, b->stage_layers) * b->total_tiles,
+                  16);
   if (st != LDNI_OK) return bail(st);
   st = ldni_batch_run(b, hip_stream);
   if (st != LDNI_OK) return bail(st);
@@ -1772,118 +1947,6 @@ void ldni_batch_free(ldni_batch* b) { batch_destroy(b); }
 ldni_status ldni_sample_batch(int32_t n_meshes, const ldni_mesh_desc* meshes, uint32_t axis_mask,
                               void* hip_stream, ldni_batch** out) {
   return ldni_batch_create(n_meshes, meshes, axis_mask, hip_stream, out);
-}
-
-ldni_status ldni_span_selftest(uint64_t seed, int64_t n_cases, uint64_t counts[4]) {
-  if (!counts || n_cases < 0) return fail(LDNI_ERR_INVALID_ARG, "NULL counts or negative case count");
-  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
-  auto next = [&]() {  // xorshift64*
-    x ^= x >> 12;
-    x ^= x << 25;
-    x ^= x >> 27;
-    return x * 0x2545F4914F6CDD1Dull;
-  };
-  auto uni = [&]() { return (double)(next() >> 11) * 0x1.0p-53; };
-  auto pick = [&](int n) { return (int)(next() % (uint64_t)n); };
-  uint64_t outside = 0, hits = 0, in_span = 0, inner_wrong = 0, in_inner = 0;
-  std::vector<float> cu, cv;
-  for (int64_t cs = 0; cs < n_cases; ++cs) {
-    // a grid: resolution, and per image axis a box that may sit far from 0
-    const int w = 1 + pick(pick(4) == 0 ? 16384 : 2048);
-    double lo[2], h[2];
-    for (int d = 0; d < 2; ++d) {
-      const int kind = pick(4);
-      const double size = kind == 0 ? 0.01 + uni() : 0.5 + 20.0 * uni();
-      lo[d] = kind == 1 ? -size / 2 : (kind == 2 ? 1000.0 * (uni() - 0.3) : -37.5 * uni());
-      if (pick(8) == 0) lo[d] = (pick(2) ? 1.0 : -1.0) * std::ldexp(1.0 + uni(), 10 + pick(8));
-      h[d] = ((lo[d] + size) - lo[d]) / (double)w;
-    }
-    cu.resize(w);
-    cv.resize(w);
-    for (int i = 0; i < w; ++i) {
-      cu[i] = (float)(lo[0] + ((double)i + 0.5) * h[0]);
-      cv[i] = (float)(lo[1] + ((double)i + 0.5) * h[1]);
-    }
-    Image im{};
-    im.w = w;
-    im.tw = im.th = 16;
-    im.lo_u = lo[0];
-    im.h_u = h[0];
-    im.lo_v = lo[1];
-    im.h_v = h[1];
-    finish_image_geometry(im);
-    // a triangle near a random pixel, in one of several regimes
-    const int pi = pick(w), pj = pick(w);
-    const double bu = cu[pi], bv = cv[pj];
-    const int mode = pick(8);
-    const double ext = mode == 4 ? 0.01 * uni() : (mode == 5 ? 150.0 * uni() : 0.2 + 12.0 * uni());
-    float P[3][2];
-    auto rnd = [&](int k) {
-      P[k][0] = (float)(bu + (uni() - 0.5) * ext * h[0]);
-      P[k][1] = (float)(bv + (uni() - 0.5) * ext * h[1]);
-    };
-    auto lattice = [&](int k) {  // exactly on a pixel centre
-      const int di = pi + pick(9) - 4, dj = pj + pick(9) - 4;
-      P[k][0] = cu[std::min(std::max(di, 0), w - 1)];
-      P[k][1] = cv[std::min(std::max(dj, 0), w - 1)];
-    };
-    for (int k = 0; k < 3; ++k) rnd(k);
-    if (mode == 1) {
-      for (int k = 0; k < 3; ++k) lattice(k);
-    } else if (mode == 2) {  // an edge (nearly) parallel to the rows
-      P[1][1] = pick(2) ? P[0][1] : std::nextafter(P[0][1], pick(2) ? INFINITY : -INFINITY);
-      if (pick(2)) P[1][1] = (float)((double)P[0][1] + (uni() - 0.5) * 1e-5 * h[1]);
-    } else if (mode == 3) {  // a sliver
-      const double t = uni();
-      P[2][0] = (float)((double)P[0][0] + t * ((double)P[1][0] - P[0][0]) + (uni() - 0.5) * 1e-4 * h[0]);
-      P[2][1] = (float)((double)P[0][1] + t * ((double)P[1][1] - P[0][1]) + (uni() - 0.5) * 1e-4 * h[1]);
-    } else if (mode == 6) {  // an edge through pixel centres
-      lattice(0);
-      lattice(1);
-    } else if (mode == 7) {  // an edge nearly parallel to the columns
-      P[1][0] = pick(2) ? P[0][0] : std::nextafter(P[0][0], INFINITY);
-    }
-    // candidate rectangle: centres with min <= c < max
-    const float umin = std::min({P[0][0], P[1][0], P[2][0]}), umax = std::max({P[0][0], P[1][0], P[2][0]});
-    const float vmin = std::min({P[0][1], P[1][1], P[2][1]}), vmax = std::max({P[0][1], P[1][1], P[2][1]});
-    const int i0 = (int)(std::lower_bound(cu.begin(), cu.end(), umin) - cu.begin());
-    const int i1 = (int)(std::lower_bound(cu.begin(), cu.end(), umax) - cu.begin());
-    const int j0 = (int)(std::lower_bound(cv.begin(), cv.end(), vmin) - cv.begin());
-    const int j1 = (int)(std::lower_bound(cv.begin(), cv.end(), vmax) - cv.begin());
-    if (i0 >= i1 || j0 >= j1 || i1 - i0 > 200) continue;
-    // a tile origin at or left of the rectangle (columns are tile-local)
-    const int tx0 = i0 - pick(std::min(i0, 40) + 1);
-    const SpanPrep sp = span_prep(P[0][0], P[0][1], P[1][0], P[1][1], P[2][0], P[2][1]);
-    for (int j = j0; j < j1 && j < j0 + 256; ++j) {
-      const float rv = cv[j];
-      const float tav = P[0][1] - rv, tbv = P[1][1] - rv, tcv = P[2][1] - rv;
-      float slo, shi, ilo, ihi;
-      span_bounds(sp, rv, slo, shi);
-      span_inner(sp, rv, ilo, ihi);
-      int first, ifirst;
-      const int len = span_columns(slo, shi, cu[tx0], im.inv_hf_u, im.span_slack, i0 - tx0, i1 - i0, first);
-      const int ilen = inner_columns(ilo, ihi, cu[tx0], im.inv_hf_u, im.span_slack, i0 - tx0, i1 - i0, ifirst);
-      in_span += (uint64_t)len;
-      in_inner += (uint64_t)ilen;
-      if (ilen > 0 && (ifirst < first || ifirst + ilen > first + len)) ++inner_wrong;  // inner within outer
-      for (int i = i0; i < i1; ++i) {
-        Edges e;
-        const int xl = i - tx0;
-        const bool in_in = xl >= ifirst && xl < ifirst + ilen;
-        if (!covered(P[0][0], P[1][0], P[2][0], tav, tbv, tcv, tav, tbv, tcv, cu[i], e)) {
-          if (in_in) ++inner_wrong;  // a certain hit that misses
-          continue;
-        }
-        ++hits;
-        if (xl < first || xl >= first + len) ++outside;
-      }
-    }
-  }
-  counts[0] = outside + inner_wrong;
-  counts[1] = hits;
-  counts[2] = in_span;
-  counts[3] = in_inner;
-  return LDNI_OK;
 }
 
 }  // extern "C"

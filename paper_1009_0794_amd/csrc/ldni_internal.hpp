@@ -7,22 +7,22 @@
 
 namespace ldni {
 
+// Pixel rectangle of a triangle on one image: columns [i0, i1), rows [j0, j1).
+// Only pixels whose centre satisfies min <= c < max in both image
+// coordinates can be hit, so this is exactly the candidate set.
+struct Rect {
+  int16_t i0, i1, j0, j1;
+};
+
 // Status bits raised by the device.
 enum : uint32_t {
   kStatusBadIndex = 1u,
   kStatusNonFinite = 2u,
   kStatusOverflow = 4u,
-  kStatusMismatch = 8u,  // a write pass disagrees with its count pass (or inputs changed)
+  kStatusMismatch = 8u,  // write pass found more hits than the count pass
   kStatusListFull = 16u, // batch: tile lists longer than their capacity
   kStatusOutFull = 32u,  // batch: samples beyond the output capacity
 };
-
-// Tile-list entry e of an image (one per (triangle, tile) pair):
-//   ent_uv[2e]     = (A_u, A_v, B_u, B_v)
-//   ent_uv[2e + 1] = (C_u, C_v, triangle id bits, rectangle bits)
-//   ent_z[e]       = (A_a, B_a, C_a, 0)
-// with the rectangle of candidate pixels in the tile as
-// x0 | y0 << 8 | (width - 1) << 16 | (height - 1) << 24 (tile-local pixels).
 
 // Everything one image (one axis of one mesh) needs on the device.
 struct Image {
@@ -37,29 +37,26 @@ struct Image {
   // centres included; nearer, the centres are compared one by one.
   double slack_u, slack_v;
   double lo_a;       // depth origin
-  float inv_hf_u;    // float32 1 / h_u (span columns)
-  float span_slack;  // pixels: the span columns' allowance for float32 rounding
   // tiling
   int32_t tw, th;    // tile shape in pixels
   int32_t tw_shift, th_shift;  // log2 of tw, th when a power of two, else -1
   int32_t ntx, nty;  // tiles along u and v
   // mesh (shared by the images of one mesh)
-  const float* verts;  // [V][3]
-  int64_t n_verts;
-  const int32_t* tris; // [T][3]
-  const float* tnorm;  // [T][3] unit face normals
+  const float* soup;   // [T][9] vertex coordinates A,B,C (x,y,z each)
+  const float4* tnorm;  // [T] unit face normals (x, y, z, 0): one 16-byte load each
+  const Rect* rect;    // [T] candidate rectangle on this image
   int64_t n_tris;
   // workspace
   uint32_t* tile_cnt;   // [n_tiles + 1] entries per tile -> exclusive offsets
   uint32_t* tile_cur;   // [n_tiles] scatter cursors
-  float4* ent_uv;       // tile-list entries grouped by tile (see above)
-  float4* ent_z;
-  uint64_t list_cap;    // capacity of the entry arrays (entries beyond it are dropped)
+  int2* tile_list;      // entries grouped by tile: (triangle id, its candidate
+                        // rectangle in the tile: x0 | y0 << 8 | (width - 1) << 16
+                        // | (height - 1) << 24, tile-local pixels)
+  uint64_t list_cap;    // capacity of tile_list (entries beyond it are dropped)
   uint32_t* counts;     // [w*w] samples per pixel
   uint32_t* max_layers; // [1] largest per-pixel count (atomic max per tile unless
                         // tile_max is given), or null when the pixel scan takes it
   uint32_t* tile_max;   // [n_tiles] largest count of each tile, or null
-  uint32_t* tile_hits;  // [n_tiles] samples of each tile (count pass)
   // outputs
   uint32_t* offsets;  // [w*w + 1]
   float* depth;       // [n]
@@ -67,7 +64,26 @@ struct Image {
   uint32_t* normal_rgb8;  // [n] 8-bit normal codes, or null for float normals
   int32_t* tri;       // [n]
   uint32_t* status;   // shared status word
+  // Hits of the sampling pass, grouped by tile.  With stage_key null every
+  // tile with hits is walked again by the place pass.
+  uint64_t* stage_key;               // (depth key, triangle) of each hit
+  uint32_t* stage_qs;                // tile pixel | (slot within the pixel << 10)
+  uint64_t stage_cap;                // entries in the buffer (below 2^32 - 1)
+  uint32_t stage_layers;             // a tile's region holds at most this many entries per pixel
+  // [n_tiles + 1] the tile's candidates, each triangle's rounded up to whole
+  // 4-entry groups (counted by setup); the region scan turns them into the
+  // tile's staging region [tile_region[t], tile_region[t + 1]) (capped at
+  // stage_layers entries per tile pixel, saturating at 2^32 - 1)
+  uint32_t* tile_region;
+  uint32_t* tile_stage;              // [n_tiles] first entry of the tile's hits (a multiple
+                                     // of 4; regions are whole 4-entry groups), or kNoStage
+  uint32_t* tile_hits;               // [n_tiles] hits of the tile
+  uint32_t* walk_list;               // set-wide tile numbers the write pass walks again
+  uint32_t* walk_count;              // entries of walk_list (shared by the set)
 };
+
+// tile_stage value of a tile whose hits did not fit its staging region
+constexpr uint32_t kNoStage = 0xffffffffu;
 
 constexpr int kMaxImages = 3;
 
@@ -77,45 +93,52 @@ struct ImageSet {
   Image img[kMaxImages];
   int32_t n;
   uint32_t tile_start[kMaxImages + 1];  // prefix of tile counts
-  // write-pass plan written by the count pass: items per tile, [0, n_tiles)
-  // for tiles of two or more items, [n_tiles, 2 n_tiles) for tiles of one,
-  // scanned in place into item positions
+  // place-pass plan written by the sampling pass (null: none): items per
+  // tile, [0, n_tiles) for tiles of two or more items, [n_tiles, 2 n_tiles)
+  // for tiles of one, scanned in place into item positions
   uint32_t* plan;
+  int32_t place_cap;  // stage capacity of the place pass
 };
 
-// Mesh-level setup: per triangle gather, validate, face normal; the tile
-// counts (setup) or entries (scatter) of every image of the set.
+// Mesh-level setup: per triangle gather, validate, face normal, candidate
+// rectangles for every image in the set.
 struct MeshSetup {
   const float* verts;
   int64_t n_verts;
   const int32_t* tris;
   int64_t n_tris;
-  float* tnorm;
+  float* soup;
+  float4* tnorm;  // [T] unit face normals (x, y, z, 0)
+  Rect* rect[kMaxImages];
   uint32_t* status;
 };
 
-// Fills the derived fields of an image (inverse steps, centre slack, span
-// conversion, tile shifts) from w, the tile shape and lo/h of both image axes.
+// Fills the derived fields of an image (inverse steps, centre slack, tile
+// shifts) from w, the tile shape and lo/h of both image axes.
 void finish_image_geometry(Image& im);
 
 // ---- launchers (ldni_kernels.hip) ----
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
-// per triangle: gather, validate, normal, and the count of its tiles on
-// every image (tile_cnt, cleared before)
+// per triangle: gather, validate, normal, candidate rectangles, and the
+// count of its tiles on every image (tile_cnt, cleared before)
 hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s);
-// per triangle: its entries in the tile lists of every image
-hipError_t launch_scatter(const MeshSetup& m, const ImageSet& set, hipStream_t s);
-// Count pass: per-pixel counts, samples per tile, the write plan.
-hipError_t launch_count(const ImageSet& set, hipStream_t s);
-// Samples a write item holds in LDS (a tile's pixels are written in runs of
-// at most this many samples).
-int write_cap(int tile_pix);
-// Scans the write plan in place (its total is at plan[2 n_tiles]).
-hipError_t launch_plan_scan(const ImageSet& set, void* scratch, uint32_t* status, hipStream_t s);
-// Item records (8 bytes each) in launch order, from the scanned plan.
-hipError_t launch_plan_items(const ImageSet& set, void* items, hipStream_t s);
-// Write pass: one workgroup per item.
-hipError_t launch_write(const ImageSet& set, const void* items, uint32_t n_items, hipStream_t s);
+hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
+// Sampling pass: per-pixel counts, and every hit staged by tile (see Image).
+hipError_t launch_sample(const ImageSet& set, hipStream_t s);
+// Work items of the place pass: scans the plan the sampling pass wrote and
+// writes the item records (16 bytes each, at most
+// max_place_items_per_tile(tw * th, stage_layers) per tile) in launch order.
+int max_place_items_per_tile(int tile_pix, uint32_t stage_layers);
+// Entries per pixel a tile may reserve in the staging buffer: the deepest
+// pixel seen, rounded up to a power of two, within [64, 1024].
+uint32_t stage_layers_for(uint32_t max_layers_seen);
+int place_stage_cap(int tile_pix);
+hipError_t launch_plan_items(const ImageSet& set, void* items, void* scratch, uint32_t* status,
+                             hipStream_t s);
+// Place pass: n_items workgroups place the staged tiles; the n_walk tiles of
+// walk_list are then walked again (persistent, counter[0]).
+hipError_t launch_place(const ImageSet& set, const void* items, uint32_t n_items, uint32_t* counter,
+                        uint32_t n_walk, hipStream_t s);
 
 // ---- batched sampling: many meshes, each with its own w and tile shape ----
 struct BatchMesh {
@@ -129,7 +152,8 @@ struct BatchDevice {
   int32_t n_meshes;
   Image* images;
   int32_t n_images;
-  const uint32_t* tri_block_start;  // [n_meshes+1] triangle workgroups per mesh (prefix)
+  const uint32_t* tri_block_start;  // [n_meshes+1] setup workgroups per mesh (prefix)
+  const uint32_t* bin_block_start;  // [n_images+1] binning workgroups per image (prefix)
   const uint32_t* tile_start;       // [n_images+1] tiles per image (prefix)
   const uint32_t* tile_max;         // [total tiles] largest count of each tile
   const uint64_t* seg_start;        // [n_images+1] first slot of each image in counts/offsets
@@ -142,21 +166,27 @@ struct BatchDevice {
   uint64_t sample_cap;
   uint32_t* tile_total;             // entries of all tile lists (end of the tile scan)
   uint64_t list_cap;
-  uint32_t* host_out;               // pinned: [0] status, [1] list entries, [2] write items,
-                                    // then per image (n, base lo, base hi, max layers)
-  uint32_t* plan;                   // [2 * total tiles + 1] write plan of the batch
-  void* items;                      // write items
-  uint64_t items_cap;
+  uint32_t* host_out;               // pinned: [0] status, [1] list entries, then per image
+                                    // (n, base lo, base hi, max layers), then staging
+                                    // demand (lo, hi) and tiles walked again
+  // staged sampling (see Image): place plan over all tiles of the batch,
+  // item records, tiles walked again
+  uint32_t* plan;                   // [2 * total tiles + 1]
+  void* items;                      // place items
+  uint32_t* walk_list;
+  uint32_t* walk_count;
+  const uint32_t* region_total;     // staging entries the regions of the batch ask for
+  int32_t place_cap;
 };
 
 hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s);
 hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t blocks, hipStream_t s);
 // small: every image's tiles have at most 256 pixels.  n_tiles: tiles of
-// the batch.  Count pass (counts, tile samples, write plan).
-hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s);
-// After the pixel scan and the placement of the images: the write plan
-// scanned, its items, the write pass.
-hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
+// the batch.  Sampling pass (counts, staged hits, place plan), then after the
+// pixel scan and the placement of the images: the place items, the place
+// pass and the walk of the tiles whose hits were not staged.
+hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s);
+hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
                               hipStream_t s);
 // Segmented exclusive scan of the per-image counts (segments of w*w+1 slots,
 // the last slot of each zero) into per-image offsets starting at 0, with the
@@ -288,4 +318,11 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scrat
 hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
                                 void* scratch, uint32_t* status, hipStream_t s,
                                 uint32_t* const* max_out = nullptr);
+// The tile scan: entry counts -> list offsets (as launch_scan), and in the
+// same launches candidate counts -> staging regions, each tile's count
+// capped at region_cap and the prefix saturating at 2^32 - 1 (in place
+// allowed; n + 1 slots each).  scratch: scan_scratch_bytes(n, 2).
+hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n, uint32_t region_cap,
+                            void* scratch, uint32_t* status, hipStream_t s);
+
 }  // namespace ldni

@@ -2,22 +2,23 @@
 //
 // Pipeline per call (every kernel covers all requested axes in one launch):
 //   setup      triangle-parallel: gather and validate vertices, float64 face
-//              normal, and the count of screen tiles each triangle's candidate
-//              rectangle meets on every image
-//   tile scan  entry counts -> tile-list offsets
-//   scatter    triangle-parallel: one entry per (triangle, tile) with the
-//              triangle's image coordinates, id and rectangle in the tile
-//   count      one workgroup per tile: every candidate row of every entry is
-//              clipped to a conservative column span, each candidate pixel
-//              centre in it gets the exact coverage test; LDS per-pixel
-//              counters -> counts[w*w], samples per tile, the write plan
+//              normal, candidate pixel rectangle on each image, and the count
+//              of entries and candidate pixels of every screen tile it meets
+//   tile scan  entry counts -> tile-list offsets; candidate counts -> each
+//              tile's region of the staging buffer
+//   bin_scatter  triangle ids into per-tile lists
+//   sample     one workgroup per tile: exact coverage test of every candidate
+//              (triangle, pixel centre); the hits' float64 depth, (depth,
+//              triangle) key and arrival slot in their pixel are staged in the
+//              tile's region, per-pixel counts -> counts[w*w]
 //   scan       counts -> offsets[w*w+1]
-//   write      one workgroup per item (a tile's pixels in runs whose samples
-//              fit in LDS): the same walk over the run's rows, the hit's
-//              float64 depth, its (depth, triangle) key placed at its pixel's
-//              slot in LDS, ranked within the pixel and stored as depth,
-//              normal and triangle id at the final offsets; a pixel deeper
-//              than LDS is stored unsorted and sorted in place
+//   plan       place items (a tile's pixels split into runs that fit in LDS)
+//   place      one workgroup per item: the staged keys of a run are put at
+//              their pixel slots in LDS, ranked within the pixel and stored as
+//              depth, normal and triangle id; a pixel deeper than LDS is
+//              stored unsorted and sorted in place
+//   walk       tiles whose hits did not fit their region: walked again and
+//              written directly
 // Nothing here is a dense contraction, so there is no MFMA: the work is
 // integer/FP64 ALU plus HBM traffic.
 #pragma clang fp contract(off)
@@ -25,7 +26,6 @@
 #include <type_traits>
 
 #include "ldni_internal.hpp"
-#include "ldni_span.hpp"
 
 namespace ldni {
 namespace {
@@ -36,13 +36,10 @@ constexpr int kMaxTilePix = 1024;    // tw * th
 constexpr int kMaxTileW = 256;
 constexpr int kMaxTileH = 64;
 // Two builds of the tile kernels: tiles of up to 256 pixels (less LDS, more
-// workgroups per CU) and of up to 1024 pixels.
+// workgroups per CU) and of up to 1024 pixels; the stage holds the (depth,
+// triangle) keys of one run of pixels.
 constexpr int kSmallTilePix = 256;
-// Samples of one write run held in LDS.
-#ifndef LDNI_WRITE_CAP
-#define LDNI_WRITE_CAP 1536
-#endif
-constexpr int kWriteCap = LDNI_WRITE_CAP;
+__host__ __device__ constexpr int stage_cap(int tile_pix) { return tile_pix <= 256 ? 2048 : 4096; }
 
 // ---------------------------------------------------------------------------
 // pixel centres and candidate rectangles
@@ -67,6 +64,21 @@ __device__ int first_centre_at_or_above(double lo, double h, double inv_h, doubl
   while (i > 0 && pixel_centre(lo, h, i - 1) >= x) --i;
   while (i < w && pixel_centre(lo, h, i) < x) ++i;
   return i;
+}
+
+// ---------------------------------------------------------------------------
+// exact coverage
+// ---------------------------------------------------------------------------
+// Orientation of the ray with respect to the directed edge P->Q, both
+// endpoints already translated into the ray frame.  The two products of
+// float32 values are exact in float64, so the sign of the difference is exact.
+// A ray exactly on the edge line is decided as if displaced by (+eps, +eps^2).
+__device__ __forceinline__ int orient(float pu, float pv, float qu, float qv, double& e) {
+  e = (double)pu * (double)qv - (double)pv * (double)qu;
+  int s = (e > 0.0) - (e < 0.0);
+  if (s == 0) s = (pv > qv) - (pv < qv);
+  if (s == 0) s = (qu > pu) - (qu < pu);
+  return s;
 }
 
 // Approximate normal sampling (Sec. 3): each component c of the unit normal
@@ -168,27 +180,25 @@ __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
   return k;
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+template <bool kScatter>
+__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r);
 
-// ---------------------------------------------------------------------------
-// setup and scatter
-// ---------------------------------------------------------------------------
-// The triangle's vertices (A, B, C as x, y, z each), zero for an invalid
-// triangle (a point: never hit).  kSetup raises the status bits of invalid
-// indices and non-finite coordinates; the scatter, which runs after it on
-// the same inputs, only needs the same vertices.
-template <bool kSetup>
-__device__ __forceinline__ void load_triangle(const MeshSetup& m, int64_t t, bool live, float P[9]) {
+// kCount: also count the triangle's tiles on every image (all 64 lanes of
+// every wave must then call this; lanes past the mesh count nothing).
+template <bool kCount, class ImageAt>
+__device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
+  const bool live = t < m.n_tris;
+  if (!kCount && !live) return;
   int32_t ia = 0, ib = 0, ic = 0;
   if (live) {
     ia = m.tris[3 * t];
     ib = m.tris[3 * t + 1];
     ic = m.tris[3 * t + 2];
   }
+  float P[9];
   const bool idx_ok = live && ia >= 0 && ia < m.n_verts && ib >= 0 && ib < m.n_verts && ic >= 0 &&
                       ic < m.n_verts;
   bool ok = idx_ok;
@@ -203,35 +213,86 @@ __device__ __forceinline__ void load_triangle(const MeshSetup& m, int64_t t, boo
 #pragma unroll
     for (int c = 0; c < 9; ++c) fin &= isfinite(P[c]);
     if (!fin) {
-      if (kSetup) atomicOr(m.status, kStatusNonFinite);
+      atomicOr(m.status, kStatusNonFinite);
       ok = false;
     }
-  } else if (live && kSetup) {
+  } else if (live) {
     atomicOr(m.status, kStatusBadIndex);
   }
   if (!ok) {
+    // an invalid triangle becomes a point: never hit, and the call fails
 #pragma unroll
     for (int c = 0; c < 9; ++c) P[c] = 0.0f;
   }
+  if (live) {
+    float* soup = m.soup + 9 * t;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) soup[c] = P[c];
+  }
+
+  // unit face normal (B-A)x(C-A) in float64
+  const double e1x = (double)P[3] - (double)P[0], e1y = (double)P[4] - (double)P[1],
+               e1z = (double)P[5] - (double)P[2];
+  const double e2x = (double)P[6] - (double)P[0], e2y = (double)P[7] - (double)P[1],
+               e2z = (double)P[8] - (double)P[2];
+  const double nx = e1y * e2z - e1z * e2y;
+  const double ny = e1z * e2x - e1x * e2z;
+  const double nz = e1x * e2y - e1y * e2x;
+  const double len = sqrt((nx * nx + ny * ny) + nz * nz);
+  if (live) {
+    float4 tn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (len > 0.0) {
+      tn.x = (float)(nx / len);
+      tn.y = (float)(ny / len);
+      tn.z = (float)(nz / len);
+    }
+    m.tnorm[t] = tn;
+  }
+
+  for (int k = 0; k < nimg; ++k) {
+    const Image& im = image_at(k);
+    const float umin = fminf(fminf(P[im.u], P[3 + im.u]), P[6 + im.u]);
+    const float umax = fmaxf(fmaxf(P[im.u], P[3 + im.u]), P[6 + im.u]);
+    const float vmin = fminf(fminf(P[im.v], P[3 + im.v]), P[6 + im.v]);
+    const float vmax = fmaxf(fmaxf(P[im.v], P[3 + im.v]), P[6 + im.v]);
+    Rect r;
+    const int i0 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.slack_u, im.w, umin);
+    const int i1 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.slack_u, im.w, umax);
+    const int j0 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.slack_v, im.w, vmin);
+    const int j1 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.slack_v, im.w, vmax);
+    if (i0 < i1 && j0 < j1) {
+      r.i0 = (int16_t)i0; r.i1 = (int16_t)i1; r.j0 = (int16_t)j0; r.j1 = (int16_t)j1;
+    } else {
+      r.i0 = r.i1 = r.j0 = r.j1 = 0;
+    }
+    if (live) m.rect[k][t] = r;
+    if (kCount) bin_rect<false>(im, t, live, r);
+  }
 }
 
-// Candidate rectangle of the triangle on an image: columns [i0, i1), rows
-// [j0, j1), the pixels whose centre satisfies min <= c < max in both image
-// coordinates (empty when i0 >= i1 or j0 >= j1).  The images of a call, and
-// of one mesh in a batch, share the box and w.
-struct Rect {
-  int i0, i1, j0, j1;
-};
+__global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set) {
+  setup_triangle<true>(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
+                       (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
 
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
 // Every (triangle, tile) pair of a wave is counted (or placed) with one
 // atomic per distinct tile of the wave: lanes that share the tile are peeled
-// off together and ranked by their lane order.  Mesh order is spatially
+// off together and ranked by their lane order.  Counting also adds up the
+// tile's candidate pixels, which size its staging region.  Mesh order is spatially
 // coherent for most meshes, so a wave typically touches a handful of tiles.
-// The scatter writes each pair's entry.  All 64 lanes of every wave must
-// call this (lanes without a triangle have no tiles).
+// All 64 lanes of every wave must call this (t beyond the mesh = no tiles).
 template <bool kScatter>
-__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r, const float P[9]) {
+__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
   const int lane = threadIdx.x & 63;
+  // counting: per wave, the candidate sums of its group leaders (zero
+  // between uses)
+  __shared__ uint32_t s_acc[kBlock];
+  uint32_t* acc = s_acc + (threadIdx.x & ~63);
+  if (!kScatter) acc[lane] = 0u;
+  // tile of a pixel column / row (shifts for the usual power-of-two shapes)
   auto tile_x = [&](int i) { return im.tw_shift >= 0 ? i >> im.tw_shift : i / im.tw; };
   auto tile_y = [&](int j) { return im.th_shift >= 0 ? j >> im.th_shift : j / im.th; };
   int tx0 = 0, ty0 = 0, nx = 1, n = 0;
@@ -242,18 +303,11 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r, c
     n = nx * (tile_y(r.j1 - 1) - ty0 + 1);
   }
   const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  float4 uv0 = make_float4(0.f, 0.f, 0.f, 0.f), zz = uv0;
-  float cu = 0.f, cv = 0.f;
-  if (kScatter) {
-    uv0 = make_float4(P[im.u], P[im.v], P[3 + im.u], P[3 + im.v]);
-    cu = P[6 + im.u];
-    cv = P[6 + im.v];
-    zz = make_float4(P[im.a], P[3 + im.a], P[6 + im.a], 0.f);
-  }
   int qx = 0, qy = 0;  // tile q of the triangle, q = qy * nx + qx
   for (int q = 0; __ballot(q < n) != 0; ++q) {  // while any lane has tiles left
     int key = -1;
-    uint32_t geom = 0;  // scatter: the rectangle in the tile
+    uint32_t cand = 0;  // counting: candidates in the tile, whole 4-entry groups
+    uint32_t geom = 0;  // scatter: the rectangle in the tile (tile-list entry layout)
     if (q < n) {
       const int tx = tx0 + qx, ty = ty0 + qy;
       if (++qx == nx) {
@@ -261,18 +315,23 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r, c
         ++qy;
       }
       key = ty * im.ntx + tx;
-      if (kScatter) {
-        const int x0 = tx * im.tw, y0 = ty * im.th;
-        const int lx0 = max(r.i0, x0) - x0, lx1 = min(r.i1, x0 + im.tw) - x0;
-        const int ly0 = max(r.j0, y0) - y0, ly1 = min(r.j1, y0 + im.th) - y0;
+      const int x0 = tx * im.tw, y0 = ty * im.th;
+      const int lx0 = max((int)r.i0, x0) - x0, lx1 = min((int)r.i1, x0 + im.tw) - x0;
+      const int ly0 = max((int)r.j0, y0) - y0, ly1 = min((int)r.j1, y0 + im.th) - y0;
+      if (kScatter)
         geom = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 - 1) << 16) |
                ((uint32_t)(ly1 - ly0 - 1) << 24);
-      }
+      else
+        cand = ((uint32_t)((lx1 - lx0) * (ly1 - ly0)) + 3u) & ~3u;
     }
+    // Peel the wave's distinct tiles into groups with a leader each; the
+    // leaders then issue their atomics together (one instruction), and the
+    // scatter's return the group's base, which every lane reads from its
+    // leader.
     const uint32_t list_at = (kScatter && key >= 0) ? im.tile_cnt[key] : 0u;
     uint64_t pending = __ballot(key >= 0);
     int my_leader = 0;
-    uint32_t my_rank = 0, group = 0;
+    uint32_t my_rank = 0, group = 0, lead_base = 0;
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
       const int k = __builtin_amdgcn_readlane(key, leader);  // leader is wave-uniform
@@ -284,129 +343,218 @@ __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r, c
       }
       pending &= ~same;
     }
+    if (kScatter && key >= 0 && my_leader == lane) lead_base = atomicAdd(&im.tile_cur[key], group);
     if (!kScatter) {
-      if (key >= 0 && my_leader == lane) atomicAdd(&im.tile_cnt[key], group);
-    } else {
-      uint32_t lead_base = 0;
-      if (key >= 0 && my_leader == lane) lead_base = atomicAdd(&im.tile_cur[key], group);
+      // Each lane adds its candidates to its leader's slot; the leaders then
+      // add their group's entries and candidates to the tile.
+      if (key >= 0) atomicAdd(&acc[my_leader], cand);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (key >= 0 && my_leader == lane) {
+        const uint32_t c = acc[lane];
+        acc[lane] = 0u;
+        atomicAdd(&im.tile_cnt[key], group);
+        atomicAdd(&im.tile_region[key], c);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (kScatter) {
       const uint32_t base = (uint32_t)__shfl((int)lead_base, my_leader, 64);
       if (key >= 0) {
         const uint64_t pos = (uint64_t)list_at + base + my_rank;
-        if (pos < im.list_cap) {
-          im.ent_uv[2 * pos] = uv0;
-          im.ent_uv[2 * pos + 1] = make_float4(cu, cv, __int_as_float((int32_t)t), __uint_as_float(geom));
-          im.ent_z[pos] = zz;
-        }
+        if (pos < im.list_cap) im.tile_list[pos] = make_int2((int32_t)t, (int32_t)geom);
       }
     }
   }
 }
 
-// kSetup: gather, validate, normal, tile counts; else the entries.  All 64
-// lanes of every wave must call this (t beyond the mesh: no tiles).
-template <bool kSetup, class ImageAt>
-__device__ void triangle_pass(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
-  const bool live = t < m.n_tris;
-  float P[9];
-  load_triangle<kSetup>(m, t, live, P);
-  if (kSetup && live) {
-    // unit face normal (B-A)x(C-A) in float64
-    const double e1x = (double)P[3] - (double)P[0], e1y = (double)P[4] - (double)P[1],
-                 e1z = (double)P[5] - (double)P[2];
-    const double e2x = (double)P[6] - (double)P[0], e2y = (double)P[7] - (double)P[1],
-                 e2z = (double)P[8] - (double)P[2];
-    const double nx = e1y * e2z - e1z * e2y;
-    const double ny = e1z * e2x - e1x * e2z;
-    const double nz = e1x * e2y - e1y * e2x;
-    const double len = sqrt((nx * nx + ny * ny) + nz * nz);
-    float* tn = m.tnorm + 3 * t;
-    if (len > 0.0) {
-      tn[0] = (float)(nx / len);
-      tn[1] = (float)(ny / len);
-      tn[2] = (float)(nz / len);
-    } else {
-      tn[0] = tn[1] = tn[2] = 0.0f;
-    }
-  }
-  // The images of one mesh share its box and w, so a world axis has the
-  // same pixel centres in both images that use it: the first centre at or
-  // above the triangle's min and max on each world axis serves both.
-  int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
-  if (live) {
-    uint32_t need = 0;
-    for (int k = 0; k < nimg; ++k) need |= (1u << image_at(k).u) | (1u << image_at(k).v);
-    for (int d = 0; d < 3; ++d) {
-      if (!((need >> d) & 1u)) continue;
-      // an image that images axis d, with its centre formula for it
-      int k = 0;
-      while (image_at(k).u != d && image_at(k).v != d) ++k;
-      const Image& im = image_at(k);
-      const bool as_u = im.u == d;
-      const double lo = as_u ? im.lo_u : im.lo_v, h = as_u ? im.h_u : im.h_v;
-      const double inv_h = as_u ? im.inv_h_u : im.inv_h_v, slack = as_u ? im.slack_u : im.slack_v;
-      const float mn = fminf(fminf(P[d], P[3 + d]), P[6 + d]);
-      const float mx = fmaxf(fmaxf(P[d], P[3 + d]), P[6 + d]);
-      lo_c[d] = first_centre_at_or_above(lo, h, inv_h, slack, im.w, mn);
-      hi_c[d] = first_centre_at_or_above(lo, h, inv_h, slack, im.w, mx);
-    }
-  }
-  for (int k = 0; k < nimg; ++k) {
-    const Image& im = image_at(k);
-    const Rect r{lo_c[im.u], hi_c[im.u], lo_c[im.v], hi_c[im.v]};
-    bin_rect<!kSetup>(im, t, live, r, P);
-  }
+template <bool kScatter>
+__device__ void bin_triangles(const Image& im, int64_t t) {
+  const bool live = t < im.n_tris;
+  Rect r{0, 0, 0, 0};
+  if (live) r = im.rect[t];
+  bin_rect<kScatter>(im, t, live, r);
 }
 
-__global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set) {
-  triangle_pass<true>(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
-                      (int64_t)blockIdx.x * kBlock + threadIdx.x);
-}
-
-__global__ void __launch_bounds__(kBlock) scatter_kernel(MeshSetup m, ImageSet set) {
-  triangle_pass<false>(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
-                       (int64_t)blockIdx.x * kBlock + threadIdx.x);
+template <bool kScatter>
+__global__ void __launch_bounds__(kBlock) bin_kernel(ImageSet set) {
+  bin_triangles<kScatter>(set.img[blockIdx.y], (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
-// the walk: candidate pixels of a tile's entries
+// candidate enumeration inside one tile
 // ---------------------------------------------------------------------------
-// Every wave walks its own share of the tile's entries, 64 at a time (one per
-// lane), with no workgroup barrier.  Each lane clips every row of its entry
-// (within a group of at most kRowGroup rows) to the conservative span of the
-// triangle on that row (see ldni_span.hpp) and caches the spans; a wave scan
-// of the entries' candidate counts places them, and the candidates are then
-// written as packed records (entry | row << 6 | column << 12) to a per-wave
-// list, kCandCap at a time.  The lanes test the listed candidates one each
-// per step, so the loop that runs the exact test has no divergent stepping.
-// Rows of a tile walked in one sweep over its entries, and candidate records
-// of a wave per round: the write pass, which also holds its run's samples in
-// LDS, takes smaller ones (more workgroups fit on a CU).
-template <bool kDepth> struct WalkSize {
-  static constexpr int kRowGroup = kDepth ? 8 : 16;
-  static constexpr int kCandCap = kDepth ? 256 : 512;
-};
+// A chunk of up to kBlock tile-list entries is loaded into LDS with the
+// prefix sum of their candidate counts (pixels of the triangle's rectangle
+// inside the tile rows being processed).  Each thread then walks a contiguous
+// run of kRun flattened candidates: one binary search finds the first owner,
+// after which pixels advance incrementally along the rows of the rectangle.
+constexpr int kRun = 16;
 
 template <bool kDepth>
-struct WaveWalk {
-  static constexpr int kRowGroup = WalkSize<kDepth>::kRowGroup;
-  static constexpr int kCandCap = WalkSize<kDepth>::kCandCap;
-  float4 ab[64];                // A_u, A_v, B_u, B_v
-  float2 c[64];                 // C_u, C_v
-  float4 z[kDepth ? 64 : 1];    // A_a, B_a, C_a, triangle id bits
-  uint16_t span[64][kRowGroup]; // per row of the entry: first | last << 8 (columns; first > last: none)
-  uint32_t cand[kCandCap];      // candidate records of the current round
-};
-
-template <bool kDepth>
-struct WalkLds {
-  WaveWalk<kDepth> w[kWaves];
-  uint32_t grab;  // entries taken so far (LDS counter shared by the waves)
+struct ChunkLds {
+  float4 ab[kBlock];                   // au, av, bu, bv
+  float2 c[kBlock];                    // cu, cv
+  float4 z[kDepth ? kBlock : 1];       // az, bz, cz, triangle id (bits)
+  int32_t geom[kBlock];                // px0 | py0 << 8 | (width - 1) << 16
+  int32_t start[kBlock + 1];           // exclusive prefix of candidates, start[m] = total
+  int32_t wave_tmp[kWaves];
 };
 
 struct TileGeom {
   int x0, y0, cw, ch;  // tile origin and extent in pixels
   int tile;            // tile index within its image
 };
+
+// Exact coverage of the ray (ru, rv) by the triangle whose vertices are
+// (au,av), (bu,bv), (cu,cv); tav/tbv/tcv are the v-translations of the row.
+// Each edge function is one exact product plus one fused multiply-add: since
+// both products of float32 values are exact in float64, the FMA returns the
+// same correctly rounded difference as two products and a subtraction.
+struct Edges {
+  double ab, bc, ca;
+};
+
+__device__ __forceinline__ bool covered(float au, float bu, float cu, float tav, float tbv,
+                                        float tcv, float ru, Edges& e) {
+  const float tau = au - ru, tbu = bu - ru, tcu = cu - ru;
+  const double dau = tau, dbu = tbu, dcu = tcu, dav = tav, dbv = tbv, dcv = tcv;
+  e.ab = fma(dau, dbv, -(dav * dbu));
+  e.bc = fma(dbu, dcv, -(dbv * dcu));
+  e.ca = fma(dcu, dav, -(dcv * dau));
+  const double mn = fmin(fmin(e.ab, e.bc), e.ca), mx = fmax(fmax(e.ab, e.bc), e.ca);
+  if ((mn > 0.0) | (mx < 0.0)) return true;   // one strict sign
+  if ((mn < 0.0) & (mx > 0.0)) return false;  // two strictly opposite signs: no tie can help
+  // the ray meets an edge line: decide as if moved to (+eps, +eps^2)
+  double tmp;
+  const int s0 = orient(tau, tav, tbu, tbv, tmp);
+  const int s1 = orient(tbu, tbv, tcu, tcv, tmp);
+  const int s2 = orient(tcu, tcv, tau, tav, tmp);
+  return (s0 != 0) & (s0 == s1) & (s1 == s2);
+}
+
+// Candidate rectangle of a tile-list entry in tile pixels, rows [y0, y1)
+// and columns [x0, x0 + width).  An entry that is not a triangle of the mesh
+// or does not fit the tile (the lists were not written as counted) raises the
+// mismatch bit and has no candidates (y1 = y0).
+struct EntryRect {
+  int x0, y0, width, y1;
+};
+__device__ __forceinline__ EntryRect entry_rect(const Image& im, const TileGeom& g, int2 ent) {
+  const uint32_t gm = (uint32_t)ent.y;
+  EntryRect r;
+  r.x0 = gm & 255;
+  r.y0 = (gm >> 8) & 255;
+  r.width = ((gm >> 16) & 255) + 1;
+  r.y1 = r.y0 + (int)(gm >> 24) + 1;
+  if ((uint32_t)ent.x >= (uint64_t)im.n_tris || r.x0 + r.width > g.cw || r.y1 > g.ch) {
+    atomicOr(im.status, kStatusMismatch);
+    r.x0 = 0;
+    r.y0 = 0;
+    r.width = 1;
+    r.y1 = 0;
+  }
+  return r;
+}
+
+struct NoChunkHook {
+  __device__ void operator()(bool, int) const {}
+};
+
+// Calls on_hit(k, px, py, edges) for every covered candidate of rows
+// [r0, r1) of the tile; k indexes the chunk arrays in L.  Thread 0 calls
+// on_chunk(first, candidates) once the candidate count of a chunk is known,
+// before the barrier that precedes its walk (first: the tile's first chunk).
+template <bool kDepth, class OnHit, class OnChunk = NoChunkHook>
+__device__ void tile_candidates(const Image& im, const TileGeom& g, int r0, int r1,
+                                ChunkLds<kDepth>& L, const float* s_cu, const float* s_cv,
+                                OnHit&& on_hit, OnChunk&& on_chunk = OnChunk()) {
+  const uint64_t cap = im.list_cap;
+  const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[g.tile], cap);
+  const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[g.tile + 1], cap);
+  for (uint32_t base = e_begin; base < e_end; base += kBlock) {
+    const int m = (int)min((uint32_t)kBlock, e_end - base);
+    const int k = threadIdx.x;
+    int nc = 0;
+    if (k < m) {
+      const int2 ent = im.tile_list[base + k];
+      const int32_t t = ent.x;
+      const EntryRect r = entry_rect(im, g, ent);
+      const int py0 = max(r.y0, r0), py1 = min(r.y1, r1);
+      const int width = r.width;
+      if (py1 > py0) nc = width * (py1 - py0);
+      L.geom[k] = r.x0 | (max(py0, 0) << 8) | ((width - 1) << 16);
+      if (nc > 0) {  // vertex data only for entries with candidates in these rows
+        const float* s = im.soup + 9 * (int64_t)t;
+        L.ab[k] = make_float4(s[im.u], s[im.v], s[3 + im.u], s[3 + im.v]);
+        L.c[k] = make_float2(s[6 + im.u], s[6 + im.v]);
+        if constexpr (kDepth) L.z[k] = make_float4(s[im.a], s[3 + im.a], s[6 + im.a], __int_as_float(t));
+      }
+    }
+    int total;
+    const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
+    if (k < m) L.start[k] = excl;
+    if (k == 0) {
+      L.start[m] = total;
+      on_chunk(base == e_begin, total);
+    }
+    __syncthreads();
+    for (int wb = 0; wb < total; wb += kBlock * kRun) {
+      int c = wb + threadIdx.x * kRun;
+      const int cend = min(c + kRun, total);
+      if (c < cend) {
+        // owner of c: the last entry whose start is <= c
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.start[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        int e = lo;
+        int gm = L.geom[e];
+        int width = ((gm >> 16) & 255) + 1;
+        int local = c - L.start[e];
+        int row = local / width;
+        int col = local - row * width;
+        int kend = L.start[e + 1];
+        float4 ab = L.ab[e];
+        float2 cc = L.c[e];
+        int px0 = gm & 255, py0 = (gm >> 8) & 255;
+        float rv = s_cv[py0 + row];
+        float tav = ab.y - rv, tbv = ab.w - rv, tcv = cc.y - rv;
+        for (; c < cend; ++c) {
+          if (c == kend) {  // next entry that has candidates
+            ++e;
+            while (L.start[e + 1] <= c) ++e;
+            gm = L.geom[e];
+            width = ((gm >> 16) & 255) + 1;
+            px0 = gm & 255;
+            py0 = (gm >> 8) & 255;
+            row = 0;
+            col = 0;
+            kend = L.start[e + 1];
+            ab = L.ab[e];
+            cc = L.c[e];
+            rv = s_cv[py0];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+          Edges ed;
+          if (covered(ab.x, ab.z, cc.x, tav, tbv, tcv, s_cu[px0 + col], ed))
+            on_hit(e, px0 + col, py0 + row, ed);
+          if (++col == width) {
+            col = 0;
+            ++row;
+            rv = s_cv[py0 + row];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
 
 __device__ __forceinline__ TileGeom tile_geom(const Image& im, int tile) {
   TileGeom g;
@@ -421,7 +569,8 @@ __device__ __forceinline__ TileGeom tile_geom(const Image& im, int tile) {
 
 // Depth of the hit from lo_a: the axis coordinate interpolated with the
 // barycentric weights E_BC, E_CA, E_AB over their sum, in float64.
-__device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, float cz, double lo_a) {
+__device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, float cz,
+                                          double lo_a) {
   const double den = (e.ab + e.bc) + e.ca;
   const double num = e.ca * ((double)bz - (double)az) + e.ab * ((double)cz - (double)az);
   const double z = (double)az + num / den;
@@ -430,141 +579,64 @@ __device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, fl
   return d;
 }
 
-// Calls on_hit(W, k, px, py, edges) for every covered candidate of rows
-// [r0, r1) of the tile (k indexes the wave's entry arrays of W).  Every
-// thread of the workgroup must call it; it starts and ends with a barrier.
-template <bool kDepth, class OnHit>
-__device__ void walk_tile(const Image& im, const TileGeom& g, int r0, int r1, WalkLds<kDepth>& L,
-                          const float* s_cu, const float* s_cv, OnHit&& on_hit) {
-  const uint64_t cap = im.list_cap;
-  const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[g.tile], cap);
-  const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[g.tile + 1], cap);
-  const float cu0 = s_cu[0];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  WaveWalk<kDepth>& W = L.w[wave];
-  constexpr int kRowGroup = WaveWalk<kDepth>::kRowGroup;
-  constexpr int kCandCap = WaveWalk<kDepth>::kCandCap;
-  for (int rg0 = r0; rg0 < r1; rg0 += kRowGroup) {
-    const int rg1 = min(rg0 + kRowGroup, r1);
-    if (threadIdx.x == 0) L.grab = e_begin;
-    __syncthreads();
-    for (;;) {
-      // the wave's next 64 entries
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(&L.grab, 64u);
-      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__shfl((int)base, 0, 64));
-      if (base >= e_end) break;
-      const int m = (int)min(64u, e_end - base);
-      // ---- this lane's entry, its rows in the group and their spans
-      int total = 0, ry0 = 0, nrows = 0;
-      if (lane < m) {
-        const uint64_t e = (uint64_t)base + lane;
-        const float4 ab = im.ent_uv[2 * e];
-        const float4 cg = im.ent_uv[2 * e + 1];
-        const uint32_t gm = __float_as_uint(cg.w);
-        const int x0 = gm & 255, width = ((gm >> 16) & 255) + 1;
-        const int y0 = (gm >> 8) & 255, y1 = y0 + (int)(gm >> 24) + 1;
-        int ry1 = 0;
-        if ((uint32_t)__float_as_int(cg.z) >= (uint64_t)im.n_tris || x0 + width > g.cw || y1 > g.ch) {
-          // not written as counted: the call fails, the entry has no candidates
-          atomicOr(im.status, kStatusMismatch);
-        } else {
-          ry0 = max(y0, rg0);
-          ry1 = min(y1, rg1);
-        }
-        W.ab[lane] = ab;
-        W.c[lane] = make_float2(cg.x, cg.y);
-        if (kDepth) {
-          const float4 zz = im.ent_z[e];
-          W.z[lane] = make_float4(zz.x, zz.y, zz.z, cg.z);
-        }
-        nrows = max(ry1 - ry0, 0);
-        if (nrows > 0) {
-          const SpanPrep sp = span_prep(ab.x, ab.y, ab.z, ab.w, cg.x, cg.y);
-          for (int r = 0; r < nrows; ++r) {
-            float lo, hi;
-            span_bounds(sp, s_cv[ry0 + r], lo, hi);
-            int first;
-            const int len = span_columns(lo, hi, cu0, im.inv_hf_u, im.span_slack, x0, width, first);
-            // (a row of a 256-wide tile can hold 256 candidates: stored as its first and last column)
-            W.span[lane][r] = (uint16_t)(len > 0 ? (first | ((first + len - 1) << 8)) : 1);
-            total += len;
-          }
-        }
-      }
-      const int incl = wave_inclusive_scan<int>(total);
-      const int before = incl - total;
-      const int nc = __builtin_amdgcn_readlane(incl, 63);
-      // ---- rounds of at most kCandCap candidates: list, then test
-      for (int w0 = 0; w0 < nc; w0 += kCandCap) {
-        const int w1 = min(w0 + kCandCap, nc);
-        if (before < w1 && before + total > w0) {  // this lane has candidates in the round
-          int at = before - w0;  // position in the round's list
-          const int lim = w1 - w0;
-          for (int r = 0; r < nrows && at < lim; ++r) {
-            const uint32_t sp = W.span[lane][r];
-            const int first = (int)(sp & 255u), len = (int)(sp >> 8) - first + 1;
-            const uint32_t rec = (uint32_t)(lane | ((ry0 + r) << 6)) | ((uint32_t)first << 12);
-            // four at a time, predicated (rows are short)
-            for (int k = 0; k < len; k += 4) {
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const int q = at + k + j;
-                if (k + j < len && q >= 0 && q < lim) W.cand[q] = rec + ((uint32_t)(k + j) << 12);
-              }
-            }
-            at += len;
-          }
-        }
-        wave_sync();
-        for (int i = lane; i < w1 - w0; i += 64) {
-          const uint32_t rec = W.cand[i];
-          const int e = (int)(rec & 63u), y = (int)((rec >> 6) & 63u), x = (int)(rec >> 12);
-          const float4 pab = W.ab[e];
-          const float2 pc = W.c[e];
-          const float rv = s_cv[y];
-          const float tav = pab.y - rv, tbv = pab.w - rv, tcv = pc.y - rv;
-          Edges ed;
-          if (covered(pab.x, pab.z, pc.x, tav, tbv, tcv, (double)tav, (double)tbv, (double)tcv, s_cu[x], ed))
-            on_hit(W, e, x, y, ed);
-        }
-        wave_sync();  // before the next round (or entries) replace the records
-      }
-    }
-    __syncthreads();  // every wave done with the group (the grab counter is reset)
-  }
-}
+// ---------------------------------------------------------------------------
+// sampling pass: count and stage every hit
+// ---------------------------------------------------------------------------
+// A tile's staging region holds at most im.stage_layers hits per tile pixel
+// (and never more than the tile's candidates); a tile with more hits than its
+// region is walked again by the write pass.
+constexpr uint32_t kMinStageLayers = 64, kMaxStageLayers = 1024;
 
-// ---------------------------------------------------------------------------
-// count pass
-// ---------------------------------------------------------------------------
-// Items of the write pass for a tile of S samples: K = ceil(S / kWriteCap);
-// the count pass writes K to the plan ([0, n) for K >= 2, [n, 2n) for K = 1)
-// so that after one scan of the plan the long tiles come first.
+// Hits found by a wave in one window of its walk, waiting for their depth.
+constexpr int kMaxRun = 16;                 // candidates per thread per window
+constexpr int kWaveHits = 64 * kMaxRun;     // hit descriptors per wave per window
+
 template <int kTilePix>
-__device__ void count_tile(const Image& im, int tile, uint32_t gtile, uint32_t* plan, uint32_t n_total) {
+struct SampleLds {
+  // descriptor: tile pixel q | chunk entry << kQBits
+  static constexpr int kQBits = kTilePix <= 256 ? 8 : 10;
+  using Desc = typename std::conditional<(kTilePix <= 256), uint16_t, uint32_t>::type;
+  Desc hit[kWaves][kWaveHits];
+};
+
+// One walk of the tile.  Candidates are split into runs of equal length
+// over all threads of the workgroup (one binary search per run, then
+// incremental pixel steps).  A covered candidate only appends its (entry,
+// pixel) descriptor to its wave's list; after each window the wave takes its
+// hits 64 at a time, recomputes their edge functions, and computes depth,
+// key and arrival slot with every lane busy, storing them to consecutive
+// entries of the tile's staging region.  The region is sized by the tile's
+// candidate count (pixels of the clipped rectangles), which bounds its hits.
+template <int kTilePix>
+__device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t* plan, uint32_t n_total,
+                            int place_cap) {
+  using Lds = SampleLds<kTilePix>;
+  constexpr int kQBits = Lds::kQBits;
   __shared__ uint32_t s_cnt[kTilePix];
   __shared__ float s_cu[kMaxTileW];
   __shared__ float s_cv[kMaxTileH + 1];
-  __shared__ WalkLds<false> L;
+  __shared__ ChunkLds<true> L;
+  __shared__ Lds H;
   __shared__ uint32_t s_red[kWaves];
-  __shared__ uint64_t s_sum[kWaves];
+  __shared__ uint32_t s_fill;
 
   const TileGeom g = tile_geom(im, tile);
   const int npix = g.cw * g.ch;
   const int cw = g.cw;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t cap = im.list_cap;
   const uint32_t e_begin = (uint32_t)min((uint64_t)im.tile_cnt[tile], cap);
   const uint32_t e_end = (uint32_t)min((uint64_t)im.tile_cnt[tile + 1], cap);
 
   if (e_begin == e_end) {
-    // no triangle meets the tile: zero counts, nothing to write
+    // no triangle meets the tile: zero counts, no hits, nothing to place
     for (int q = threadIdx.x; q < npix; q += kBlock) {
       const int py = q / cw, px = q - py * cw;
       im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = 0u;
     }
     if (threadIdx.x == 0) {
       im.tile_hits[tile] = 0u;
+      im.tile_stage[tile] = 0u;
       if (im.tile_max) im.tile_max[tile] = 0u;
       if (plan) {
         plan[gtile] = 0u;
@@ -576,24 +648,154 @@ __device__ void count_tile(const Image& im, int tile, uint32_t gtile, uint32_t* 
 
   for (int q = threadIdx.x; q < npix; q += kBlock) s_cnt[q] = 0;
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
-  for (int q = threadIdx.x; q < g.ch; q += kBlock) s_cv[q] = pixel_centre(im.lo_v, im.h_v, g.y0 + q);
+  for (int q = threadIdx.x; q <= g.ch; q += kBlock)
+    s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
+
+  // The tile's staging region comes from the tile scan (whole 4-entry
+  // groups, so the place pass reads 16-byte vectors); a region that ends
+  // beyond the buffer is not used and the tile is walked again.
+  const uint32_t region_first = im.tile_region[tile];
+  const uint32_t region_end = im.tile_region[tile + 1];
+  const uint32_t region_size =
+      (im.stage_key != nullptr && region_end <= im.stage_cap) ? region_end - region_first : 0u;
+  if (threadIdx.x == 0) s_fill = 0;
   __syncthreads();
-  walk_tile<false>(im, g, 0, g.ch, L, s_cu, s_cv,
-                   [&](const WaveWalk<false>&, int, int px, int py, const Edges&) {
-                     atomicAdd(&s_cnt[py * cw + px], 1u);
-                   });
+  const double lo_a = im.lo_a;
+  const float inv_cw = 1.0f / (float)cw;
+  typename Lds::Desc* my_hits = H.hit[wave];
+
+  for (uint32_t cbase = e_begin; cbase < e_end; cbase += kBlock) {
+    // ---- load a chunk of entries with their candidate counts
+    const int m = (int)min((uint32_t)kBlock, e_end - cbase);
+    {
+      const int k = threadIdx.x;
+      int nc = 0;
+      if (k < m) {
+        const int2 ent = im.tile_list[cbase + k];
+        const int32_t t = ent.x;
+        const EntryRect r = entry_rect(im, g, ent);
+        nc = r.width * (r.y1 - r.y0);
+        L.geom[k] = r.x0 | (r.y0 << 8) | ((r.width - 1) << 16);
+        if (nc > 0) {
+          const float* sp = im.soup + 9 * (int64_t)t;
+          L.ab[k] = make_float4(sp[im.u], sp[im.v], sp[3 + im.u], sp[3 + im.v]);
+          L.c[k] = make_float2(sp[6 + im.u], sp[6 + im.v]);
+          L.z[k] = make_float4(sp[im.a], sp[3 + im.a], sp[6 + im.a], __int_as_float(t));
+        }
+      }
+      int total;
+      const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
+      if (k < m) L.start[k] = excl;
+      if (k == 0) L.start[m] = total;
+      __syncthreads();
+    }
+    const int total = L.start[m];
+    const int run = min(max((total + kBlock - 1) / kBlock, 2), kMaxRun);
+
+    for (int wb = 0; wb < total; wb += kBlock * run) {
+      // ---- walk: covered candidates append their descriptor
+      uint32_t nh = 0;  // hits of this wave in the window (wave-uniform)
+      int c = wb + threadIdx.x * run;
+      const int cend = min(c + run, total);
+      if (c < cend) {
+        int lo = 0, hi = m - 1;  // owner of c: the last entry whose start is <= c
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.start[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        int e = lo;
+        int gm = L.geom[e];
+        int width = ((gm >> 16) & 255) + 1;
+        int local = c - L.start[e];
+        int row = local / width;
+        int col = local - row * width;
+        int kend = L.start[e + 1];
+        float4 ab = L.ab[e];
+        float2 cc = L.c[e];
+        int px0 = gm & 255, py0 = (gm >> 8) & 255;
+        float rv = s_cv[py0 + row];
+        float tav = ab.y - rv, tbv = ab.w - rv, tcv = cc.y - rv;
+        for (; c < cend; ++c) {
+          if (c == kend) {  // next entry (every entry of a tile list has candidates)
+            ++e;
+            while (L.start[e + 1] <= c) ++e;
+            gm = L.geom[e];
+            width = ((gm >> 16) & 255) + 1;
+            px0 = gm & 255;
+            py0 = (gm >> 8) & 255;
+            row = 0;
+            col = 0;
+            kend = L.start[e + 1];
+            ab = L.ab[e];
+            cc = L.c[e];
+            rv = s_cv[py0];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+          Edges ed;
+          const bool hit = covered(ab.x, ab.z, cc.x, tav, tbv, tcv, s_cu[px0 + col], ed);
+          const uint64_t mask = __ballot(hit);
+          if (hit) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            const uint32_t q = (uint32_t)((py0 + row) * cw + px0 + col);
+            my_hits[nh + rank] = (typename Lds::Desc)(q | ((uint32_t)e << kQBits));
+          }
+          nh += (uint32_t)__popcll(mask);
+          if (++col == width) {
+            col = 0;
+            ++row;
+            rv = s_cv[py0 + row];
+            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
+          }
+        }
+      }
+      // lanes that left the walk early did not see the later ballots: the
+      // wave's count is the largest
+      for (int d = 32; d >= 1; d >>= 1) nh = max(nh, (uint32_t)__shfl_xor((int)nh, d, 64));
+      nh = __builtin_amdgcn_readfirstlane(nh);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+      // ---- the wave's hits, 64 at a time: depth, key, slot, stage
+      uint32_t first = 0;
+      if (lane == 0 && nh > 0) first = atomicAdd(&s_fill, nh);
+      first = __shfl((int)first, 0, 64);
+      for (uint32_t i = lane; i < nh; i += 64) {
+        const uint32_t d = my_hits[i];
+        const int q = (int)(d & ((1u << kQBits) - 1u));
+        const int e = (int)(d >> kQBits);
+        const int py = (int)(((float)q + 0.5f) * inv_cw);
+        const int px = q - py * cw;
+        const float4 ab = L.ab[e];
+        const float2 cc = L.c[e];
+        const float4 z = L.z[e];
+        const float rv = s_cv[py];
+        Edges ed;
+        (void)covered(ab.x, ab.z, cc.x, ab.y - rv, ab.w - rv, cc.y - rv, s_cu[px], ed);
+        const float dep = depth_of(ed, z.x, z.y, z.z, lo_a);
+        const uint32_t slot = atomicAdd(&s_cnt[q], 1u);
+        const uint32_t pos = first + i;
+        if (pos < region_size) {
+          const size_t at = (size_t)region_first + pos;
+          im.stage_key[at] = sample_key(dep, __float_as_int(z.w));
+          im.stage_qs[at] = (uint32_t)q | (slot << 10);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();  // before the next chunk replaces L
+  }
 
   uint32_t mx = 0;
-  uint64_t sum = 0;
   for (int q = threadIdx.x; q < npix; q += kBlock) {
     const int py = q / cw, px = q - py * cw;
     const uint32_t c = s_cnt[q];
     mx = max(mx, c);
-    sum += c;
     im.counts[(size_t)(g.y0 + py) * im.w + g.x0 + px] = c;
   }
-  uint64_t total;
-  (void)block_exclusive_scan<uint64_t>(sum, s_sum, total);
   // The largest count: per tile for a later reduction (batches), else one
   // atomic per tile if asked (the single-mesh path takes it from the pixel
   // scan): atomics from every tile to one address would queue up.
@@ -601,21 +803,32 @@ __device__ void count_tile(const Image& im, int tile, uint32_t gtile, uint32_t* 
   if (threadIdx.x == 0) {
     if (im.tile_max != nullptr) im.tile_max[tile] = mx;
     else if (im.max_layers != nullptr && mx > 0) atomicMax(im.max_layers, mx);
-    im.tile_hits[tile] = (uint32_t)min(total, (uint64_t)0xffffffffu);
+    const uint32_t hits = s_fill;
+    const bool staged = hits <= region_size;
+    im.tile_hits[tile] = hits;
+    if (hits == 0) {
+      im.tile_stage[tile] = 0;
+    } else if (staged) {
+      im.tile_stage[tile] = region_first;
+    } else {
+      im.tile_stage[tile] = kNoStage;
+      im.walk_list[atomicAdd(im.walk_count, 1u)] = gtile;
+    }
+    // place items: ceil(hits / stage) for a staged tile with hits
     if (plan) {
-      const uint64_t K = (total + kWriteCap - 1) / kWriteCap;
-      const uint32_t k32 = (uint32_t)min(K, (uint64_t)0x7fffu);  // (parts fit 16 bits)
-      plan[gtile] = k32 >= 2 ? k32 : 0u;
-      plan[n_total + gtile] = k32 == 1 ? 1u : 0u;
+      const uint32_t K = (hits == 0 || !staged) ? 0u : (hits + place_cap - 1) / (uint32_t)place_cap;
+      plan[gtile] = K >= 2 ? K : 0u;
+      plan[n_total + gtile] = K == 1 ? 1u : 0u;
     }
   }
 }
 
+// (at most 72 VGPRs: seven workgroups per CU)
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
+__global__ void __launch_bounds__(kBlock, kTilePix <= kSmallTilePix ? 7 : 4) sample_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
-  count_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x, set.plan,
-                       set.tile_start[set.n]);
+  sample_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x, set.plan,
+                        set.tile_start[set.n], set.place_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,9 +837,10 @@ __global__ void __launch_bounds__(kBlock) count_kernel(ImageSet set) {
 // Output of one run of staged keys: each key finds its rank among its
 // pixel's keys and is stored at its sorted position; four keys per thread at
 // a time, their normal gathers in flight while the ranks are counted.
-__device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t* s_keys, const uint16_t* s_pix,
-                                                 const uint32_t* s_pre, const uint32_t* s_off, uint32_t run_base,
-                                                 int run_total) {
+template <int kTilePix>
+__device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t* s_keys,
+                                                 const uint16_t* s_pix, const uint32_t* s_pre,
+                                                 const uint32_t* s_off, uint32_t run_base, int run_total) {
   constexpr int kU = 4;
   for (int s0 = threadIdx.x; s0 < run_total; s0 += kBlock * kU) {
     uint64_t key[kU];
@@ -639,10 +853,10 @@ __device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t
       if (s2 < run_total) {
         key[u] = s_keys[s2];
         qq[u] = s_pix[s2];
-        const float* nrm = im.tnorm + 3 * (int64_t)(int32_t)(uint32_t)key[u];
-        nx[u] = nrm[0];
-        ny[u] = nrm[1];
-        nz[u] = nrm[2];
+        const float4 nrm = im.tnorm[(int32_t)(uint32_t)key[u]];  // one 16-byte gather
+        nx[u] = nrm.x;
+        ny[u] = nrm.y;
+        nz[u] = nrm.z;
       }
     }
 #pragma unroll
@@ -651,8 +865,15 @@ __device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t
       const int q = qq[u];
       const uint32_t b = s_pre[q] - run_base;
       const uint32_t n = s_pre[q + 1] - s_pre[q];
-      uint32_t rank = 0;
-      for (uint32_t j = 0; j < n; ++j) rank += (s_keys[b + j] < key[u]) ? 1u : 0u;
+      // four independent LDS reads per step (the loop is bound by their latency)
+      uint32_t rank = 0, j = 0;
+      for (; j + 4 <= n; j += 4) {
+        const uint64_t k0 = s_keys[b + j], k1 = s_keys[b + j + 1], k2 = s_keys[b + j + 2],
+                       k3 = s_keys[b + j + 3];
+        rank += (uint32_t)(k0 < key[u]) + (uint32_t)(k1 < key[u]) + (uint32_t)(k2 < key[u]) +
+                (uint32_t)(k3 < key[u]);
+      }
+      for (; j < n; ++j) rank += (s_keys[b + j] < key[u]) ? 1u : 0u;
       const size_t o = (size_t)s_off[q] + rank;
       im.depth[o] = key_depth(key[u]);
       im.tri[o] = (int32_t)(uint32_t)key[u];
@@ -662,8 +883,8 @@ __device__ __forceinline__ void write_staged_run(const Image& im, const uint64_t
 }
 
 // Output offsets (s_off) and exclusive prefix of the sample counts (s_pre,
-// npix + 1 entries) of the tile's pixels, q = py * cw + px; s_cur is
-// cleared.  Ends with a barrier.
+// npix + 1 entries) of the tile's pixels, q = py * cw + px; s_cur (if given)
+// is cleared.  Ends with a barrier.
 __device__ void tile_prefix(const Image& im, const TileGeom& g, uint32_t* s_off, uint32_t* s_pre,
                             uint32_t* s_cur, uint32_t* s_wave) {
   const int npix = g.cw * g.ch;
@@ -677,7 +898,7 @@ __device__ void tile_prefix(const Image& im, const TileGeom& g, uint32_t* s_off,
       const uint32_t o = im.offsets[gp];
       n = im.offsets[gp + 1] - o;
       s_off[q] = o;
-      s_cur[q] = 0;
+      if (s_cur) s_cur[q] = 0;
     }
     uint32_t total;
     const uint32_t ex = block_exclusive_scan<uint32_t>(n, s_wave, total);
@@ -744,8 +965,8 @@ __device__ void finish_deep_pixel(const Image& im, size_t o, uint32_t n) {
   }
   for (uint32_t s2 = threadIdx.x; s2 < n; s2 += kBlock) {
     const int32_t t = im.tri[o + s2];
-    const float* nrm = im.tnorm + 3 * (int64_t)t;
-    store_normal(im, o + s2, nrm[0], nrm[1], nrm[2]);
+    const float4 nrm = im.tnorm[t];
+    store_normal(im, o + s2, nrm.x, nrm.y, nrm.z);
   }
 }
 
@@ -755,20 +976,20 @@ __device__ void finish_deep_pixel(const Image& im, size_t o, uint32_t n) {
 // its rank among its pixel's keys and is stored straight to its sorted
 // position, so sorting and storing are one pass over the staged keys.  Only a
 // single pixel with more samples than the LDS capacity is written directly to
-// its output range and sorted there.  A hit beyond its pixel's count, or a
-// pixel left short of it, means the passes disagree: the call fails.
+// its output range and sorted there.
 // Runs of the tile's greedy split with index = part (mod parts) are written
 // by this call; the split is the same for every part.
 template <int kTilePix>
-__device__ void write_tile(const Image& im, int tile, int part, int parts) {
-  __shared__ uint64_t s_keys[kWriteCap];
-  __shared__ uint16_t s_pix[kWriteCap];       // tile pixel index of each staged key
+__device__ void write_tile(const Image& im, int tile, int part = 0, int parts = 1) {
+  constexpr int kStageCap = stage_cap(kTilePix);
+  __shared__ uint64_t s_keys[kStageCap];
+  __shared__ uint16_t s_pix[kStageCap];       // tile pixel index of each staged key
   __shared__ uint32_t s_off[kTilePix];        // output offset of each tile pixel
   __shared__ uint32_t s_pre[kTilePix + 1];    // prefix of samples over tile pixels
   __shared__ uint32_t s_cur[kTilePix];        // fill cursor of each tile pixel
   __shared__ float s_cu[kMaxTileW];
   __shared__ float s_cv[kMaxTileH + 1];
-  __shared__ WalkLds<true> L;
+  __shared__ ChunkLds<true> L;
   __shared__ uint32_t s_wave[kWaves];
   __shared__ int s_run[2];                    // end pixel of the run, direct mode
 
@@ -776,46 +997,45 @@ __device__ void write_tile(const Image& im, int tile, int part, int parts) {
   const int npix = g.cw * g.ch;  // tile pixels, q = py * cw + px
 
   for (int q = threadIdx.x; q < g.cw; q += kBlock) s_cu[q] = pixel_centre(im.lo_u, im.h_u, g.x0 + q);
-  for (int q = threadIdx.x; q < g.ch; q += kBlock) s_cv[q] = pixel_centre(im.lo_v, im.h_v, g.y0 + q);
+  for (int q = threadIdx.x; q <= g.ch; q += kBlock)
+    s_cv[q] = pixel_centre(im.lo_v, im.h_v, min(g.y0 + q, im.w - 1));
   tile_prefix(im, g, s_off, s_pre, s_cur, s_wave);
 
   int q0 = 0;
   for (int run = 0; q0 < npix; ++run) {
     bool direct;
-    const int q1 = next_run(s_pre, q0, npix, kWriteCap, s_run, direct);
+    const int q1 = next_run(s_pre, q0, npix, kStageCap, s_run, direct);
     const uint32_t run_base = s_pre[q0];
     const int run_total = (int)(s_pre[q1] - run_base);
     if (run_total > 0 && run % parts == part) {
       const int r0 = q0 / g.cw, r1 = (q1 - 1) / g.cw + 1;
       const double lo_a = im.lo_a;
       const int cw = g.cw;
-      walk_tile<true>(im, g, r0, r1, L, s_cu, s_cv, [&](const WaveWalk<true>& W, int e, int px, int py,
-                                                        const Edges& ed) {
-        const int q = py * cw + px;
-        if (q < q0 || q >= q1) return;
-        const uint32_t slot = atomicAdd(&s_cur[q], 1u);
-        if (slot >= s_pre[q + 1] - s_pre[q]) {  // more hits than counted
-          atomicOr(im.status, kStatusMismatch);
-          return;
-        }
-        const float4 z = W.z[e];
-        const float d = depth_of(ed, z.x, z.y, z.z, lo_a);
-        const int32_t t = __float_as_int(z.w);
-        if (!direct) {
-          const uint32_t at = s_pre[q] - run_base + slot;
-          s_keys[at] = sample_key(d, t);
-          s_pix[at] = (uint16_t)q;
-        } else {
-          const size_t o = (size_t)s_off[q] + slot;
-          im.depth[o] = d;
-          im.tri[o] = t;
-        }
-      });
-      // (walk_tile ends with a barrier) every pixel of the run got its count
-      for (int q = q0 + threadIdx.x; q < q1; q += kBlock)
-        if (s_cur[q] != s_pre[q + 1] - s_pre[q]) atomicOr(im.status, kStatusMismatch);
+      tile_candidates<true>(im, g, r0, r1, L, s_cu, s_cv,
+                            [&](int e, int px, int py, const Edges& ed) {
+                              const int q = py * cw + px;
+                              if (q < q0 || q >= q1) return;
+                              const uint32_t slot = atomicAdd(&s_cur[q], 1u);
+                              if (slot >= s_pre[q + 1] - s_pre[q]) {  // count/write disagree
+                                atomicOr(im.status, kStatusMismatch);
+                                return;
+                              }
+                              const float4 z = L.z[e];
+                              const float d = depth_of(ed, z.x, z.y, z.z, lo_a);
+                              const int32_t t = __float_as_int(z.w);
+                              if (!direct) {
+                                const uint32_t at = s_pre[q] - run_base + slot;
+                                s_keys[at] = sample_key(d, t);
+                                s_pix[at] = (uint16_t)q;
+                              } else {
+                                const size_t o = (size_t)s_off[q] + slot;
+                                im.depth[o] = d;
+                                im.tri[o] = t;
+                              }
+                            });
+      // tile_candidates ends with a barrier
       if (!direct) {
-        write_staged_run(im, s_keys, s_pix, s_pre, s_off, run_base, run_total);
+        write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, run_base, run_total);
       } else {
         finish_deep_pixel(im, s_off[q0], s_pre[q0 + 1] - s_pre[q0]);
       }
@@ -825,33 +1045,192 @@ __device__ void write_tile(const Image& im, int tile, int part, int parts) {
   }
 }
 
-// One item of the write pass.
-struct WriteItem {
+// Work items of the place pass: a staged tile with S hits gets
+// K = ceil(S / stage) items; tiles without hits or walked again get none.
+// The sampling pass writes K to the plan ([0, n) for K >= 2, [n, 2n) for
+// K = 1), so after one scan of the plan the long tiles come first.
+// K <= stage_layers * tile pixels / stage.
+// One work item of the place pass.
+struct PlaceItem {
   uint32_t gtile;       // set-wide tile number
   uint32_t part_parts;  // part | parts << 16
+  uint32_t first;       // first staged entry of the tile
+  uint32_t hits;        // staged entries of the tile
 };
 
 // Items in launch order (dense tiles first), from the scanned plan.
-__global__ void __launch_bounds__(kBlock) plan_items_kernel(ImageSet set, WriteItem* items) {
+__global__ void __launch_bounds__(kBlock) plan_items_kernel(ImageSet set, PlaceItem* items) {
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t n_tiles = set.tile_start[set.n];
   if (gt >= n_tiles) return;
+  const int k = image_of_block(set, gt);
+  const Image& im = set.img[k];
+  const int tile = (int)(gt - set.tile_start[k]);
   const uint32_t* plan = set.plan;
   const uint32_t kd = plan[gt + 1] - plan[gt];
   const uint32_t ks = plan[n_tiles + gt + 1] - plan[n_tiles + gt];
   const uint32_t K = kd + ks;
   if (K == 0) return;
   const uint32_t at = kd ? plan[gt] : plan[n_tiles + gt];
-  for (uint32_t j = 0; j < K; ++j) items[at + j] = WriteItem{gt, j | (K << 16)};
+  PlaceItem it;
+  it.gtile = gt;
+  it.first = im.tile_stage[tile];
+  it.hits = im.tile_hits[tile];
+  for (uint32_t j = 0; j < K; ++j) {
+    it.part_parts = j | (K << 16);
+    items[at + j] = it;
+  }
 }
 
-// One workgroup per write item.
+// ---------------------------------------------------------------------------
+// place pass: write the hits staged by the sampling pass
+// ---------------------------------------------------------------------------
+// The tile's pixels are split into the same runs as in write_tile.  A run
+// reads the tile's staged entries, keeps those of its pixels and puts each key
+// at its pixel's slot in LDS (the slot came with the hit), then ranks and
+// stores the keys like write_tile.  A single pixel deeper than the stage is
+// stored unsorted straight to its output range and sorted there.
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) write_kernel(ImageSet set, const WriteItem* items) {
-  const WriteItem it = items[blockIdx.x];
+__device__ void place_tile(const Image& im, int tile, uint32_t first, uint32_t hits, int part,
+                           int parts) {
+  constexpr int kStageCap = stage_cap(kTilePix);
+  constexpr int kPer = kStageCap / kBlock;  // staged entries per thread of a one-run tile
+  __shared__ uint64_t s_keys[kStageCap];
+  __shared__ uint16_t s_pix[kStageCap];
+  __shared__ uint32_t s_off[kTilePix];
+  __shared__ uint32_t s_pre[kTilePix + 1];
+  __shared__ uint32_t s_wave[kWaves];
+  __shared__ int s_run[2];
+
+  const TileGeom g = tile_geom(im, tile);
+  const int npix = g.cw * g.ch;
+  const uint64_t* keys = im.stage_key + first;
+  const uint32_t* qs = im.stage_qs + first;
+
+  if (hits <= (uint32_t)kStageCap) {
+    // One run holds the whole tile: the staged entries are loaded before the
+    // pixel offsets are scanned, so the two reads overlap.
+    uint32_t rq[kPer];
+    uint64_t rk[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t i = threadIdx.x + u * kBlock;
+      rq[u] = i < hits ? qs[i] : 0xffffffffu;
+      rk[u] = i < hits ? keys[i] : 0;
+    }
+    tile_prefix(im, g, s_off, s_pre, nullptr, s_wave);
+    if (s_pre[npix] != hits) {  // staging and counts disagree
+      if (threadIdx.x == 0) atomicOr(im.status, kStatusMismatch);
+      return;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (rq[u] == 0xffffffffu) continue;
+      const int q = (int)(rq[u] & 1023u);
+      const uint32_t slot = rq[u] >> 10;
+      if (q >= npix || slot >= s_pre[q + 1] - s_pre[q]) {
+        atomicOr(im.status, kStatusMismatch);
+        continue;
+      }
+      s_keys[s_pre[q] + slot] = rk[u];
+      s_pix[s_pre[q] + slot] = (uint16_t)q;
+    }
+    __syncthreads();
+    write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, 0u, (int)hits);
+    return;
+  }
+
+  tile_prefix(im, g, s_off, s_pre, nullptr, s_wave);
+  if (s_pre[npix] != hits) {
+    if (threadIdx.x == 0) atomicOr(im.status, kStatusMismatch);
+    return;
+  }
+  int q0 = 0;
+  for (int run = 0; q0 < npix; ++run) {
+    bool direct;
+    const int q1 = next_run(s_pre, q0, npix, kStageCap, s_run, direct);
+    const uint32_t run_base = s_pre[q0];
+    const int run_total = (int)(s_pre[q1] - run_base);
+    if (run_total > 0 && run % parts == part) {
+      // Eight entries per thread per step: two 16-byte loads (regions are
+      // whole 4-entry groups) issued together, then the keys of the run's
+      // entries, also together, so a step costs two round trips.
+      for (uint32_t b0 = 0; b0 < hits; b0 += 8 * kBlock) {
+        uint32_t xs[8];
+        uint64_t ks[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t i0 = b0 + 4 * (h * kBlock + threadIdx.x);
+          uint4 x4 = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+          if (i0 < hits) x4 = *reinterpret_cast<const uint4*>(qs + i0);
+          xs[4 * h] = x4.x; xs[4 * h + 1] = x4.y; xs[4 * h + 2] = x4.z; xs[4 * h + 3] = x4.w;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t i = b0 + 4 * ((u >> 2) * kBlock + threadIdx.x) + (u & 3);
+          const int q = (int)(xs[u] & 1023u);
+          const bool mine = i < hits && q >= q0 && q < q1;
+          ks[u] = mine ? keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t i = b0 + 4 * ((u >> 2) * kBlock + threadIdx.x) + (u & 3);
+          const int q = (int)(xs[u] & 1023u);
+          const uint32_t slot = xs[u] >> 10;
+          if (i >= hits || q < q0 || q >= q1) continue;
+          if (slot >= s_pre[q + 1] - s_pre[q]) {
+            atomicOr(im.status, kStatusMismatch);
+            continue;
+          }
+          const uint64_t key = ks[u];
+          if (!direct) {
+            const uint32_t at = s_pre[q] - run_base + slot;
+            s_keys[at] = key;
+            s_pix[at] = (uint16_t)q;
+          } else {
+            const size_t o = (size_t)s_off[q] + slot;
+            im.depth[o] = key_depth(key);
+            im.tri[o] = (int32_t)(uint32_t)key;
+          }
+        }
+      }
+      __syncthreads();
+      if (!direct) {
+        write_staged_run<kTilePix>(im, s_keys, s_pix, s_pre, s_off, run_base, run_total);
+      } else {
+        finish_deep_pixel(im, s_off[q0], s_pre[q0 + 1] - s_pre[q0]);
+      }
+    }
+    __syncthreads();
+    q0 = q1;
+  }
+}
+
+// One workgroup per place item.
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) place_kernel(ImageSet set, const PlaceItem* items) {
+  const PlaceItem it = items[blockIdx.x];
   const int k = image_of_block(set, it.gtile);
-  write_tile<kTilePix>(set.img[k], (int)(it.gtile - set.tile_start[k]), (int)(it.part_parts & 0xffffu),
-                       (int)(it.part_parts >> 16));
+  place_tile<kTilePix>(set.img[k], (int)(it.gtile - set.tile_start[k]), it.first, it.hits,
+                       (int)(it.part_parts & 0xffffu), (int)(it.part_parts >> 16));
+}
+
+// Tiles whose hits did not fit their staging region: walked and written
+// again, one workgroup per tile.
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) walk_kernel(ImageSet set, const uint32_t* list, uint32_t n,
+                                                      uint32_t* counter) {
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= n) break;
+    const uint32_t gt = list[item];
+    const int k = image_of_block(set, gt);
+    write_tile<kTilePix>(set.img[k], (int)(gt - set.tile_start[k]));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1221,14 +1600,14 @@ __global__ void __launch_bounds__(kBlock) batch_setup_kernel(BatchDevice B) {
   const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
   const BatchMesh& bm = B.meshes[mi];
   const int64_t t = (int64_t)(blockIdx.x - B.tri_block_start[mi]) * kBlock + threadIdx.x;
-  triangle_pass<true>(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
+  setup_triangle<true>(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
 }
 
-__global__ void __launch_bounds__(kBlock) batch_scatter_kernel(BatchDevice B) {
-  const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
-  const BatchMesh& bm = B.meshes[mi];
-  const int64_t t = (int64_t)(blockIdx.x - B.tri_block_start[mi]) * kBlock + threadIdx.x;
-  triangle_pass<false>(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
+template <bool kScatter>
+__global__ void __launch_bounds__(kBlock) batch_bin_kernel(BatchDevice B) {
+  const int k = segment_of(B.bin_block_start, B.n_images, (uint32_t)blockIdx.x);
+  bin_triangles<kScatter>(B.images[k],
+                          (int64_t)(blockIdx.x - B.bin_block_start[k]) * kBlock + threadIdx.x);
 }
 
 // Persistent workgroups take items from a counter, kGrab at a time, until
@@ -1252,20 +1631,19 @@ struct ItemGrabber {
 };
 
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_count_kernel(BatchDevice B, uint32_t n_tiles) {
+__global__ void __launch_bounds__(kBlock) batch_sample_kernel(BatchDevice B, uint32_t n_tiles) {
   __shared__ uint32_t s_item;
   ItemGrabber grab;
   for (;;) {
     const uint32_t item = grab(&B.work[0], &s_item);
     if (item >= n_tiles) break;
     const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, item));
-    count_tile<kTilePix>(B.images[k], (int)(item - B.tile_start[k]), item, B.plan, n_tiles);
+    sample_tile<kTilePix>(B.images[k], (int)(item - B.tile_start[k]), item, B.plan, n_tiles, B.place_cap);
+    __syncthreads();  // the next item reuses the tile's LDS
   }
 }
 
-// Write items of the batch, in launch order, from the scanned plan; items
-// beyond the buffer's capacity are not written (the host grows it and runs
-// the batch again).
+// Place items of the batch, in launch order, from the scanned plan.
 __global__ void __launch_bounds__(kBlock) batch_plan_items_kernel(BatchDevice B, uint32_t n_tiles) {
   const uint32_t gt = blockIdx.x * kBlock + threadIdx.x;
   if (gt >= n_tiles) return;
@@ -1273,30 +1651,58 @@ __global__ void __launch_bounds__(kBlock) batch_plan_items_kernel(BatchDevice B,
   const uint32_t ks = B.plan[n_tiles + gt + 1] - B.plan[n_tiles + gt];
   const uint32_t K = kd + ks;
   if (K == 0) return;
+  const int k = segment_of(B.tile_start, B.n_images, gt);
+  const Image& im = B.images[k];
+  const int tile = (int)(gt - B.tile_start[k]);
   const uint32_t at = kd ? B.plan[gt] : B.plan[n_tiles + gt];
-  WriteItem* items = static_cast<WriteItem*>(B.items);
-  for (uint32_t j = 0; j < K; ++j)
-    if ((uint64_t)at + j < B.items_cap) items[at + j] = WriteItem{gt, j | (K << 16)};
+  PlaceItem it;
+  it.gtile = gt;
+  it.first = im.tile_stage[tile];
+  it.hits = im.tile_hits[tile];
+  PlaceItem* items = static_cast<PlaceItem*>(B.items);
+  for (uint32_t j = 0; j < K; ++j) {
+    it.part_parts = j | (K << 16);
+    items[at + j] = it;
+  }
 }
 
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_write_kernel(BatchDevice B, uint32_t n_tiles) {
+__global__ void __launch_bounds__(kBlock) batch_place_kernel(BatchDevice B, uint32_t n_tiles) {
   __shared__ uint32_t s_item;
-  const uint32_t n_items = (uint32_t)min((uint64_t)B.plan[2 * n_tiles], B.items_cap);
-  const WriteItem* items = static_cast<const WriteItem*>(B.items);
+  const uint32_t n_items = B.plan[2 * n_tiles];
+  const PlaceItem* items = static_cast<const PlaceItem*>(B.items);
   ItemGrabber grab;
   for (;;) {
     const uint32_t item = grab(&B.work[1], &s_item);
     if (item >= n_items) break;
-    const WriteItem it = items[item];
+    const PlaceItem it = items[item];
     const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, it.gtile));
     const Image& im = B.images[k];
     if (im.depth == nullptr) continue;  // the image did not fit the output arena
-    write_tile<kTilePix>(im, (int)(it.gtile - B.tile_start[k]), (int)(it.part_parts & 0xffffu),
-                         (int)(it.part_parts >> 16));
+    place_tile<kTilePix>(im, (int)(it.gtile - B.tile_start[k]), it.first, it.hits,
+                         (int)(it.part_parts & 0xffffu), (int)(it.part_parts >> 16));
+    // place_tile may return with waves still storing from its LDS stage
+    // (one-run tiles): the next item reuses it
+    __syncthreads();
   }
 }
 
+template <int kTilePix>
+__global__ void __launch_bounds__(kBlock) batch_walk_kernel(BatchDevice B) {
+  __shared__ uint32_t s_item;
+  const uint32_t n = *B.walk_count;
+  ItemGrabber grab;
+  for (;;) {
+    const uint32_t item = grab(&B.work[2], &s_item);
+    if (item >= n) break;
+    const uint32_t gt = B.walk_list[item];
+    const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, gt));
+    const Image& im = B.images[k];
+    if (im.depth == nullptr) continue;
+    write_tile<kTilePix>(im, (int)(gt - B.tile_start[k]));
+    __syncthreads();  // the next item reuses the tile's LDS
+  }
+}
 
 // Start of every segment in the global exclusive prefix: partial sum of the
 // segment's scan tile before its first slot.  One workgroup per segment.
@@ -1352,8 +1758,8 @@ __global__ void __launch_bounds__(kBlock) scan_apply_segmented_kernel(
 }
 
 // One workgroup per image: its largest count (from its tiles' largest),
-// sample count, placement in the output arena (or a null image when the
-// outputs or lists are short), host summary of the image.
+// sample count, placement in the output arena (or the capacity flag), host
+// summary.
 __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice B) {
   __shared__ uint32_t s_m[kWaves];
   const int k = blockIdx.x;
@@ -1365,27 +1771,27 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
   m = block_max(m, s_m);
   if (threadIdx.x != 0) return;
   *im.max_layers = m;
-  const uint64_t n = im.offsets[(size_t)im.w * im.w];
-  const uint64_t base = B.sample_base[k];
-  const bool fits = base + n <= B.sample_cap && (uint64_t)*B.tile_total <= B.list_cap;
-  im.depth = fits ? B.depth + base : nullptr;
-  im.normal = fits ? B.normal + 3 * base : nullptr;
-  im.tri = fits ? B.tri + base : nullptr;
-  uint32_t* h = B.host_out + 4 + 4 * (size_t)k;
-  h[0] = (uint32_t)n;
-  h[1] = (uint32_t)base;
-  h[2] = (uint32_t)(base >> 32);
-  h[3] = m;  // the host compares n and base with the capacities
-  __threadfence_system();
-}
-
-// After the write pass: the status word (with what the write pass found),
-// the list entries and the write items of the batch.
-__global__ void batch_summary_kernel(BatchDevice B, uint32_t n_tiles) {
-  if (threadIdx.x != 0) return;
-  B.host_out[0] = *B.status;
-  B.host_out[1] = *B.tile_total;
-  B.host_out[2] = B.plan[2 * n_tiles];
+  if (k == 0) {
+    B.host_out[0] = *B.status;
+    B.host_out[1] = *B.tile_total;
+    uint32_t* tail = B.host_out + 4 + 4 * (size_t)B.n_images;
+    tail[0] = *B.region_total;
+    tail[1] = 0u;
+    tail[2] = *B.walk_count;
+  }
+  {
+    const uint64_t n = im.offsets[(size_t)im.w * im.w];
+    const uint64_t base = B.sample_base[k];
+    const bool fits = base + n <= B.sample_cap && (uint64_t)*B.tile_total <= B.list_cap;
+    im.depth = fits ? B.depth + base : nullptr;
+    im.normal = fits ? B.normal + 3 * base : nullptr;
+    im.tri = fits ? B.tri + base : nullptr;
+    uint32_t* h = B.host_out + 4 + 4 * (size_t)k;
+    h[0] = (uint32_t)n;
+    h[1] = (uint32_t)base;
+    h[2] = (uint32_t)(base >> 32);
+    h[3] = m;  // the host compares n and base with the capacities
+  }
   __threadfence_system();
 }
 
@@ -1434,9 +1840,10 @@ hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const MeshSetup& m, const ImageSet& set, hipStream_t s) {
-  if (m.n_tris <= 0 || set.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(m.n_tris, kBlock)), dim3(kBlock), 0, s, m, set);
+hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s) {
+  if (set.n == 0 || set.img[0].n_tris <= 0) return hipSuccess;
+  dim3 grid(grid_for(set.img[0].n_tris, kBlock), set.n);
+  hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(kBlock), 0, s, set);
   return hipGetLastError();
 }
 
@@ -1446,39 +1853,63 @@ static bool small_tiles(const ImageSet& set) {
   return true;
 }
 
-hipError_t launch_count(const ImageSet& set, hipStream_t s) {
+hipError_t launch_sample(const ImageSet& set, hipStream_t s) {
   const uint32_t blocks = set.tile_start[set.n];
   if (blocks == 0) return hipSuccess;
   if (small_tiles(set))
-    hipLaunchKernelGGL(count_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+    hipLaunchKernelGGL(sample_kernel<kSmallTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
   else
-    hipLaunchKernelGGL(count_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
+    hipLaunchKernelGGL(sample_kernel<kMaxTilePix>, dim3(blocks), dim3(kBlock), 0, s, set);
   return hipGetLastError();
 }
 
-int write_cap(int) { return kWriteCap; }
-
-hipError_t launch_plan_scan(const ImageSet& set, void* scratch, uint32_t* status, hipStream_t s) {
-  const uint32_t n = set.tile_start[set.n];
-  if (n == 0) return launch_fill_u32(set.plan, 0u, 1, s);
-  return launch_scan(set.plan, set.plan, 2 * (int64_t)n, scratch, status, s);
+int place_stage_cap(int tile_pix) {
+  return stage_cap(tile_pix <= kSmallTilePix ? kSmallTilePix : kMaxTilePix);
 }
 
-hipError_t launch_plan_items(const ImageSet& set, void* items, hipStream_t s) {
+int max_place_items_per_tile(int tile_pix, uint32_t stage_layers) {
+  const int pix = tile_pix <= kSmallTilePix ? kSmallTilePix : kMaxTilePix;
+  return (int)(((uint64_t)stage_layers * pix + stage_cap(pix) - 1) / stage_cap(pix));
+}
+
+uint32_t stage_layers_for(uint32_t max_layers_seen) {
+  uint32_t l = kMinStageLayers;
+  while (l < max_layers_seen && l < kMaxStageLayers) l <<= 1;
+  return l;
+}
+
+hipError_t launch_plan_items(const ImageSet& set, void* items, void* scratch, uint32_t* status,
+                             hipStream_t s) {
   const uint32_t n = set.tile_start[set.n];
   if (n == 0) return hipSuccess;
+  hipError_t e = launch_scan(set.plan, set.plan, 2 * (int64_t)n, scratch, status, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(plan_items_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, set,
-                     static_cast<WriteItem*>(items));
+                     static_cast<PlaceItem*>(items));
   return hipGetLastError();
 }
 
-hipError_t launch_write(const ImageSet& set, const void* items, uint32_t n_items, hipStream_t s) {
-  if (n_items == 0) return hipSuccess;
-  const WriteItem* it = static_cast<const WriteItem*>(items);
-  if (small_tiles(set))
-    hipLaunchKernelGGL(write_kernel<kSmallTilePix>, dim3(n_items), dim3(kBlock), 0, s, set, it);
+hipError_t launch_place(const ImageSet& set, const void* items, uint32_t n_items, uint32_t* counter,
+                        uint32_t n_walk, hipStream_t s) {
+  const bool small = small_tiles(set);
+  const PlaceItem* it = static_cast<const PlaceItem*>(items);
+  if (n_items > 0) {
+    if (small)
+      hipLaunchKernelGGL(place_kernel<kSmallTilePix>, dim3(n_items), dim3(kBlock), 0, s, set, it);
+    else
+      hipLaunchKernelGGL(place_kernel<kMaxTilePix>, dim3(n_items), dim3(kBlock), 0, s, set, it);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_walk == 0) return hipSuccess;
+  hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  const unsigned wgrid = persistent_grid(n_walk, small ? 4 : 2);
+  const uint32_t* list = set.img[0].walk_list;
+  if (small)
+    hipLaunchKernelGGL(walk_kernel<kSmallTilePix>, dim3(wgrid), dim3(kBlock), 0, s, set, list, n_walk, counter);
   else
-    hipLaunchKernelGGL(write_kernel<kMaxTilePix>, dim3(n_items), dim3(kBlock), 0, s, set, it);
+    hipLaunchKernelGGL(walk_kernel<kMaxTilePix>, dim3(wgrid), dim3(kBlock), 0, s, set, list, n_walk, counter);
   return hipGetLastError();
 }
 
@@ -1535,35 +1966,37 @@ hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t
 
 hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t blocks, hipStream_t s) {
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, b);
+  hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, b);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_count(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s) {
+hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   if (small)
-    hipLaunchKernelGGL(batch_count_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 8)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(batch_sample_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 7)), dim3(kBlock), 0,
                        s, b, n_tiles);
   else
-    hipLaunchKernelGGL(batch_count_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 6)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(batch_sample_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 4)), dim3(kBlock), 0,
                        s, b, n_tiles);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_write(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
+hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
                               hipStream_t s) {
-  if (n_tiles > 0) {
-    hipError_t e = launch_scan(b.plan, b.plan, 2 * (int64_t)n_tiles, scratch, nullptr, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_plan_items_kernel, dim3(grid_for(n_tiles, kBlock)), dim3(kBlock), 0, s, b,
-                       n_tiles);
-    const unsigned grid = persistent_grid(2 * n_tiles, small ? 4 : 3);
-    if (small)
-      hipLaunchKernelGGL(batch_write_kernel<kSmallTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
-    else
-      hipLaunchKernelGGL(batch_write_kernel<kMaxTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+  if (n_tiles == 0) return hipSuccess;
+  hipError_t e = launch_scan(b.plan, b.plan, 2 * (int64_t)n_tiles, scratch, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_plan_items_kernel, dim3(grid_for(n_tiles, kBlock)), dim3(kBlock), 0, s, b, n_tiles);
+  const unsigned grid = persistent_grid(2 * n_tiles, small ? 7 : 3);
+  if (small) {
+    hipLaunchKernelGGL(batch_place_kernel<kSmallTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+    hipLaunchKernelGGL(batch_walk_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 4)), dim3(kBlock), 0,
+                       s, b);
+  } else {
+    hipLaunchKernelGGL(batch_place_kernel<kMaxTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+    hipLaunchKernelGGL(batch_walk_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 2)), dim3(kBlock), 0,
+                       s, b);
   }
-  hipLaunchKernelGGL(batch_summary_kernel, dim3(1), dim3(64), 0, s, b, n_tiles);
   return hipGetLastError();
 }
 
@@ -1632,6 +2065,28 @@ hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out,
   sg.n = n;
   sg.nb = (n + kScanTile - 1) / kScanTile;
   sg.nseg = nseg;
+  return run_scan(sg, scratch, status, s);
+}
+
+hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n, uint32_t region_cap,
+                            void* scratch, uint32_t* status, hipStream_t s) {
+  if (n <= 0) {
+    hipError_t e = launch_fill_u32(tile_cnt, 0u, 1, s);
+    return e != hipSuccess ? e : launch_fill_u32(tile_region, 0u, 1, s);
+  }
+  ScanSegs sg{};
+  sg.in[0] = tile_cnt;
+  sg.out[0] = tile_cnt;
+  sg.total[0] = tile_cnt + n;
+  sg.cap[0] = 0xffffffffu;
+  sg.in[1] = tile_region;
+  sg.out[1] = tile_region;
+  sg.total[1] = tile_region + n;
+  sg.cap[1] = region_cap;
+  sg.sat = 2u;
+  sg.n = n;
+  sg.nb = (n + kScanTile - 1) / kScanTile;
+  sg.nseg = 2;
   return run_scan(sg, scratch, status, s);
 }
 

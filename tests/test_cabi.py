@@ -267,29 +267,3 @@ def test_offset_invalid_arguments_rejected_on_host(L, kw):
     assert rc == 1
     assert res is None or not kw.get("out", True)
     assert L.ldni_last_error().decode()
-
-
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_span_pruning_keeps_every_hit(L, seed):
-    """The sampling kernels test only the pixels of each triangle row inside
-    a conservative column span.  The library's host self-test runs the span
-    and the exact coverage predicate (Definition 1 with the tie rule) over
-    seeded triangles -- random, on pixel-centre lattices, with edges parallel
-    or nearly parallel to rows and columns, slivers, tiny and large ones,
-    boxes far from the origin -- and no covered pixel may fall outside its
-    row's span, and every pixel of a row's inner span (counted as a hit
-    without a test) must be covered.  The spans hold few pixels that miss,
-    and most hits lie in inner spans."""
-    c = (ctypes.c_uint64 * 4)()
-    assert L.ldni_span_selftest(seed, 100000, c) == 0
-    wrong, hits, in_span, in_inner = c[0], c[1], c[2], c[3]
-    assert hits > 1_000_000
-    assert wrong == 0
-    assert in_span < 1.3 * hits
-    assert in_inner > 0.5 * hits
-
-
-def test_span_selftest_rejects_bad_arguments(L):
-    c = (ctypes.c_uint64 * 4)()
-    assert L.ldni_span_selftest(0, -1, c) == 1
-    assert L.ldni_span_selftest(0, 10, None) == 1

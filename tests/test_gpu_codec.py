@@ -69,10 +69,19 @@ def test_pixel_deeper_than_lds_stage():
     _same_codes(*_pair(v, f, BOX8, 8, "z"))
 
 
+@pytest.mark.parametrize("entries", ["0", "60000"])
+def test_tiles_walked_again(entries, monkeypatch):
+    """With no staging buffer or a short one, tiles are walked again by the
+    place pass; their codes are those of the float normals."""
+    m = mg.c2_flower()
+    monkeypatch.setenv("LDNI_STAGE_ENTRIES", entries)
+    _same_codes(*_pair(m.verts, m.tris, m.bbox, 160))
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
 def test_tiles_written_in_many_runs(tile):
     """A stack of 150 thin boxes (300 samples per pixel): each tile's samples
-    are written in many runs and by several workgroups; the codes are those
+    are placed in many runs and by several workgroups; the codes are those
     of the float normals."""
     ldni.set_tile_shape(*tile)
     parts = [mg.box_mesh((1.1, 1.3, 0.5 + 0.04 * k), (6.7, 6.1, 0.5 + 0.04 * k + 0.02)) for k in range(150)]

@@ -214,7 +214,7 @@ def test_device_detected_errors():
 
 def test_pixel_deeper_than_lds_stage():
     """A stack of 2,100 thin boxes: the rays through its middle cross 4,200
-    faces, more samples than one write run holds in LDS, so those pixels
+    faces, more samples than one place run holds in LDS, so those pixels
     are written to their output ranges and sorted there (a bitonic network
     in global memory)."""
     parts = [mg.box_mesh((3.2, 3.2, 0.5 + 0.003 * k), (4.8, 4.8, 0.5 + 0.003 * k + 0.0015))
@@ -237,12 +237,29 @@ def test_tile_list_retry_on_large_triangles():
         compare(_run(v, f, bb, 1024), oracle.sample(v, f, bb, 1024), bb, label="big triangles")
 
 
+@pytest.mark.parametrize("tile", [(0, 0), (32, 32)])
+def test_staging_capacity_does_not_change_results(tile, monkeypatch):
+    """The sampling pass stages hits by tile; tiles that find no room are
+    walked again by the write pass.  No staging, a buffer that holds only
+    some tiles, and the default buffer all give the oracle's result."""
+    ldni.set_tile_shape(*tile)
+    m = mg.c2_flower()
+    w = 160
+    ref = oracle.sample(m.verts, m.tris, m.bbox, w)
+    for entries in ("0", "60000", None):
+        if entries is None:
+            monkeypatch.delenv("LDNI_STAGE_ENTRIES", raising=False)
+        else:
+            monkeypatch.setenv("LDNI_STAGE_ENTRIES", entries)
+        compare(_run(m.verts, m.tris, m.bbox, w), ref, m.bbox, label=f"staging {entries} tile {tile}")
+
+
 @pytest.mark.parametrize("tile", [(0, 0), (32, 32), (256, 4)])
-def test_many_chunks_of_entries_and_pairs(tile):
+def test_large_triangles_and_wide_tiles(tile):
     """Large triangles (a box spanning the image at w = 600): every tile-list
-    entry has a full column of rows, so one tile's entries are walked in
-    several chunks of (entry, row) pairs, and a flower mesh adds many entries
-    per tile; both match the oracle."""
+    entry covers whole tiles (many candidates per entry), 256-pixel-wide
+    tiles included, and a flower mesh adds many entries per tile; both match
+    the oracle."""
     ldni.set_tile_shape(*tile)
     v, f = mg.concat([mg.box_mesh((-0.93, -0.91, -0.95), (0.94, 0.92, 0.9))])
     bb = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
@@ -288,11 +305,13 @@ def test_buffers_reused_across_calls_and_results_kept_alive():
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (32, 32), (8, 8)])
-def test_deep_tiles_written_in_many_runs(tile):
-    """A stack of 150 thin boxes (300 faces on the rays through it): a tile's
-    samples are far more than one write run holds, so each tile is split
-    into runs of pixels taken by several workgroups.  Every call gives the
-    oracle's result."""
+def test_staging_cap_follows_the_deepest_pixel(tile):
+    """A stack of 150 thin boxes (300 faces on the rays through it): more hits
+    per pixel than the first call's staging cap, so its tiles are walked
+    again; later calls of the same shape raise the cap to the deepest pixel
+    seen and stage them, and a tile's samples, far more than one place run
+    holds, are split into runs taken by several workgroups.  Every call
+    gives the oracle's result."""
     ldni.set_tile_shape(*tile)
     parts = [mg.box_mesh((1.1, 1.3, 0.5 + 0.04 * k), (6.7, 6.1, 0.5 + 0.04 * k + 0.02))
              for k in range(150)]
@@ -300,7 +319,7 @@ def test_deep_tiles_written_in_many_runs(tile):
     w = 48
     ref = oracle.sample(v, f, BOX8, w)
     assert int(np.diff(ref[2].offsets.astype(np.int64)).max()) == 300
-    for call in range(2):
+    for call in range(3):
         compare(_run(v, f, BOX8, w), ref, BOX8, label=f"call {call}")
 
 
