@@ -199,6 +199,26 @@ ldni_status ldni_backward(const float *verts, int64_t n_verts, const int32_t *tr
                           const float *const grad_normal[3], float *grad_verts, void *hip_stream);
 
 /*
+ * ldni_backward_noalloc -- ldni_backward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same arguments, result and errors
+ * as ldni_backward, computed by the same kernels; the per-triangle partial
+ * sums live in a fixed scratch array of the library (12 floats per triangle
+ * for up to 262,144 triangles, 12 MiB, held on each device the library runs
+ * on until the process ends) instead of pool memory, and the call makes no
+ * allocation of any kind (no hipMalloc or hipFree, no allocating library
+ * routine).  n_tris above 262,144 gives LDNI_ERR_INVALID_ARG.  Every call on
+ * one device shares that device's scratch, cleared by a kernel at the start
+ * of each call: calls that overlap on one device (different streams or host
+ * threads) race and must be ordered by the caller.  No host
+ * synchronisation.
+ */
+ldni_status ldni_backward_noalloc(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                                  const float bbox[6], int32_t w, uint32_t axis_mask,
+                                  const ldni_axis_view views[3], const float *const grad_depth[3],
+                                  const float *const grad_normal[3], float *grad_verts, void *hip_stream);
+
+/*
  * ldni_boolean -- Boolean operation of two solids given as LDNIs of one axis
  * sampled on the same grid (same box and w), Sec. 4.1 and Fig. 5: in every
  * pixel a solid's samples, read as consecutive (enter, exit) pairs, bound its

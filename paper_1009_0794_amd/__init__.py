@@ -167,11 +167,13 @@ def _view(l: LDNI) -> _lib.AxisView:
 
 
 def ldni_backward(verts, tris, bbox, w: int, ldnis: Dict[int, LDNI], grad_depth=None,
-                  grad_normal=None, grad_verts=None):
+                  grad_normal=None, grad_verts=None, no_alloc=False):
     """Adds to ``grad_verts`` (created as zeros if None) the vertex gradient of
     sum(gd * depth) + sum(gn . normal) over the samples of ``ldnis``;
     ``grad_depth``/``grad_normal`` map axis -> float32 device tensors [n] and
-    [n, 3] (missing axes are zero).  Returns grad_verts."""
+    [n, 3] (missing axes are zero).  Returns grad_verts.  With ``no_alloc``
+    the call goes to ``ldni_backward_noalloc`` (no device allocation by the
+    library; at most 262,144 triangles)."""
     torch = _torch()
     verts, tris = _check_mesh(verts, tris)
     if grad_verts is None:
@@ -200,7 +202,7 @@ def ldni_backward(verts, tris, bbox, w: int, ldnis: Dict[int, LDNI], grad_depth=
     if not (grad_verts.is_contiguous() and grad_verts.dtype == torch.float32
             and tuple(grad_verts.shape) == tuple(verts.shape)):
         raise ValueError("grad_verts must be a contiguous float32 tensor shaped like verts")
-    fn = _lib.lib().ldni_backward
+    fn = _lib.lib().ldni_backward_noalloc if no_alloc else _lib.lib().ldni_backward
     _lib.check(fn(verts.data_ptr(), verts.shape[0], tris.data_ptr(), tris.shape[0], _bbox(bbox), int(w), mask,
                   views, gd, gn, grad_verts.data_ptr(), _stream(verts.device)))
     return grad_verts

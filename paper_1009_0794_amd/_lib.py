@@ -87,6 +87,9 @@ def lib():
     L.ldni_backward.argtypes = [vp, i64, vp, i64, vp, i32, u32, ctypes.POINTER(AxisView),
                                 ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp]
     L.ldni_backward.restype = st
+    L.ldni_backward_noalloc.argtypes = [vp, i64, vp, i64, vp, i32, u32, ctypes.POINTER(AxisView),
+                                ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp]
+    L.ldni_backward_noalloc.restype = st
     L.ldni_batch_create.argtypes = [i32, ctypes.POINTER(MeshDesc), u32, vp, ctypes.POINTER(vp)]
     L.ldni_batch_create.restype = st
     L.ldni_sample_batch.argtypes = [i32, ctypes.POINTER(MeshDesc), u32, vp, ctypes.POINTER(vp)]
@@ -144,4 +147,4 @@ def exported_symbols():
             "ldni_profile_enable", "ldni_profile_read", "ldni_backward", "ldni_batch_create",
             "ldni_batch_run", "ldni_batch_axis", "ldni_batch_free", "ldni_sample_batch",
             "ldni_boolean", "ldni_sample_finish_rgb8", "ldni_classify_nodes", "ldni_node_words",
-            "ldni_offset"]
+            "ldni_offset", "ldni_backward_noalloc"]

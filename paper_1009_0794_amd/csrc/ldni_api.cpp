@@ -1003,6 +1003,32 @@ ldni_status backward_args(const float* verts, int64_t n_verts, const int32_t* tr
   return LDNI_OK;
 }
 
+// The no-allocation backward's scratch: per triangle 3 floats for each image
+// and 3 for the normal sums (12 floats), for up to kNoAllocTris triangles.
+// Each device holds its own copy from the library's load to the process
+// end; host code uses only the address hipGetSymbolAddress gives per device.
+constexpr int64_t kNoAllocTris = 262144;
+__device__ __align__(256) float scratch[12 * kNoAllocTris];
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[64] = {};
+
+// The scratch array's device address on the current device (looked up once
+// per device, with that device current).
+ldni_status scratch_address(float** out) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  if (device < 0 || device >= 64) return fail(LDNI_ERR_DEVICE, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    if (!p) return fail(LDNI_ERR_DEVICE, "scratch address");
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return LDNI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1031,6 +1057,33 @@ ldni_status ldni_backward(const float* verts, int64_t n_verts, const int32_t* tr
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, (int64_t)(per * (nimg + 1) / 4), stream);
   if (e == hipSuccess) e = timed("backward", stream, [&] { return launch_backward(args, stream); });
   cache_put(ws, ws_bytes, stream);
+  if (e != hipSuccess) return hip_fail(e, "backward kernels");
+  return LDNI_OK;
+}
+
+ldni_status ldni_backward_noalloc(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                                  const float bbox[6], int32_t w, uint32_t axis_mask,
+                                  const ldni_axis_view views[3], const float* const grad_depth[3],
+                                  const float* const grad_normal[3], float* grad_verts, void* hip_stream) {
+  if (n_tris > kNoAllocTris)
+    return fail(LDNI_ERR_INVALID_ARG, "n_tris beyond the 262144 triangles of the no-allocation scratch");
+  BackwardArgs args{};
+  int nimg = 0;
+  ldni_status st = backward_args(verts, n_verts, tris, n_tris, bbox, w, axis_mask, views, grad_depth,
+                                 grad_normal, grad_verts, args, &nimg);
+  if (st != LDNI_OK || nimg == 0) return st;
+  float* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != LDNI_OK) return st;
+  const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  // the same layout as ldni_backward's workspace, without the 256-byte
+  // rounding: the sums of image k at k * 3T, the normal sums at nimg * 3T
+  const int64_t per = 3 * n_tris;
+  for (int k = 0; k < nimg; ++k) args.axis[k].acc = ws + k * per;
+  args.gnsum = ws + nimg * per;
+  // the last call's sums are still there: cleared by a fill kernel
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, per * (nimg + 1), stream);
+  if (e == hipSuccess) e = launch_backward(args, stream);
   if (e != hipSuccess) return hip_fail(e, "backward kernels");
   return LDNI_OK;
 }
