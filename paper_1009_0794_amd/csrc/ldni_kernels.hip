@@ -249,17 +249,31 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
     m.tnorm[t] = tn;
   }
 
+  // The images of one mesh share its box and w, so a world axis has the
+  // same pixel centres in both images that use it: the first centre at or
+  // above the triangle's min and max on each world axis serves both.
+  int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
+  {
+    uint32_t need = 0;
+    for (int k = 0; k < nimg; ++k) need |= (1u << image_at(k).u) | (1u << image_at(k).v);
+    for (int d = 0; d < 3; ++d) {
+      if (!((need >> d) & 1u)) continue;
+      int k = 0;  // an image that images axis d, with its centre formula for it
+      while (image_at(k).u != d && image_at(k).v != d) ++k;
+      const Image& im = image_at(k);
+      const bool as_u = im.u == d;
+      const double lo = as_u ? im.lo_u : im.lo_v, h = as_u ? im.h_u : im.h_v;
+      const double inv_h = as_u ? im.inv_h_u : im.inv_h_v, slack = as_u ? im.slack_u : im.slack_v;
+      const float mn = fminf(fminf(P[d], P[3 + d]), P[6 + d]);
+      const float mx = fmaxf(fmaxf(P[d], P[3 + d]), P[6 + d]);
+      lo_c[d] = first_centre_at_or_above(lo, h, inv_h, slack, im.w, mn);
+      hi_c[d] = first_centre_at_or_above(lo, h, inv_h, slack, im.w, mx);
+    }
+  }
   for (int k = 0; k < nimg; ++k) {
     const Image& im = image_at(k);
-    const float umin = fminf(fminf(P[im.u], P[3 + im.u]), P[6 + im.u]);
-    const float umax = fmaxf(fmaxf(P[im.u], P[3 + im.u]), P[6 + im.u]);
-    const float vmin = fminf(fminf(P[im.v], P[3 + im.v]), P[6 + im.v]);
-    const float vmax = fmaxf(fmaxf(P[im.v], P[3 + im.v]), P[6 + im.v]);
     Rect r;
-    const int i0 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.slack_u, im.w, umin);
-    const int i1 = first_centre_at_or_above(im.lo_u, im.h_u, im.inv_h_u, im.slack_u, im.w, umax);
-    const int j0 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.slack_v, im.w, vmin);
-    const int j1 = first_centre_at_or_above(im.lo_v, im.h_v, im.inv_h_v, im.slack_v, im.w, vmax);
+    const int i0 = lo_c[im.u], i1 = hi_c[im.u], j0 = lo_c[im.v], j1 = hi_c[im.v];
     if (i0 < i1 && j0 < j1) {
       r.i0 = (int16_t)i0; r.i1 = (int16_t)i1; r.j0 = (int16_t)j0; r.j1 = (int16_t)j1;
     } else {
