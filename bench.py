@@ -402,7 +402,7 @@ def measure_fwd_bwd(ldni, torch, mg, reps):
                               "frac": round(bwd_bytes / (kb[1] / kb[0] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
                               if kb[1] > 0 else None,
                               # counter bytes of one call (both backward kernels)
-                              "traffic": read_traffic("flower-512-fwdbwd", "backward")},
+                              "traffic": read_traffic("flower-512-fwdbwd", "backward", "ldni_backward.hip")},
     }
 
 

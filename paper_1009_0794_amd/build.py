@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libldni.so")
-SOURCES = ["ldni_kernels.hip", "ldni_boolean.hip", "ldni_nodes.hip", "ldni_offset.hip", "ldni_api.cpp"]
+SOURCES = ["ldni_kernels.hip", "ldni_backward.hip", "ldni_boolean.hip", "ldni_nodes.hip", "ldni_offset.hip",
+           "ldni_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
