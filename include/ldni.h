@@ -319,12 +319,13 @@ ldni_status ldni_node_words(int32_t w, uint64_t *n_words);
  *   eps     finite, >= 0 (the paper uses 1e-5).
  *   out     a new three-axis result owned by the caller (ldni_free).
  * A ray may meet any number of events (its paired samples plus two per
- * sphere that hits it): they are swept in depth windows of 1024.  A ray
- * fails with LDNI_ERR_OVERFLOW when more than 896 of its events share one
- * float32 depth or its result has more than 512 end points before small
- * volumes are removed; fewer than 2^32 sphere hits over all rays and result
- * samples per axis.  Two host synchronisations (the size of the per-ray
- * sphere lists, the result size).
+ * sphere that hits it) and have any number of end points: events are swept
+ * in depth windows of 1024, a group of equal float32 depth too large for a
+ * window is taken whole by its sums, and end points are passed to the small
+ * volume removal in batches of 512.  Fewer than 2^32 sphere hits over all
+ * rays and result samples per axis (else LDNI_ERR_OVERFLOW).  Two host
+ * synchronisations (the size of the per-ray sphere lists, the result
+ * size).
  */
 ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], float r, float eps,
                         void *hip_stream, ldni_result **out);

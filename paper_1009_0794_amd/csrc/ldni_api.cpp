@@ -1437,9 +1437,6 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   }
   if (rb[0] & kStatusMismatch)
     return bail(fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples"));
-  if (rb[0] & kStatusOutFull)
-    return bail(fail(LDNI_ERR_OVERFLOW, "a ray has more than 896 events at one depth or more than 512 end "
-                                        "points before small volumes are removed"));
   if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more result samples on one axis"));
   const uint64_t n_out[3] = {rb[1], rb[2], rb[3]};
   const uint32_t max_layers[3] = {rb[4], rb[5], rb[6]};

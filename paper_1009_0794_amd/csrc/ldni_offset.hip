@@ -325,8 +325,107 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   int carry_h = 0, carry_s = 0;
   bool prev_res = false;
   uint32_t n_emit = 0;
-  bool failed = false;
-  while (more && !failed) {
+  uint32_t kept = 0;         // end-point pairs kept so far
+  uint32_t big = 0xffffffffu;  // a depth whose group was found larger than a window
+  auto depth_of = [&](uint64_t k) -> float {
+    if (!(k & kSphereOrder)) return H.depth[o0 + (uint32_t)(k & 0x7fffffffu)];
+    return sphere_sample(g, a, cu, cv, (uint32_t)((k & 0x7fffffffu) >> 1), (k & 1u) != 0).depth;
+  };
+  // Small interval removal over the first np end-point pairs of emit, which
+  // are then counted or written (pairs are independent volumes, so the
+  // emitted end points are taken in batches); an unpaired last end point
+  // moves to the front.
+  auto flush = [&](uint32_t np) {
+    for (uint32_t m0 = 0; m0 < np; m0 += 64) {
+      const uint32_t m = m0 + lane;
+      bool keep = false;
+      uint64_t ea = 0, eb = 0;
+      if (m < np) {
+        ea = emit[2 * m];
+        eb = emit[2 * m + 1];
+        const double th = (double)depth_of(eb) - (double)depth_of(ea);
+        keep = th > 0.0 && th >= g.eps;
+      }
+      const uint64_t km = __ballot(keep);
+      const uint32_t rank = kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull));
+      // the sweep is deterministic, so the write pass keeps what the count
+      // pass counted; a disagreement (checked at the end) never writes
+      // outside the ray's slot
+      if (kWrite && keep && 2 * rank + 1 < cnt) {
+        write_event(g, a, p, cu, cv, ea, (size_t)out + 2 * rank);
+        write_event(g, a, p, cu, cv, eb, (size_t)out + 2 * rank + 1);
+      }
+      if (!kWrite && keep && g.saved && 2 * rank + 1 < (uint32_t)kOffsetSaved) {
+        g.saved[(size_t)ray * kOffsetSaved + 2 * rank] = ea;
+        g.saved[(size_t)ray * kOffsetSaved + 2 * rank + 1] = eb;
+      }
+      kept += (uint32_t)__popcll(km);
+    }
+    wave_sync();
+    const uint32_t rest = n_emit - 2 * np;
+    if (rest > 0 && lane == 0) emit[0] = emit[2 * np];
+    n_emit = rest;
+    wave_sync();
+  };
+  while (more) {
+    if (big == lower) {
+      // The group of equal depth `big`, from its sums over all the ray's
+      // events: H's samples in it, the spheres entering minus those leaving
+      // in it, and its first event (the smallest key).  The result state
+      // after the group against the one before decides whether it emits,
+      // exactly as the sweep decides for a group inside a window.
+      uint32_t ch = 0;
+      int cs = 0;
+      uint64_t first = ~0ull;
+      for (uint32_t k0 = 0; k0 < nh; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        if (k < nh && orderable(H.depth[o0 + k]) == big) {
+          ++ch;
+          first = min(first, ((uint64_t)big << 32) | k);
+        }
+      }
+      for (uint32_t base = l0; base < l1; base += 64) {
+        const uint32_t e = base + lane;
+        if (e < l1) {
+          const uint32_t sph = g.list[e];
+          const double* c = g.centres + 3 * (size_t)sph;
+          const double du = cu - c[u], dv = cv - c[v];
+          const double rho2 = du * du + dv * dv;
+          if (rho2 < r2) {
+            const double t = sqrt(r2 - rho2);
+            const float d0 = (float)((c[a] - t) - g.lo[a]), d1 = (float)((c[a] + t) - g.lo[a]);
+            if (orderable(d0) == big) {
+              ++cs;
+              first = min(first, ((uint64_t)big << 32) | kSphereOrder | (sph << 1));
+            }
+            if (orderable(d1) == big) {
+              --cs;
+              first = min(first, ((uint64_t)big << 32) | kSphereOrder | (sph << 1) | 1u);
+            }
+          }
+        }
+      }
+      for (int d = 32; d >= 1; d >>= 1) {
+        ch += (uint32_t)__shfl_xor((int)ch, d, 64);
+        cs += __shfl_xor(cs, d, 64);
+        const uint64_t o = __shfl_xor(first, d, 64);
+        first = min(first, o);
+      }
+      carry_h += (int)ch;
+      carry_s += cs;
+      const bool res = g.union_op ? ((carry_h & 1) != 0 || carry_s > 0) : ((carry_h & 1) != 0 && carry_s <= 0);
+      if (res != prev_res) {
+        if (n_emit + 1 > (uint32_t)kOffsetEmit) flush(n_emit / 2);
+        if (lane == 0) emit[n_emit] = first;
+        ++n_emit;
+        wave_sync();
+      }
+      prev_res = res;
+      more = big != 0xffffffffu;
+      lower = big + 1u;
+      big = 0xffffffffu;
+      continue;
+    }
     uint32_t upper = 0;
     bool bounded = false;
     uint32_t n = 0;
@@ -354,7 +453,9 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
         bounded = true;
         upper = cut;
         n = m;
-        if (m == 0) failed = true;  // one group of equal depth larger than a window
+        // one group of equal depth fills the window: the window ends before
+        // it and the group is taken whole, by its sums, when it is reached
+        if (m == 0) big = cut;
         h0 = has0 && in_window(k0);
         h1 = has1 && in_window(k1);
         wave_sync();
@@ -366,7 +467,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       if (h1) key[pos] = k1;
       n += (uint32_t)__popcll(m0) + (uint32_t)__popcll(m1);
     };
-    for (uint32_t k0 = 0; k0 < nh && !failed; k0 += 64) {
+    for (uint32_t k0 = 0; k0 < nh; k0 += 64) {
       const uint32_t k = k0 + lane;
       const bool has = k < nh;
       const uint64_t kk = has ? (((uint64_t)orderable(H.depth[o0 + k]) << 32) | k) : 0ull;
@@ -384,7 +485,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       ca1 = c[a];
     }
     if (l0 + 64 + lane < l1) sph2 = g.list[l0 + 64 + lane];
-    for (uint32_t base = l0; base < l1 && !failed; base += 64) {
+    for (uint32_t base = l0; base < l1; base += 64) {
       const uint32_t e = base + lane;
       const uint32_t sph = sph1;
       const double pu = cu1, pv = cv1, pa = ca1;
@@ -411,7 +512,6 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       }
       append(ka, hit, kb, hit);
     }
-    if (failed) break;
     wave_sync();
     if (n > 0) {
       wave_sort(key, n);
@@ -443,10 +543,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
         }
         const uint64_t em = __ballot(e);
         const uint32_t ne = (uint32_t)__popcll(em);
-        if (n_emit + ne > (uint32_t)kOffsetEmit) {
-          failed = true;
-          break;
-        }
+        if (n_emit + ne > (uint32_t)kOffsetEmit) flush(n_emit / 2);  // (then at most one is left)
         if (e) emit[n_emit + (uint32_t)__popcll(em & ((1ull << lane) - 1ull))] = key[fq];
         n_emit += ne;
         carry_h = __shfl(ph, 63);
@@ -462,45 +559,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
     more = bounded;
     lower = upper;
   }
-  if (failed) {
-    // the count pass flags the ray as too full for the call; in the write
-    // pass (the count pass kept this ray) it is a disagreement of the passes
-    if (lane == 0) atomicOr(g.status, kWrite ? kStatusMismatch : kStatusOutFull);
-    if (!kWrite && lane == 0) g.counts[a][p] = 0;
-    return;
-  }
-  // small interval removal over the end-point pairs, then count or write
-  const uint32_t pairs = n_emit / 2;
-  uint32_t kept = 0;
-  auto depth_of = [&](uint64_t k) -> float {
-    if (!(k & kSphereOrder)) return H.depth[o0 + (uint32_t)(k & 0x7fffffffu)];
-    return sphere_sample(g, a, cu, cv, (uint32_t)((k & 0x7fffffffu) >> 1), (k & 1u) != 0).depth;
-  };
-  for (uint32_t m0 = 0; m0 < pairs; m0 += 64) {
-    const uint32_t m = m0 + lane;
-    bool keep = false;
-    uint64_t ea = 0, eb = 0;
-    if (m < pairs) {
-      ea = emit[2 * m];
-      eb = emit[2 * m + 1];
-      const double th = (double)depth_of(eb) - (double)depth_of(ea);
-      keep = th > 0.0 && th >= g.eps;
-    }
-    const uint64_t km = __ballot(keep);
-    const uint32_t rank = kept + (uint32_t)__popcll(km & ((1ull << lane) - 1ull));
-    // the sweep is deterministic, so the write pass keeps what the count
-    // pass counted; a disagreement (checked below) never writes outside the
-    // ray's slot
-    if (kWrite && keep && 2 * rank + 1 < cnt) {
-      write_event(g, a, p, cu, cv, ea, (size_t)out + 2 * rank);
-      write_event(g, a, p, cu, cv, eb, (size_t)out + 2 * rank + 1);
-    }
-    if (!kWrite && keep && g.saved && 2 * rank + 1 < (uint32_t)kOffsetSaved) {
-      g.saved[(size_t)ray * kOffsetSaved + 2 * rank] = ea;
-      g.saved[(size_t)ray * kOffsetSaved + 2 * rank + 1] = eb;
-    }
-    kept += (uint32_t)__popcll(km);
-  }
+  flush(n_emit / 2);
   if (!kWrite && lane == 0) g.counts[a][p] = 2 * kept;
   // more or fewer end points than the count pass kept: slots unwritten or
   // surplus ones dropped, so the call fails

@@ -159,31 +159,46 @@ def test_large_radius_in_depth_windows(w, r):
         _same(got[a], ref[a], f"axis {a}")
 
 
-def test_too_many_end_points_is_an_error():
-    """A ray whose result has more than 512 end points before small volumes
-    are removed (300 separate volumes of the solid and a tiny radius) fails
-    with LDNI_ERR_OVERFLOW; the next call works."""
-    w = 4
+def _one_ray_solid(w, depths, pixel=5):
+    """x-axis LDNI with the given depths on one ray, y and z empty."""
+    n = len(depths)
     off = np.zeros(w * w + 1, np.uint32)
-    off[6:] = 600
-    d = np.concatenate([[0.002 * k, 0.002 * k + 0.001] for k in range(300)]).astype(np.float32)
-    x = oracle.AxisLDNI(w=w, offsets=off, depth=d, normal=np.zeros((600, 3), np.float32),
-                        tri=np.arange(600, dtype=np.int32))
+    off[pixel + 1:] = n
+    x = oracle.AxisLDNI(w=w, offsets=off, depth=np.asarray(depths, np.float32),
+                        normal=np.zeros((n, 3), np.float32), tri=np.arange(n, dtype=np.int32))
     e = oracle.AxisLDNI(w=w, offsets=np.zeros(w * w + 1, np.uint32), depth=np.zeros(0, np.float32),
                         normal=np.zeros((0, 3), np.float32), tri=np.zeros(0, np.int32))
-    G = {0: _to_gpu(0, x), 1: _to_gpu(1, e), 2: _to_gpu(2, e)}
-    with pytest.raises(LDNIError) as err:
-        ldni.offset(G, BBOX, 1e-5)
-    assert err.value.code == 4
-    # 200 volumes (400 end points) fit
-    off2 = np.zeros(w * w + 1, np.uint32)
-    off2[6:] = 400
-    x2 = oracle.AxisLDNI(w=w, offsets=off2, depth=d[:400].copy(), normal=np.zeros((400, 3), np.float32),
-                         tri=np.arange(400, dtype=np.int32))
-    ref = oo.offset({0: x2, 1: e, 2: e}, BBOX, w, 1e-5)
-    got = ldni.offset({0: _to_gpu(0, x2), 1: G[1], 2: G[2]}, BBOX, 1e-5)
+    return {0: x, 1: e, 2: e}
+
+
+@pytest.mark.parametrize("volumes", [300, 700])
+def test_rays_with_many_end_points(volumes):
+    """A ray whose result has 600 and 1,400 end points before small volumes
+    are removed (that many separate volumes of the solid and a tiny radius),
+    more than one batch of 512: the end points go to the small volume
+    removal in batches and the result matches the oracle."""
+    w = 4
+    d = np.concatenate([[0.002 * k, 0.002 * k + 0.001] for k in range(volumes)]).astype(np.float32)
+    L = _one_ray_solid(w, d)
+    ref = oo.offset(L, BBOX, w, 1e-5)
+    assert int(np.diff(ref[0].offsets.astype(np.int64)).max()) == 2 * volumes
+    got = ldni.offset({a: _to_gpu(a, L[a]) for a in range(3)}, BBOX, 1e-5)
     for a in range(3):
-        _same(got[a], ref[a], f"axis {a}")
+        _same(got[a], ref[a], f"{volumes} volumes, axis {a}")
+
+
+@pytest.mark.parametrize("r", [1e-5, -1e-5, 0.3])
+def test_group_of_equal_depth_larger_than_a_window(r):
+    """1,200 samples of the solid at one float32 depth on one ray, with
+    volumes before and after it: the group fills a whole window (1,024
+    events) and is taken whole; the result matches the oracle."""
+    w = 4
+    d = ([0.001 * k for k in range(40)] + [0.5] * 1200 + [0.6 + 0.001 * k for k in range(40)])
+    L = _one_ray_solid(w, d)
+    ref = oo.offset(L, BBOX, w, r)
+    got = ldni.offset({a: _to_gpu(a, L[a]) for a in range(3)}, BBOX, r)
+    for a in range(3):
+        _same(got[a], ref[a], f"r={r} axis {a}")
 
 
 def test_bad_offsets_rejected():
