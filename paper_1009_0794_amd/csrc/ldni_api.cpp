@@ -541,8 +541,14 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   const size_t o_tcnt = off; off += sizeof(uint32_t) * (size_t)(n_all + 1);
   const size_t o_treg = (off + 15) & ~(size_t)15; off = o_treg + sizeof(uint32_t) * (size_t)(n_all + 1);
   const size_t o_tcur = off; off += sizeof(uint32_t) * (size_t)n_all;
+  const size_t o_tovf = off; off += sizeof(uint32_t) * (size_t)n_all;
+  off = (off + 7) & ~(size_t)7;
+  const size_t o_tpack = off; off += sizeof(uint64_t) * (size_t)n_all;
   const int64_t n_clear = (int64_t)(off / sizeof(uint32_t));
   off = align_up(off);
+  const int64_t n_chunks = (n_tris + kBinChunkTris - 1) / kBinChunkTris;
+  const size_t o_brec = off; off = align_up(off + sizeof(uint4) * kBinSlots * (size_t)n_chunks);
+  const size_t o_bnrec = off; off = align_up(off + sizeof(uint32_t) * (size_t)n_chunks);
   const size_t o_soup = off; off = align_up(off + sizeof(float) * 9 * (size_t)n_tris);
   const size_t o_tnorm = off; off = align_up(off + sizeof(float4) * (size_t)n_tris);
   size_t o_rect[kMaxImages], o_counts[kMaxImages], o_tstage[kMaxImages], o_thits[kMaxImages];
@@ -581,6 +587,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   ms.soup = reinterpret_cast<float*>(ws + o_soup);
   ms.tnorm = reinterpret_cast<float4*>(ws + o_tnorm);
   ms.status = status;
+  ms.bin_rec = reinterpret_cast<uint4*>(ws + o_brec);
+  ms.bin_nrec = reinterpret_cast<uint32_t*>(ws + o_bnrec);
 
   ImageSet& set = p->set;
   set.n = nimg;
@@ -609,6 +617,8 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     im.n_tris = n_tris;
     im.tile_cnt = reinterpret_cast<uint32_t*>(ws + o_tcnt) + k * n_tiles;
     im.tile_cur = reinterpret_cast<uint32_t*>(ws + o_tcur) + k * n_tiles;
+    im.tile_ovf = reinterpret_cast<uint32_t*>(ws + o_tovf) + k * n_tiles;
+    im.tile_pack = reinterpret_cast<uint64_t*>(ws + o_tpack) + k * n_tiles;
     im.tile_region = reinterpret_cast<uint32_t*>(ws + o_treg) + k * n_tiles;
     im.tile_list = nullptr;
     im.counts = reinterpret_cast<uint32_t*>(ws + o_counts[k]);
@@ -678,7 +688,9 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
   // each other in one array), and over their candidate counts (the images'
   // staging regions follow each other in the staging buffer)
   STEP(timed("scan_tiles", stream, [&] {
-         return launch_tile_scan(tile_cnt_all, tile_region_all, n_all, stage_layers * (uint32_t)(tw * th),
+         return launch_tile_scan(reinterpret_cast<const uint64_t*>(ws + o_tpack),
+                                 reinterpret_cast<const uint32_t*>(ws + o_tovf), tile_cnt_all, tile_region_all,
+                                 n_all, stage_layers * (uint32_t)(tw * th),
                                  scan_scratch, status, stream);
        }), "tile scan");
   // Tile lists are sized from the largest entries-per-triangle ratio seen so
@@ -724,7 +736,7 @@ ldni_status ldni_sample_begin(const float* verts, int64_t n_verts, const int32_t
     max_k[k] = status + 1 + k;
   }
   for (int attempt = 0; attempt < 2; ++attempt) {
-    STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(set, stream); }), "bin scatter kernel");
+    STEP(timed("bin_scatter", stream, [&] { return launch_bin_scatter(ms, set, stream); }), "bin scatter kernel");
     STEP(timed("sample", stream, [&] { return launch_sample(set, stream); }), "sampling kernel");
     STEP(timed("scan_pixels", stream, [&] {
            return launch_scan_segments(counts_k, offsets_k, nimg, npix, scan_scratch, status, stream, max_k);
@@ -1596,7 +1608,7 @@ hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)(b->region_arena - b->tile_arena) + (int64_t)b->total_tiles + 1, s));
   Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
   Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles and candidates
-  Q(launch_tile_scan(b->tile_arena, b->region_arena, (int64_t)b->total_tiles,
+  Q(launch_tile_scan(nullptr, nullptr, b->tile_arena, b->region_arena, (int64_t)b->total_tiles,
                      b->stage_layers * (uint32_t)(b->small ? 256 : 1024), b->scan_scratch, b->dev.status, s));
   Q(launch_batch_scatter(b->dev, b->bin_block_start.back(), s));
   Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, b->small, s));

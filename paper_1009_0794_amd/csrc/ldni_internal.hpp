@@ -48,7 +48,11 @@ struct Image {
   int64_t n_tris;
   // workspace
   uint32_t* tile_cnt;   // [n_tiles + 1] entries per tile -> exclusive offsets
-  uint32_t* tile_cur;   // [n_tiles] scatter cursors
+  uint32_t* tile_cur;   // [n_tiles] scatter cursors (of the entries counted in tile_ovf)
+  uint32_t* tile_ovf;   // [n_tiles] entries counted outside the chunk tables (listed
+                        // first in the tile), or null where binning is per triangle
+  uint64_t* tile_pack;  // [n_tiles] chunk binning: entries reserved by the chunk
+                        // tables (low half) and candidates (high half), or null
   int2* tile_list;      // entries grouped by tile: (triangle id, its candidate
                         // rectangle in the tile: x0 | y0 << 8 | (width - 1) << 16
                         // | (height - 1) << 24, tile-local pixels)
@@ -111,7 +115,16 @@ struct MeshSetup {
   float4* tnorm;  // [T] unit face normals (x, y, z, 0)
   Rect* rect[kMaxImages];
   uint32_t* status;
+  // binning by chunks of kBinChunkTris triangles: per chunk up to kBinSlots
+  // records (image << 30 | tile, table slot, first reserved list entry, 0)
+  // and their number
+  uint4* bin_rec;
+  uint32_t* bin_nrec;
 };
+
+// Triangles per binning chunk and the size of its LDS table of tiles.
+constexpr int kBinChunkTris = 512;
+constexpr int kBinSlots = 1024;
 
 // Fills the derived fields of an image (inverse steps, centre slack, tile
 // shifts) from w, the tile shape and lo/h of both image axes.
@@ -119,10 +132,14 @@ void finish_image_geometry(Image& im);
 
 // ---- launchers (ldni_kernels.hip) ----
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
-// per triangle: gather, validate, normal, candidate rectangles, and the
-// count of its tiles on every image (tile_cnt, cleared before)
+// per chunk of triangles: gather, validate, normal, candidate rectangles,
+// and the entries and candidates of every tile met, reserved per chunk
+// (tile_cnt, tile_region, tile_ovf cleared before; m.bin_rec/bin_nrec
+// written)
 hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s);
-hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s);
+// per chunk: the tile-list entries at the ranges launch_setup reserved (after
+// the tile scan; tile_cur cleared before)
+hipError_t launch_bin_scatter(const MeshSetup& m, const ImageSet& set, hipStream_t s);
 // Sampling pass: per-pixel counts, and every hit staged by tile (see Image).
 hipError_t launch_sample(const ImageSet& set, hipStream_t s);
 // Work items of the place pass: scans the plan the sampling pass wrote and
@@ -318,11 +335,14 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, void* scrat
 hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out, int nseg, int64_t n,
                                 void* scratch, uint32_t* status, hipStream_t s,
                                 uint32_t* const* max_out = nullptr);
-// The tile scan: entry counts -> list offsets (as launch_scan), and in the
-// same launches candidate counts -> staging regions, each tile's count
-// capped at region_cap and the prefix saturating at 2^32 - 1 (in place
-// allowed; n + 1 slots each).  scratch: scan_scratch_bytes(n, 2).
-hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n, uint32_t region_cap,
-                            void* scratch, uint32_t* status, hipStream_t s);
+// The tile scan: entry counts -> list offsets (as launch_scan, into
+// tile_cnt), and in the same launches candidate counts -> staging regions
+// (tile_region), each tile's count capped at region_cap and the prefix
+// saturating at 2^32 - 1 (n + 1 slots each).  The counts come from tile_pack
+// and tile_ovf when tile_pack is given, else from tile_cnt and tile_region
+// themselves (in place).  scratch: scan_scratch_bytes(n, 2).
+hipError_t launch_tile_scan(const uint64_t* tile_pack, const uint32_t* tile_ovf, uint32_t* tile_cnt,
+                            uint32_t* tile_region, int64_t n, uint32_t region_cap, void* scratch, uint32_t* status,
+                            hipStream_t s);
 
 }  // namespace ldni

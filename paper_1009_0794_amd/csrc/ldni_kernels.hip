@@ -186,12 +186,12 @@ __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
 template <bool kScatter>
 __device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r);
 
-// kCount: also count the triangle's tiles on every image (all 64 lanes of
-// every wave must then call this; lanes past the mesh count nothing).
-template <bool kCount, class ImageAt>
-__device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
-  const bool live = t < m.n_tris;
-  if (!kCount && !live) return;
+// One triangle (live: t is a triangle of the mesh): gather and validate its
+// vertices, store them and its unit face normal, and its candidate rectangle
+// on every image (also returned in r).
+template <class ImageAt>
+__device__ void setup_one(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t, bool live,
+                          Rect* r) {
   int32_t ia = 0, ib = 0, ic = 0;
   if (live) {
     ia = m.tris[3 * t];
@@ -270,24 +270,33 @@ __device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at,
       hi_c[d] = first_centre_at_or_above(lo, h, inv_h, slack, im.w, mx);
     }
   }
-  for (int k = 0; k < nimg; ++k) {
+  // (loops over the images are unrolled so that r stays in registers)
+#pragma unroll
+  for (int k = 0; k < kMaxImages; ++k) {
+    if (k >= nimg) break;
     const Image& im = image_at(k);
-    Rect r;
     const int i0 = lo_c[im.u], i1 = hi_c[im.u], j0 = lo_c[im.v], j1 = hi_c[im.v];
     if (i0 < i1 && j0 < j1) {
-      r.i0 = (int16_t)i0; r.i1 = (int16_t)i1; r.j0 = (int16_t)j0; r.j1 = (int16_t)j1;
+      r[k].i0 = (int16_t)i0; r[k].i1 = (int16_t)i1; r[k].j0 = (int16_t)j0; r[k].j1 = (int16_t)j1;
     } else {
-      r.i0 = r.i1 = r.j0 = r.j1 = 0;
+      r[k].i0 = r[k].i1 = r[k].j0 = r[k].j1 = 0;
     }
-    if (live) m.rect[k][t] = r;
-    if (kCount) bin_rect<false>(im, t, live, r);
+    if (live) m.rect[k][t] = r[k];
   }
 }
 
-__global__ void __launch_bounds__(kBlock) setup_kernel(MeshSetup m, ImageSet set) {
-  setup_triangle<true>(m, set.n, [&](int k) -> const Image& { return set.img[k]; },
-                       (int64_t)blockIdx.x * kBlock + threadIdx.x);
+// setup_one for triangle t, then the count of its tiles on every image (all
+// 64 lanes of every wave call this; lanes past the mesh count nothing).
+template <class ImageAt>
+__device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
+  const bool live = t < m.n_tris;
+  Rect r[kMaxImages];
+  setup_one(m, nimg, image_at, t, live, r);
+#pragma unroll
+  for (int k = 0; k < kMaxImages; ++k)
+    if (k < nimg) bin_rect<false>(image_at(k), t, live, r[k]);
 }
+
 
 // ---------------------------------------------------------------------------
 // binning
@@ -393,9 +402,240 @@ __device__ void bin_triangles(const Image& im, int64_t t) {
   bin_rect<kScatter>(im, t, live, r);
 }
 
+// ---------------------------------------------------------------------------
+// setup and binning by chunks of triangles
+// ---------------------------------------------------------------------------
+// A workgroup takes kBinChunkTris consecutive triangles; mesh order is
+// spatially coherent for most meshes, so a chunk meets few tiles.  Global
+// atomics are the scarce resource here (a few tens of G per second on the
+// whole chip against hundreds of G plain stores), so they are spent per
+// (chunk, tile), not per (triangle, tile) or (wave, tile):
+//   count    every (triangle, tile) pair is added into an LDS table keyed by
+//            (image, tile), one addition per group of a wave's lanes that
+//            share the tile; at the end the chunk reserves a range of each
+//            tile's list with one global atomic per table slot and records
+//            (key, slot, base of the range)
+//   scatter  the table is rebuilt slot for slot from the records; a pair's
+//            list position is its slot's range start plus a rank from an LDS
+//            atomic
+// A key that finds no free slot within kBinProbe probes of its home slot is
+// counted in tile_ovf and scattered with a global cursor in front of the
+// tile's reserved ranges.  Slots never free, so such a key misses in the
+// rebuilt table as well, and every pair of one key takes the same path.
+constexpr uint32_t kBinEmpty = 0xffffffffu;
+constexpr int kBinProbe = 16;
+constexpr int kBinSlotBits = 10;
+static_assert((1 << kBinSlotBits) == kBinSlots, "table size");
+constexpr int kBinBlock = 512;  // 8 waves per workgroup, one triangle per thread
+static_assert(kBinChunkTris % kBinBlock == 0, "whole sub-chunks");
+
+struct BinLds {
+  uint32_t key[kBinSlots];  // (image << 30) | tile, or kBinEmpty
+  uint32_t a[kBinSlots];    // count: entries; scatter: list position of the slot's range
+  uint32_t b[kBinSlots];    // count: candidates; scatter: entries placed so far
+  uint32_t n_rec;
+};
+
+// A wave's lanes split into runs of consecutive lanes with equal keys (key
+// < 0: no entry, never in a run).  For a lane with an entry: leader = first
+// lane of its run, rank = lane - leader; group = lanes in the run (valid at
+// the leader).
+struct LaneRuns {
+  int leader;
+  uint32_t rank, group;
+};
+__device__ __forceinline__ LaneRuns lane_runs(int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool live = key >= 0;
+  const uint64_t heads = __ballot(live && (lane == 0 || prev != key));
+  const uint64_t breaks = heads | __ballot(!live);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
+  const uint64_t mine = heads & upto;
+  LaneRuns r;
+  r.leader = mine ? 63 - __clzll((long long)mine) : lane;
+  r.rank = (uint32_t)(lane - r.leader);
+  const uint64_t above = breaks & ~upto;
+  r.group = (uint32_t)((above ? __ffsll((unsigned long long)above) - 1 : 64) - lane);
+  return r;
+}
+
+__device__ __forceinline__ uint32_t bin_home(uint32_t hk) { return (hk * 2654435761u) >> (32 - kBinSlotBits); }
+
+__device__ __forceinline__ int bin_insert(BinLds& h, uint32_t hk) {
+  uint32_t s = bin_home(hk);
+  for (int i = 0; i < kBinProbe; ++i) {
+    const uint32_t prev = atomicCAS(&h.key[s], kBinEmpty, hk);
+    if (prev == kBinEmpty || prev == hk) return (int)s;
+    s = (s + 1) & (kBinSlots - 1);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int bin_find(const BinLds& h, uint32_t hk) {
+  uint32_t s = bin_home(hk);
+  for (int i = 0; i < kBinProbe; ++i) {
+    const uint32_t k = h.key[s];
+    if (k == hk) return (int)s;
+    if (k == kBinEmpty) return -1;
+    s = (s + 1) & (kBinSlots - 1);
+  }
+  return -1;
+}
+
+// The (triangle, tile) pairs of one image for one triangle per lane, counted
+// into (kScatter false) or placed from (true) the chunk table.  All 64 lanes
+// of every wave call this (t beyond the chunk = no tiles).
 template <bool kScatter>
-__global__ void __launch_bounds__(kBlock) bin_kernel(ImageSet set) {
-  bin_triangles<kScatter>(set.img[blockIdx.y], (int64_t)blockIdx.x * kBlock + threadIdx.x);
+__device__ void bin_rect_chunk(const Image& im, uint32_t kimg, int64_t t, bool live, const Rect& r, BinLds& h) {
+  const int lane = threadIdx.x & 63;
+  auto tile_x = [&](int i) { return im.tw_shift >= 0 ? i >> im.tw_shift : i / im.tw; };
+  auto tile_y = [&](int j) { return im.th_shift >= 0 ? j >> im.th_shift : j / im.th; };
+  int tx0 = 0, ty0 = 0, nx = 1, n = 0;
+  if (live && r.i0 < r.i1 && r.j0 < r.j1) {
+    tx0 = tile_x(r.i0);
+    ty0 = tile_y(r.j0);
+    nx = tile_x(r.i1 - 1) - tx0 + 1;
+    n = nx * (tile_y(r.j1 - 1) - ty0 + 1);
+  }
+  int qx = 0, qy = 0;
+  for (int q = 0; __ballot(q < n) != 0; ++q) {
+    int key = -1;
+    uint32_t cand = 0, geom = 0;
+    if (q < n) {
+      const int tx = tx0 + qx, ty = ty0 + qy;
+      if (++qx == nx) {
+        qx = 0;
+        ++qy;
+      }
+      key = ty * im.ntx + tx;
+      const int x0 = tx * im.tw, y0 = ty * im.th;
+      const int lx0 = max((int)r.i0, x0) - x0, lx1 = min((int)r.i1, x0 + im.tw) - x0;
+      const int ly0 = max((int)r.j0, y0) - y0, ly1 = min((int)r.j1, y0 + im.th) - y0;
+      if (kScatter)
+        geom = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 - 1) << 16) |
+               ((uint32_t)(ly1 - ly0 - 1) << 24);
+      else
+        cand = ((uint32_t)((lx1 - lx0) * (ly1 - ly0)) + 3u) & ~3u;
+    }
+    // groups: runs of consecutive lanes with the same tile (neighbouring
+    // triangles mostly share theirs); a tile may form several runs
+    const LaneRuns g = lane_runs(key);
+    const int my_leader = g.leader;
+    const uint32_t my_rank = g.rank, group = g.group;
+    const bool lead = key >= 0 && my_leader == lane;
+    const uint32_t hk = (kimg << 30) | (uint32_t)key;
+    if (!kScatter) {
+      // the run's candidates: inclusive prefix at its last lane minus the
+      // prefix before its leader
+      const uint32_t incl = wave_inclusive_scan<uint32_t>(cand);
+      const uint32_t at_end = (uint32_t)__shfl((int)incl, lead ? lane + (int)group - 1 : lane, 64);
+      if (lead) {
+        const uint32_t c = at_end - incl + cand;
+        const int sl = bin_insert(h, hk);
+        if (sl >= 0) {
+          atomicAdd(&h.a[sl], group);
+          atomicAdd(&h.b[sl], c);
+        } else {
+          atomicAdd(&im.tile_ovf[key], group);
+          atomicAdd(&im.tile_pack[key], (uint64_t)c << 32);
+        }
+      }
+    } else {
+      uint32_t lead_base = 0;
+      if (lead) {
+        const int sl = bin_find(h, hk);
+        lead_base = sl >= 0 ? h.a[sl] + atomicAdd(&h.b[sl], group)
+                            : im.tile_cnt[key] + atomicAdd(&im.tile_cur[key], group);
+      }
+      const uint32_t base = (uint32_t)__shfl((int)lead_base, my_leader, 64);
+      if (key >= 0) {
+        const uint64_t pos = (uint64_t)base + my_rank;
+        if (pos < im.list_cap) im.tile_list[pos] = make_int2((int32_t)t, (int32_t)geom);
+      }
+    }
+  }
+}
+
+// Counting pass of one chunk [t0, t1): setup of every triangle, its pairs
+// into the table, then the reservations and their records.
+template <class ImageAt>
+__device__ void setup_count_chunk(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t0, int64_t t1,
+                                  uint32_t chunk) {
+  __shared__ BinLds h;
+  for (int i = threadIdx.x; i < kBinSlots; i += kBinBlock) {
+    h.key[i] = kBinEmpty;
+    h.a[i] = 0u;
+    h.b[i] = 0u;
+  }
+  if (threadIdx.x == 0) h.n_rec = 0u;
+  __syncthreads();
+  for (int64_t tb = t0; tb < t1; tb += kBinBlock) {
+    const int64_t t = tb + threadIdx.x;
+    const bool live = t < t1;
+    Rect r[kMaxImages];
+    setup_one(m, nimg, image_at, t, live, r);
+#pragma unroll
+    for (int k = 0; k < kMaxImages; ++k)
+      if (k < nimg) bin_rect_chunk<false>(image_at(k), (uint32_t)k, t, live, r[k], h);
+  }
+  __syncthreads();
+  uint4* rec = m.bin_rec + (size_t)chunk * kBinSlots;
+  for (int i = threadIdx.x; i < kBinSlots; i += kBinBlock) {
+    const uint32_t hk = h.key[i];
+    if (hk == kBinEmpty) continue;
+    const Image& im = image_at((int)(hk >> 30));
+    const uint32_t key = hk & 0x3fffffffu;
+    // one 64-bit atomic adds both and returns the entries reserved before
+    const uint32_t base = (uint32_t)atomicAdd(&im.tile_pack[key], ((uint64_t)h.b[i] << 32) | h.a[i]);
+    rec[atomicAdd(&h.n_rec, 1u)] = make_uint4(hk, (uint32_t)i, base, 0u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) m.bin_nrec[chunk] = h.n_rec;
+}
+
+// Scatter pass of one chunk (after the tile scan turned tile_cnt into list
+// offsets).
+template <class ImageAt>
+__device__ void scatter_chunk(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t0, int64_t t1,
+                              uint32_t chunk) {
+  __shared__ BinLds h;
+  for (int i = threadIdx.x; i < kBinSlots; i += kBinBlock) h.key[i] = kBinEmpty;
+  __syncthreads();
+  const uint32_t n = min(m.bin_nrec[chunk], (uint32_t)kBinSlots);
+  const uint4* rec = m.bin_rec + (size_t)chunk * kBinSlots;
+  for (uint32_t i = threadIdx.x; i < n; i += kBinBlock) {
+    const uint4 q = rec[i];
+    const Image& im = image_at((int)(q.x >> 30));
+    const uint32_t key = q.x & 0x3fffffffu;
+    const uint32_t sl = q.y & (kBinSlots - 1);
+    h.key[sl] = q.x;
+    h.a[sl] = im.tile_cnt[key] + im.tile_ovf[key] + q.z;
+    h.b[sl] = 0u;
+  }
+  __syncthreads();
+  for (int64_t tb = t0; tb < t1; tb += kBinBlock) {
+    const int64_t t = tb + threadIdx.x;
+    const bool live = t < t1;
+    for (int k = 0; k < nimg; ++k) {
+      const Image& im = image_at(k);
+      Rect r{0, 0, 0, 0};
+      if (live) r = im.rect[t];
+      bin_rect_chunk<true>(im, (uint32_t)k, t, live, r, h);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBinBlock) setup_kernel(MeshSetup m, ImageSet set) {
+  const int64_t t0 = (int64_t)blockIdx.x * kBinChunkTris;
+  setup_count_chunk(m, set.n, [&](int k) -> const Image& { return set.img[k]; }, t0,
+                    min(t0 + kBinChunkTris, m.n_tris), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBinBlock) bin_kernel(MeshSetup m, ImageSet set) {
+  const int64_t t0 = (int64_t)blockIdx.x * kBinChunkTris;
+  scatter_chunk(m, set.n, [&](int k) -> const Image& { return set.img[k]; }, t0,
+                min(t0 + kBinChunkTris, m.n_tris), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1262,8 +1502,7 @@ __global__ void __launch_bounds__(kBlock) fill_u32_kernel(uint32_t* p, uint32_t 
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;  // 4096 values per workgroup
 
-__device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i, uint32_t cap,
-                                       uint32_t v[16]) {
+__device__ __forceinline__ void load16_raw(const uint32_t* in, int64_t n, int64_t i, uint32_t v[16]) {
   if (i + 16 <= n) {
     const uint4* p = reinterpret_cast<const uint4*>(in + i);
 #pragma unroll
@@ -1275,8 +1514,32 @@ __device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i,
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = (i + k < n) ? in[i + k] : 0u;
   }
+}
+
+// 16 values of in, each capped at cap
+__device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i, uint32_t cap, uint32_t v[16]) {
+  load16_raw(in, n, i, v);
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = min(v[k], cap);
+}
+
+// 16 values of a packed tile count (entries in the low half, candidates in
+// the high half) plus the entries counted apart (add): seg 0 the entries
+// (saturating), seg 1 the candidates.  A tile's candidates (at most 1024 per
+// entry) fit the high half while it has fewer than 2^22 entries; beyond, the
+// candidates count as 2^32 - 1.  Each value is capped at cap.
+__device__ __forceinline__ void load16_pack(const uint64_t* pack, const uint32_t* add, int64_t n, int64_t i,
+                                            int seg, uint32_t cap, uint32_t v[16]) {
+  uint32_t w[16];
+  load16_raw(add, n, i, w);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint64_t q = (i + k < n) ? pack[i + k] : 0ull;
+    const uint64_t cnt = (uint64_t)(uint32_t)q + w[k];
+    const uint32_t x = seg == 0 ? (uint32_t)min(cnt, 0xffffffffull)
+                                : (cnt >= (1ull << 22) ? 0xffffffffu : (uint32_t)(q >> 32));
+    v[k] = min(x, cap);
+  }
 }
 
 // Up to kMaxImages scans of n values each (input, output and where the
@@ -1285,6 +1548,10 @@ __device__ __forceinline__ void load16(const uint32_t* in, int64_t n, int64_t i,
 // prefixes at 2^32 - 1 instead of raising the overflow bit.
 struct ScanSegs {
   const uint32_t* in[kMaxImages];
+  // or, when pack is set, two segments read from packed tile counts (see
+  // load16_pack)
+  const uint64_t* pack;
+  const uint32_t* pack_add;
   uint32_t* out[kMaxImages];
   uint32_t* total[kMaxImages];
   uint32_t* max_out[kMaxImages];  // largest value of the segment, or null
@@ -1301,7 +1568,10 @@ __global__ void __launch_bounds__(kBlock) scan_reduce_kernel(ScanSegs sg, uint64
   const int64_t b = (int64_t)blockIdx.x - (int64_t)seg * sg.nb;
   const int64_t i = b * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[16];
-  load16(sg.in[seg], sg.n, i, sg.cap[seg], v);
+  if (sg.pack)
+    load16_pack(sg.pack, sg.pack_add, sg.n, i, seg, sg.cap[seg], v);
+  else
+    load16(sg.in[seg], sg.n, i, sg.cap[seg], v);
   uint64_t s = 0;
   uint32_t m = 0;
 #pragma unroll
@@ -1358,7 +1628,10 @@ __global__ void __launch_bounds__(kBlock) scan_apply_kernel(ScanSegs sg, const u
   const int64_t n = sg.n;
   uint32_t* out = sg.out[seg];
   uint32_t v[16];
-  load16(sg.in[seg], n, i, sg.cap[seg], v);
+  if (sg.pack)
+    load16_pack(sg.pack, sg.pack_add, n, i, seg, sg.cap[seg], v);
+  else
+    load16(sg.in[seg], n, i, sg.cap[seg], v);
   uint64_t s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) s += v[k];
@@ -1389,7 +1662,7 @@ __global__ void __launch_bounds__(kBlock) batch_setup_kernel(BatchDevice B) {
   const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
   const BatchMesh& bm = B.meshes[mi];
   const int64_t t = (int64_t)(blockIdx.x - B.tri_block_start[mi]) * kBlock + threadIdx.x;
-  setup_triangle<true>(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
+  setup_triangle(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
 }
 
 template <bool kScatter>
@@ -1625,14 +1898,13 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 
 hipError_t launch_setup(const MeshSetup& m, const ImageSet& set, hipStream_t s) {
   if (m.n_tris <= 0) return hipSuccess;
-  hipLaunchKernelGGL(setup_kernel, dim3(grid_for(m.n_tris, kBlock)), dim3(kBlock), 0, s, m, set);
+  hipLaunchKernelGGL(setup_kernel, dim3(grid_for(m.n_tris, kBinChunkTris)), dim3(kBinBlock), 0, s, m, set);
   return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const ImageSet& set, hipStream_t s) {
-  if (set.n == 0 || set.img[0].n_tris <= 0) return hipSuccess;
-  dim3 grid(grid_for(set.img[0].n_tris, kBlock), set.n);
-  hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(kBlock), 0, s, set);
+hipError_t launch_bin_scatter(const MeshSetup& m, const ImageSet& set, hipStream_t s) {
+  if (set.n == 0 || m.n_tris <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_kernel, dim3(grid_for(m.n_tris, kBinChunkTris)), dim3(kBinBlock), 0, s, m, set);
   return hipGetLastError();
 }
 
@@ -1821,14 +2093,17 @@ hipError_t launch_scan_segments(const uint32_t* const* in, uint32_t* const* out,
   return run_scan(sg, scratch, status, s);
 }
 
-hipError_t launch_tile_scan(uint32_t* tile_cnt, uint32_t* tile_region, int64_t n, uint32_t region_cap,
-                            void* scratch, uint32_t* status, hipStream_t s) {
+hipError_t launch_tile_scan(const uint64_t* tile_pack, const uint32_t* tile_ovf, uint32_t* tile_cnt,
+                            uint32_t* tile_region, int64_t n, uint32_t region_cap, void* scratch, uint32_t* status,
+                            hipStream_t s) {
   if (n <= 0) {
     hipError_t e = launch_fill_u32(tile_cnt, 0u, 1, s);
     return e != hipSuccess ? e : launch_fill_u32(tile_region, 0u, 1, s);
   }
   ScanSegs sg{};
   sg.in[0] = tile_cnt;
+  sg.pack = tile_pack;
+  sg.pack_add = tile_ovf;
   sg.out[0] = tile_cnt;
   sg.total[0] = tile_cnt + n;
   sg.cap[0] = 0xffffffffu;

@@ -38,7 +38,8 @@ def test_committed_traffic_summaries_match_their_sources():
     """Every committed traffic summary names the current hash of its kernel's
     source, so bench.py reports its bytes (a kernel edited since its counters
     were taken would report null)."""
-    sources = {"sample": "ldni_kernels.hip", "place": "ldni_kernels.hip", "backward": "ldni_backward.hip",
+    sources = {"sample": "ldni_kernels.hip", "place": "ldni_kernels.hip", "setup": "ldni_kernels.hip",
+               "bin": "ldni_kernels.hip", "backward": "ldni_backward.hip",
                "classify_nodes": "ldni_nodes.hip", "boolean_write": "ldni_boolean.hip"}
     names = [n for n in os.listdir(os.path.join(ROOT, "profiles")) if n.endswith("_traffic.txt")]
     assert names
