@@ -1515,7 +1515,7 @@ struct ldni_batch {
   int32_t n_img = 0;
   std::vector<ldni_mesh_desc> desc;
   std::vector<int32_t> img_mesh, img_axis;
-  std::vector<uint32_t> tri_block_start, bin_block_start, tile_start;
+  std::vector<uint32_t> tri_block_start, tile_start;
   std::vector<uint64_t> seg_start;
   hipStream_t cs = nullptr;  // private stream the graph is captured on
   void* ws = nullptr;
@@ -1530,13 +1530,16 @@ struct ldni_batch {
   void* items = nullptr;  // place items, sized for stage_layers
   uint64_t items_cap = 0;
   bool small = true;      // every image's tiles have at most 256 pixels
+  uint64_t small_tiles = 0;  // tiles of the images with small tiles (numbered first)
   uint32_t* host_out = nullptr;
   BatchDevice dev{};
   uint32_t* offsets_arena = nullptr;
   uint32_t* counts_arena = nullptr;
   uint32_t* tile_arena = nullptr;
   uint32_t* region_arena = nullptr;  // candidate counts -> staging regions (after tile_arena)
-  uint32_t* cur_arena = nullptr;
+  uint32_t* cur_arena = nullptr;     // scatter cursors of the entries counted apart
+  uint32_t* ovf_arena = nullptr;     // entries counted apart (outside the chunk tables)
+  uint64_t* pack_arena = nullptr;    // chunk reservations and candidates, packed
   uint32_t* max_layers = nullptr;
   void* scan_scratch = nullptr;
   uint64_t total_tiles = 0, total_slots = 0;
@@ -1605,17 +1608,17 @@ hipError_t batch_enqueue(ldni_batch* b, hipStream_t s) {
   Q(launch_fill_u32(b->dev.status, 0u, 20, s));  // status, work counters, walk count
   Q(launch_fill_u32(b->max_layers, 0u, b->n_img, s));
   // tile entry counts and (after them) candidate counts
-  Q(launch_fill_u32(b->tile_arena, 0u, (int64_t)(b->region_arena - b->tile_arena) + (int64_t)b->total_tiles + 1, s));
-  Q(launch_fill_u32(b->cur_arena, 0u, (int64_t)b->total_tiles, s));
+  // scatter cursors, entries counted apart and packed tile counts (adjacent)
+  Q(launch_fill_u32(b->cur_arena, 0u, 4 * (int64_t)b->total_tiles, s));
   Q(launch_batch_setup(b->dev, b->tri_block_start.back(), s));  // also counts tiles and candidates
-  Q(launch_tile_scan(nullptr, nullptr, b->tile_arena, b->region_arena, (int64_t)b->total_tiles,
+  Q(launch_tile_scan(b->pack_arena, b->ovf_arena, b->tile_arena, b->region_arena, (int64_t)b->total_tiles,
                      b->stage_layers * (uint32_t)(b->small ? 256 : 1024), b->scan_scratch, b->dev.status, s));
-  Q(launch_batch_scatter(b->dev, b->bin_block_start.back(), s));
-  Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, b->small, s));
+  Q(launch_batch_scatter(b->dev, b->tri_block_start.back(), s));
+  Q(launch_batch_sample(b->dev, (uint32_t)b->total_tiles, (uint32_t)b->small_tiles, s));
   Q(launch_batch_pixel_scan(b->dev, b->counts_arena, b->offsets_arena, (int64_t)b->total_slots,
                             b->scan_scratch, s));
   Q(launch_batch_finish_counts(b->dev, s));
-  Q(launch_batch_place(b->dev, (uint32_t)b->total_tiles, b->small, b->scan_scratch, s));
+  Q(launch_batch_place(b->dev, (uint32_t)b->total_tiles, (uint32_t)b->small_tiles, b->scan_scratch, s));
 #undef Q
   return hipSuccess;
 }
@@ -1773,7 +1776,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
 
   // ---- tables ----
   b->tri_block_start.push_back(0);
-  b->bin_block_start.push_back(0);
   b->tile_start.push_back(0);
   b->seg_start.push_back(0);
   uint64_t tris_total = 0, rect_total = 0;
@@ -1782,21 +1784,29 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     const ldni_mesh_desc& d = meshes[m];
     tri_off[m] = tris_total;
     tris_total += (uint64_t)d.n_tris;
-    const uint32_t tb = (uint32_t)((d.n_tris + 255) / 256);
+    const uint32_t tb = (uint32_t)((d.n_tris + kBinChunkTris - 1) / kBinChunkTris);
     b->tri_block_start.push_back(b->tri_block_start.back() + tb);
-    for (int a = 0; a < 3; ++a) {
-      if (!((axis_mask >> a) & 1u)) continue;
+  }
+  // images of meshes with small tiles (at most 256 pixels) first, so that
+  // each tile class is one range of the batch's tiles
+  for (int cls = 0; cls < 2; ++cls) {
+    for (int m = 0; m < n_meshes; ++m) {
+      const ldni_mesh_desc& d = meshes[m];
       int tw = 0, th = 0;
       tile_shape(d.w, d.n_tris, d.tile_w, d.tile_h, &tw, &th);
+      if ((tw * th > 256) != (cls == 1)) continue;
       const uint64_t tiles = (uint64_t)((d.w + tw - 1) / tw) * ((d.w + th - 1) / th);
-      b->img_mesh.push_back(m);
-      b->img_axis.push_back(a);
-      rect_off.push_back(rect_total);
-      rect_total += (uint64_t)d.n_tris;
-      b->bin_block_start.push_back(b->bin_block_start.back() + tb);
-      b->tile_start.push_back((uint32_t)(b->tile_start.back() + tiles));
-      b->seg_start.push_back(b->seg_start.back() + (uint64_t)d.w * d.w + 1);
+      for (int a = 0; a < 3; ++a) {
+        if (!((axis_mask >> a) & 1u)) continue;
+        b->img_mesh.push_back(m);
+        b->img_axis.push_back(a);
+        rect_off.push_back(rect_total);
+        rect_total += (uint64_t)d.n_tris;
+        b->tile_start.push_back((uint32_t)(b->tile_start.back() + tiles));
+        b->seg_start.push_back(b->seg_start.back() + (uint64_t)d.w * d.w + 1);
+      }
     }
+    if (cls == 0) b->small_tiles = b->tile_start.back();
   }
   b->n_img = (int32_t)b->img_mesh.size();
   b->total_tiles = b->tile_start.back();
@@ -1818,7 +1828,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   const size_t o_meshes = take(sizeof(BatchMesh) * n_meshes);
   const size_t o_images = take(sizeof(Image) * n_img);
   const size_t o_tbs = take(sizeof(uint32_t) * (n_meshes + 1));
-  const size_t o_bbs = take(sizeof(uint32_t) * (n_img + 1));
   const size_t o_ts = take(sizeof(uint32_t) * (n_img + 1));
   const size_t o_ss = take(sizeof(uint64_t) * (n_img + 1));
   const size_t o_sb = take(sizeof(uint64_t) * n_img);
@@ -1829,7 +1838,10 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   // tile entry counts, then (16-byte aligned) tile candidate counts
   const uint64_t region_at = (b->total_tiles + 1 + 3) & ~(uint64_t)3;
   const size_t o_tile = take(sizeof(uint32_t) * (region_at + b->total_tiles + 1));
-  const size_t o_cur = take(sizeof(uint32_t) * b->total_tiles);
+  // scatter cursors, entries counted apart, packed counts: cleared by one fill
+  const size_t o_cur = take(sizeof(uint32_t) * 4 * b->total_tiles);
+  const size_t o_brec = take(sizeof(uint4) * kBinSlots * (size_t)b->tri_block_start.back());
+  const size_t o_bnrec = take(sizeof(uint32_t) * (size_t)b->tri_block_start.back());
   const size_t o_counts = take(sizeof(uint32_t) * b->total_slots);
   const size_t o_offs = take(sizeof(uint32_t) * b->total_slots);
   b->small = true;
@@ -1840,7 +1852,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
       tile_shape(meshes[m].w, meshes[m].n_tris, meshes[m].tile_w, meshes[m].tile_h, &tw, &th);
       b->small = b->small && tw * th <= 256;
     }
-  const int tile_pix = b->small ? 256 : 1024;
   const size_t o_tstage = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_thits = take(sizeof(uint32_t) * b->total_tiles);
   const size_t o_tmax = take(sizeof(uint32_t) * b->total_tiles);
@@ -1864,7 +1875,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   D.images = reinterpret_cast<Image*>(ws + o_images);
   D.n_images = n_img;
   D.tri_block_start = reinterpret_cast<uint32_t*>(ws + o_tbs);
-  D.bin_block_start = reinterpret_cast<uint32_t*>(ws + o_bbs);
   D.tile_start = reinterpret_cast<uint32_t*>(ws + o_ts);
   D.seg_start = reinterpret_cast<uint64_t*>(ws + o_ss);
   D.sample_base = reinterpret_cast<uint64_t*>(ws + o_sb);
@@ -1873,6 +1883,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   b->tile_arena = reinterpret_cast<uint32_t*>(ws + o_tile);
   b->region_arena = b->tile_arena + region_at;
   b->cur_arena = reinterpret_cast<uint32_t*>(ws + o_cur);
+  b->ovf_arena = b->cur_arena + b->total_tiles;
+  b->pack_arena = reinterpret_cast<uint64_t*>(b->cur_arena + 2 * b->total_tiles);
   b->counts_arena = reinterpret_cast<uint32_t*>(ws + o_counts);
   b->offsets_arena = reinterpret_cast<uint32_t*>(ws + o_offs);
   b->scan_scratch = ws + o_scan;
@@ -1881,7 +1893,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   D.walk_list = reinterpret_cast<uint32_t*>(ws + o_walk);
   D.walk_count = D.status + 18;
   D.region_total = b->region_arena + b->total_tiles;
-  D.place_cap = place_stage_cap(tile_pix);
   uint32_t* tstage = reinterpret_cast<uint32_t*>(ws + o_tstage);
   uint32_t* thits = reinterpret_cast<uint32_t*>(ws + o_thits);
   uint32_t* tmax = reinterpret_cast<uint32_t*>(ws + o_tmax);
@@ -1901,6 +1912,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     bm.m.soup = soup + 9 * tri_off[m];
     bm.m.tnorm = tnorm + tri_off[m];
     bm.m.status = D.status;
+    bm.m.bin_rec = reinterpret_cast<uint4*>(ws + o_brec) + (size_t)kBinSlots * b->tri_block_start[m];
+    bm.m.bin_nrec = reinterpret_cast<uint32_t*>(ws + o_bnrec) + b->tri_block_start[m];
     bm.nimg = 0;
   }
   for (int k = 0; k < n_img; ++k) {
@@ -1929,6 +1942,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
     im.n_tris = d.n_tris;
     im.tile_cnt = b->tile_arena + b->tile_start[k];
     im.tile_cur = b->cur_arena + b->tile_start[k];
+    im.tile_ovf = b->ovf_arena + b->tile_start[k];
+    im.tile_pack = b->pack_arena + b->tile_start[k];
     im.counts = b->counts_arena + b->seg_start[k];
     im.max_layers = b->max_layers + k;
     im.offsets = b->offsets_arena + b->seg_start[k];
@@ -1942,9 +1957,6 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   }
   e = hipMemcpy(const_cast<uint32_t*>(D.tri_block_start), b->tri_block_start.data(),
                 sizeof(uint32_t) * (n_meshes + 1), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(const_cast<uint32_t*>(D.bin_block_start), b->bin_block_start.data(),
-                  sizeof(uint32_t) * (n_img + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(const_cast<uint32_t*>(D.tile_start), b->tile_start.data(), sizeof(uint32_t) * (n_img + 1),
                   hipMemcpyHostToDevice);

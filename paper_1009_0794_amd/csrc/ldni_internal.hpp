@@ -116,8 +116,8 @@ struct MeshSetup {
   Rect* rect[kMaxImages];
   uint32_t* status;
   // binning by chunks of kBinChunkTris triangles: per chunk up to kBinSlots
-  // records (image << 30 | tile, table slot, first reserved list entry, 0)
-  // and their number
+  // records (image << 30 | tile, table slot, first list entry reserved in the
+  // tile, 0) and their number
   uint4* bin_rec;
   uint32_t* bin_nrec;
 };
@@ -169,8 +169,7 @@ struct BatchDevice {
   int32_t n_meshes;
   Image* images;
   int32_t n_images;
-  const uint32_t* tri_block_start;  // [n_meshes+1] setup workgroups per mesh (prefix)
-  const uint32_t* bin_block_start;  // [n_images+1] binning workgroups per image (prefix)
+  const uint32_t* tri_block_start;  // [n_meshes+1] binning chunks per mesh (prefix)
   const uint32_t* tile_start;       // [n_images+1] tiles per image (prefix)
   const uint32_t* tile_max;         // [total tiles] largest count of each tile
   const uint64_t* seg_start;        // [n_images+1] first slot of each image in counts/offsets
@@ -193,17 +192,19 @@ struct BatchDevice {
   uint32_t* walk_list;
   uint32_t* walk_count;
   const uint32_t* region_total;     // staging entries the regions of the batch ask for
-  int32_t place_cap;
 };
 
-hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s);
-hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t blocks, hipStream_t s);
-// small: every image's tiles have at most 256 pixels.  n_tiles: tiles of
-// the batch.  Sampling pass (counts, staged hits, place plan), then after the
-// pixel scan and the placement of the images: the place items, the place
-// pass and the walk of the tiles whose hits were not staged.
-hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s);
-hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
+// setup and tile counts, then (after the tile scan) the scatter: chunks of
+// kBinChunkTris triangles of all meshes (tri_block_start.back() of them)
+hipError_t launch_batch_setup(const BatchDevice& b, uint32_t chunks, hipStream_t s);
+hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t chunks, hipStream_t s);
+// n_tiles: tiles of the batch, the first n_small of them those of the
+// images whose tiles have at most 256 pixels (each class runs its own build of
+// the tile kernels).  Sampling pass (counts, staged hits, place plan), then
+// after the pixel scan and the placement of the images: the place items, the
+// place pass and the walk of the tiles whose hits were not staged.
+hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, uint32_t n_small, hipStream_t s);
+hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, uint32_t n_small, void* scratch,
                               hipStream_t s);
 // Segmented exclusive scan of the per-image counts (segments of w*w+1 slots,
 // the last slot of each zero) into per-image offsets starting at 0, with the

@@ -183,8 +183,6 @@ __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-template <bool kScatter>
-__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r);
 
 // One triangle (live: t is a triangle of the mesh): gather and validate its
 // vertices, store them and its unit face normal, and its candidate rectangle
@@ -285,123 +283,6 @@ __device__ void setup_one(const MeshSetup& m, int nimg, ImageAt&& image_at, int6
   }
 }
 
-// setup_one for triangle t, then the count of its tiles on every image (all
-// 64 lanes of every wave call this; lanes past the mesh count nothing).
-template <class ImageAt>
-__device__ void setup_triangle(const MeshSetup& m, int nimg, ImageAt&& image_at, int64_t t) {
-  const bool live = t < m.n_tris;
-  Rect r[kMaxImages];
-  setup_one(m, nimg, image_at, t, live, r);
-#pragma unroll
-  for (int k = 0; k < kMaxImages; ++k)
-    if (k < nimg) bin_rect<false>(image_at(k), t, live, r[k]);
-}
-
-
-// ---------------------------------------------------------------------------
-// binning
-// ---------------------------------------------------------------------------
-// Every (triangle, tile) pair of a wave is counted (or placed) with one
-// atomic per distinct tile of the wave: lanes that share the tile are peeled
-// off together and ranked by their lane order.  Counting also adds up the
-// tile's candidate pixels, which size its staging region.  Mesh order is spatially
-// coherent for most meshes, so a wave typically touches a handful of tiles.
-// All 64 lanes of every wave must call this (t beyond the mesh = no tiles).
-template <bool kScatter>
-__device__ void bin_rect(const Image& im, int64_t t, bool live, const Rect& r) {
-  const int lane = threadIdx.x & 63;
-  // counting: per wave, the candidate sums of its group leaders (zero
-  // between uses)
-  __shared__ uint32_t s_acc[kBlock];
-  uint32_t* acc = s_acc + (threadIdx.x & ~63);
-  if (!kScatter) acc[lane] = 0u;
-  // tile of a pixel column / row (shifts for the usual power-of-two shapes)
-  auto tile_x = [&](int i) { return im.tw_shift >= 0 ? i >> im.tw_shift : i / im.tw; };
-  auto tile_y = [&](int j) { return im.th_shift >= 0 ? j >> im.th_shift : j / im.th; };
-  int tx0 = 0, ty0 = 0, nx = 1, n = 0;
-  if (live && r.i0 < r.i1 && r.j0 < r.j1) {
-    tx0 = tile_x(r.i0);
-    ty0 = tile_y(r.j0);
-    nx = tile_x(r.i1 - 1) - tx0 + 1;
-    n = nx * (tile_y(r.j1 - 1) - ty0 + 1);
-  }
-  const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int qx = 0, qy = 0;  // tile q of the triangle, q = qy * nx + qx
-  for (int q = 0; __ballot(q < n) != 0; ++q) {  // while any lane has tiles left
-    int key = -1;
-    uint32_t cand = 0;  // counting: candidates in the tile, whole 4-entry groups
-    uint32_t geom = 0;  // scatter: the rectangle in the tile (tile-list entry layout)
-    if (q < n) {
-      const int tx = tx0 + qx, ty = ty0 + qy;
-      if (++qx == nx) {
-        qx = 0;
-        ++qy;
-      }
-      key = ty * im.ntx + tx;
-      const int x0 = tx * im.tw, y0 = ty * im.th;
-      const int lx0 = max((int)r.i0, x0) - x0, lx1 = min((int)r.i1, x0 + im.tw) - x0;
-      const int ly0 = max((int)r.j0, y0) - y0, ly1 = min((int)r.j1, y0 + im.th) - y0;
-      if (kScatter)
-        geom = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 - 1) << 16) |
-               ((uint32_t)(ly1 - ly0 - 1) << 24);
-      else
-        cand = ((uint32_t)((lx1 - lx0) * (ly1 - ly0)) + 3u) & ~3u;
-    }
-    // Peel the wave's distinct tiles into groups with a leader each; the
-    // leaders then issue their atomics together (one instruction), and the
-    // scatter's return the group's base, which every lane reads from its
-    // leader.
-    const uint32_t list_at = (kScatter && key >= 0) ? im.tile_cnt[key] : 0u;
-    uint64_t pending = __ballot(key >= 0);
-    int my_leader = 0;
-    uint32_t my_rank = 0, group = 0, lead_base = 0;
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int k = __builtin_amdgcn_readlane(key, leader);  // leader is wave-uniform
-      const uint64_t same = __ballot(key == k);
-      if (key == k) {
-        my_leader = leader;
-        my_rank = (uint32_t)__popcll(same & lower);
-        group = (uint32_t)__popcll(same);
-      }
-      pending &= ~same;
-    }
-    if (kScatter && key >= 0 && my_leader == lane) lead_base = atomicAdd(&im.tile_cur[key], group);
-    if (!kScatter) {
-      // Each lane adds its candidates to its leader's slot; the leaders then
-      // add their group's entries and candidates to the tile.
-      if (key >= 0) atomicAdd(&acc[my_leader], cand);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (key >= 0 && my_leader == lane) {
-        const uint32_t c = acc[lane];
-        acc[lane] = 0u;
-        atomicAdd(&im.tile_cnt[key], group);
-        atomicAdd(&im.tile_region[key], c);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (kScatter) {
-      const uint32_t base = (uint32_t)__shfl((int)lead_base, my_leader, 64);
-      if (key >= 0) {
-        const uint64_t pos = (uint64_t)list_at + base + my_rank;
-        if (pos < im.list_cap) im.tile_list[pos] = make_int2((int32_t)t, (int32_t)geom);
-      }
-    }
-  }
-}
-
-template <bool kScatter>
-__device__ void bin_triangles(const Image& im, int64_t t) {
-  const bool live = t < im.n_tris;
-  Rect r{0, 0, 0, 0};
-  if (live) r = im.rect[t];
-  bin_rect<kScatter>(im, t, live, r);
-}
-
 // ---------------------------------------------------------------------------
 // setup and binning by chunks of triangles
 // ---------------------------------------------------------------------------
@@ -420,8 +301,10 @@ __device__ void bin_triangles(const Image& im, int64_t t) {
 //            atomic
 // A key that finds no free slot within kBinProbe probes of its home slot is
 // counted in tile_ovf and scattered with a global cursor in front of the
-// tile's reserved ranges.  Slots never free, so such a key misses in the
-// rebuilt table as well, and every pair of one key takes the same path.
+// tile's reserved ranges.  Slots never free, so every pair of such a key
+// overflows, and in the rebuilt table (the same slots) its kBinProbe probe
+// slots hold other keys: it misses there too, while a recorded key is found
+// within kBinProbe probes, as when it was inserted.
 constexpr uint32_t kBinEmpty = 0xffffffffu;
 constexpr int kBinProbe = 16;
 constexpr int kBinSlotBits = 10;
@@ -1658,18 +1541,23 @@ __global__ void __launch_bounds__(kBlock) scan_apply_kernel(ScanSegs sg, const u
 // ---------------------------------------------------------------------------
 // batched sampling
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) batch_setup_kernel(BatchDevice B) {
+// The setup and scatter chunks of all meshes, numbered mesh after mesh.
+__global__ void __launch_bounds__(kBinBlock) batch_setup_kernel(BatchDevice B) {
   const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
   const BatchMesh& bm = B.meshes[mi];
-  const int64_t t = (int64_t)(blockIdx.x - B.tri_block_start[mi]) * kBlock + threadIdx.x;
-  setup_triangle(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t);
+  const uint32_t chunk = blockIdx.x - B.tri_block_start[mi];
+  const int64_t t0 = (int64_t)chunk * kBinChunkTris;
+  setup_count_chunk(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t0,
+                    min(t0 + kBinChunkTris, bm.m.n_tris), chunk);
 }
 
-template <bool kScatter>
-__global__ void __launch_bounds__(kBlock) batch_bin_kernel(BatchDevice B) {
-  const int k = segment_of(B.bin_block_start, B.n_images, (uint32_t)blockIdx.x);
-  bin_triangles<kScatter>(B.images[k],
-                          (int64_t)(blockIdx.x - B.bin_block_start[k]) * kBlock + threadIdx.x);
+__global__ void __launch_bounds__(kBinBlock) batch_bin_kernel(BatchDevice B) {
+  const int mi = segment_of(B.tri_block_start, B.n_meshes, (uint32_t)blockIdx.x);
+  const BatchMesh& bm = B.meshes[mi];
+  const uint32_t chunk = blockIdx.x - B.tri_block_start[mi];
+  const int64_t t0 = (int64_t)chunk * kBinChunkTris;
+  scatter_chunk(bm.m, bm.nimg, [&](int k) -> const Image& { return B.images[bm.img[k]]; }, t0,
+                min(t0 + kBinChunkTris, bm.m.n_tris), chunk);
 }
 
 // Persistent workgroups take items from a counter, kGrab at a time, until
@@ -1692,15 +1580,18 @@ struct ItemGrabber {
   }
 };
 
+// Tiles [t0, t1) of the batch (the images of one tile class), work counter
+// `counter`, place runs of at most place_cap keys.
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_sample_kernel(BatchDevice B, uint32_t n_tiles) {
+__global__ void __launch_bounds__(kBlock) batch_sample_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0,
+                                                              uint32_t t1, int counter, int place_cap) {
   __shared__ uint32_t s_item;
   ItemGrabber grab;
   for (;;) {
-    const uint32_t item = grab(&B.work[0], &s_item);
-    if (item >= n_tiles) break;
+    const uint32_t item = t0 + grab(&B.work[counter], &s_item);
+    if (item >= t1) break;
     const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, item));
-    sample_tile<kTilePix>(B.images[k], (int)(item - B.tile_start[k]), item, B.plan, n_tiles, B.place_cap);
+    sample_tile<kTilePix>(B.images[k], (int)(item - B.tile_start[k]), item, B.plan, n_tiles, place_cap);
     __syncthreads();  // the next item reuses the tile's LDS
   }
 }
@@ -1728,15 +1619,22 @@ __global__ void __launch_bounds__(kBlock) batch_plan_items_kernel(BatchDevice B,
   }
 }
 
+// The place items of tiles [t0, t1): in launch order the items of tiles
+// with several items come first, then those of single-item tiles, each part
+// in tile order, so the class's items are two ranges.
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_place_kernel(BatchDevice B, uint32_t n_tiles) {
+__global__ void __launch_bounds__(kBlock) batch_place_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0,
+                                                             uint32_t t1, int counter) {
   __shared__ uint32_t s_item;
-  const uint32_t n_items = B.plan[2 * n_tiles];
+  const uint32_t a0 = B.plan[t0], a1 = B.plan[t1];
+  const uint32_t b0 = B.plan[n_tiles + t0], b1 = B.plan[n_tiles + t1];
+  const uint32_t n_items = (a1 - a0) + (b1 - b0);
   const PlaceItem* items = static_cast<const PlaceItem*>(B.items);
   ItemGrabber grab;
   for (;;) {
-    const uint32_t item = grab(&B.work[1], &s_item);
-    if (item >= n_items) break;
+    const uint32_t q = grab(&B.work[counter], &s_item);
+    if (q >= n_items) break;
+    const uint32_t item = q < a1 - a0 ? a0 + q : b0 + (q - (a1 - a0));
     const PlaceItem it = items[item];
     const int k = __builtin_amdgcn_readfirstlane(segment_of(B.tile_start, B.n_images, it.gtile));
     const Image& im = B.images[k];
@@ -1983,45 +1881,48 @@ hipError_t launch_gather(const uint32_t* const* src, int n, uint32_t* host_dst, 
   return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(const BatchDevice& b, uint32_t blocks, hipStream_t s) {
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_setup_kernel, dim3(blocks), dim3(kBlock), 0, s, b);
+hipError_t launch_batch_setup(const BatchDevice& b, uint32_t chunks, hipStream_t s) {
+  if (chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_setup_kernel, dim3(chunks), dim3(kBinBlock), 0, s, b);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t blocks, hipStream_t s) {
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_bin_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, b);
+hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t chunks, hipStream_t s) {
+  if (chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_bin_kernel, dim3(chunks), dim3(kBinBlock), 0, s, b);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, bool small, hipStream_t s) {
-  if (n_tiles == 0) return hipSuccess;
-  if (small)
-    hipLaunchKernelGGL(batch_sample_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 7)), dim3(kBlock), 0,
-                       s, b, n_tiles);
-  else
-    hipLaunchKernelGGL(batch_sample_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 4)), dim3(kBlock), 0,
-                       s, b, n_tiles);
+hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, uint32_t n_small, hipStream_t s) {
+  if (n_small > 0)
+    hipLaunchKernelGGL(batch_sample_kernel<kSmallTilePix>, dim3(persistent_grid(n_small, 7)), dim3(kBlock), 0, s,
+                       b, n_tiles, 0u, n_small, 0, place_stage_cap(kSmallTilePix));
+  if (n_tiles > n_small)
+    hipLaunchKernelGGL(batch_sample_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles - n_small, 4)), dim3(kBlock),
+                       0, s, b, n_tiles, n_small, n_tiles, 3, place_stage_cap(kMaxTilePix));
   return hipGetLastError();
 }
 
-hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, bool small, void* scratch,
+hipError_t launch_batch_place(const BatchDevice& b, uint32_t n_tiles, uint32_t n_small, void* scratch,
                               hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   hipError_t e = launch_scan(b.plan, b.plan, 2 * (int64_t)n_tiles, scratch, nullptr, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batch_plan_items_kernel, dim3(grid_for(n_tiles, kBlock)), dim3(kBlock), 0, s, b, n_tiles);
-  const unsigned grid = persistent_grid(2 * n_tiles, small ? 7 : 3);
-  if (small) {
-    hipLaunchKernelGGL(batch_place_kernel<kSmallTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+  if (n_small > 0)
+    hipLaunchKernelGGL(batch_place_kernel<kSmallTilePix>, dim3(persistent_grid(2 * n_small, 7)), dim3(kBlock), 0,
+                       s, b, n_tiles, 0u, n_small, 1);
+  if (n_tiles > n_small)
+    hipLaunchKernelGGL(batch_place_kernel<kMaxTilePix>, dim3(persistent_grid(2 * (n_tiles - n_small), 3)),
+                       dim3(kBlock), 0, s, b, n_tiles, n_small, n_tiles, 4);
+  // tiles walked again: one build for all (the large one as soon as any
+  // image has large tiles)
+  if (n_tiles == n_small)
     hipLaunchKernelGGL(batch_walk_kernel<kSmallTilePix>, dim3(persistent_grid(n_tiles, 4)), dim3(kBlock), 0,
                        s, b);
-  } else {
-    hipLaunchKernelGGL(batch_place_kernel<kMaxTilePix>, dim3(grid), dim3(kBlock), 0, s, b, n_tiles);
+  else
     hipLaunchKernelGGL(batch_walk_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles, 2)), dim3(kBlock), 0,
                        s, b);
-  }
   return hipGetLastError();
 }
 
