@@ -1367,7 +1367,8 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   const size_t o_start = align_up(o_cursor + sizeof(uint32_t) * (size_t)n_rays);
   const size_t o_scratch = align_up(o_start + sizeof(uint32_t) * (size_t)(n_rays + 1));
   const size_t scratch = std::max(scan_scratch_bytes(n_rays, 1), scan_scratch_bytes(npix, 3));
-  const size_t o_centres = align_up(o_scratch + scratch);
+  const size_t o_deep = align_up(o_scratch + scratch);
+  const size_t o_centres = align_up(o_deep + sizeof(uint32_t) * (size_t)n_rays);
   // the end points the count pass keeps for the write pass (when this stays modest)
   const size_t saved_bytes = sizeof(uint64_t) * kOffsetSaved * 3 * (size_t)npix;
   const bool use_saved = saved_bytes <= ((size_t)1 << 30);
@@ -1411,6 +1412,8 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   g.ray_start = reinterpret_cast<uint32_t*>(wb + o_start);
   g.centres = reinterpret_cast<double*>(wb + o_centres);
   g.saved = use_saved ? reinterpret_cast<uint64_t*>(wb + o_saved) : nullptr;
+  g.deep = reinterpret_cast<uint32_t*>(wb + o_deep);
+  g.n_deep = 0;
   void* scr = wb + o_scratch;
 #define OSTEP(expr, what)                                  \
   do {                                                     \
@@ -1422,11 +1425,13 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   OSTEP(timed("offset_centres", stream, [&] { return launch_offset_centres(g, stream); }), "centre kernel");
   OSTEP(timed("offset_bin", stream, [&] { return launch_offset_bin(g, false, stream); }), "binning kernel");
   OSTEP(launch_scan(g.ray_count, g.ray_start, n_rays, scr, g.status, stream), "ray list scan");
+  OSTEP(launch_offset_deep(g, stream), "deep ray list");
   {
-    const uint32_t* src[2] = {g.status, g.ray_start + n_rays};
-    OSTEP(launch_gather(src, 2, rb, stream), "readback");
+    const uint32_t* src[3] = {g.status, g.ray_start + n_rays, g.status + 16};
+    OSTEP(launch_gather(src, 3, rb, stream), "readback");
     OSTEP(hipStreamSynchronize(stream), "synchronise");
   }
+  g.n_deep = std::min<uint32_t>(rb[2], (uint32_t)n_rays);
   if (rb[0] & kStatusMismatch)
     return bail(fail(LDNI_ERR_INVALID_ARG, "the offsets of an input view are not a prefix of its samples"));
   if (rb[0] & kStatusOverflow) return bail(fail(LDNI_ERR_OVERFLOW, "2^32 or more sphere hits on the rays"));

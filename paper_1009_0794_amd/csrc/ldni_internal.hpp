@@ -295,8 +295,9 @@ hipError_t launch_node_stats(const NodeArgs& g, hipStream_t s);
 // output arrays of the write pass.
 constexpr int kOffsetBuf = 1024;              // events of one depth window of one ray, in LDS
 constexpr int kOffsetKeep = 896;              // a full window is cut back to fewer events than this
-constexpr int kOffsetEmit = 512;              // end points of one ray's result before small volumes go
+constexpr int kOffsetEmit = 128;              // end points of one ray's result before small volumes go
 constexpr int kOffsetSaved = 16;              // end points per ray kept by the count pass for the write pass
+constexpr int kOffsetDeep = 512;              // a ray with more spheres than this is started first
 constexpr uint32_t kMaxSpheres = 1u << 30;    // sphere numbers fit 30 bits of the sort key
 struct OffsetArgs {
   AxisArrays in[3];
@@ -314,10 +315,17 @@ struct OffsetArgs {
   float* out_normal[3];
   int32_t* out_tri[3];
   uint64_t* saved;   // [3 * w * w][kOffsetSaved] kept end-point keys, or null (the write pass recomputes)
+  // rays with more than kOffsetDeep spheres, listed (any order) so that the
+  // ray passes start them first; n_deep of them (known to the host before
+  // the ray passes; status[16] counts them on the device)
+  uint32_t* deep;
+  uint32_t n_deep;
   uint32_t* status;  // kStatusMismatch: bad input offsets; kStatusOutFull: a ray's window or end points overflow
 };
 hipError_t launch_offset_centres(const OffsetArgs& g, hipStream_t s);
 hipError_t launch_offset_bin(const OffsetArgs& g, bool scatter, hipStream_t s);
+// the list of deep rays (after the ray-list scan)
+hipError_t launch_offset_deep(const OffsetArgs& g, hipStream_t s);
 hipError_t launch_offset_rays(const OffsetArgs& g, bool write, hipStream_t s);
 
 // Copies n <= kMaxGather scattered device words to pinned host memory.

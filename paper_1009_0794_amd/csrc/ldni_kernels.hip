@@ -26,11 +26,17 @@
 #include <type_traits>
 
 #include "ldni_internal.hpp"
+#include "ldni_bin.hpp"
 
 namespace ldni {
 namespace {
 
 constexpr int kBlock = 256;          // 4 wave64 per workgroup
+// runs of place items per XCD (xcd_runs): the items of a tile split into
+// several read the same staged lines.  (Runs of neighbouring tiles in the
+// sampling pass line up with the rows of tiles and give some XCDs the dense
+// columns of an image.)
+constexpr uint32_t kPlaceRun = 16;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxTilePix = 1024;    // tw * th
 constexpr int kMaxTileW = 256;
@@ -174,6 +180,19 @@ __device__ __forceinline__ int segment_of(const T* start, int n, T x) {
 }
 
 // Map a workgroup to (image, tile).
+// Workgroups are dealt to the 8 XCDs round robin (block b to XCD b mod 8),
+// each with its own L2.  This renumbering gives every XCD runs of R
+// consecutive work items, the runs themselves dealt round robin: items that
+// read the same lines share an L2 while the load stays spread.  A bijection
+// on [0, n).
+template <uint32_t R>
+__device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t n) {
+  const uint32_t full = n - n % (8u * R);
+  if (b >= full) return b;
+  const uint32_t x = b & 7u, s = b >> 3;
+  return ((s / R) * 8u + x) * R + s % R;
+}
+
 __device__ __forceinline__ int image_of_block(const ImageSet& set, uint32_t b) {
   int k = 0;
   while (k + 1 < set.n && b >= set.tile_start[k + 1]) ++k;
@@ -305,66 +324,8 @@ __device__ void setup_one(const MeshSetup& m, int nimg, ImageAt&& image_at, int6
 // overflows, and in the rebuilt table (the same slots) its kBinProbe probe
 // slots hold other keys: it misses there too, while a recorded key is found
 // within kBinProbe probes, as when it was inserted.
-constexpr uint32_t kBinEmpty = 0xffffffffu;
-constexpr int kBinProbe = 16;
-constexpr int kBinSlotBits = 10;
-static_assert((1 << kBinSlotBits) == kBinSlots, "table size");
 constexpr int kBinBlock = 512;  // 8 waves per workgroup, one triangle per thread
 static_assert(kBinChunkTris % kBinBlock == 0, "whole sub-chunks");
-
-struct BinLds {
-  uint32_t key[kBinSlots];  // (image << 30) | tile, or kBinEmpty
-  uint32_t a[kBinSlots];    // count: entries; scatter: list position of the slot's range
-  uint32_t b[kBinSlots];    // count: candidates; scatter: entries placed so far
-  uint32_t n_rec;
-};
-
-// A wave's lanes split into runs of consecutive lanes with equal keys (key
-// < 0: no entry, never in a run).  For a lane with an entry: leader = first
-// lane of its run, rank = lane - leader; group = lanes in the run (valid at
-// the leader).
-struct LaneRuns {
-  int leader;
-  uint32_t rank, group;
-};
-__device__ __forceinline__ LaneRuns lane_runs(int key) {
-  const int lane = threadIdx.x & 63;
-  const int prev = __shfl_up(key, 1, 64);
-  const bool live = key >= 0;
-  const uint64_t heads = __ballot(live && (lane == 0 || prev != key));
-  const uint64_t breaks = heads | __ballot(!live);
-  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
-  const uint64_t mine = heads & upto;
-  LaneRuns r;
-  r.leader = mine ? 63 - __clzll((long long)mine) : lane;
-  r.rank = (uint32_t)(lane - r.leader);
-  const uint64_t above = breaks & ~upto;
-  r.group = (uint32_t)((above ? __ffsll((unsigned long long)above) - 1 : 64) - lane);
-  return r;
-}
-
-__device__ __forceinline__ uint32_t bin_home(uint32_t hk) { return (hk * 2654435761u) >> (32 - kBinSlotBits); }
-
-__device__ __forceinline__ int bin_insert(BinLds& h, uint32_t hk) {
-  uint32_t s = bin_home(hk);
-  for (int i = 0; i < kBinProbe; ++i) {
-    const uint32_t prev = atomicCAS(&h.key[s], kBinEmpty, hk);
-    if (prev == kBinEmpty || prev == hk) return (int)s;
-    s = (s + 1) & (kBinSlots - 1);
-  }
-  return -1;
-}
-
-__device__ __forceinline__ int bin_find(const BinLds& h, uint32_t hk) {
-  uint32_t s = bin_home(hk);
-  for (int i = 0; i < kBinProbe; ++i) {
-    const uint32_t k = h.key[s];
-    if (k == hk) return (int)s;
-    if (k == kBinEmpty) return -1;
-    s = (s + 1) & (kBinSlots - 1);
-  }
-  return -1;
-}
 
 // The (triangle, tile) pairs of one image for one triangle per lane, counted
 // into (kScatter false) or placed from (true) the chunk table.  All 64 lanes
@@ -1346,7 +1307,7 @@ __device__ void place_tile(const Image& im, int tile, uint32_t first, uint32_t h
 // One workgroup per place item.
 template <int kTilePix>
 __global__ void __launch_bounds__(kBlock) place_kernel(ImageSet set, const PlaceItem* items) {
-  const PlaceItem it = items[blockIdx.x];
+  const PlaceItem it = items[xcd_runs<kPlaceRun>(blockIdx.x, gridDim.x)];
   const int k = image_of_block(set, it.gtile);
   place_tile<kTilePix>(set.img[k], (int)(it.gtile - set.tile_start[k]), it.first, it.hits,
                        (int)(it.part_parts & 0xffffu), (int)(it.part_parts >> 16));

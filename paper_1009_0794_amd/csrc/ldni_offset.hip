@@ -30,6 +30,7 @@
 #pragma clang fp contract(off)
 
 #include "ldni_internal.hpp"
+#include "ldni_bin.hpp"
 
 namespace ldni {
 namespace {
@@ -83,14 +84,27 @@ __device__ __forceinline__ void pixel_range(const OffsetArgs& g, int b, double x
 
 // Binning: for sphere s and image a, the rays of the pixels in its range
 // that the sphere hits (rho^2 < r^2, the test of the ray pass); count
-// (kScatter false) or write the sphere into those rays' lists.  Neighbouring
-// samples (neighbouring threads) mostly hit the same rays, so the lanes of a
-// wave that hold the same ray add to its counter with one atomic, issued by
-// the first of them.
+// (kScatter false) or write the sphere into those rays' lists.  A workgroup
+// (256 consecutive spheres of one image, which mostly hit the same rays)
+// first adds its (sphere, ray) pairs per ray into an LDS table, one addition
+// per run of lanes holding the same ray, and then touches each ray's global
+// counter once: the count pass adds its pairs to ray_count; the scatter pass
+// reserves a range of the ray's list from ray_cursor and, in a second sweep
+// over the same pairs, places each run in its slot's range with an LDS
+// atomic.  A ray that finds no free slot (kBinProbe probes) is counted and
+// placed run by run with global atomics; slots never free, so it misses the
+// table in the second sweep as well.
 template <bool kScatter>
 __global__ __launch_bounds__(kOffBlock) void offset_bin_kernel(OffsetArgs g) {
+  __shared__ BinLds h;
+  for (int i = threadIdx.x; i < kBinSlots; i += kOffBlock) {
+    h.key[i] = kBinEmpty;
+    h.a[i] = 0u;
+    h.b[i] = 0u;
+  }
+  __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * kOffBlock + threadIdx.x;
-  const uint32_t lane = __lane_id();
+  const int lane = (int)__lane_id();
   int a = 0, u = 0, v = 0, ni = 0, n_my = 0, iu0 = 0, iv0 = 0;
   uint32_t s = 0;
   double pu = 0.0, pv = 0.0;
@@ -112,32 +126,45 @@ __global__ __launch_bounds__(kOffBlock) void offset_bin_kernel(OffsetArgs g) {
   }
   const double r2 = g.r * g.r;
   const int64_t npix = (int64_t)g.w * g.w;
-  // the j-th pixel of every lane's range, j = 0, 1, ... while any lane has one
-  for (int j = 0; __ballot(j < n_my) != 0; ++j) {
-    uint32_t my = 0xffffffffu;
-    if (j < n_my) {
-      const int iu = iu0 + j % ni, iv = iv0 + j / ni;
-      const double du = centre_of(g, u, iu) - pu, dv = centre_of(g, v, iv) - pv;
-      if (du * du + dv * dv < r2) my = (uint32_t)(a * npix + (int64_t)iv * g.w + iu);
-    }
-    uint64_t pending = __ballot(my != 0xffffffffu);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const uint32_t ray = __shfl(my, leader);
-      const uint64_t same = __ballot(my == ray);
-      uint32_t base = 0;
-      if ((int)lane == leader) {
-        if (kScatter) base = atomicAdd(&g.ray_cursor[ray], (uint32_t)__popcll(same));
-        else atomicAdd(&g.ray_count[ray], (uint32_t)__popcll(same));
+  // every lane's j-th pixel, j = 0, 1, ... while any lane has one; the ray
+  // it hits (or -1) and the runs of equal rays
+  auto sweep = [&](auto&& on_run) {
+    for (int j = 0; __ballot(j < n_my) != 0; ++j) {
+      int my = -1;
+      if (j < n_my) {
+        const int iu = iu0 + j % ni, iv = iv0 + j / ni;
+        const double du = centre_of(g, u, iu) - pu, dv = centre_of(g, v, iv) - pv;
+        if (du * du + dv * dv < r2) my = (int)(a * npix + (int64_t)iv * g.w + iu);
       }
-      if (kScatter) {
-        base = __shfl(base, leader);
-        if (my == ray) g.list[g.ray_start[ray] + base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull))] = s;
-      }
-      if (my == ray) my = 0xffffffffu;
-      pending &= ~same;
+      on_run(my, lane_runs(my));
     }
+  };
+  sweep([&](int my, const LaneRuns& r) {
+    if (my >= 0 && r.leader == lane) {
+      const int sl = bin_insert(h, (uint32_t)my);
+      if (sl >= 0) atomicAdd(&h.a[sl], r.group);
+      else if (!kScatter) atomicAdd(&g.ray_count[my], r.group);
+    }
+  });
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBinSlots; i += kOffBlock) {
+    const uint32_t k = h.key[i];
+    if (k == kBinEmpty) continue;
+    if (!kScatter) atomicAdd(&g.ray_count[k], h.a[i]);
+    else h.a[i] = g.ray_start[k] + atomicAdd(&g.ray_cursor[k], h.a[i]);
   }
+  if (!kScatter) return;
+  __syncthreads();
+  sweep([&](int my, const LaneRuns& r) {
+    uint32_t lead_base = 0;
+    if (my >= 0 && r.leader == lane) {
+      const int sl = bin_find(h, (uint32_t)my);
+      lead_base = sl >= 0 ? h.a[sl] + atomicAdd(&h.b[sl], r.group)
+                          : g.ray_start[my] + atomicAdd(&g.ray_cursor[my], r.group);
+    }
+    const uint32_t base = (uint32_t)__shfl((int)lead_base, r.leader, 64);
+    if (my >= 0) g.list[base + r.rank] = s;
+  });
 }
 
 // One event's world-order normal and depth for a sphere g on the ray of axis
@@ -222,6 +249,8 @@ __device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
 // pass, with a 32-bin histogram in hist (32 words; the ray pass lends it
 // the wave's state bits, which hold kOffsetBuf / 32 words).
 static_assert(kOffsetBuf / 32 >= 32, "the radix select's 32-bin histogram must fit the wave's state bits");
+// a sweep step appends up to 64 end points after a flush that leaves one
+static_assert(kOffsetEmit >= 65, "the emit buffer takes one step after a flush");
 __device__ __forceinline__ uint32_t select_depth(const uint64_t* key, uint32_t n, uint32_t rank, uint32_t* hist) {
   const uint32_t lane = lane_id();
   uint32_t prefix = 0, mask = 0;
@@ -286,8 +315,18 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   const int wv = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   const int64_t npix = (int64_t)g.w * g.w;
-  const int64_t ray = (int64_t)blockIdx.x * kOffWaves + wv;
-  if (ray >= 3 * npix) return;
+  // Waves take the deep rays first (workgroups start in index order, so the
+  // longest rays do not end up as the launch's tail), then every ray in
+  // order, skipping the deep ones.
+  const int64_t wave_no = (int64_t)blockIdx.x * kOffWaves + wv;
+  int64_t ray;
+  if (wave_no < (int64_t)g.n_deep) {
+    ray = g.deep[wave_no];
+  } else {
+    ray = wave_no - g.n_deep;
+    if (ray >= 3 * npix) return;
+    if (g.n_deep > 0 && g.ray_start[ray + 1] - g.ray_start[ray] > (uint32_t)kOffsetDeep) return;
+  }
   const int a = (int)(ray / npix);
   const int64_t p = ray - a * npix;
   const int u = (a + 1) % 3, v = (a + 2) % 3;
@@ -583,8 +622,21 @@ hipError_t launch_offset_bin(const OffsetArgs& g, bool scatter, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_offset_rays(const OffsetArgs& g, bool write, hipStream_t s) {
+__global__ __launch_bounds__(kOffBlock) void offset_deep_kernel(OffsetArgs g) {
+  const int64_t ray = (int64_t)blockIdx.x * kOffBlock + threadIdx.x;
+  if (ray >= 3 * (int64_t)g.w * g.w) return;
+  if (g.ray_start[ray + 1] - g.ray_start[ray] > (uint32_t)kOffsetDeep) g.deep[atomicAdd(&g.status[16], 1u)] = (uint32_t)ray;
+}
+
+hipError_t launch_offset_deep(const OffsetArgs& g, hipStream_t s) {
   const int64_t rays = 3 * (int64_t)g.w * g.w;
+  hipLaunchKernelGGL(offset_deep_kernel, dim3((unsigned)((rays + kOffBlock - 1) / kOffBlock)), dim3(kOffBlock), 0, s,
+                     g);
+  return hipGetLastError();
+}
+
+hipError_t launch_offset_rays(const OffsetArgs& g, bool write, hipStream_t s) {
+  const int64_t rays = 3 * (int64_t)g.w * g.w + g.n_deep;
   const dim3 grid((unsigned)((rays + kOffWaves - 1) / kOffWaves));
   if (write) hipLaunchKernelGGL(offset_ray_kernel<true>, grid, dim3(kOffBlock), 0, s, g);
   else hipLaunchKernelGGL(offset_ray_kernel<false>, grid, dim3(kOffBlock), 0, s, g);
