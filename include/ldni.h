@@ -203,8 +203,8 @@ ldni_status ldni_backward(const float *verts, int64_t n_verts, const int32_t *tr
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  The same arguments, result and errors
  * as ldni_backward, computed by the same kernels; the per-triangle partial
- * sums live in a fixed scratch array of the library (12 floats per triangle
- * for up to 262,144 triangles, 12 MiB, held on each device the library runs
+ * sums live in a fixed scratch array of the library (18 floats per triangle
+ * for up to 262,144 triangles, 18 MiB, held on each device the library runs
  * on until the process ends) instead of pool memory, and the call makes no
  * allocation of any kind (no hipMalloc or hipFree, no allocating library
  * routine).  n_tris above 262,144 gives LDNI_ERR_INVALID_ARG.  Every call on

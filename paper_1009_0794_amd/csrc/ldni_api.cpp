@@ -1015,12 +1015,12 @@ ldni_status backward_args(const float* verts, int64_t n_verts, const int32_t* tr
   return LDNI_OK;
 }
 
-// The no-allocation backward's scratch: per triangle 3 floats for each image
-// and 3 for the normal sums (12 floats), for up to kNoAllocTris triangles.
+// The no-allocation backward's scratch: per triangle 6 floats for each image
+// (18 floats), for up to kNoAllocTris triangles.
 // Each device holds its own copy from the library's load to the process
 // end; host code uses only the address hipGetSymbolAddress gives per device.
 constexpr int64_t kNoAllocTris = 262144;
-__device__ __align__(256) float scratch[12 * kNoAllocTris];
+__device__ __align__(256) float scratch[18 * kNoAllocTris];
 std::mutex g_scratch_mu;
 float* g_scratch_ptr[64] = {};
 
@@ -1060,13 +1060,12 @@ ldni_status ldni_backward(const float* verts, int64_t n_verts, const int32_t* tr
   prepare_pool(device);
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  const size_t per = align_up(sizeof(float) * 3 * (size_t)n_tris);
-  hipError_t e = cache_get(&ws, per * (nimg + 1), stream, &ws_bytes);
+  const size_t per = align_up(sizeof(float) * 6 * (size_t)n_tris);
+  hipError_t e = cache_get(&ws, per * nimg, stream, &ws_bytes);
   if (e != hipSuccess) return hip_fail(e, "backward workspace");
   char* base = static_cast<char*>(ws);
   for (int k = 0; k < nimg; ++k) args.axis[k].acc = reinterpret_cast<float*>(base + k * per);
-  args.gnsum = reinterpret_cast<float*>(base + nimg * per);
-  e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, (int64_t)(per * (nimg + 1) / 4), stream);
+  e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, (int64_t)(per * nimg / 4), stream);
   if (e == hipSuccess) e = timed("backward", stream, [&] { return launch_backward(args, stream); });
   cache_put(ws, ws_bytes, stream);
   if (e != hipSuccess) return hip_fail(e, "backward kernels");
@@ -1089,12 +1088,11 @@ ldni_status ldni_backward_noalloc(const float* verts, int64_t n_verts, const int
   if (st != LDNI_OK) return st;
   const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   // the same layout as ldni_backward's workspace, without the 256-byte
-  // rounding: the sums of image k at k * 3T, the normal sums at nimg * 3T
-  const int64_t per = 3 * n_tris;
+  // rounding: the sums of image k at k * 6T
+  const int64_t per = 6 * n_tris;
   for (int k = 0; k < nimg; ++k) args.axis[k].acc = ws + k * per;
-  args.gnsum = ws + nimg * per;
   // the last call's sums are still there: cleared by a fill kernel
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, per * (nimg + 1), stream);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws), 0u, per * nimg, stream);
   if (e == hipSuccess) e = launch_backward(args, stream);
   if (e != hipSuccess) return hip_fail(e, "backward kernels");
   return LDNI_OK;

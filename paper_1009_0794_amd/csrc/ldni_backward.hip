@@ -22,8 +22,8 @@ inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_
 //   normal: n = N/|N|, N = (B-A)x(C-A): dL/dN = (gn - n (n.gn)) / |N| and
 //           dL/dA = (B-C) x dL/dN, dL/dB = (C-A) x dL/dN, dL/dC = (A-B) x dL/dN.
 // n / n_a and the normal Jacobian are constant per triangle, so the
-// sample-parallel kernel only accumulates sum(gd * lambda_X) per (triangle,
-// image) and sum(gn) per triangle; the triangle-parallel kernel applies the
+// sample-parallel kernel only accumulates, per (triangle, image), the sums of
+// gd * lambda_X and of gn; the triangle-parallel kernel applies the
 // per-triangle factors and adds to the three vertices.
 struct BackwardImage {
   int32_t a, u, v, w;
@@ -32,7 +32,7 @@ struct BackwardImage {
   const int32_t* tri;       // [n]
   const float* gd;          // [n] or null
   const float* gn;          // [n][3] or null
-  float* acc;               // [T][3] sum of gd * lambda per vertex
+  float* acc;               // [T][6] sums of gd * lambda per vertex, then of gn
 };
 
 struct BackwardSet {
@@ -43,17 +43,43 @@ struct BackwardSet {
   int64_t n_verts;
   const int32_t* tris;
   int64_t n_tris;
-  float* gnsum;                          // [T][3] sum of gn
 };
 
 // One workgroup per kBwdTile x kBwdTile pixel tile.  The tile's samples (one
 // contiguous range per pixel row) are spread over the threads; each sample's
 // six values (gd * lambda per vertex, gn) are summed per triangle in an LDS
-// hash table, and every triangle of the tile then adds its sums to global
-// memory once.  A sample that finds no free slot adds its own directly.
+// hash table, and every triangle of the tile then writes its sums once: with
+// plain stores when every pixel centre its projection can cover lies in the
+// tile (no other tile has samples of it on this image: the common case, and
+// stores cost far less than global atomics), else with atomic additions.  A
+// sample that finds no free slot adds its own directly (its triangle then has
+// no slot in this tile, so nothing stores over it).
 constexpr int kBwdTile = 16;
 constexpr int kBwdSlots = 1024;
 constexpr int kBwdProbe = 32;
+
+// Whether every pixel whose centre can lie in the projection of triangle t
+// on image im is a pixel of the tile (x0, y0, cw, ch): the centres within the
+// projection's bounding box, widened by a pixel for the rounding of the
+// centres.  Only then does the tile hold all of t's samples on im.
+__device__ __forceinline__ bool projection_in_tile(const BackwardSet& bs, const BackwardImage& im, int64_t t,
+                                                   int x0, int y0, int cw, int ch) {
+  const int32_t* fv = bs.tris + 3 * t;
+  double umin = HUGE_VAL, umax = -HUGE_VAL, vmin = HUGE_VAL, vmax = -HUGE_VAL;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float* P = bs.verts + 3 * (int64_t)min(max(fv[q], 0), (int32_t)(bs.n_verts - 1));
+    umin = fmin(umin, (double)P[im.u]);
+    umax = fmax(umax, (double)P[im.u]);
+    vmin = fmin(vmin, (double)P[im.v]);
+    vmax = fmax(vmax, (double)P[im.v]);
+  }
+  // pixel i has centre lo + (i + 0.5) h; a centre in [mn, mx] has i within
+  // [floor(tmn), ceil(tmx)] for t = (x - lo) / h - 0.5, widened by one
+  const double iu0 = floor((umin - im.lo_u) / im.h_u - 0.5) - 1.0, iu1 = ceil((umax - im.lo_u) / im.h_u - 0.5) + 1.0;
+  const double iv0 = floor((vmin - im.lo_v) / im.h_v - 0.5) - 1.0, iv1 = ceil((vmax - im.lo_v) / im.h_v - 0.5) + 1.0;
+  return iu0 >= (double)x0 && iu1 < (double)(x0 + cw) && iv0 >= (double)y0 && iv1 < (double)(y0 + ch);
+}
 
 __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs) {
   __shared__ uint32_t s_row[kBwdTile + 1][kBwdTile + 1];  // offsets of the tile's rows
@@ -150,13 +176,10 @@ __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs
       for (int c = 0; c < 6; ++c)
         if (v[c] != 0.0f) atomicAdd(&s_val[slot][c], v[c]);
     } else {
-      float* a3 = accp + 3 * (int64_t)t;
-      float* g3 = bs.gnsum + 3 * (int64_t)t;
+      float* a6 = accp + 6 * (int64_t)t;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (v[c] != 0.0f) atomicAdd(a3 + c, v[c]);
-        if (v[3 + c] != 0.0f) atomicAdd(g3 + c, v[3 + c]);
-      }
+      for (int c = 0; c < 6; ++c)
+        if (v[c] != 0.0f) atomicAdd(a6 + c, v[c]);
     }
   }
   __syncthreads();
@@ -164,23 +187,26 @@ __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs
     const uint32_t key = s_key[q];
     if (key == 0u) continue;
     const int64_t t = (int64_t)(key - 1u);
-    float* a3 = accp + 3 * t;
-    float* g3 = bs.gnsum + 3 * t;
+    float* a6 = accp + 6 * t;
+    if (projection_in_tile(bs, im, t, x0, y0, cw, ch)) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (s_val[q][c] != 0.0f) atomicAdd(a3 + c, s_val[q][c]);
-      if (s_val[q][3 + c] != 0.0f) atomicAdd(g3 + c, s_val[q][3 + c]);
+      for (int c = 0; c < 6; ++c) a6[c] = s_val[q][c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (s_val[q][c] != 0.0f) atomicAdd(a6 + c, s_val[q][c]);
     }
   }
 }
 
-__global__ void __launch_bounds__(kBlock) backward_triangles_kernel(BackwardSet bs, int64_t n_tris,
-                                                                    float* grad) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n_tris) return;
+// The gradient of triangle t's three vertices (false: t is not a valid
+// triangle, or degenerate, and adds nothing).
+__device__ bool triangle_gradient(const BackwardSet& bs, int64_t t, int32_t (&vid)[3], double (&g)[3][3]) {
   const int32_t* f = bs.tris + 3 * t;
-  for (int q = 0; q < 3; ++q)
-    if (f[q] < 0 || f[q] >= bs.n_verts) return;  // not a valid triangle
+  for (int q = 0; q < 3; ++q) {
+    vid[q] = f[q];
+    if (f[q] < 0 || f[q] >= bs.n_verts) return false;  // not a valid triangle
+  }
   double P[3][3];
 #pragma unroll
   for (int q = 0; q < 3; ++q)
@@ -195,13 +221,19 @@ __global__ void __launch_bounds__(kBlock) backward_triangles_kernel(BackwardSet 
   const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
                        e1[0] * e2[1] - e1[1] * e2[0]};
   const double len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-  if (!(len > 0.0)) return;
+  if (!(len > 0.0)) return false;
   const double n[3] = {N[0] / len, N[1] / len, N[2] / len};
-  double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // per vertex
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[q][c] = 0.0;
+  double G[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < bs.n; ++k) {
     const BackwardImage& im = bs.img[k];
+    const float* acc = im.acc + 6 * t;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) G[c] += (double)acc[3 + c];
     if (n[im.a] == 0.0) continue;
-    const float* acc = im.acc + 3 * t;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const double s = (double)acc[q] / n[im.a];
@@ -209,8 +241,6 @@ __global__ void __launch_bounds__(kBlock) backward_triangles_kernel(BackwardSet 
       for (int c = 0; c < 3; ++c) g[q][c] += s * n[c];
     }
   }
-  const float* gsum = bs.gnsum + 3 * t;
-  const double G[3] = {gsum[0], gsum[1], gsum[2]};
   if (G[0] != 0.0 || G[1] != 0.0 || G[2] != 0.0) {
     const double dot = n[0] * G[0] + n[1] * G[1] + n[2] * G[2];
     double gN[3];
@@ -230,11 +260,24 @@ __global__ void __launch_bounds__(kBlock) backward_triangles_kernel(BackwardSet 
       g[q][2] += ed[q][0] * gN[1] - ed[q][1] * gN[0];
     }
   }
+  return true;
+}
+
+// One thread per triangle, adding to its three vertices with global atomics.
+// (Neighbouring lanes add to neighbouring vertices, so a wave's atomics meet
+// few cache lines; summing per vertex in an LDS table first was slower:
+// 80 against 30 us on the flower.)
+__global__ void __launch_bounds__(kBlock) backward_triangles_kernel(BackwardSet bs, int64_t n_tris,
+                                                                    float* grad) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int32_t vid[3];
+  double g[3][3];
+  if (t >= n_tris || !triangle_gradient(bs, t, vid, g)) return;
 #pragma unroll
   for (int q = 0; q < 3; ++q)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      if (g[q][c] != 0.0) atomicAdd(grad + 3 * (int64_t)f[q] + c, (float)g[q][c]);
+      if (g[q][c] != 0.0) atomicAdd(grad + 3 * (int64_t)vid[q] + c, (float)g[q][c]);
 }
 
 }  // namespace
@@ -246,7 +289,6 @@ hipError_t launch_backward(const BackwardArgs& args, hipStream_t s) {
   bs.n_verts = args.n_verts;
   bs.tris = args.tris;
   bs.n_tris = args.n_tris;
-  bs.gnsum = args.gnsum;
   bs.block_start[0] = 0;
   for (int k = 0; k < args.n; ++k) {
     const BackwardAxis& a = args.axis[k];

@@ -223,7 +223,7 @@ struct BackwardAxis {
   const int32_t* tri;
   const float* gd;  // may be null
   const float* gn;  // may be null
-  float* acc;       // workspace [T][3], zeroed
+  float* acc;       // workspace [T][6], zeroed
 };
 struct BackwardArgs {
   BackwardAxis axis[kMaxImages];
@@ -234,7 +234,6 @@ struct BackwardArgs {
   int64_t n_verts;
   const int32_t* tris;
   int64_t n_tris;
-  float* gnsum;  // workspace [T][3], zeroed
   float* grad;   // [V][3], accumulated
 };
 hipError_t launch_backward(const BackwardArgs& args, hipStream_t s);
