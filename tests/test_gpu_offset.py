@@ -210,3 +210,27 @@ def test_bad_offsets_rejected():
     with pytest.raises(LDNIError) as e:
         ldni.offset({0: G[0], 1: bad, 2: G[2]}, BBOX, 0.1)
     assert e.value.code == 1
+
+
+def test_binning_tables_overflow():
+    """A small sphere offset by a radius three times its own: the 256
+    spheres of a binning workgroup hit more rays than its LDS table holds
+    (1,024 slots), so some rays are counted and placed through the global
+    fallback (in both binning passes) while the others go through the
+    table; the result matches the oracle bit for bit."""
+    w, r = 64, 0.6
+    v, f = mg.icosphere(1, radius=0.2, center=(0.05, -0.03, 0.02))
+    L = oracle.sample(v, f, BBOX, w, axes="xyz")
+    centres = oo.sphere_centres(L, BBOX, w)
+    assert len(centres) >= 256
+    b = oracle.bbox_f32(BBOX)
+    # the rays of image 0 that the first workgroup's 256 spheres hit
+    cu = ((b[1] + (np.arange(w) + 0.5) * (b[4] - b[1]) / w).astype(np.float32)).astype(np.float64)
+    cv = ((b[2] + (np.arange(w) + 0.5) * (b[5] - b[2]) / w).astype(np.float32)).astype(np.float64)
+    c = centres[:256]
+    d2 = (cu[None, None, :] - c[:, 1, None, None]) ** 2 + (cv[None, :, None] - c[:, 2, None, None]) ** 2
+    assert int((d2 < r * r).any(axis=0).sum()) > 1024
+    ref = oo.offset(L, BBOX, w, r)
+    got = ldni.offset({a: _to_gpu(a, L[a]) for a in range(3)}, BBOX, r)
+    for a in range(3):
+        _same(got[a], ref[a], f"axis {a}")

@@ -359,3 +359,32 @@ def test_samples_beyond_32_bits_rejected():
     m = mg.c1_icosphere()
     compare(_run(m.verts, m.tris, m.bbox, m.w), oracle.sample(m.verts, m.tris, m.bbox, m.w), m.bbox,
             label="after overflow")
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_binning_tables_overflow(tile):
+    """Few large triangles at a high resolution: the first chunk of 512
+    triangles meets more (image, tile) pairs than its LDS table holds (1,024
+    slots), so the binning counts and scatters some tiles through the global
+    fallback and the others through the table; the result matches the
+    oracle bit for bit."""
+    ldni.set_tile_shape(*tile)
+    v, f = mg.icosphere(2, radius=0.8, center=(0.03, -0.02, 0.01))
+    bb = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
+    w = 1024
+    assert len(f) <= 512
+    # distinct (image, tile) pairs of the chunk, from the triangles' bounding boxes
+    b = np.asarray(oracle.bbox_f32(bb), np.float64)
+    keys = set()
+    P = v[f].astype(np.float64)
+    for a in range(3):
+        u, vv = (a + 1) % 3, (a + 2) % 3
+        h = (b[3 + u] - b[u]) / w
+        for tri in P:
+            i0 = int(np.floor((tri[:, u].min() - b[u]) / h)) // tile[0]
+            i1 = int(np.floor((tri[:, u].max() - b[u]) / h)) // tile[0]
+            j0 = int(np.floor((tri[:, vv].min() - b[vv]) / h)) // tile[1]
+            j1 = int(np.floor((tri[:, vv].max() - b[vv]) / h)) // tile[1]
+            keys.update((a, i, j) for i in range(i0, i1 + 1) for j in range(j0, j1 + 1))
+    assert len(keys) > 2048
+    compare(_run(v, f, bb, w), oracle.sample(v, f, bb, w), bb, label=f"icosphere tile {tile}")
