@@ -479,12 +479,13 @@ class Batch:
 def sample_batch(meshes, axes="xyz", tiles="auto") -> Batch:
     """Create (and run once) a batch; see ``Batch``.  With tiles="auto",
     meshes given without a tile shape get the autotuned one for their
-    resolution and triangle density (``autotune.lookup``)."""
+    resolution and triangle density, tuned inside a batch where that table
+    has the bucket (``autotune.batch_lookup``)."""
     if tiles == "auto":
         from . import autotune
-        table = autotune.load_table()
+        table, btable = autotune.load_table(), autotune.load_table(autotune.BATCH_TABLE_PATH)
         meshes = [tuple(m[:4]) + ((m[4] if len(m) > 4 and m[4] is not None
-                                   else autotune.lookup(int(m[3]), int(m[1].shape[0]), table)),)
+                                   else autotune.batch_lookup(int(m[3]), int(m[1].shape[0]), btable, table)),)
                   for m in meshes]
     return Batch(meshes, axes)
 

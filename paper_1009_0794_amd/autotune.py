@@ -10,6 +10,12 @@ not depend on the shape, only speed does.
 
 The table is JSON: {"arch": "...", "entries": {"w<W>_d<D>": [tw, th], ...}},
 where W is the resolution rounded to a power of two and D = round(log2(T / w^2)).
+
+Inside a batch the best shapes differ: the images share one graph and the
+persistent kernels of each tile class, so ``tune_batch`` times whole batch
+replays (``ldni_batch_run``) and changes one bucket's shape at a time
+(coordinate descent from the plain table), writing a second table that
+``sample_batch`` prefers.
 """
 from __future__ import annotations
 
@@ -22,6 +28,7 @@ SHAPES = [(32, 32), (16, 16), (64, 16), (32, 8), (64, 8), (128, 8), (16, 32), (8
 DEFAULT = (0, 0)  # the library chooses from the triangle density
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.environ.get("LDNI_TILE_TABLE", os.path.join(HERE, "tile_table.json"))
+BATCH_TABLE_PATH = os.environ.get("LDNI_BATCH_TILE_TABLE", os.path.join(HERE, "tile_table_batch.json"))
 
 
 def bucket(w: int, n_tris: int) -> str:
@@ -96,6 +103,69 @@ def tune(meshes: Iterable, shapes=SHAPES, reps=5, table=None, verbose=False) -> 
     return table
 
 
+def batch_lookup(w: int, n_tris: int, batch_table=None, table=None) -> Tuple[int, int]:
+    """Tile shape for a mesh inside a batch: the batch table's bucket if it
+    has one, else ``lookup``."""
+    batch_table = load_table(BATCH_TABLE_PATH) if batch_table is None else batch_table
+    k = bucket(w, n_tris)
+    if k in batch_table:
+        return batch_table[k]
+    return lookup(w, n_tris, table)
+
+
+def time_batch(ldni, torch, meshes, shapes, reps=3) -> float:
+    """Mean milliseconds of one replay of the batch of meshes ((verts, tris,
+    bbox, w) with device tensors), mesh k sampled with tile shape shapes[k]."""
+    b = ldni.sample_batch([(v, t, bb, w, sh) for (v, t, bb, w), sh in zip(meshes, shapes)], "xyz", tiles=None)
+    try:
+        b.run()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            b.run()
+        e.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(e) / reps
+    finally:
+        b.free()
+
+
+def tune_batch(meshes, shapes=SHAPES, reps=4, table=None, rounds=1, top=16, gain=0.995,
+               verbose=False) -> Dict[str, Tuple[int, int]]:
+    """Coordinate descent over the buckets of one batch: start from the plain
+    table's shapes and, bucket by bucket (the `top` buckets with the most
+    work, triangles plus pixels of three images, first), keep a shape whose
+    batch replay is faster by more than the noise (below `gain` times the
+    best so far).  Returns the buckets' shapes (the batch table)."""
+    import torch
+
+    import paper_1009_0794_amd as ldni
+    table = dict(load_table() if table is None else table)
+    keys = [bucket(w, int(t.shape[0])) for _, t, _, w in meshes]
+    cur = {k: tuple(lookup(w, int(t.shape[0]), table)) for k, (_, t, _, w) in zip(keys, meshes)}
+    weight: Dict[str, int] = {}
+    for k, (_, t, _, w) in zip(keys, meshes):
+        weight[k] = weight.get(k, 0) + int(t.shape[0]) + 3 * w * w
+    order = sorted(weight, key=lambda k: -weight[k])[:top]
+    best = time_batch(ldni, torch, meshes, [cur[k] for k in keys], reps)
+    if verbose:
+        print(f"start: {best:.3f} ms", flush=True)
+    for _ in range(rounds):
+        for k in order:
+            for sh in shapes:
+                if sh == cur[k]:
+                    continue
+                trial = dict(cur)
+                trial[k] = sh
+                ms = time_batch(ldni, torch, meshes, [trial[q] for q in keys], reps)
+                if verbose:
+                    print(f"{k} tile {sh[0]}x{sh[1]}: {ms:.3f} ms (best {best:.3f})", flush=True)
+                if ms < gain * best:
+                    best, cur = ms, trial
+    return cur
+
+
 if __name__ == "__main__":
     # Tune on the seeded batch workload and the single-mesh workloads, then
     # write the table next to this file (or to $LDNI_TILE_TABLE).
@@ -106,6 +176,14 @@ if __name__ == "__main__":
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_1009_0794_amd import meshgen as mg
 
+    if "--batch" in sys.argv:
+        # the batch table, tuned on the seeded 256-mesh batch itself
+        ms = mg.c4_batch256()
+        meshes = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.tris).cuda(), m.bbox, m.w) for m in ms]
+        btable = tune_batch(meshes, verbose=True)
+        save_table(btable, torch.cuda.get_device_properties(0).gcnArchName, BATCH_TABLE_PATH)
+        print(json.dumps({k: list(v) for k, v in sorted(btable.items())}))
+        sys.exit(0)
     meshes = []
     pool = mg.c4_batch256(n=48) + [mg.c2_flower(), mg.c1_icosphere()]
     seen = set()

@@ -37,3 +37,20 @@ def test_shipped_table_holds_valid_shapes():
     for k, (tw, th) in table.items():
         assert k.startswith("w") and "_d" in k
         assert 8 <= tw <= 256 and 1 <= th <= 64 and tw * th <= 1024, (k, tw, th)
+
+
+def test_batch_lookup_prefers_the_batch_table():
+    table = {"w512_d0": (8, 8), "w512_d-4": (32, 32)}
+    btable = {"w512_d0": (16, 16)}
+    assert autotune.batch_lookup(512, 512 * 512, btable, table) == (16, 16)
+    assert autotune.batch_lookup(512, 512 * 512 // 16, btable, table) == (32, 32)  # not in the batch table
+    assert autotune.batch_lookup(2048, 10 ** 6, {}, {}) == autotune.DEFAULT
+
+
+def test_shipped_batch_table_holds_valid_shapes():
+    table = autotune.load_table(autotune.BATCH_TABLE_PATH)
+    if not table:
+        pytest.skip("no batch table in the package")
+    for k, (tw, th) in table.items():
+        assert k.startswith("w") and "_d" in k
+        assert 8 <= tw <= 256 and 1 <= th <= 64 and tw * th <= 1024, (k, tw, th)
