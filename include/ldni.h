@@ -72,6 +72,13 @@ typedef enum {
 
 enum { LDNI_AXIS_X = 1u, LDNI_AXIS_Y = 2u, LDNI_AXIS_Z = 4u, LDNI_AXIS_ALL = 7u };
 
+/* Option bit for the axis_mask of ldni_sample, ldni_batch_create and
+ * ldni_sample_batch: store each sample's normal as the 8-bit colour code of
+ * Sec. 3's approximate normal sampling (one u32: x | y << 8 | z << 16, each
+ * byte the rounded colour (c + 1) / 2 * 255) in the view's normal_rgb8
+ * instead of three floats in normal.  Every other entry point rejects it. */
+enum { LDNI_NORMAL_RGB8 = 256u };
+
 /* Read-only view of one axis of a result (borrowed; valid until the result
  * is freed). */
 typedef struct {
@@ -82,6 +89,9 @@ typedef struct {
   const float *depth;      /* device [n_samples] */
   const float *normal;     /* device [n_samples][3] */
   const int32_t *tri;      /* device [n_samples], id of the hit triangle */
+  const uint32_t *normal_rgb8; /* device [n_samples] 8-bit normal codes of a
+                                  result made with LDNI_NORMAL_RGB8 (normal is
+                                  then NULL), else NULL; ignored in inputs */
 } ldni_axis_view;
 
 typedef struct ldni_result ldni_result; /* opaque; owns its device buffers */
@@ -95,7 +105,8 @@ typedef struct ldni_plan ldni_plan;     /* opaque; a sampling call split in two 
  *             paper's working envelope (Sec. 3): it fixes the pixel grid
  *             and the depth origin; it does not clip.
  *   w         resolution, 1..16384.
- *   axis_mask any non-empty subset of LDNI_AXIS_{X,Y,Z}.
+ *   axis_mask any non-empty subset of LDNI_AXIS_{X,Y,Z}, optionally with
+ *             LDNI_NORMAL_RGB8 (8-bit normal codes instead of float normals).
  *   out       receives a result that owns every output buffer (device memory
  *             from the stream-ordered pool of the current device); release it
  *             with ldni_free.  Axes not in the mask have empty views.

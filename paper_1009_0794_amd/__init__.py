@@ -30,6 +30,15 @@ AXES = "xyz"
 library_path = _lib.LIB_PATH
 
 
+NORMAL_RGB8 = 256  # option bit of the axis mask: 8-bit normal codes (LDNI_NORMAL_RGB8)
+
+
+def _normals_flag(normals: str) -> int:
+    if normals not in ("f32", "rgb8"):
+        raise ValueError("normals must be 'f32' or 'rgb8'")
+    return NORMAL_RGB8 if normals == "rgb8" else 0
+
+
 def axis_mask(axes) -> int:
     if isinstance(axes, int):
         return axes
@@ -161,9 +170,12 @@ def sample(verts, tris, bbox, w: int, axes="xyz", normals="f32") -> Dict[int, LD
 
 
 def _view(l: LDNI) -> _lib.AxisView:
+    """An input view; an LDNI with 8-bit normal codes passes no float normals
+    (the operations that read normals then reject it)."""
     ptr = lambda t: None if t is None else t.data_ptr()
+    normal = l.normal if (l.normal is not None and l.normal.dtype == _torch().float32) else None
     return _lib.AxisView(int(l.w), int(max(l.max_layers, 0)), int(l.tri.shape[0]),
-                         l.offsets.data_ptr(), ptr(l.depth), ptr(l.normal), l.tri.data_ptr())
+                         l.offsets.data_ptr(), ptr(l.depth), ptr(normal), l.tri.data_ptr())
 
 
 def ldni_backward(verts, tris, bbox, w: int, ldnis: Dict[int, LDNI], grad_depth=None,
@@ -310,14 +322,15 @@ class Result:
             pass
 
 
-def ldni_sample(verts, tris, bbox, w: int, axes="xyz", stream=None) -> Result:
-    """The one-call C ABI: the library allocates and owns the outputs."""
+def ldni_sample(verts, tris, bbox, w: int, axes="xyz", stream=None, normals="f32") -> Result:
+    """The one-call C ABI: the library allocates and owns the outputs.
+    normals="rgb8" stores 8-bit normal codes (the views' normal_rgb8)."""
     verts, tris = _check_mesh(verts, tris)
     h = ctypes.c_void_p()
     st = _stream(verts.device) if stream is None else ctypes.c_void_p(stream)
     _lib.check(_lib.lib().ldni_sample(verts.data_ptr(), verts.shape[0], tris.data_ptr(),
-                                      tris.shape[0], _bbox(bbox), int(w), axis_mask(axes), st,
-                                      ctypes.byref(h)))
+                                      tris.shape[0], _bbox(bbox), int(w),
+                                      axis_mask(axes) | _normals_flag(normals), st, ctypes.byref(h)))
     return Result(h)
 
 
@@ -406,17 +419,22 @@ def offset(ldnis, bbox, r: float, eps: float = 1e-5) -> Dict[int, LDNI]:
 
 
 def _copy_view(v: _lib.AxisView, axis: int, device) -> LDNI:
+    """Copies a view into new tensors; a view with 8-bit normal codes gives
+    an int32 [n] ``normal`` tensor of the codes."""
     torch = _torch()
     n = int(v.n_samples)
+    rgb8 = bool(v.normal_rgb8)
     out = LDNI(axis, int(v.w), int(v.max_layers),
                torch.empty(int(v.w) * int(v.w) + 1, dtype=torch.int32, device=device),
                torch.empty(n, dtype=torch.float32, device=device),
-               torch.empty((n, 3), dtype=torch.float32, device=device),
+               (torch.empty(n, dtype=torch.int32, device=device) if rgb8 else
+                torch.empty((n, 3), dtype=torch.float32, device=device)),
                torch.empty(n, dtype=torch.int32, device=device))
     H = _lib.hip()
     st = _stream(device)
     for dst, src, nbytes in ((out.offsets, v.offsets, 4 * out.offsets.numel()),
-                             (out.depth, v.depth, 4 * n), (out.normal, v.normal, 12 * n),
+                             (out.depth, v.depth, 4 * n),
+                             (out.normal, v.normal_rgb8 if rgb8 else v.normal, (4 if rgb8 else 12) * n),
                              (out.tri, v.tri, 4 * n)):
         if nbytes:
             rc = H.hipMemcpyAsync(dst.data_ptr(), src, nbytes, 3, st)
@@ -432,8 +450,9 @@ class Batch:
     (tile_w, tile_h)) with device tensors, which must stay alive and at the
     same addresses; ``run()`` samples their current contents again."""
 
-    def __init__(self, meshes, axes="xyz"):
+    def __init__(self, meshes, axes="xyz", normals="f32"):
         torch = _torch()
+        flag = _normals_flag(normals)
         self._keep = []
         descs = (_lib.MeshDesc * len(meshes))()
         dev = None
@@ -450,7 +469,7 @@ class Batch:
         self.n_meshes = len(meshes)
         self.mask = axis_mask(axes)
         self.handle = ctypes.c_void_p()
-        _lib.check(_lib.lib().ldni_batch_create(len(meshes), descs, self.mask, _stream(self.device),
+        _lib.check(_lib.lib().ldni_batch_create(len(meshes), descs, self.mask | flag, _stream(self.device),
                                                 ctypes.byref(self.handle)))
 
     def run(self):
@@ -476,7 +495,7 @@ class Batch:
             pass
 
 
-def sample_batch(meshes, axes="xyz", tiles="auto") -> Batch:
+def sample_batch(meshes, axes="xyz", tiles="auto", normals="f32") -> Batch:
     """Create (and run once) a batch; see ``Batch``.  With tiles="auto",
     meshes given without a tile shape get the autotuned one for their
     resolution and triangle density, tuned inside a batch where that table
@@ -487,7 +506,7 @@ def sample_batch(meshes, axes="xyz", tiles="auto") -> Batch:
         meshes = [tuple(m[:4]) + ((m[4] if len(m) > 4 and m[4] is not None
                                    else autotune.batch_lookup(int(m[3]), int(m[1].shape[0]), btable, table)),)
                   for m in meshes]
-    return Batch(meshes, axes)
+    return Batch(meshes, axes, normals)
 
 
 def ldni_result_axis(result: Result, axis: int) -> _lib.AxisView:

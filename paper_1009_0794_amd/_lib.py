@@ -17,7 +17,7 @@ class AxisView(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int32), ("max_layers", ctypes.c_uint32),
                 ("n_samples", ctypes.c_uint64), ("offsets", ctypes.c_void_p),
                 ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
-                ("tri", ctypes.c_void_p)]
+                ("tri", ctypes.c_void_p), ("normal_rgb8", ctypes.c_void_p)]
 
 
 class MeshDesc(ctypes.Structure):

@@ -893,6 +893,8 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
                         ldni_result** out) {
   if (out) *out = nullptr;
   if (!out) return fail(LDNI_ERR_INVALID_ARG, "NULL result pointer");
+  const bool rgb8 = (axis_mask & LDNI_NORMAL_RGB8) != 0;
+  axis_mask &= ~(uint32_t)LDNI_NORMAL_RGB8;
   ldni_status st = validate(verts, n_verts, tris, n_tris, bbox, w, axis_mask);
   if (st != LDNI_OK) return st;
   const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
@@ -926,7 +928,7 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
   size_t bytes = 0;
   for (int a = 0; a < 3; ++a) {
     o_depth[a] = bytes; bytes = align_up(bytes + sizeof(float) * n[a]);
-    o_normal[a] = bytes; bytes = align_up(bytes + sizeof(float) * 3 * n[a]);
+    o_normal[a] = bytes; bytes = align_up(bytes + (rgb8 ? sizeof(uint32_t) : 3 * sizeof(float)) * n[a]);
     o_tri[a] = bytes; bytes = align_up(bytes + sizeof(int32_t) * n[a]);
   }
   e = cache_get(&r->samples_buf, bytes, stream, &r->samples_bytes);
@@ -939,12 +941,14 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
   char* sb = static_cast<char*>(r->samples_buf);
   float* dp[3];
   float* np_[3];
+  uint32_t* cp[3];
   int32_t* tp[3];
   uint32_t ml[3];
   ldni_plan_max_layers(plan, ml);
   for (int a = 0; a < 3; ++a) {
     dp[a] = reinterpret_cast<float*>(sb + o_depth[a]);
-    np_[a] = reinterpret_cast<float*>(sb + o_normal[a]);
+    np_[a] = rgb8 ? nullptr : reinterpret_cast<float*>(sb + o_normal[a]);
+    cp[a] = rgb8 ? reinterpret_cast<uint32_t*>(sb + o_normal[a]) : nullptr;
     tp[a] = reinterpret_cast<int32_t*>(sb + o_tri[a]);
     if ((axis_mask >> a) & 1u) {
       ldni_axis_view& v = r->view[a];
@@ -954,10 +958,11 @@ ldni_status ldni_sample(const float* verts, int64_t n_verts, const int32_t* tris
       v.offsets = offs[a];
       v.depth = dp[a];
       v.normal = np_[a];
+      v.normal_rgb8 = cp[a];
       v.tri = tp[a];
     }
   }
-  st = finish_plan(plan, dp, np_, nullptr, tp, r);
+  st = rgb8 ? finish_plan(plan, dp, nullptr, cp, tp, r) : finish_plan(plan, dp, np_, nullptr, tp, r);
   if (st != LDNI_OK) {
     ldni_free(r);
     return st;
@@ -1532,6 +1537,7 @@ struct ldni_batch {
   uint32_t stage_layers = 64;  // staging entries per tile pixel (grows with the deepest pixel)
   void* items = nullptr;  // place items, sized for stage_layers
   uint64_t items_cap = 0;
+  bool rgb8 = false;      // 8-bit normal codes instead of float normals
   bool small = true;      // every image's tiles have at most 256 pixels
   uint64_t small_tiles = 0;  // tiles of the images with small tiles (numbered first)
   uint32_t* host_out = nullptr;
@@ -1585,9 +1591,13 @@ hipError_t batch_upload(ldni_batch* b) {
     b->images_h[k].list_cap = b->list_cap;
   }
   b->dev.list_cap = b->list_cap;
+  // sample arena: depth [cap], normals [cap][3] (or codes [cap]), tri [cap]
+  const uint64_t nw = b->rgb8 ? 1 : 3;
   b->dev.depth = static_cast<float*>(b->samples);
-  b->dev.normal = b->samples ? static_cast<float*>(b->samples) + b->sample_cap : nullptr;
-  b->dev.tri = b->samples ? reinterpret_cast<int32_t*>(static_cast<float*>(b->samples) + 4 * b->sample_cap)
+  b->dev.normal = (b->samples && !b->rgb8) ? static_cast<float*>(b->samples) + b->sample_cap : nullptr;
+  b->dev.normal_rgb8 =
+      (b->samples && b->rgb8) ? reinterpret_cast<uint32_t*>(static_cast<float*>(b->samples) + b->sample_cap) : nullptr;
+  b->dev.tri = b->samples ? reinterpret_cast<int32_t*>(static_cast<float*>(b->samples) + (1 + nw) * b->sample_cap)
                           : nullptr;
   b->dev.sample_cap = b->sample_cap;
   for (int k = 0; k < b->n_img; ++k) {
@@ -1697,8 +1707,8 @@ ldni_status ldni_batch_run(ldni_batch* b, void* hip_stream) {
       continue;
     }
     if (need > b->sample_cap) {
-      // 5 floats per sample: depth, normal[3], tri
-      ldni_status st = batch_grow(b, &b->samples, &b->sample_cap, need, 5 * sizeof(float));
+      // per sample: depth, normal[3] (or one code), tri
+      ldni_status st = batch_grow(b, &b->samples, &b->sample_cap, need, (b->rgb8 ? 3 : 5) * sizeof(float));
       if (st != LDNI_OK) return st;
       batch_release_graph(b);
       continue;
@@ -1744,6 +1754,8 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
                               void* hip_stream, ldni_batch** out) {
   if (out) *out = nullptr;
   if (!out || !meshes || n_meshes < 1) return fail(LDNI_ERR_INVALID_ARG, "need meshes and an output handle");
+  const bool rgb8 = (axis_mask & LDNI_NORMAL_RGB8) != 0;
+  axis_mask &= ~(uint32_t)LDNI_NORMAL_RGB8;
   if (axis_mask == 0 || axis_mask > 7) return fail(LDNI_ERR_INVALID_ARG, "axis_mask must be in [1, 7]");
   const int naxes = __builtin_popcount(axis_mask);
   if ((int64_t)n_meshes * naxes > 65536) return fail(LDNI_ERR_INVALID_ARG, "too many images in one batch");
@@ -1767,6 +1779,7 @@ ldni_status ldni_batch_create(int32_t n_meshes, const ldni_mesh_desc* meshes, ui
   };
   b->n_meshes = n_meshes;
   b->mask = axis_mask;
+  b->rgb8 = rgb8;
   b->desc.assign(meshes, meshes + n_meshes);
   hipError_t e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(hip_fail(e, "stream"));
@@ -2011,10 +2024,14 @@ ldni_status ldni_batch_axis(const ldni_batch* b, int32_t mesh, int axis, ldni_ax
     view->max_layers = b->ml[k];
     view->n_samples = b->n[k];
     view->offsets = b->offsets_arena + b->seg_start[k];
-    view->depth = static_cast<const float*>(b->samples) + b->base[k];
-    view->normal = static_cast<const float*>(b->samples) + b->sample_cap + 3 * b->base[k];
-    view->tri = reinterpret_cast<const int32_t*>(static_cast<const float*>(b->samples) + 4 * b->sample_cap) +
-                b->base[k];
+    const uint64_t nw = b->rgb8 ? 1 : 3;
+    const float* arena = static_cast<const float*>(b->samples);
+    view->depth = arena + b->base[k];
+    if (b->rgb8)
+      view->normal_rgb8 = reinterpret_cast<const uint32_t*>(arena + b->sample_cap) + b->base[k];
+    else
+      view->normal = arena + b->sample_cap + 3 * b->base[k];
+    view->tri = reinterpret_cast<const int32_t*>(arena + (1 + nw) * b->sample_cap) + b->base[k];
   }
   return LDNI_OK;
 }

@@ -177,7 +177,8 @@ struct BatchDevice {
   uint32_t* work;                   // [2] work counters of the persistent kernels
   uint32_t* status;
   float* depth;                     // output arenas, sample_cap samples
-  float* normal;
+  float* normal;                    // float normals, or null
+  uint32_t* normal_rgb8;            // 8-bit normal codes, or null
   int32_t* tri;
   uint64_t sample_cap;
   uint32_t* tile_total;             // entries of all tile lists (end of the tile scan)

@@ -1705,7 +1705,8 @@ __global__ void __launch_bounds__(kBlock) batch_finish_counts_kernel(BatchDevice
     const uint64_t base = B.sample_base[k];
     const bool fits = base + n <= B.sample_cap && (uint64_t)*B.tile_total <= B.list_cap;
     im.depth = fits ? B.depth + base : nullptr;
-    im.normal = fits ? B.normal + 3 * base : nullptr;
+    im.normal = (fits && B.normal) ? B.normal + 3 * base : nullptr;
+    im.normal_rgb8 = (fits && B.normal_rgb8) ? B.normal_rgb8 + base : nullptr;
     im.tri = fits ? B.tri + base : nullptr;
     uint32_t* h = B.host_out + 4 + 4 * (size_t)k;
     h[0] = (uint32_t)n;

@@ -39,7 +39,8 @@ def _call(L, verts=1, nv=3, tris=1, nt=1, bbox=(0, 0, 0, 1, 1, 1), w=8, mask=7):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(w=0), dict(w=16385), dict(w=-3), dict(mask=0), dict(mask=8),
+    dict(w=0), dict(w=16385), dict(w=-3), dict(mask=0), dict(mask=8), dict(mask=256), dict(mask=256 | 8),
+    dict(mask=512 | 7),
     dict(bbox=(0, 0, 0, 0, 1, 1)), dict(bbox=(0, 0, 0, 1, -1, 1)),
     dict(bbox=(0, 0, float("nan"), 1, 1, 1)), dict(bbox=(0, 0, 0, float("inf"), 1, 1)),
     dict(nv=-1), dict(nt=-1), dict(verts=None), dict(tris=None), dict(bbox=None),
@@ -267,3 +268,27 @@ def test_offset_invalid_arguments_rejected_on_host(L, kw):
     assert rc == 1
     assert res is None or not kw.get("out", True)
     assert L.ldni_last_error().decode()
+
+
+def test_rgb8_option_only_where_declared(L):
+    """LDNI_NORMAL_RGB8 (256) is an option of ldni_sample and the batch
+    calls; ldni_sample_begin rejects it as an axis bit."""
+    offs = (ctypes.c_void_p * 3)(1, 1, 1)
+    n = (ctypes.c_uint64 * 3)()
+    plan = ctypes.c_void_p()
+    bb = (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1)
+    assert L.ldni_sample_begin(1, 3, 1, 1, bb, 8, 256 | 7, offs, None, ctypes.byref(plan), n) == 1
+
+
+def test_axis_view_layout_matches_the_header():
+    """The ctypes view has the header's eight fields in order (the last one
+    the 8-bit normal codes)."""
+    from paper_1009_0794_amd import _lib
+    names = [f[0] for f in _lib.AxisView._fields_]
+    assert names == ["w", "max_layers", "n_samples", "offsets", "depth", "normal", "tri", "normal_rgb8"]
+    assert ctypes.sizeof(_lib.AxisView) == 4 + 4 + 8 + 5 * 8
+    hdr = open(os.path.join(ROOT, "include", "ldni.h")).read()
+    body = hdr[hdr.index("typedef struct {\n  int32_t w;"):hdr.index("} ldni_axis_view;")]
+    fields = [m.group(1) for l in body.splitlines()
+              for m in [re.match(r"\s*(?:const\s+)?\w+\s*\*?\s*(\w+);", l)] if m]
+    assert fields == names, fields

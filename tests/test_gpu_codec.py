@@ -90,3 +90,55 @@ def test_tiles_written_in_many_runs(tile):
         _same_codes(*_pair(v, f, BOX8, 48))
     finally:
         ldni.set_tile_shape(0, 0)
+
+
+def test_one_call_result_with_codes():
+    """ldni_sample with LDNI_NORMAL_RGB8: the library-owned result's views
+    carry the codes (normal is NULL), bit for bit those of the oracle's
+    normals, with offsets, depths and ids equal to the float-normal call."""
+    m = mg.c1_icosphere()
+    v, f = _dev(m.verts, np.float32), _dev(m.tris, np.int32)
+    ref = oracle.sample(m.verts, m.tris, m.bbox, 131, axes="xyz")
+    res = ldni.ldni_sample(v, f, m.bbox, 131, "xyz", normals="rgb8")
+    f32 = ldni.ldni_sample(v, f, m.bbox, 131, "xyz")
+    for a in range(3):
+        view = res.view(a)
+        assert not view.normal and view.normal_rgb8
+        got = res.to_torch(a)
+        want = f32.to_torch(a)
+        assert got.normal.dtype == torch.int32 and got.normal.dim() == 1
+        assert torch.equal(got.offsets, want.offsets) and torch.equal(got.depth, want.depth)
+        assert torch.equal(got.tri, want.tri)
+        assert np.array_equal(got.normal.cpu().numpy().view(np.uint32), nc.encode(ref[a].normal))
+    res.free()
+    f32.free()
+
+
+def test_batch_with_codes():
+    """A batch made with LDNI_NORMAL_RGB8: every mesh's codes equal the codes
+    of a plain float-normal call, and the other outputs are identical."""
+    meshes = [mg.c1_icosphere(), mg.c2_flower()]
+    ws = [131, 160]
+    dev = [(_dev(m.verts, np.float32), _dev(m.tris, np.int32), m.bbox, w) for m, w in zip(meshes, ws)]
+    b = ldni.sample_batch(dev, "xyz", normals="rgb8")
+    b.run()
+    for k, (v, f, bb, w) in enumerate(dev):
+        plain = ldni.sample(v, f, bb, w, "xyz")
+        for a in range(3):
+            got = b.to_torch(k, a)
+            assert got.normal.dtype == torch.int32 and got.normal.dim() == 1
+            assert torch.equal(got.offsets, plain[a].offsets) and torch.equal(got.depth, plain[a].depth)
+            assert torch.equal(got.tri, plain[a].tri)
+            assert np.array_equal(got.normal.cpu().numpy().view(np.uint32),
+                                  nc.encode(plain[a].normal.cpu().numpy()))
+    b.free()
+
+
+def test_codes_rejected_as_operation_inputs():
+    """LDNIs with 8-bit normal codes carry no float normals: a Boolean
+    operation on them is an argument error, not a silent misread."""
+    m = mg.c1_icosphere()
+    v, f = _dev(m.verts, np.float32), _dev(m.tris, np.int32)
+    r8 = ldni.sample(v, f, m.bbox, 64, "xyz", normals="rgb8")
+    with pytest.raises(ldni.LDNIError):
+        ldni.boolean(r8[0], r8[0], "union")
