@@ -70,6 +70,36 @@ def read_traffic(workload: str, kernel: str, source: str = "ldni_kernels.hip"):
     return float(m.group(1)) if m else None
 
 
+def read_atomics(workload: str, source: str = "ldni_kernels.hip"):
+    """Global atomic requests per launch of each forward kernel, from the
+    committed counter summary ({} if there is none or the source changed)."""
+    path = os.path.join(ROOT, "profiles", f"forward_kernels_{workload}_atomics.txt")
+    if not os.path.exists(path):
+        return {}
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    if not m or m.group(1) != kernel_source_hash(source):
+        return {}
+    return {k: float(v) for k, v in re.findall(r"^(\w+): requests_per_launch ([0-9.eE+]+)", txt, re.M)}
+
+
+def atomic_probe(torch, n: int = 1 << 21, words: int = 49152, reps: int = 10):
+    """Float atomic adds at random addresses (torch's index_add_, one atomic
+    per element): the global atomic rate a plain kernel reaches on this GPU,
+    the ceiling the kernels' atomic rates are compared with."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    idx = torch.randint(0, words, (n,), device="cuda", generator=g)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.zeros(words, dtype=torch.float32, device="cuda")
+    dst.index_add_(0, idx, src)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            dst.index_add_(0, idx, src)
+    return {"atomics_per_call": n, "G_per_s": round(n * reps / (t.ms / 1e3) / 1e9, 2),
+            "how": f"index_add_ of {n} float32 values at random indices of {words} words"}
+
+
 def fwd_bytes(mesh, samples):
     """Algorithmic bytes of one 3-axis forward: read the mesh once, write the
     offsets and the (depth, normal) samples once."""
@@ -647,6 +677,13 @@ def main():
                      "path_roofline": r["path_roofline"],
                      "kernels_ms_per_step": r["kernels_ms_per_step"]})
         line["hbm_copy_probe"] = copy_bandwidth(torch)
+        probe = atomic_probe(torch)
+        req = read_atomics(head)
+        ks = r["kernels_ms_per_step"]
+        line["atomics"] = {"probe": probe, "kernels": {
+            k: {"requests_per_launch": int(n), "G_per_s": round(n / (ks[k] / 1e3) / 1e9, 3) if ks.get(k) else None,
+                "frac_of_probe": round(n / (ks[k] / 1e3) / 1e9 / probe["G_per_s"], 4) if ks.get(k) else None}
+            for k, n in req.items()}}
         line["normal_rgb8"] = measure_rgb8(ldni, torch, mesh, max(2, args.steps // 2))
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_seconds)

@@ -46,3 +46,15 @@ def test_committed_traffic_summaries_match_their_sources():
     for n in names:
         kernel, workload = n[:-len("_traffic.txt")].split("_kernel_")
         assert bench.read_traffic(workload, kernel, sources[kernel]) is not None, n
+
+
+def test_committed_atomic_summaries_match_their_sources():
+    """Every committed atomics summary names the current hash of the kernel
+    source, so bench.py reports the kernels' atomic rates from it."""
+    names = [n for n in os.listdir(os.path.join(ROOT, "profiles")) if n.endswith("_atomics.txt")]
+    assert names
+    for n in names:
+        workload = n[len("forward_kernels_"):-len("_atomics.txt")]
+        got = bench.read_atomics(workload)
+        assert got and "setup" in got, n
+        assert all(v >= 0 for v in got.values())
