@@ -1399,6 +1399,11 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
     g.in[d] = AxisArrays{v.n_samples, v.offsets, v.depth, v.normal, v.tri};
     g.lo[d] = (double)bbox[d];
     g.h[d] = ((double)bbox[3 + d] - (double)bbox[d]) / (double)w;
+    // a centre f32(lo + (i + 0.5) h) is within 2^-24 (|lo| + (w + 1) h) of
+    // the real value, and the index estimate carries a float64 error of a
+    // few 2^-53 (w + 1); twice their sum in pixels, plus a millionth
+    g.margin[d] = 2.0 * (std::ldexp(std::fabs(g.lo[d]) + ((double)w + 1.0) * g.h[d], -24) / g.h[d] +
+                         std::ldexp((double)w + 1.0, -48)) + 1e-6;
     g.base[d] = base;
     base += v.n_samples;
     g.counts[d] = static_cast<uint32_t*>(res->offsets_buf) + d * (npix + 1);

@@ -305,6 +305,9 @@ struct OffsetArgs {
   uint32_t n_spheres;
   uint64_t base[3];
   double lo[3], h[3];
+  // per axis, the pixels by which a centre index can differ from the real
+  // (x - lo) / h - 0.5 for the float32 rounding of the centres
+  double margin[3];
   double r, eps;
   int32_t union_op;
   double* centres;

@@ -73,11 +73,13 @@ __global__ __launch_bounds__(kOffBlock) void offset_centres_kernel(OffsetArgs g)
   }
 }
 
-// Pixel range [i0, i1] of an image axis whose centres may lie within r of x
-// (one pixel of margin for the rounding of the centres); i0 > i1 if none.
+// Pixel range [i0, i1] of an image axis whose centres may lie within r of x:
+// a centre c_i with |c_i - x| < r has i within [t0 - m, t1 + m] for
+// t = (x -+ r - lo) / h - 0.5 and m the axis's rounding margin in pixels;
+// i0 > i1 if none.
 __device__ __forceinline__ void pixel_range(const OffsetArgs& g, int b, double x, int& i0, int& i1) {
   const double t0 = (x - g.r - g.lo[b]) / g.h[b] - 0.5, t1 = (x + g.r - g.lo[b]) / g.h[b] - 0.5;
-  const double f0 = floor(t0) - 1.0, f1 = ceil(t1) + 1.0;
+  const double f0 = floor(t0 - g.margin[b]), f1 = ceil(t1 + g.margin[b]);
   i0 = f0 < 0.0 ? 0 : f0 > (double)(g.w - 1) ? g.w : (int)f0;
   i1 = f1 < 0.0 ? -1 : f1 > (double)(g.w - 1) ? g.w - 1 : (int)f1;
 }
