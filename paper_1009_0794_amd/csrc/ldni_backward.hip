@@ -55,8 +55,7 @@ struct BackwardSet {
 // sample that finds no free slot adds its own directly (its triangle then has
 // no slot in this tile, so nothing stores over it).
 constexpr int kBwdTile = 16;
-constexpr int kBwdSlotBits = 10;
-constexpr int kBwdSlots = 1 << kBwdSlotBits;
+constexpr int kBwdSlots = 1024;
 constexpr int kBwdProbe = 32;
 
 // Whether every pixel whose centre can lie in the projection of triangle t
@@ -162,7 +161,7 @@ __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs
       continue;
     // slot of t in the table (linear probing, a bounded number of steps)
     const uint32_t key = (uint32_t)t + 1u;
-    uint32_t h = ((uint32_t)t * 2654435761u) >> (32 - kBwdSlotBits);
+    uint32_t h = ((uint32_t)t * 2654435761u) >> 22;  // 10 bits
     int slot = -1;
     for (int step = 0; step < kBwdProbe; ++step) {
       const uint32_t old = atomicCAS(&s_key[h], 0u, key);
