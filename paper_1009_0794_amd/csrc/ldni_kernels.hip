@@ -502,6 +502,16 @@ struct ChunkLds {
   int32_t wave_tmp[kWaves];
 };
 
+// Per-entry data of one chunk of a tile list for the sampling walk; an
+// entry's candidates end where cg.w says (an exclusive prefix over the chunk),
+// so its start is the end of the entry before it.
+struct SampleChunk {
+  float4 ab[kBlock];        // au, av, bu, bv
+  float4 cg[kBlock];        // cu, cv, px0 | py0 << 8 | (width - 1) << 16 (bits), end of candidates (bits)
+  float4 z[kBlock];         // az, bz, cz, triangle id (bits)
+  int32_t wave_tmp[kWaves];
+};
+
 struct TileGeom {
   int x0, y0, cw, ch;  // tile origin and extent in pixels
   int tile;            // tile index within its image
@@ -532,6 +542,28 @@ __device__ __forceinline__ bool covered(float au, float bu, float cu, float tav,
   const int s1 = orient(tbu, tbv, tcu, tcv, tmp);
   const int s2 = orient(tcu, tcv, tau, tav, tmp);
   return (s0 != 0) & (s0 == s1) & (s1 == s2);
+}
+
+// The same decision as covered(), first from float32 edge functions: the
+// product tav * tbu is rounded once (error at most 2^-24 of it, or 2^-150
+// below the normal range) and the FMA once more, so an edge value larger
+// in magnitude than 2^-22 |tav * tbu| + 2^-100 has the sign of the exact
+// edge function.  When all three are that large their signs decide (all
+// equal: covered); otherwise covered() decides in float64.
+__device__ __forceinline__ bool covered_sign(float au, float bu, float cu, float tav, float tbv, float tcv,
+                                             float ru) {
+  const float tau = au - ru, tbu = bu - ru, tcu = cu - ru;
+  const float p0 = tav * tbu, p1 = tbv * tcu, p2 = tcv * tau;
+  const float e0 = fmaf(tau, tbv, -p0), e1 = fmaf(tbu, tcv, -p1), e2 = fmaf(tcu, tav, -p2);
+  const bool sure = (fabsf(e0) > fmaf(fabsf(p0), 0x1p-22f, 0x1p-100f)) &
+                    (fabsf(e1) > fmaf(fabsf(p1), 0x1p-22f, 0x1p-100f)) &
+                    (fabsf(e2) > fmaf(fabsf(p2), 0x1p-22f, 0x1p-100f));
+  if (__builtin_expect(sure, 1)) {
+    const int32_t x0 = __float_as_int(e0), x1 = __float_as_int(e1), x2 = __float_as_int(e2);
+    return ((x0 ^ x1) | (x1 ^ x2)) >= 0;
+  }
+  Edges ed;
+  return covered(au, bu, cu, tav, tbv, tcv, ru, ed);
 }
 
 // Candidate rectangle of a tile-list entry in tile pixels, rows [y0, y1)
@@ -713,7 +745,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   __shared__ uint32_t s_cnt[kTilePix];
   __shared__ float s_cu[kMaxTileW];
   __shared__ float s_cv[kMaxTileH + 1];
-  __shared__ ChunkLds<true> L;
+  __shared__ SampleChunk L;
   __shared__ Lds H;
   __shared__ uint32_t s_red[kWaves];
   __shared__ uint32_t s_fill;
@@ -765,29 +797,37 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   for (uint32_t cbase = e_begin; cbase < e_end; cbase += kBlock) {
     // ---- load a chunk of entries with their candidate counts
     const int m = (int)min((uint32_t)kBlock, e_end - cbase);
+    int total;
     {
       const int k = threadIdx.x;
-      int nc = 0;
+      int nc = 0, gm = 0;
+      float4 ab = make_float4(0.f, 0.f, 0.f, 0.f), z = ab;
+      float2 cc = make_float2(0.f, 0.f);
       if (k < m) {
         const int2 ent = im.tile_list[cbase + k];
-        const int32_t t = ent.x;
         const EntryRect r = entry_rect(im, g, ent);
-        nc = r.width * (r.y1 - r.y0);
-        L.geom[k] = r.x0 | (r.y0 << 8) | ((r.width - 1) << 16);
-        if (nc > 0) {
-          const float* sp = im.soup + 9 * (int64_t)t;
-          L.ab[k] = make_float4(sp[im.u], sp[im.v], sp[3 + im.u], sp[3 + im.v]);
-          L.c[k] = make_float2(sp[6 + im.u], sp[6 + im.v]);
-          L.z[k] = make_float4(sp[im.a], sp[3 + im.a], sp[6 + im.a], __int_as_float(t));
+        if (r.y1 > r.y0) {
+          nc = r.width * (r.y1 - r.y0);
+          gm = r.x0 | (r.y0 << 8) | ((r.width - 1) << 16);
+          const float* sp = im.soup + 9 * (int64_t)ent.x;
+          ab = make_float4(sp[im.u], sp[im.v], sp[3 + im.u], sp[3 + im.v]);
+          cc = make_float2(sp[6 + im.u], sp[6 + im.v]);
+          z = make_float4(sp[im.a], sp[3 + im.a], sp[6 + im.a], __int_as_float(ent.x));
+        } else {
+          // an entry that does not fit (already reported): one candidate,
+          // pixel (0, 0), with all vertices at the origin, which covers
+          // nothing, so that every entry of the walk has candidates
+          nc = 1;
         }
       }
-      int total;
       const int excl = block_exclusive_scan<int>(nc, L.wave_tmp, total);
-      if (k < m) L.start[k] = excl;
-      if (k == 0) L.start[m] = total;
+      if (k < m) {
+        L.ab[k] = ab;
+        L.cg[k] = make_float4(cc.x, cc.y, __int_as_float(gm), __int_as_float(excl + nc));
+        L.z[k] = z;
+      }
       __syncthreads();
     }
-    const int total = L.start[m];
     const int run = min(max((total + kBlock - 1) / kBlock, 2), kMaxRun);
 
     for (int wb = 0; wb < total; wb += kBlock * run) {
@@ -796,55 +836,49 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
       int c = wb + threadIdx.x * run;
       const int cend = min(c + run, total);
       if (c < cend) {
-        int lo = 0, hi = m - 1;  // owner of c: the last entry whose start is <= c
+        int lo = 0, hi = m - 1;  // owner of c: the first entry whose candidates end after c
         while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (L.start[mid] <= c) lo = mid; else hi = mid - 1;
+          const int mid = (lo + hi) >> 1;
+          if (__float_as_int(L.cg[mid].w) > c) hi = mid; else lo = mid + 1;
         }
         int e = lo;
-        int gm = L.geom[e];
-        int width = ((gm >> 16) & 255) + 1;
-        int local = c - L.start[e];
-        int row = local / width;
-        int col = local - row * width;
-        int kend = L.start[e + 1];
+        const int first = e > 0 ? __float_as_int(L.cg[e - 1].w) : 0;
         float4 ab = L.ab[e];
-        float2 cc = L.c[e];
-        int px0 = gm & 255, py0 = (gm >> 8) & 255;
-        float rv = s_cv[py0 + row];
-        float tav = ab.y - rv, tbv = ab.w - rv, tcv = cc.y - rv;
+        float4 cg = L.cg[e];
+        int gm = __float_as_int(cg.z);
+        int width = ((gm >> 16) & 255) + 1;
+        int px0 = gm & 255;
+        int kend = __float_as_int(cg.w);
+        const int local = c - first;
+        const int row = local / width;
+        int col = local - row * width;
+        int py = ((gm >> 8) & 255) + row;
         for (; c < cend; ++c) {
-          if (c == kend) {  // next entry (every entry of a tile list has candidates)
-            ++e;
-            while (L.start[e + 1] <= c) ++e;
-            gm = L.geom[e];
-            width = ((gm >> 16) & 255) + 1;
-            px0 = gm & 255;
-            py0 = (gm >> 8) & 255;
-            row = 0;
-            col = 0;
-            kend = L.start[e + 1];
-            ab = L.ab[e];
-            cc = L.c[e];
-            rv = s_cv[py0];
-            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
-          }
-          Edges ed;
-          const bool hit = covered(ab.x, ab.z, cc.x, tav, tbv, tcv, s_cu[px0 + col], ed);
+          const float rv = s_cv[py];
+          const int px = px0 + col;
+          const bool hit = covered_sign(ab.x, ab.z, cg.x, ab.y - rv, ab.w - rv, cg.y - rv, s_cu[px]);
           const uint64_t mask = __ballot(hit);
           if (hit) {
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-            const uint32_t q = (uint32_t)((py0 + row) * cw + px0 + col);
+            const uint32_t q = __umul24((uint32_t)py, (uint32_t)cw) + (uint32_t)px;
             my_hits[nh + rank] = (typename Lds::Desc)(q | ((uint32_t)e << kQBits));
           }
           nh += (uint32_t)__popcll(mask);
-          if (++col == width) {
-            col = 0;
-            ++row;
-            rv = s_cv[py0 + row];
-            tav = ab.y - rv; tbv = ab.w - rv; tcv = cc.y - rv;
-          }
+          // the next candidate: the next column, row or entry, without
+          // branches (the entry's data is read again either way)
+          ++col;
+          const bool next_entry = c + 1 == kend;
+          const bool next_row = col == width;
+          e = min(e + (next_entry ? 1 : 0), m - 1);
+          ab = L.ab[e];
+          cg = L.cg[e];
+          gm = __float_as_int(cg.z);
+          col = (next_entry || next_row) ? 0 : col;
+          py = next_entry ? ((gm >> 8) & 255) : py + (next_row ? 1 : 0);
+          px0 = gm & 255;
+          width = ((gm >> 16) & 255) + 1;
+          kend = __float_as_int(cg.w);
         }
       }
       // lanes that left the walk early did not see the later ballots: the
@@ -866,7 +900,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
         const int py = (int)(((float)q + 0.5f) * inv_cw);
         const int px = q - py * cw;
         const float4 ab = L.ab[e];
-        const float2 cc = L.c[e];
+        const float4 cc = L.cg[e];
         const float4 z = L.z[e];
         const float rv = s_cv[py];
         Edges ed;
@@ -1543,9 +1577,10 @@ struct ItemGrabber {
 
 // Tiles [t0, t1) of the batch (the images of one tile class), work counter
 // `counter`, place runs of at most place_cap keys.
+// (the occupancy of sample_kernel: seven workgroups per CU for small tiles)
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_sample_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0,
-                                                              uint32_t t1, int counter, int place_cap) {
+__global__ void __launch_bounds__(kBlock, kTilePix <= kSmallTilePix ? 7 : 4)
+    batch_sample_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0, uint32_t t1, int counter, int place_cap) {
   __shared__ uint32_t s_item;
   ItemGrabber grab;
   for (;;) {
@@ -1583,9 +1618,11 @@ __global__ void __launch_bounds__(kBlock) batch_plan_items_kernel(BatchDevice B,
 // The place items of tiles [t0, t1): in launch order the items of tiles
 // with several items come first, then those of single-item tiles, each part
 // in tile order, so the class's items are two ranges.
+// (the occupancy the persistent grid is sized for: seven workgroups per CU
+// for small tiles, three for large ones)
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock) batch_place_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0,
-                                                             uint32_t t1, int counter) {
+__global__ void __launch_bounds__(kBlock, kTilePix <= kSmallTilePix ? 7 : 3)
+    batch_place_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0, uint32_t t1, int counter) {
   __shared__ uint32_t s_item;
   const uint32_t a0 = B.plan[t0], a1 = B.plan[t1];
   const uint32_t b0 = B.plan[n_tiles + t0], b1 = B.plan[n_tiles + t1];
