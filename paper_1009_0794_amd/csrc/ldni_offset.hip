@@ -175,6 +175,17 @@ struct SphereHit {
   float depth;
   float n[3];
 };
+// the depth alone (the count pass's small-volume test needs no normal)
+__device__ __forceinline__ float sphere_depth(const OffsetArgs& g, int a, double cu, double cv, uint32_t s,
+                                              bool is_exit) {
+  const int u = (a + 1) % 3, v = (a + 2) % 3;
+  const double* c = g.centres + 3 * (size_t)s;
+  const double du = cu - c[u], dv = cv - c[v];
+  const double rho2 = du * du + dv * dv;
+  const double t = sqrt(g.r * g.r - rho2);
+  const double z = is_exit ? c[a] + t : c[a] - t;
+  return (float)(z - g.lo[a]);
+}
 __device__ __forceinline__ SphereHit sphere_sample(const OffsetArgs& g, int a, double cu, double cv, uint32_t s,
                                                    bool is_exit) {
   const int u = (a + 1) % 3, v = (a + 2) % 3;
@@ -184,11 +195,16 @@ __device__ __forceinline__ SphereHit sphere_sample(const OffsetArgs& g, int a, d
   const double t = sqrt(g.r * g.r - rho2);
   const double z = is_exit ? c[a] + t : c[a] - t;
   const double sign = g.union_op ? 1.0 : -1.0;
+  const float nu = (float)(sign * (du / g.r)), nv = (float)(sign * (dv / g.r)),
+              na = (float)(sign * ((z - c[a]) / g.r));
+  // to world order by selects (an array indexed by the axis would live in
+  // scratch memory): x, y, z are (a, u, v) for a = 0, (v, a, u) for a = 1
+  // and (u, v, a) for a = 2
   SphereHit h;
   h.depth = (float)(z - g.lo[a]);
-  h.n[u] = (float)(sign * (du / g.r));
-  h.n[v] = (float)(sign * (dv / g.r));
-  h.n[a] = (float)(sign * ((z - c[a]) / g.r));
+  h.n[0] = a == 0 ? na : (a == 1 ? nv : nu);
+  h.n[1] = a == 0 ? nu : (a == 1 ? na : nv);
+  h.n[2] = a == 0 ? nv : (a == 1 ? nu : na);
   return h;
 }
 
@@ -221,27 +237,56 @@ __device__ __forceinline__ int wave_scan_max(int x) {
   return x;
 }
 
-// Bitonic sort of key[0..n) ascending by one wave (padded with ~0 to a power
-// of two of at least 64, within the buffer).
+// Sort of key[0..n) ascending by one wave: a bitonic network over the next
+// power of two in which every comparator puts the smaller key first (each
+// merge of blocks of k starts with a mirrored stage, pairing blk + r with
+// blk + k - 1 - r, followed by half-cleaners).  Keys beyond n count as
+// larger than all, so no comparator ever moves them: comparators that reach
+// beyond n are skipped, blocks wholly beyond n are not visited, and nothing
+// beyond n is read or written.  A lane takes up to four comparators of a
+// stage at a time, loading all of them before storing any (the comparators
+// of a stage are disjoint), so their LDS round trips overlap.
 __device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
   const uint32_t lane = lane_id();
-  uint32_t n2 = 64;
-  while (n2 < n) n2 <<= 1;
-  for (uint32_t k = n + lane; k < n2; k += 64) key[k] = ~0ull;
-  wave_sync();
-  for (uint32_t size = 2; size <= n2; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t q = lane; q < n2 / 2; q += 64) {
-        const uint32_t lo = 2 * q - (q & (stride - 1));
-        const uint32_t hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = key[lo], y = key[hi];
-        if ((x > y) == up) {
-          key[lo] = y;
-          key[hi] = x;
+  constexpr int kPairs = 4;
+  auto stage = [&](uint32_t pairs, auto&& pair_of) {
+    for (uint32_t h0 = lane; h0 < pairs; h0 += 64 * kPairs) {
+      uint64_t x[kPairs], y[kPairs];
+      uint32_t lo[kPairs], hi[kPairs];
+      bool act[kPairs];
+#pragma unroll
+      for (int j = 0; j < kPairs; ++j) {
+        const uint32_t h = h0 + 64u * j;
+        pair_of(h, lo[j], hi[j]);
+        act[j] = h < pairs && hi[j] < n;
+        if (act[j]) {
+          x[j] = key[lo[j]];
+          y[j] = key[hi[j]];
         }
       }
-      wave_sync();
+#pragma unroll
+      for (int j = 0; j < kPairs; ++j) {
+        if (act[j] && x[j] > y[j]) {
+          key[lo[j]] = y[j];
+          key[hi[j]] = x[j];
+        }
+      }
+    }
+    wave_sync();
+  };
+  for (uint32_t lk = 1; (1u << (lk - 1)) < n; ++lk) {  // blocks of k = 2^lk
+    const uint32_t k = 1u << lk, hk = k >> 1;
+    stage(((n + k - 1) >> lk) << (lk - 1), [&](uint32_t h, uint32_t& lo, uint32_t& hi) {
+      const uint32_t blk = (h >> (lk - 1)) << lk, r = h & (hk - 1);
+      lo = blk + r;
+      hi = blk + k - 1 - r;
+    });
+    for (uint32_t lj = lk - 1; lj-- > 0;) {  // half-cleaners, j = 2^lj = k/4 .. 1
+      const uint32_t jj = 1u << lj;
+      stage(((n + 2 * jj - 1) >> (lj + 1)) << lj, [&](uint32_t h, uint32_t& lo, uint32_t& hi) {
+        lo = ((h >> lj) << (lj + 1)) + (h & (jj - 1));
+        hi = lo + jj;
+      });
     }
   }
 }
@@ -370,7 +415,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   uint32_t big = 0xffffffffu;  // a depth whose group was found larger than a window
   auto depth_of = [&](uint64_t k) -> float {
     if (!(k & kSphereOrder)) return H.depth[o0 + (uint32_t)(k & 0x7fffffffu)];
-    return sphere_sample(g, a, cu, cv, (uint32_t)((k & 0x7fffffffu) >> 1), (k & 1u) != 0).depth;
+    return sphere_depth(g, a, cu, cv, (uint32_t)((k & 0x7fffffffu) >> 1), (k & 1u) != 0);
   };
   // Small interval removal over the first np end-point pairs of emit, which
   // are then counted or written (pairs are independent volumes, so the
