@@ -117,8 +117,11 @@ __global__ void __launch_bounds__(kBlock) backward_samples_kernel(BackwardSet bs
   float* const accp = im.acc;
 
   for (uint32_t f = threadIdx.x; f < S; f += kBlock) {
-    int r = 0;  // row of f: the last r with s_pre[r] <= f
-    while (r + 1 < ch && s_pre[r + 1] <= f) ++r;
+    int r = 0;  // row of f: the last r with s_pre[r] <= f (binary search)
+    for (int hi = ch - 1; r < hi;) {
+      const int mid = (r + hi + 1) >> 1;
+      if (s_pre[mid] <= f) r = mid; else hi = mid - 1;
+    }
     const uint32_t s = s_row[r][0] + (f - s_pre[r]);
     const int32_t t = im.tri[s];
     if (t < 0 || t >= bs.n_tris) continue;  // not a triangle of this mesh
