@@ -115,6 +115,21 @@ def test_noncubic_box_and_hits_outside_box():
     compare(_run(v, f, bb, 97), oracle.sample(v, f, bb, 97), bb, label="outside")
 
 
+@pytest.mark.parametrize("scale", [1e-20, 1e-12, 1e12, 3e19])
+def test_extreme_coordinate_scales(scale):
+    """The walk decides coverage from float32 edge functions where their
+    rounding bound allows and falls back to the float64 test elsewhere: tiny
+    coordinates (products below the float32 normal range) and huge ones
+    (products near or past its largest value) take the fallback or the
+    bound's edge, and must still match the oracle bit for bit."""
+    rng = np.random.default_rng(11)
+    v, f = mg.concat([mg.icosphere(2, 0.8, (0.05, -0.03, 0.02), mg.random_rotation(rng)),
+                      mg.torus(24, 12, 0.5, 0.15, (0.1, 0.1, -0.1), mg.random_rotation(rng))])
+    v = (v.astype(np.float64) * scale).astype(np.float32)
+    bb = tuple(float(np.float32(x * scale)) for x in (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0))
+    compare(_run(v, f, bb, 61), oracle.sample(v, f, bb, 61), bb, label=f"scale {scale:g}")
+
+
 def test_random_meshes_many_axes_masks():
     rng = np.random.default_rng(9)
     for k, axes in enumerate(["x", "y", "z", "xy", "yz", "xz", "xyz"]):
