@@ -3,6 +3,8 @@
 // with the sample set held fixed.
 #pragma clang fp contract(off)
 
+#include <cmath>
+
 #include "ldni_internal.hpp"
 
 namespace ldni {
@@ -28,6 +30,9 @@ inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_
 struct BackwardImage {
   int32_t a, u, v, w;
   double lo_u, h_u, lo_v, h_v;
+  // bound, in pixels, on the distance between a float32 pixel centre and
+  // its float64 position estimate (x - lo) / h - 0.5 for x within the image
+  double margin_u, margin_v;
   const uint32_t* offsets;  // [w*w+1]
   const int32_t* tri;       // [n]
   const float* gd;          // [n] or null
@@ -60,8 +65,8 @@ constexpr int kBwdProbe = 32;
 
 // Whether every pixel whose centre can lie in the projection of triangle t
 // on image im is a pixel of the tile (x0, y0, cw, ch): the centres within the
-// projection's bounding box, widened by a pixel for the rounding of the
-// centres.  Only then does the tile hold all of t's samples on im.
+// projection's bounding box, its index range widened by the image's rounding
+// margin.  Only then does the tile hold all of t's samples on im.
 __device__ __forceinline__ bool projection_in_tile(const BackwardSet& bs, const BackwardImage& im, int64_t t,
                                                    int x0, int y0, int cw, int ch) {
   const int32_t* fv = bs.tris + 3 * t;
@@ -74,10 +79,12 @@ __device__ __forceinline__ bool projection_in_tile(const BackwardSet& bs, const 
     vmin = fmin(vmin, (double)P[im.v]);
     vmax = fmax(vmax, (double)P[im.v]);
   }
-  // pixel i has centre lo + (i + 0.5) h; a centre in [mn, mx] has i within
-  // [floor(tmn), ceil(tmx)] for t = (x - lo) / h - 0.5, widened by one
-  const double iu0 = floor((umin - im.lo_u) / im.h_u - 0.5) - 1.0, iu1 = ceil((umax - im.lo_u) / im.h_u - 0.5) + 1.0;
-  const double iv0 = floor((vmin - im.lo_v) / im.h_v - 0.5) - 1.0, iv1 = ceil((vmax - im.lo_v) / im.h_v - 0.5) + 1.0;
+  // pixel i has centre f32(lo + (i + 0.5) h); a centre in [mn, mx] has i
+  // within [tmn - m, tmx + m] for t = (x - lo) / h - 0.5 and m the margin
+  const double iu0 = floor((umin - im.lo_u) / im.h_u - 0.5 - im.margin_u),
+               iu1 = ceil((umax - im.lo_u) / im.h_u - 0.5 + im.margin_u);
+  const double iv0 = floor((vmin - im.lo_v) / im.h_v - 0.5 - im.margin_v),
+               iv1 = ceil((vmax - im.lo_v) / im.h_v - 0.5 + im.margin_v);
   return iu0 >= (double)x0 && iu1 < (double)(x0 + cw) && iv0 >= (double)y0 && iv1 < (double)(y0 + ch);
 }
 
@@ -304,6 +311,14 @@ hipError_t launch_backward(const BackwardArgs& args, hipStream_t s) {
     im.h_u = (args.bbox[3 + im.u] - args.bbox[im.u]) / (double)args.w;
     im.lo_v = args.bbox[im.v];
     im.h_v = (args.bbox[3 + im.v] - args.bbox[im.v]) / (double)args.w;
+    // a centre's float32 rounding (2^-24 of its magnitude, at most
+    // |lo| + (w + 1) h) plus the float64 rounding of the estimate, doubled
+    const auto margin = [&](double lo, double h) {
+      return 2.0 * (std::ldexp(std::fabs(lo) + ((double)args.w + 1.0) * h, -24) / h +
+                    std::ldexp((double)args.w + 1.0, -48)) + 1e-6;
+    };
+    im.margin_u = margin(im.lo_u, im.h_u);
+    im.margin_v = margin(im.lo_v, im.h_v);
     im.offsets = a.offsets;
     im.tri = a.tri;
     im.gd = a.gd;

@@ -555,9 +555,9 @@ __device__ __forceinline__ bool covered_sign(float au, float bu, float cu, float
   const float tau = au - ru, tbu = bu - ru, tcu = cu - ru;
   const float p0 = tav * tbu, p1 = tbv * tcu, p2 = tcv * tau;
   const float e0 = fmaf(tau, tbv, -p0), e1 = fmaf(tbu, tcv, -p1), e2 = fmaf(tcu, tav, -p2);
-  const bool sure = (fabsf(e0) > fmaf(fabsf(p0), 0x1p-22f, 0x1p-100f)) &
-                    (fabsf(e1) > fmaf(fabsf(p1), 0x1p-22f, 0x1p-100f)) &
-                    (fabsf(e2) > fmaf(fabsf(p2), 0x1p-22f, 0x1p-100f));
+  const bool sure = ((int)(fabsf(e0) > fmaf(fabsf(p0), 0x1p-22f, 0x1p-100f)) &
+                     (int)(fabsf(e1) > fmaf(fabsf(p1), 0x1p-22f, 0x1p-100f)) &
+                     (int)(fabsf(e2) > fmaf(fabsf(p2), 0x1p-22f, 0x1p-100f))) != 0;
   if (__builtin_expect(sure, 1)) {
     const int32_t x0 = __float_as_int(e0), x1 = __float_as_int(e1), x2 = __float_as_int(e2);
     return ((x0 ^ x1) | (x1 ^ x2)) >= 0;

@@ -50,6 +50,36 @@ def test_backward_matches_oracle_gradient(w):
     assert np.abs(g - ref).max() <= 1e-4 * scale, np.abs(g - ref).max() / scale
 
 
+@pytest.mark.parametrize("name", ["box_on_centres", "polycube_on_centres", "lattice_hull"])
+def test_backward_vertices_on_centres_across_tile_borders(name):
+    """Meshes whose vertices sit on pixel centres, moved so that they span the
+    border between 16-pixel tiles (centres 15.5 and 16.5 of a 32-pixel grid):
+    a tile stores a triangle's sums with plain stores only when every pixel
+    that can hold its samples is in the tile, so triangles ending exactly on
+    the centres next to the border must still get every contribution."""
+    from tests.golden.fixture_meshes import FIXTURES
+    v0, f, _, _ = FIXTURES[name]
+    v = (np.asarray(v0, np.float64) + 12.0).astype(np.float32)
+    bb, w = (0.0, 0.0, 0.0, 32.0, 32.0, 32.0), 32
+    vt, ft = _dev(v, f)
+    res = ldni.sample(vt, ft, bb, w, "xyz")
+    rng = np.random.default_rng(7)
+    gd = {a: rng.normal(size=res[a].n).astype(np.float32) for a in res}
+    gn = {a: rng.normal(size=(res[a].n, 3)).astype(np.float32) for a in res}
+    g = ldni.ldni_backward(vt, ft, bb, w, res,
+                           {a: torch.from_numpy(x).to(DEV) for a, x in gd.items()},
+                           {a: torch.from_numpy(x).to(DEV) for a, x in gn.items()})
+    g = g.cpu().numpy().astype(np.float64)
+    ref = np.zeros_like(g)
+    orc = oracle.sample(v, f, bb, w)
+    for a in range(3):
+        assert res[a].n == orc[a].n
+        ref += oracle.backward(v, f, bb, w, a, orc[a], gd[a], gn[a])
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(g - ref).max() <= 1e-4 * scale, np.abs(g - ref).max() / scale
+
+
 def test_backward_accumulates_and_axes_optional():
     v, f, bb = _generic(5)
     vt, ft = _dev(v, f)
