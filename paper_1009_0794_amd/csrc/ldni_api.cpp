@@ -1372,9 +1372,12 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   const size_t scratch = std::max(scan_scratch_bytes(n_rays, 1), scan_scratch_bytes(npix, 3));
   const size_t o_deep = align_up(o_scratch + scratch);
   const size_t o_centres = align_up(o_deep + sizeof(uint32_t) * (size_t)n_rays);
-  // the end points the count pass keeps for the write pass (when this stays modest)
-  const size_t saved_bytes = sizeof(uint64_t) * kOffsetSaved * 3 * (size_t)npix;
-  const bool use_saved = saved_bytes <= ((size_t)1 << 30);
+  // the end points the count pass keeps for the write pass: as many per ray
+  // (64, 32 or 16) as fit in 1 GiB, else none (the write pass recomputes)
+  uint32_t n_saved = kOffsetSavedMax;
+  while (n_saved >= 16 && sizeof(uint64_t) * n_saved * 3 * (size_t)npix > ((size_t)1 << 30)) n_saved /= 2;
+  const bool use_saved = n_saved >= 16;
+  const size_t saved_bytes = use_saved ? sizeof(uint64_t) * n_saved * 3 * (size_t)npix : 0;
   const size_t o_saved = align_up(o_centres + 3 * sizeof(double) * (size_t)std::max<uint64_t>(n_total, 1));
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -1420,6 +1423,7 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   g.ray_start = reinterpret_cast<uint32_t*>(wb + o_start);
   g.centres = reinterpret_cast<double*>(wb + o_centres);
   g.saved = use_saved ? reinterpret_cast<uint64_t*>(wb + o_saved) : nullptr;
+  g.n_saved = use_saved ? n_saved : 0u;
   g.deep = reinterpret_cast<uint32_t*>(wb + o_deep);
   g.n_deep = 0;
   void* scr = wb + o_scratch;

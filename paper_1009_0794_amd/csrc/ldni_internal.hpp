@@ -296,7 +296,7 @@ hipError_t launch_node_stats(const NodeArgs& g, hipStream_t s);
 constexpr int kOffsetBuf = 1024;              // events of one depth window of one ray, in LDS
 constexpr int kOffsetKeep = 896;              // a full window is cut back to fewer events than this
 constexpr int kOffsetEmit = 128;              // end points of one ray's result before small volumes go
-constexpr int kOffsetSaved = 16;              // end points per ray kept by the count pass for the write pass
+constexpr int kOffsetSavedMax = 64;           // most end points per ray the count pass keeps for the write pass
 constexpr int kOffsetDeep = 512;              // a ray with more spheres than this is started first
 constexpr uint32_t kMaxSpheres = 1u << 30;    // sphere numbers fit 30 bits of the sort key
 struct OffsetArgs {
@@ -317,7 +317,8 @@ struct OffsetArgs {
   float* out_depth[3];
   float* out_normal[3];
   int32_t* out_tri[3];
-  uint64_t* saved;   // [3 * w * w][kOffsetSaved] kept end-point keys, or null (the write pass recomputes)
+  uint64_t* saved;   // [3 * w * w][n_saved] kept end-point keys, or null (the write pass recomputes)
+  uint32_t n_saved;  // end points kept per ray (at most kOffsetSavedMax)
   // rays with more than kOffsetDeep spheres, listed (any order) so that the
   // ray passes start them first; n_deep of them (known to the host before
   // the ray passes; status[16] counts them on the device)

@@ -298,6 +298,8 @@ __device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
 static_assert(kOffsetBuf / 32 >= 32, "the radix select's 32-bin histogram must fit the wave's state bits");
 // a sweep step appends up to 64 end points after a flush that leaves one
 static_assert(kOffsetEmit >= 65, "the emit buffer takes one step after a flush");
+// a ray's kept end points are expanded by one wave, one per lane
+static_assert(kOffsetSavedMax <= 64, "kept end points are written one per lane");
 __device__ __forceinline__ uint32_t select_depth(const uint64_t* key, uint32_t n, uint32_t rank, uint32_t* hist) {
   const uint32_t lane = lane_id();
   uint32_t prefix = 0, mask = 0;
@@ -391,8 +393,8 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
     cnt = g.out_offsets[a][p + 1] - out;
     if (cnt == 0) return;
     // a ray whose end points the count pass kept: expand them
-    if (g.saved && cnt <= (uint32_t)kOffsetSaved) {
-      if (lane < cnt) write_event(g, a, p, cu, cv, g.saved[(size_t)ray * kOffsetSaved + lane], (size_t)out + lane);
+    if (g.saved && cnt <= g.n_saved) {
+      if (lane < cnt) write_event(g, a, p, cu, cv, g.saved[(size_t)ray * g.n_saved + lane], (size_t)out + lane);
       return;
     }
   }
@@ -441,9 +443,9 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
         write_event(g, a, p, cu, cv, ea, (size_t)out + 2 * rank);
         write_event(g, a, p, cu, cv, eb, (size_t)out + 2 * rank + 1);
       }
-      if (!kWrite && keep && g.saved && 2 * rank + 1 < (uint32_t)kOffsetSaved) {
-        g.saved[(size_t)ray * kOffsetSaved + 2 * rank] = ea;
-        g.saved[(size_t)ray * kOffsetSaved + 2 * rank + 1] = eb;
+      if (!kWrite && keep && g.saved && 2 * rank + 1 < g.n_saved) {
+        g.saved[(size_t)ray * g.n_saved + 2 * rank] = ea;
+        g.saved[(size_t)ray * g.n_saved + 2 * rank + 1] = eb;
       }
       kept += (uint32_t)__popcll(km);
     }
