@@ -717,16 +717,22 @@ __device__ __forceinline__ float depth_of(const Edges& e, float az, float bz, fl
 // region is walked again by the write pass.
 constexpr uint32_t kMinStageLayers = 64, kMaxStageLayers = 1024;
 
-// Hits found by a wave in one window of its walk, waiting for their depth.
-constexpr int kMaxRun = 16;                 // candidates per thread per window
-constexpr int kWaveHits = 64 * kMaxRun;     // hit descriptors per wave per window
+// Workgroups per CU the sampling kernels are built for: seven for small
+// tiles, five for large ones (their LDS: 32-bit hit descriptors, larger
+// count and centre arrays).
+template <int kTilePix>
+constexpr int sample_wgs_per_cu() { return kTilePix <= kSmallTilePix ? 7 : 5; }
 
+// Hits found by a wave in one window of its walk, waiting for their depth:
+// at most kRun candidates per thread per window (12 for large tiles, so that
+// five of their workgroups fit a CU's LDS).
 template <int kTilePix>
 struct SampleLds {
   // descriptor: tile pixel q | chunk entry << kQBits
   static constexpr int kQBits = kTilePix <= 256 ? 8 : 10;
+  static constexpr int kRun = kTilePix <= kSmallTilePix ? 16 : 12;
   using Desc = typename std::conditional<(kTilePix <= 256), uint16_t, uint32_t>::type;
-  Desc hit[kWaves][kWaveHits];
+  Desc hit[kWaves][64 * kRun];
 };
 
 // One walk of the tile.  Candidates are split into runs of equal length
@@ -828,7 +834,7 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
       }
       __syncthreads();
     }
-    const int run = min(max((total + kBlock - 1) / kBlock, 2), kMaxRun);
+    const int run = min(max((total + kBlock - 1) / kBlock, 2), Lds::kRun);
 
     for (int wb = 0; wb < total; wb += kBlock * run) {
       // ---- walk: covered candidates append their descriptor
@@ -955,9 +961,9 @@ __device__ void sample_tile(const Image& im, int tile, uint32_t gtile, uint32_t*
   }
 }
 
-// (at most 72 VGPRs: seven workgroups per CU)
+// (small tiles: at most 72 VGPRs, seven workgroups per CU)
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock, kTilePix <= kSmallTilePix ? 7 : 4) sample_kernel(ImageSet set) {
+__global__ void __launch_bounds__(kBlock, sample_wgs_per_cu<kTilePix>()) sample_kernel(ImageSet set) {
   const int k = image_of_block(set, blockIdx.x);
   sample_tile<kTilePix>(set.img[k], (int)(blockIdx.x - set.tile_start[k]), blockIdx.x, set.plan,
                         set.tile_start[set.n], set.place_cap);
@@ -1577,9 +1583,9 @@ struct ItemGrabber {
 
 // Tiles [t0, t1) of the batch (the images of one tile class), work counter
 // `counter`, place runs of at most place_cap keys.
-// (the occupancy of sample_kernel: seven workgroups per CU for small tiles)
+// (the occupancy of sample_kernel)
 template <int kTilePix>
-__global__ void __launch_bounds__(kBlock, kTilePix <= kSmallTilePix ? 7 : 4)
+__global__ void __launch_bounds__(kBlock, sample_wgs_per_cu<kTilePix>())
     batch_sample_kernel(BatchDevice B, uint32_t n_tiles, uint32_t t0, uint32_t t1, int counter, int place_cap) {
   __shared__ uint32_t s_item;
   ItemGrabber grab;
@@ -1894,10 +1900,10 @@ hipError_t launch_batch_scatter(const BatchDevice& b, uint32_t chunks, hipStream
 
 hipError_t launch_batch_sample(const BatchDevice& b, uint32_t n_tiles, uint32_t n_small, hipStream_t s) {
   if (n_small > 0)
-    hipLaunchKernelGGL(batch_sample_kernel<kSmallTilePix>, dim3(persistent_grid(n_small, 7)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(batch_sample_kernel<kSmallTilePix>, dim3(persistent_grid(n_small, sample_wgs_per_cu<kSmallTilePix>())), dim3(kBlock), 0, s,
                        b, n_tiles, 0u, n_small, 0, place_stage_cap(kSmallTilePix));
   if (n_tiles > n_small)
-    hipLaunchKernelGGL(batch_sample_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles - n_small, 4)), dim3(kBlock),
+    hipLaunchKernelGGL(batch_sample_kernel<kMaxTilePix>, dim3(persistent_grid(n_tiles - n_small, sample_wgs_per_cu<kMaxTilePix>())), dim3(kBlock),
                        0, s, b, n_tiles, n_small, n_tiles, 3, place_stage_cap(kMaxTilePix));
   return hipGetLastError();
 }
