@@ -1374,8 +1374,11 @@ ldni_status ldni_offset(const ldni_axis_view views[3], const float bbox[6], floa
   const size_t o_centres = align_up(o_deep + sizeof(uint32_t) * (size_t)n_rays);
   // the end points the count pass keeps for the write pass: as many per ray
   // (64, 32 or 16) as fit in 1 GiB, else none (the write pass recomputes)
+  size_t saved_cap = (size_t)1 << 30;
+  // test hook: a smaller budget for them (0: none kept)
+  if (const char* env = std::getenv("LDNI_OFFSET_KEEP_BYTES")) saved_cap = std::strtoull(env, nullptr, 10);
   uint32_t n_saved = kOffsetSavedMax;
-  while (n_saved >= 16 && sizeof(uint64_t) * n_saved * 3 * (size_t)npix > ((size_t)1 << 30)) n_saved /= 2;
+  while (n_saved >= 16 && sizeof(uint64_t) * n_saved * 3 * (size_t)npix > saved_cap) n_saved /= 2;
   const bool use_saved = n_saved >= 16;
   const size_t saved_bytes = use_saved ? sizeof(uint64_t) * n_saved * 3 * (size_t)npix : 0;
   const size_t o_saved = align_up(o_centres + 3 * sizeof(double) * (size_t)std::max<uint64_t>(n_total, 1));

@@ -127,6 +127,36 @@ def test_flower_sampled_rays(w, r_pix):
                                       np.array([n for _, n, _ in res], np.float32).reshape(-1, 3).view(np.uint32))
 
 
+@pytest.mark.parametrize("keep", [None, 32, 16, 0])
+def test_kept_end_points_do_not_change_results(keep, monkeypatch):
+    """The count pass keeps up to 64 end points per ray (as many as fit its
+    buffer budget) and the write pass expands those rays from them, sweeping
+    only the others again; every budget (64, 32, 16 or none kept) gives the
+    same offsets as the oracle on sampled rays of the flower at w = 128."""
+    w = 128
+    if keep is not None:
+        monkeypatch.setenv("LDNI_OFFSET_KEEP_BYTES", str(8 * keep * 3 * w * w))
+    m = mg.c2_flower()
+    L = oracle.sample(m.verts, m.tris, m.bbox, w, axes="xyz")
+    G = {a: _to_gpu(a, L[a]) for a in range(3)}
+    h = (m.bbox[3] - m.bbox[0]) / w
+    rng = np.random.default_rng(5)
+    for r in (2.0 * h, -2.0 * h):
+        got = ldni.offset(G, m.bbox, r)
+        for a in range(3):
+            off = got[a].offsets.cpu().numpy().view(np.uint32).astype(np.int64)
+            dep = got[a].depth.cpu().numpy()
+            tri = got[a].tri.cpu().numpy()
+            cnt = np.diff(off)
+            # rays with many end points first: they take the kept or the swept path by budget
+            pix = np.concatenate([np.argsort(-cnt)[:100], rng.integers(0, w * w, 200)])
+            ref = oo.offset_rays(L, m.bbox, w, r, a, pix)
+            for p, res in zip(pix, ref):
+                s = slice(off[p], off[p + 1])
+                assert dep[s].view(np.uint32).tolist() == [np.float32(d).view(np.uint32) for d, _, _ in res]
+                assert tri[s].tolist() == [t for _, _, t in res]
+
+
 def test_empty_solid():
     w = 9
     e = oracle.AxisLDNI(w=w, offsets=np.zeros(w * w + 1, np.uint32), depth=np.zeros(0, np.float32),
