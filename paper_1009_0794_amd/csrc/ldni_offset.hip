@@ -293,9 +293,10 @@ __device__ __forceinline__ void wave_sort(uint64_t* key, uint32_t n) {
 
 // The orderable depth of the event of the given rank (0-based) among
 // key[0..n) by one wave: a radix select over the 32 depth bits, five bits a
-// pass, with a 32-bin histogram in hist (32 words; the ray pass lends it
-// the wave's state bits, which hold kOffsetBuf / 32 words).
-static_assert(kOffsetBuf / 32 >= 32, "the radix select's 32-bin histogram must fit the wave's state bits");
+// pass, with a 32-bin histogram in hist (32 words of the wave's own).
+// A cut window keeps fewer than kOffsetKeep events and then takes one more
+// step of the sphere loop (two events per lane).
+static_assert(kOffsetKeep + 128 <= kOffsetBuf, "a cut window takes one more step of 128 events");
 // a sweep step appends up to 64 end points after a flush that leaves one
 static_assert(kOffsetEmit >= 65, "the emit buffer takes one step after a flush");
 // a ray's kept end points are expanded by one wave, one per lane
@@ -360,6 +361,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
   __shared__ uint64_t s_key[kOffWaves][kOffsetBuf];
   __shared__ uint64_t s_emit[kOffWaves][kOffsetEmit];
   __shared__ uint32_t s_rbit[kOffWaves][kOffsetBuf / 32];
+  __shared__ uint32_t s_hist[kOffWaves][32];
 
   const int wv = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(kOffBlock) void offset_ray_kernel(OffsetArgs g) {
       if (n + total > (uint32_t)kOffsetBuf) {
         // the depth of the kOffsetKeep-th smallest event becomes the bound;
         // the events before it are compacted to the front (unsorted)
-        const uint32_t cut = select_depth(key, n, (uint32_t)kOffsetKeep, rbit);
+        const uint32_t cut = select_depth(key, n, (uint32_t)kOffsetKeep, s_hist[wv]);
         uint32_t m = 0;
         for (uint32_t c0 = 0; c0 < n; c0 += 64) {
           const uint32_t q = c0 + lane;
