@@ -89,16 +89,32 @@ __device__ __forceinline__ uint32_t sweep(const float* da, uint32_t na, const fl
   return n;
 }
 
-// Stores result sample at (output index) from input sample src of A or B.
-__device__ __forceinline__ void put(const BooleanArgs& g, uint64_t at, bool from_b, uint64_t src) {
+// One input sample of A or B, read whole before anything is stored (the
+// compiler cannot reorder loads past stores to other arrays, so reading and
+// storing field by field would wait for each load in turn).
+struct Sample {
+  float d, nx, ny, nz;
+  int32_t t;
+};
+__device__ __forceinline__ Sample get(const BooleanArgs& g, bool from_b, uint64_t src) {
   const AxisArrays& in = from_b ? g.b : g.a;
+  Sample x;
+  x.d = in.depth[src];
+  x.nx = in.normal[3 * src];
+  x.ny = in.normal[3 * src + 1];
+  x.nz = in.normal[3 * src + 2];
+  x.t = in.tri[src];
+  return x;
+}
+
+// Stores result sample at (output index) from a sample of A or B.
+__device__ __forceinline__ void put(const BooleanArgs& g, uint64_t at, bool from_b, const Sample& x) {
   const float sign = (from_b && g.op == kBoolDifference) ? -1.0f : 1.0f;
-  g.out_depth[at] = in.depth[src];
-  g.out_normal[3 * at] = sign * in.normal[3 * src];
-  g.out_normal[3 * at + 1] = sign * in.normal[3 * src + 1];
-  g.out_normal[3 * at + 2] = sign * in.normal[3 * src + 2];
-  const int32_t t = in.tri[src];
-  g.out_tri[at] = from_b ? -1 - t : t;
+  g.out_depth[at] = x.d;
+  g.out_normal[3 * at] = sign * x.nx;
+  g.out_normal[3 * at + 1] = sign * x.ny;
+  g.out_normal[3 * at + 2] = sign * x.nz;
+  g.out_tri[at] = from_b ? -1 - x.t : x.t;
 }
 
 // A wave takes 64 consecutive pixels.  Their samples are contiguous in both
@@ -270,17 +286,19 @@ __global__ void __launch_bounds__(kBoolBlock) boolean_write_kernel(BooleanArgs g
       base[u] = from_b[u] ? s_b0[wave][lo] : s_a0[wave][lo];
       src[u] = rf & ~kFromB;
     }
+    // the four samples' reads, all issued before the stores
+    Sample x[4];
+    bool ok[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t k = k0 + (uint32_t)lane + 64u * u;
-      if (!any[u]) continue;
       const uint64_t si = (uint64_t)base[u] + src[u];
-      if (si >= (from_b[u] ? g.b.n : g.a.n)) {  // inputs changed between the passes
-        atomicOr(g.status, kStatusMismatch);
-        continue;
-      }
-      put(g, k, from_b[u], si);
+      ok[u] = any[u] && si < (from_b[u] ? g.b.n : g.a.n);
+      if (any[u] && !ok[u]) atomicOr(g.status, kStatusMismatch);  // inputs changed between the passes
+      if (ok[u]) x[u] = get(g, from_b[u], si);
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ok[u]) put(g, k0 + (uint32_t)lane + 64u * u, from_b[u], x[u]);
   }
 }
 
