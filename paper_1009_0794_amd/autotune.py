@@ -24,7 +24,7 @@ import math
 import os
 from typing import Dict, Iterable, Tuple
 
-SHAPES = [(32, 32), (16, 16), (64, 16), (32, 8), (64, 8), (128, 8), (16, 32), (8, 8)]
+SHAPES = [(32, 32), (16, 16), (64, 16), (32, 8), (64, 8), (128, 8), (16, 32), (8, 32), (8, 8)]
 DEFAULT = (0, 0)  # the library chooses from the triangle density
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.environ.get("LDNI_TILE_TABLE", os.path.join(HERE, "tile_table.json"))
